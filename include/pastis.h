@@ -1,0 +1,168 @@
+/*
+ * pastis.h -- C ABI of the gfx950 (MI355X) many-to-many protein similarity
+ * search library: sequences in, weighted similarity edges out.
+ *
+ * The operation is the one stated in the paper's problem definition (Selvitopi
+ * et al., SC20, Section II): given a set S of n protein sequences and similarity
+ * constraints, compute the protein similarity graph G = (V = S, E), where an
+ * edge joins two sequences that exceed the similarity threshold and carries a
+ * weight.  The pipeline is that of Section IV: candidate pairs from shared
+ * (optionally substitute) k-mers through a sparse product A A^T or A S A^T
+ * (Sections IV-A to IV-C), pairwise alignment of every candidate by
+ * Smith-Waterman or x-drop seed extension (Section IV-E), and the
+ * identity/coverage filter (Section IV-F).
+ *
+ * Conventions for every entry point:
+ *   - Every call returns a pastis_status; nothing aborts and no exception
+ *     crosses this boundary.  pastis_last_error(ctx) gives a detail string.
+ *   - Pointers marked "device" are HIP device pointers; "host" are host
+ *     pointers.  Arguments with an `*_on_device` flag accept either.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     device work of a call is ordered on it.  Inputs are borrowed: the caller
+ *     keeps them alive and unmodified until that work completes.  Calls that
+ *     return sizes to the host synchronise the stream before returning.
+ *   - A pastis_ctx is bound to one device and is not thread-safe; use one per
+ *     host thread.  The library owns every buffer it allocates; results are
+ *     owned until pastis_result_free.
+ *   - Residues are ASCII letters of ARNDCQEGHILKMFPSTWYVBZX* (upper case);
+ *     any other byte is rejected with PASTIS_E_BAD_RESIDUE.
+ *   - Sequence lengths must be <= 65535 (positions are 16-bit in the kernels);
+ *     longer sequences are rejected with PASTIS_E_INVAL.  Sequences shorter
+ *     than k are valid and yield no k-mers; n = 0 yields no edges.
+ */
+#ifndef PASTIS_H
+#define PASTIS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pastis_status {
+    PASTIS_OK = 0,
+    PASTIS_E_INVAL = 1,       /* bad argument or parameter */
+    PASTIS_E_BAD_RESIDUE = 2, /* a byte outside the 24-letter alphabet */
+    PASTIS_E_NOMEM = 3,       /* device or host allocation failed */
+    PASTIS_E_DEVICE = 4,      /* a HIP runtime error (see pastis_last_error) */
+    PASTIS_E_CAPACITY = 5,    /* destination buffer too small; nothing written */
+    PASTIS_E_STATE = 6        /* call out of order (e.g. no candidates yet) */
+} pastis_status;
+
+typedef enum pastis_align_mode {
+    PASTIS_ALIGN_SW = 0, /* Smith-Waterman over whole sequences (Section IV-E) */
+    PASTIS_ALIGN_XD = 1  /* seed-and-extend with gapped x-drop from each seed (Section IV-E) */
+} pastis_align_mode;
+
+typedef enum pastis_weight_mode {
+    PASTIS_WEIGHT_ANI = 0, /* identity weight; identity/coverage cut applies (Section VI-B) */
+    PASTIS_WEIGHT_NS = 1   /* score / shorter length; no cut-off (Section VI-B) */
+} pastis_weight_mode;
+
+/* Parameters of one search.  Defaults (pastis_default_params) are the paper's
+ * settings of Section VI: k = 6, BLOSUM62, gap open 11, gap extend 1,
+ * x-drop 49, identity >= 30%, coverage >= 70%. */
+typedef struct pastis_params {
+    int32_t k;                /* k-mer length, 1..6 */
+    int32_t n_subs;           /* m substitute k-mers per k-mer (0 = exact k-mers), 0..64 */
+    int32_t sub_alphabet;     /* residues substitutes are drawn from: 20 (standard) or 24 */
+    int32_t ck_min;           /* keep candidate pairs sharing >= ck_min k-mers (>= 1) */
+    int32_t align_mode;       /* pastis_align_mode */
+    int32_t gap_open;         /* a gap of length L costs gap_open + gap_extend * L */
+    int32_t gap_extend;
+    int32_t xdrop;            /* XD: X */
+    int32_t min_identity_pct; /* ANI cut: 100 * matches >= pct * columns */
+    int32_t min_coverage_pct; /* ANI cut: 100 * aligned span >= pct * shorter length */
+    int32_t weight_mode;      /* pastis_weight_mode */
+    int32_t score_width;      /* 0 = automatic, 16 or 32: DP word width request */
+    int32_t full_records;     /* 1: traceback statistics (beg, matches, columns) for every
+                                 aligned pair; 0: only for pairs whose coverage cut can
+                                 still hold (the others report beg = -1, passed = 0) */
+    int32_t reserved[7];      /* must be zero */
+} pastis_params;
+
+/* One similarity edge, 48 bytes.  i < j; edges are sorted by (i, j).
+ * Positions are 0-based and inclusive.  identity = matches / columns and
+ * ns_weight = score / min(len_i, len_j), both IEEE float32 round-to-nearest. */
+typedef struct pastis_edge {
+    uint32_t i, j;
+    int32_t score;
+    uint32_t matches, columns;
+    uint32_t beg_i, end_i, beg_j, end_j;
+    uint16_t shared_kmers; /* candidate count (capped at 65535) */
+    uint8_t seed_used;     /* XD: 0 or 1; SW: 255 */
+    uint8_t flags;         /* bit 0: the alignment's rows were sequence j (j shorter) */
+    float identity;
+    float ns_weight;
+} pastis_edge;
+
+/* Per-pair alignment record returned by pastis_align_pairs, 48 bytes, in the
+ * orientation rows = a = the shorter sequence of the pair (the first on equal
+ * length), columns = b.  Fields are -1 / 0 when there is no alignment. */
+typedef struct pastis_pair_record {
+    int32_t score;
+    int32_t beg_a, end_a, beg_b, end_b;
+    int32_t matches, columns;
+    int32_t seed_used; /* XD: index of the chosen seed, -1 if none; SW: -1 */
+    int32_t passed;    /* 1 when the identity and coverage cut holds */
+    int32_t swapped;   /* 1 when a is the second sequence of the pair */
+    int64_t cells;     /* DP cells evaluated for this pair */
+} pastis_pair_record;
+
+typedef struct pastis_run_stats {
+    int64_t n_sequences;
+    int64_t n_residues;
+    int64_t n_kmers;          /* nnz(A): distinct (sequence, k-mer) entries */
+    int64_t n_candidates;     /* pairs passing the common-k-mer threshold */
+    int64_t n_aligned;        /* pairs aligned */
+    int64_t n_edges;
+    int64_t cells;            /* DP cells evaluated */
+    int64_t stats_pass_pairs; /* pairs that needed the statistics pass */
+    int64_t int32_pairs;      /* pairs computed with 32-bit DP words */
+    double ms_total;
+    double ms_stage[8]; /* encode, k-mers, S, SpGEMM, schedule, align, filter, other */
+} pastis_run_stats;
+
+typedef struct pastis_ctx pastis_ctx;
+typedef struct pastis_result pastis_result;
+
+/* Fill *p with the defaults listed above (n_subs 0, ck_min 1, SW, ANI). */
+void pastis_default_params(pastis_params *p);
+
+/* Create a context on HIP device `device` with a validated copy of *p.
+ * Errors: PASTIS_E_INVAL (bad parameter), PASTIS_E_DEVICE. */
+pastis_status pastis_create(const pastis_params *p, int device, pastis_ctx **out);
+void pastis_destroy(pastis_ctx *ctx);
+
+const char *pastis_status_string(pastis_status s);
+/* Detail of the last failure on ctx (empty string if none); owned by ctx. */
+const char *pastis_last_error(const pastis_ctx *ctx);
+/* First offending byte index of the last PASTIS_E_BAD_RESIDUE, else -1. */
+int64_t pastis_bad_residue_index(const pastis_ctx *ctx);
+
+/* Stage 1 of Section IV: encode residues (Section V-B numbering) into
+ * `codes` (device, n_residues bytes).  residues: device or host per flag.
+ * Errors: PASTIS_E_BAD_RESIDUE (index via pastis_bad_residue_index). */
+pastis_status pastis_encode(pastis_ctx *ctx, const uint8_t *residues, int64_t n_residues, int input_on_device,
+                            uint8_t *codes, void *stream);
+
+/* Align a given list of pairs (Section IV-E) and apply the filter of
+ * Section IV-F, with the context's align_mode and scoring parameters.
+ *   residues [offsets[n]] ASCII, offsets [n+1] int64: device or host per flag;
+ *   pi, pj [npairs] uint32 sequence indices (pi != pj), device;
+ *   seed1, seed2 [npairs] uint32 seed keys (pos_in_min(pi,pj) << 16 |
+ *     pos_in_max(pi,pj)), 0xFFFFFFFF = absent, device; may be NULL for SW;
+ *   out [npairs] pastis_pair_record, device.
+ * Errors: PASTIS_E_INVAL (index out of range, length > 65535),
+ * PASTIS_E_BAD_RESIDUE, PASTIS_E_DEVICE. */
+pastis_status pastis_align_pairs(pastis_ctx *ctx, const uint8_t *residues, const int64_t *offsets, int64_t n,
+                                 int input_on_device, const uint32_t *pi, const uint32_t *pj, const uint32_t *seed1,
+                                 const uint32_t *seed2, int64_t npairs, pastis_pair_record *out, void *stream);
+
+/* Counters and per-stage times of the last pastis_search / pastis_align_pairs. */
+pastis_status pastis_stats(const pastis_ctx *ctx, pastis_run_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

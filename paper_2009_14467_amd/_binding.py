@@ -1,0 +1,260 @@
+"""ctypes binding of libpastis_hip.so (the C ABI in include/pastis.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  torch supplies device memory and the current stream.  There is no
+fallback: if the library is missing this module raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpastis_hip.so")
+
+OK = 0
+STATUS_NAMES = {0: "OK", 1: "E_INVAL", 2: "E_BAD_RESIDUE", 3: "E_NOMEM", 4: "E_DEVICE", 5: "E_CAPACITY", 6: "E_STATE"}
+
+RECORD_DTYPE = np.dtype(
+    [
+        ("score", np.int32),
+        ("beg_a", np.int32),
+        ("end_a", np.int32),
+        ("beg_b", np.int32),
+        ("end_b", np.int32),
+        ("matches", np.int32),
+        ("columns", np.int32),
+        ("seed_used", np.int32),
+        ("passed", np.int32),
+        ("swapped", np.int32),
+        ("cells", np.int64),
+    ],
+    align=True,
+)
+assert RECORD_DTYPE.itemsize == 48
+
+EDGE_DTYPE = np.dtype(
+    [
+        ("i", np.uint32),
+        ("j", np.uint32),
+        ("score", np.int32),
+        ("matches", np.uint32),
+        ("columns", np.uint32),
+        ("beg_i", np.uint32),
+        ("end_i", np.uint32),
+        ("beg_j", np.uint32),
+        ("end_j", np.uint32),
+        ("shared_kmers", np.uint16),
+        ("seed_used", np.uint8),
+        ("flags", np.uint8),
+        ("identity", np.float32),
+        ("ns_weight", np.float32),
+    ]
+)
+assert EDGE_DTYPE.itemsize == 48
+
+
+class PastisError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {detail}")
+        self.status = status
+        self.detail = detail
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("k", ctypes.c_int32),
+        ("n_subs", ctypes.c_int32),
+        ("sub_alphabet", ctypes.c_int32),
+        ("ck_min", ctypes.c_int32),
+        ("align_mode", ctypes.c_int32),
+        ("gap_open", ctypes.c_int32),
+        ("gap_extend", ctypes.c_int32),
+        ("xdrop", ctypes.c_int32),
+        ("min_identity_pct", ctypes.c_int32),
+        ("min_coverage_pct", ctypes.c_int32),
+        ("weight_mode", ctypes.c_int32),
+        ("score_width", ctypes.c_int32),
+        ("full_records", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 7),
+    ]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [
+        ("n_sequences", ctypes.c_int64),
+        ("n_residues", ctypes.c_int64),
+        ("n_kmers", ctypes.c_int64),
+        ("n_candidates", ctypes.c_int64),
+        ("n_aligned", ctypes.c_int64),
+        ("n_edges", ctypes.c_int64),
+        ("cells", ctypes.c_int64),
+        ("stats_pass_pairs", ctypes.c_int64),
+        ("int32_pairs", ctypes.c_int64),
+        ("ms_total", ctypes.c_double),
+        ("ms_stage", ctypes.c_double * 8),
+    ]
+
+
+@dataclasses.dataclass
+class Params:
+    """Mirror of pastis_params; defaults are the paper's Section VI settings."""
+
+    k: int = 6
+    n_subs: int = 0
+    sub_alphabet: int = 20
+    ck_min: int = 1
+    align_mode: str = "sw"  # "sw" | "xd"
+    gap_open: int = 11
+    gap_extend: int = 1
+    xdrop: int = 49
+    min_identity_pct: int = 30
+    min_coverage_pct: int = 70
+    weight_mode: str = "ani"  # "ani" | "ns"
+    score_width: int = 0
+    full_records: bool = False
+
+    def to_c(self) -> _Params:
+        p = _Params()
+        p.k = self.k
+        p.n_subs = self.n_subs
+        p.sub_alphabet = self.sub_alphabet
+        p.ck_min = self.ck_min
+        p.align_mode = {"sw": 0, "xd": 1}[self.align_mode]
+        p.gap_open = self.gap_open
+        p.gap_extend = self.gap_extend
+        p.xdrop = self.xdrop
+        p.min_identity_pct = self.min_identity_pct
+        p.min_coverage_pct = self.min_coverage_pct
+        p.weight_mode = {"ani": 0, "ns": 1}[self.weight_mode]
+        p.score_width = self.score_width
+        p.full_records = int(self.full_records)
+        return p
+
+
+_lib = None
+
+# (name, restype, argtypes) of every exported entry point
+_VP = ctypes.c_void_p
+_SIGNATURES = [
+    ("pastis_default_params", None, [ctypes.POINTER(_Params)]),
+    ("pastis_create", ctypes.c_int, [ctypes.POINTER(_Params), ctypes.c_int, ctypes.POINTER(_VP)]),
+    ("pastis_destroy", None, [_VP]),
+    ("pastis_status_string", ctypes.c_char_p, [ctypes.c_int]),
+    ("pastis_last_error", ctypes.c_char_p, [_VP]),
+    ("pastis_bad_residue_index", ctypes.c_int64, [_VP]),
+    ("pastis_encode", ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int, _VP, _VP]),
+    ("pastis_align_pairs", ctypes.c_int,
+     [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_int, _VP, _VP, _VP, _VP, ctypes.c_int64, _VP, _VP]),
+    ("pastis_stats", ctypes.c_int, [_VP, ctypes.POINTER(_Stats)]),
+]
+
+
+def lib():
+    """Load the HIP library; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build the HIP library first (python -c "
+                "'import __graft_entry__; __graft_entry__.build()')"
+            )
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in _SIGNATURES:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_names():
+    return [name for name, _, _ in _SIGNATURES]
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _dev_ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream_ptr(stream) -> int | None:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Context:
+    """A pastis_ctx bound to one GPU.  Not thread-safe."""
+
+    def __init__(self, params: Params | None = None, device: int = 0):
+        self.params = params or Params()
+        self.device = device
+        self._ctx = _VP()
+        self._cp = self.params.to_c()
+        st = lib().pastis_create(ctypes.byref(self._cp), device, ctypes.byref(self._ctx))
+        if st != OK:
+            raise PastisError(st, "pastis_create failed (bad parameters or device)")
+
+    def close(self):
+        if self._ctx:
+            lib().pastis_destroy(self._ctx)
+            self._ctx = _VP()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int):
+        if st != OK:
+            detail = lib().pastis_last_error(self._ctx) or b""
+            raise PastisError(st, detail.decode(errors="replace"))
+
+    @property
+    def bad_residue_index(self) -> int:
+        return int(lib().pastis_bad_residue_index(self._ctx))
+
+    def stats(self) -> dict:
+        s = _Stats()
+        self._check(lib().pastis_stats(self._ctx, ctypes.byref(s)))
+        out = {f: getattr(s, f) for f, _ in _Stats._fields_ if f != "ms_stage"}
+        out["ms_stage"] = list(s.ms_stage)
+        return out
+
+    def encode(self, residues, stream=None):
+        """residues: uint8 torch tensor (device or host) -> device codes tensor."""
+        torch = _torch()
+        on_dev = int(residues.is_cuda)
+        codes = torch.empty(residues.numel(), dtype=torch.uint8, device=f"cuda:{self.device}")
+        self._check(lib().pastis_encode(self._ctx, _dev_ptr(residues), residues.numel(), on_dev,
+                                        _dev_ptr(codes), _stream_ptr(stream)))
+        return codes
+
+    def align_pairs(self, residues, offsets, pi, pj, seed1=None, seed2=None, stream=None):
+        """Align pairs (pi[q], pj[q]); returns a device uint8 tensor of npairs
+        48-byte pastis_pair_record entries (view with RECORD_DTYPE on the host)."""
+        torch = _torch()
+        n = offsets.numel() - 1
+        npairs = pi.numel()
+        on_dev = int(residues.is_cuda)
+        if on_dev != int(offsets.is_cuda):
+            raise ValueError("residues and offsets must both be on the device or both on the host")
+        out = torch.empty(max(npairs, 1) * RECORD_DTYPE.itemsize, dtype=torch.uint8, device=f"cuda:{self.device}")
+        self._check(lib().pastis_align_pairs(self._ctx, _dev_ptr(residues), _dev_ptr(offsets), n, on_dev,
+                                             _dev_ptr(pi), _dev_ptr(pj), _dev_ptr(seed1), _dev_ptr(seed2), npairs,
+                                             _dev_ptr(out), _stream_ptr(stream)))
+        return out[: npairs * RECORD_DTYPE.itemsize]
+
+
+def records_to_numpy(t) -> np.ndarray:
+    return t.cpu().numpy().view(RECORD_DTYPE)

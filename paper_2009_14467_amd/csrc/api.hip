@@ -1,0 +1,337 @@
+// C ABI entry points: context, staging, error handling, and the align stage.
+#include <algorithm>
+#include <chrono>
+
+#include "internal.hpp"
+
+using namespace pastis;
+
+namespace pastis {
+
+pastis_status set_error(pastis_ctx *ctx, pastis_status s, const std::string &msg) {
+    if (ctx) ctx->last_error = msg;
+    return s;
+}
+
+pastis_status hip_error(pastis_ctx *ctx, hipError_t e, const char *what) {
+    return set_error(ctx, PASTIS_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+pastis_status ensure(pastis_ctx *ctx, int id, size_t bytes, void **out) {
+    DeviceBuffer &b = ctx->buf[id];
+    if (bytes == 0) bytes = 256;
+    if (b.bytes < bytes) {
+        if (b.ptr) {
+            hipError_t e = hipFree(b.ptr);
+            if (e != hipSuccess) return hip_error(ctx, e, "hipFree");
+            b.ptr = nullptr;
+            b.bytes = 0;
+        }
+        size_t want = bytes + bytes / 4;  // some headroom against regrowth
+        hipError_t e = hipMalloc(&b.ptr, want);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(ctx, PASTIS_E_NOMEM, "device allocation of " + std::to_string(want) + " bytes failed");
+        }
+        b.bytes = want;
+    }
+    *out = b.ptr;
+    return PASTIS_OK;
+}
+
+pastis_status ensure_pinned(pastis_ctx *ctx, size_t bytes, void **out) {
+    if (ctx->h_pinned_bytes < bytes) {
+        if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
+        ctx->h_pinned = nullptr;
+        ctx->h_pinned_bytes = 0;
+        hipError_t e = hipHostMalloc(&ctx->h_pinned, bytes, hipHostMallocDefault);
+        if (e != hipSuccess) return set_error(ctx, PASTIS_E_NOMEM, "pinned host allocation failed");
+        ctx->h_pinned_bytes = bytes;
+    }
+    *out = ctx->h_pinned;
+    return PASTIS_OK;
+}
+
+}  // namespace pastis
+
+namespace {
+
+#define PASTIS_TRY(expr)                     \
+    do {                                     \
+        pastis_status _s = (expr);           \
+        if (_s != PASTIS_OK) return _s;      \
+    } while (0)
+
+#define HIP_TRY(ctx, expr, what)                          \
+    do {                                                  \
+        hipError_t _e = (expr);                           \
+        if (_e != hipSuccess) return hip_error(ctx, _e, what); \
+    } while (0)
+
+pastis_status validate(const pastis_params *p, std::string &why) {
+    if (p->k < 1 || p->k > 6) return why = "k must be in 1..6", PASTIS_E_INVAL;
+    if (p->n_subs < 0 || p->n_subs > 64) return why = "n_subs must be in 0..64", PASTIS_E_INVAL;
+    if (p->sub_alphabet != 20 && p->sub_alphabet != 24) return why = "sub_alphabet must be 20 or 24", PASTIS_E_INVAL;
+    if (p->ck_min < 1) return why = "ck_min must be >= 1", PASTIS_E_INVAL;
+    if (p->align_mode != PASTIS_ALIGN_SW && p->align_mode != PASTIS_ALIGN_XD)
+        return why = "align_mode must be SW or XD", PASTIS_E_INVAL;
+    if (p->gap_open < 0 || p->gap_open > 1000 || p->gap_extend < 0 || p->gap_extend > 1000)
+        return why = "gap costs must be in 0..1000", PASTIS_E_INVAL;
+    if (p->xdrop < 0 || p->xdrop > 1000000) return why = "xdrop must be in 0..1e6", PASTIS_E_INVAL;
+    if (p->min_identity_pct < 0 || p->min_identity_pct > 100 || p->min_coverage_pct < 0 ||
+        p->min_coverage_pct > 100)
+        return why = "identity/coverage percentages must be in 0..100", PASTIS_E_INVAL;
+    if (p->weight_mode != PASTIS_WEIGHT_ANI && p->weight_mode != PASTIS_WEIGHT_NS)
+        return why = "weight_mode must be ANI or NS", PASTIS_E_INVAL;
+    if (p->score_width != 0 && p->score_width != 16 && p->score_width != 32)
+        return why = "score_width must be 0, 16 or 32", PASTIS_E_INVAL;
+    if (p->full_records != 0 && p->full_records != 1) return why = "full_records must be 0 or 1", PASTIS_E_INVAL;
+    for (int t = 0; t < 7; ++t)
+        if (p->reserved[t] != 0) return why = "reserved fields must be zero", PASTIS_E_INVAL;
+    return PASTIS_OK;
+}
+
+// Host copy of the offsets plus the device residues/offsets of a call.
+struct Staged {
+    const uint8_t *d_res = nullptr;
+    const int64_t *d_off = nullptr;
+    std::vector<int64_t> h_off;
+    int64_t n_res = 0;
+    int max_len = 0;
+};
+
+pastis_status stage_sequences(pastis_ctx *ctx, const uint8_t *residues, const int64_t *offsets, int64_t n,
+                              int on_device, hipStream_t s, Staged &st) {
+    if (n < 0) return set_error(ctx, PASTIS_E_INVAL, "n must be >= 0");
+    if (!offsets) return set_error(ctx, PASTIS_E_INVAL, "offsets is NULL");
+    st.h_off.resize((size_t)n + 1);
+    if (on_device) {
+        HIP_TRY(ctx, hipMemcpyAsync(st.h_off.data(), offsets, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s),
+                "copy offsets");
+        HIP_TRY(ctx, hipStreamSynchronize(s), "sync");
+    } else {
+        memcpy(st.h_off.data(), offsets, sizeof(int64_t) * (n + 1));
+    }
+    if (st.h_off[0] != 0) return set_error(ctx, PASTIS_E_INVAL, "offsets[0] must be 0");
+    int64_t mx = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t len = st.h_off[i + 1] - st.h_off[i];
+        if (len < 0) return set_error(ctx, PASTIS_E_INVAL, "offsets must be non-decreasing");
+        if (len > kMaxLen)
+            return set_error(ctx, PASTIS_E_INVAL,
+                             "sequence " + std::to_string(i) + " is longer than 65535 residues");
+        mx = std::max(mx, len);
+    }
+    st.n_res = st.h_off[n];
+    st.max_len = (int)mx;
+    if (on_device) {
+        st.d_res = residues;
+        st.d_off = offsets;
+    } else {
+        void *dr = nullptr, *doff = nullptr;
+        PASTIS_TRY(ensure(ctx, kBufResidues, (size_t)std::max<int64_t>(st.n_res, 1), &dr));
+        PASTIS_TRY(ensure(ctx, kBufOffsets, sizeof(int64_t) * (n + 1), &doff));
+        if (st.n_res > 0)
+            HIP_TRY(ctx, hipMemcpyAsync(dr, residues, (size_t)st.n_res, hipMemcpyHostToDevice, s), "copy residues");
+        HIP_TRY(ctx, hipMemcpyAsync(doff, st.h_off.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s),
+                "copy offsets");
+        st.d_res = (const uint8_t *)dr;
+        st.d_off = (const int64_t *)doff;
+    }
+    return PASTIS_OK;
+}
+
+// Encodes into kBufCodes; the bad-residue flag lives in kBufFlag[0].
+pastis_status encode_into(pastis_ctx *ctx, const uint8_t *d_res, int64_t n_res, uint8_t **codes_out,
+                          unsigned long long *flag, hipStream_t s) {
+    void *codes = nullptr;
+    PASTIS_TRY(ensure(ctx, kBufCodes, (size_t)std::max<int64_t>(n_res, 1), &codes));
+    HIP_TRY(ctx, launch_encode(d_res, n_res, (uint8_t *)codes, flag, s), "encode kernel");
+    *codes_out = (uint8_t *)codes;
+    return PASTIS_OK;
+}
+
+pastis_status read_flags(pastis_ctx *ctx, unsigned long long *d_flags, unsigned long long *h_flags, int count,
+                         hipStream_t s) {
+    HIP_TRY(ctx, hipMemcpyAsync(h_flags, d_flags, sizeof(unsigned long long) * count, hipMemcpyDeviceToHost, s),
+            "read flags");
+    HIP_TRY(ctx, hipStreamSynchronize(s), "sync");
+    return PASTIS_OK;
+}
+
+// flags[0]: smallest bad residue index (init ~0), flags[1]: pair errors
+pastis_status reset_flags(pastis_ctx *ctx, unsigned long long **d_flags, hipStream_t s) {
+    void *f = nullptr;
+    PASTIS_TRY(ensure(ctx, kBufFlag, 4 * sizeof(unsigned long long), &f));
+    const unsigned long long init[4] = {~0ull, 0ull, 0ull, 0ull};
+    HIP_TRY(ctx, hipMemcpyAsync(f, init, sizeof(init), hipMemcpyHostToDevice, s), "reset flags");
+    *d_flags = (unsigned long long *)f;
+    return PASTIS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void pastis_default_params(pastis_params *p) {
+    memset(p, 0, sizeof(*p));
+    p->k = 6;
+    p->n_subs = 0;
+    p->sub_alphabet = 20;
+    p->ck_min = 1;
+    p->align_mode = PASTIS_ALIGN_SW;
+    p->gap_open = 11;
+    p->gap_extend = 1;
+    p->xdrop = 49;
+    p->min_identity_pct = 30;
+    p->min_coverage_pct = 70;
+    p->weight_mode = PASTIS_WEIGHT_ANI;
+    p->score_width = 0;
+    p->full_records = 0;
+}
+
+const char *pastis_status_string(pastis_status s) {
+    switch (s) {
+        case PASTIS_OK: return "ok";
+        case PASTIS_E_INVAL: return "invalid argument";
+        case PASTIS_E_BAD_RESIDUE: return "residue outside the 24-letter alphabet";
+        case PASTIS_E_NOMEM: return "out of memory";
+        case PASTIS_E_DEVICE: return "HIP device error";
+        case PASTIS_E_CAPACITY: return "destination too small";
+        case PASTIS_E_STATE: return "call out of order";
+    }
+    return "unknown status";
+}
+
+pastis_status pastis_create(const pastis_params *p, int device, pastis_ctx **out) {
+    if (!p || !out) return PASTIS_E_INVAL;
+    *out = nullptr;
+    std::string why;
+    if (validate(p, why) != PASTIS_OK) return PASTIS_E_INVAL;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
+        (void)hipGetLastError();
+        return PASTIS_E_DEVICE;
+    }
+    if (hipSetDevice(device) != hipSuccess) return PASTIS_E_DEVICE;
+    pastis_ctx *ctx = new pastis_ctx();
+    ctx->params = *p;
+    ctx->device = device;
+    // 25 x 25 scoring table: residues 0..23 plus the pad code, whose scores
+    // are the most negative int8 so padded cells never raise a maximum.
+    int8_t table[25 * 25];
+    for (int a = 0; a < 25; ++a)
+        for (int b = 0; b < 25; ++b)
+            table[a * 25 + b] = (a < kAlpha && b < kAlpha) ? kBlosum62[a * kAlpha + b] : (int8_t)-128;
+    if (hipMalloc(&ctx->d_blosum, sizeof(table)) != hipSuccess ||
+        hipMemcpy(ctx->d_blosum, table, sizeof(table), hipMemcpyHostToDevice) != hipSuccess) {
+        delete ctx;
+        return PASTIS_E_DEVICE;
+    }
+    *out = ctx;
+    return PASTIS_OK;
+}
+
+void pastis_destroy(pastis_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    for (auto &b : ctx->buf)
+        if (b.ptr) (void)hipFree(b.ptr);
+    if (ctx->d_blosum) (void)hipFree(ctx->d_blosum);
+    if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
+    delete ctx;
+}
+
+const char *pastis_last_error(const pastis_ctx *ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+int64_t pastis_bad_residue_index(const pastis_ctx *ctx) { return ctx ? ctx->bad_residue : -1; }
+
+pastis_status pastis_stats(const pastis_ctx *ctx, pastis_run_stats *out) {
+    if (!ctx || !out) return PASTIS_E_INVAL;
+    *out = ctx->stats;
+    return PASTIS_OK;
+}
+
+pastis_status pastis_encode(pastis_ctx *ctx, const uint8_t *residues, int64_t n_residues, int input_on_device,
+                            uint8_t *codes, void *stream) {
+    if (!ctx) return PASTIS_E_INVAL;
+    if (n_residues < 0 || (n_residues > 0 && (!residues || !codes)))
+        return set_error(ctx, PASTIS_E_INVAL, "bad encode arguments");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    ctx->bad_residue = -1;
+    const uint8_t *d_res = residues;
+    if (!input_on_device && n_residues > 0) {
+        void *dr = nullptr;
+        PASTIS_TRY(ensure(ctx, kBufResidues, (size_t)n_residues, &dr));
+        HIP_TRY(ctx, hipMemcpyAsync(dr, residues, (size_t)n_residues, hipMemcpyHostToDevice, s), "copy residues");
+        d_res = (const uint8_t *)dr;
+    }
+    unsigned long long *d_flags = nullptr, h_flags[4];
+    PASTIS_TRY(reset_flags(ctx, &d_flags, s));
+    HIP_TRY(ctx, launch_encode(d_res, n_residues, codes, d_flags, s), "encode kernel");
+    PASTIS_TRY(read_flags(ctx, d_flags, h_flags, 1, s));
+    if (h_flags[0] != ~0ull) {
+        ctx->bad_residue = (int64_t)h_flags[0];
+        return set_error(ctx, PASTIS_E_BAD_RESIDUE, "bad residue at index " + std::to_string(h_flags[0]));
+    }
+    return PASTIS_OK;
+}
+
+pastis_status pastis_align_pairs(pastis_ctx *ctx, const uint8_t *residues, const int64_t *offsets, int64_t n,
+                                 int input_on_device, const uint32_t *pi, const uint32_t *pj, const uint32_t *seed1,
+                                 const uint32_t *seed2, int64_t npairs, pastis_pair_record *out, void *stream) {
+    if (!ctx) return PASTIS_E_INVAL;
+    if (npairs < 0 || (npairs > 0 && (!pi || !pj || !out)))
+        return set_error(ctx, PASTIS_E_INVAL, "bad pair arguments");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    auto t0 = std::chrono::steady_clock::now();
+    ctx->bad_residue = -1;
+    ctx->stats = pastis_run_stats{};
+    Staged st;
+    PASTIS_TRY(stage_sequences(ctx, residues, offsets, n, input_on_device, s, st));
+    unsigned long long *d_flags = nullptr, h_flags[4];
+    PASTIS_TRY(reset_flags(ctx, &d_flags, s));
+    uint8_t *codes = nullptr;
+    PASTIS_TRY(encode_into(ctx, st.d_res, st.n_res, &codes, d_flags, s));
+    void *pairs = nullptr;
+    PASTIS_TRY(ensure(ctx, kBufPairs, sizeof(PairDesc) * (size_t)std::max<int64_t>(npairs, 1), &pairs));
+    HIP_TRY(ctx,
+            launch_orient_pairs(st.d_off, n, pi, pj, seed1, seed2, npairs, ctx->params.k, (PairDesc *)pairs,
+                                d_flags + 1, s),
+            "orient kernel");
+    PASTIS_TRY(read_flags(ctx, d_flags, h_flags, 2, s));
+    if (h_flags[0] != ~0ull) {
+        ctx->bad_residue = (int64_t)h_flags[0];
+        return set_error(ctx, PASTIS_E_BAD_RESIDUE, "bad residue at index " + std::to_string(h_flags[0]));
+    }
+    if (h_flags[1] & 1ull) return set_error(ctx, PASTIS_E_INVAL, "pair index out of range or pi == pj");
+    if (npairs == 0) return PASTIS_OK;
+
+    const pastis_params &P = ctx->params;
+    Scoring sc{P.gap_open, P.gap_extend, P.xdrop, P.min_identity_pct, P.min_coverage_pct};
+    void *p1 = nullptr, *scratch = nullptr;
+    PASTIS_TRY(ensure(ctx, kBufPass1, sizeof(SwPass1Out) * (size_t)npairs, &p1));
+    // whole blocks of four waves; each launched wave owns one scratch slice
+    int waves = (int)((std::min<int64_t>(npairs, 8192) + 3) / 4 * 4);
+    const int64_t per_wave = 8 * (int64_t)std::max(st.max_len, 1);
+    PASTIS_TRY(ensure(ctx, kBufScratch, sizeof(int32_t) * (size_t)per_wave * (size_t)waves, &scratch));
+    if (P.align_mode == PASTIS_ALIGN_SW) {
+        HIP_TRY(ctx,
+                launch_sw(codes, (const PairDesc *)pairs, npairs, ctx->d_blosum, sc, (SwPass1Out *)p1, out,
+                          (int32_t *)scratch, per_wave, P.full_records, waves, s),
+                "sw kernels");
+    } else {
+        return set_error(ctx, PASTIS_E_INVAL, "x-drop alignment is not available in this build");
+    }
+    HIP_TRY(ctx, hipStreamSynchronize(s), "sync");
+    auto t1 = std::chrono::steady_clock::now();
+    ctx->stats.n_sequences = n;
+    ctx->stats.n_residues = st.n_res;
+    ctx->stats.n_aligned = npairs;
+    ctx->stats.ms_total = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    return PASTIS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,99 @@
+// Internal declarations of the gfx950 library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pastis.h"
+
+namespace pastis {
+
+// Residue codes 0..23 follow the paper's numbering (Section V-B):
+// A R N D C Q E G H I L K M F P S T W Y V B Z X *.
+constexpr int kAlpha = 24;
+// Column code used for DP cells outside the target sequence: every score
+// against it is kPadScore, so such cells never raise a running maximum.
+constexpr int kPadCode = 24;
+constexpr int kPadScore = -10000;
+constexpr uint32_t kNoSeed = 0xFFFFFFFFu;
+constexpr int kMaxLen = 65535;
+
+// BLOSUM62 in the residue order above (host copy; uploaded at context creation).
+extern const int8_t kBlosum62[kAlpha * kAlpha];
+
+struct DeviceBuffer {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct Scoring {
+    int gap_open, gap_extend, xdrop, id_pct, cov_pct;
+};
+
+// Oriented pair descriptor: rows a = shorter sequence (first on a tie).
+struct PairDesc {
+    int64_t a_off, b_off;
+    int32_t la, lb;
+    int32_t pa1, pb1, pa2, pb2;  // oriented seeds (-1 when absent)
+    int32_t swapped, pad;
+};
+
+struct RunTimes {
+    double ms[8];
+};
+
+}  // namespace pastis
+
+struct pastis_ctx {
+    pastis_params params;
+    int device = 0;
+    std::string last_error;
+    int64_t bad_residue = -1;
+    pastis_run_stats stats{};
+    int8_t *d_blosum = nullptr;  // 24 x 24 int8 + pad row (25 x 25 when padded)
+    // grow-only device buffers, reused across calls
+    pastis::DeviceBuffer buf[32];
+    void *h_pinned = nullptr;
+    size_t h_pinned_bytes = 0;
+};
+
+namespace pastis {
+
+enum BufId {
+    kBufResidues = 0,
+    kBufOffsets,
+    kBufCodes,
+    kBufFlag,
+    kBufPairs,
+    kBufPass1,
+    kBufScratch,
+    kBufCount  // first free id
+};
+
+pastis_status set_error(pastis_ctx *ctx, pastis_status s, const std::string &msg);
+pastis_status hip_error(pastis_ctx *ctx, hipError_t e, const char *what);
+// Make buffer `id` at least `bytes` long (contents not preserved on growth).
+pastis_status ensure(pastis_ctx *ctx, int id, size_t bytes, void **out);
+pastis_status ensure_pinned(pastis_ctx *ctx, size_t bytes, void **out);
+
+// ---- kernels' host launchers (each returns hipGetLastError()) ----
+hipError_t launch_encode(const uint8_t *ascii, int64_t n, uint8_t *codes, unsigned long long *bad, hipStream_t s);
+hipError_t launch_orient_pairs(const int64_t *offsets, int64_t n, const uint32_t *pi, const uint32_t *pj,
+                               const uint32_t *seed1, const uint32_t *seed2, int64_t npairs, int k, PairDesc *out,
+                               unsigned long long *bad, hipStream_t s);
+
+struct SwPass1Out {
+    int32_t score;
+    int32_t end_a, end_b;
+    int32_t pad;
+};
+
+hipError_t launch_sw(const uint8_t *codes, const PairDesc *pairs, int64_t npairs, const int8_t *blosum,
+                     const Scoring &sc, SwPass1Out *p1, pastis_pair_record *out, int32_t *scratch,
+                     int64_t scratch_ints_per_wave, int full, int waves, hipStream_t s);
+
+}  // namespace pastis

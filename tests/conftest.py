@@ -19,3 +19,21 @@ def orc():
 
     oracle.lib()
     return oracle
+
+
+def pytest_runtest_logstart(nodeid, location):
+    # name the case before any GPU work starts, so a hard failure still shows it
+    if "gpu" in nodeid:
+        print(f"\n[start] {nodeid}", flush=True)
+
+
+@pytest.fixture(scope="session")
+def gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2009_14467_amd as P
+
+    P.lib()
+    return torch.device("cuda:0")

@@ -1,0 +1,128 @@
+"""Parity of the HIP Smith-Waterman path with the CPU oracle (Section IV-E).
+
+Every record field is compared element by element; all of it is integer work,
+so the bar is bit-exact.
+"""
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("score", "beg_a", "end_a", "beg_b", "end_b", "matches", "columns", "seed_used", "passed", "swapped", "cells")
+
+
+def _to_dev(x, dev, dtype=None):
+    import torch
+
+    a = np.ascontiguousarray(x)
+    if a.dtype == np.uint32:
+        a = a.view(np.int32)
+    return torch.from_numpy(a).to(dev)
+
+
+def _gpu_records(dev, s, lo, hi, s1=None, s2=None, **params):
+    import paper_2009_14467_amd as P
+
+    ctx = P.Context(P.Params(**params))
+    out = ctx.align_pairs(
+        _to_dev(s.residues, dev), _to_dev(s.offsets, dev), _to_dev(lo, dev), _to_dev(hi, dev),
+        None if s1 is None else _to_dev(s1, dev), None if s2 is None else _to_dev(s2, dev),
+    )
+    return P.records_to_numpy(out)
+
+
+def _compare(got, want, fields=FIELDS, mask=None):
+    assert got.shape == want.shape
+    for f in fields:
+        g, w = got[f], want[f]
+        if mask is not None:
+            g, w = g[mask], w[mask]
+        bad = np.nonzero(g != w)[0]
+        assert bad.size == 0, f"{f}: {bad.size} mismatches, first at {bad[:5]}: got {g[bad[:5]]} want {w[bad[:5]]}"
+
+
+@pytest.fixture(scope="module")
+def tiny(orc):
+    from synth import workload
+
+    s = workload("tiny")
+    codes = orc.encode(s.residues)
+    cand = orc.candidates(codes, s.offsets, 6, ck_min=1)
+    want = orc.align_pairs(codes, s.offsets, cand["lo"], cand["hi"], mode="sw")
+    return s, cand, want
+
+
+def test_sw_full_records_tiny(gpu, tiny):
+    s, cand, want = tiny
+    got = _gpu_records(gpu, s, cand["lo"], cand["hi"], full_records=True)
+    _compare(got, want)
+
+
+def test_sw_fast_records_tiny(gpu, tiny):
+    s, cand, want = tiny
+    got = _gpu_records(gpu, s, cand["lo"], cand["hi"], full_records=False)
+    _compare(got, want, ("score", "end_a", "end_b", "passed", "swapped", "cells"))
+    _compare(got, want, FIELDS, mask=want["passed"] == 1)
+
+
+def test_sw_reversed_pair_order(gpu, tiny):
+    """(j, i) gives the same alignment as (i, j): orientation is by length."""
+    s, cand, want = tiny
+    got = _gpu_records(gpu, s, cand["hi"], cand["lo"], full_records=True)
+    w2 = want.copy()
+    # same rows/columns unless the lengths tie, where the first of the pair is a
+    L = np.diff(s.offsets)
+    tie = L[cand["lo"]] == L[cand["hi"]]
+    _compare(got[~tie], w2[~tie], tuple(f for f in FIELDS if f != "swapped"))
+    assert (got["swapped"][~tie] == 1 - w2["swapped"][~tie]).all()
+
+
+def test_sw_multi_strip_long_pairs(gpu, orc):
+    """Rows beyond 512 cross strips through the global boundary buffer."""
+    from synth import make_family_set
+
+    s = make_family_set(n_families=4, family_size=4, mean_len=900, min_len=500, max_len=1800, divergence=0.3,
+                        stream=91)
+    codes = orc.encode(s.residues)
+    n = s.n
+    lo, hi = np.triu_indices(n, 1)
+    lo = lo.astype(np.uint32)
+    hi = hi.astype(np.uint32)
+    want = orc.align_pairs(codes, s.offsets, lo, hi, mode="sw")
+    got = _gpu_records(gpu, s, lo, hi, full_records=True)
+    assert (want["end_a"] >= 512).any()
+    _compare(got, want)
+
+
+def test_sw_edge_cases(gpu, orc):
+    from synth.families import FamilySet
+
+    seqs = [b"", b"W", b"WW", b"A", b"WWWWWWWWWW", b"WWWWWGWWWWW", b"PPP", b"X*BZ", b"A" * 700, b"A" * 700 + b"W"]
+    lens = np.array([len(x) for x in seqs])
+    off = np.zeros(len(seqs) + 1, np.int64)
+    np.cumsum(lens, out=off[1:])
+    s = FamilySet(np.frombuffer(b"".join(seqs), np.uint8).copy(), off, np.zeros(len(seqs), np.int32), {})
+    codes = orc.encode(s.residues)
+    lo, hi = np.triu_indices(len(seqs), 1)
+    lo = lo.astype(np.uint32)
+    hi = hi.astype(np.uint32)
+    want = orc.align_pairs(codes, s.offsets, lo, hi, mode="sw")
+    got = _gpu_records(gpu, s, lo, hi, full_records=True)
+    _compare(got, want)
+
+
+def test_sw_rejects_bad_input(gpu):
+    import paper_2009_14467_amd as P
+    from synth.families import FamilySet
+
+    res = np.frombuffer(b"ACDEFJKL", np.uint8).copy()
+    off = np.array([0, 4, 8], np.int64)
+    s = FamilySet(res, off, np.zeros(2, np.int32), {})
+    with pytest.raises(P.PastisError, match="BAD_RESIDUE"):
+        _gpu_records(gpu, s, np.array([0], np.uint32), np.array([1], np.uint32))
+    s = FamilySet(np.frombuffer(b"ACDEFGKL", np.uint8).copy(), off, np.zeros(2, np.int32), {})
+    with pytest.raises(P.PastisError, match="INVAL"):
+        _gpu_records(gpu, s, np.array([0], np.uint32), np.array([2], np.uint32))
+    with pytest.raises(P.PastisError, match="INVAL"):
+        _gpu_records(gpu, s, np.array([1], np.uint32), np.array([1], np.uint32))

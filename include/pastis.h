@@ -119,8 +119,10 @@ typedef struct pastis_run_stats {
     int64_t cells;            /* DP cells evaluated */
     int64_t stats_pass_pairs; /* pairs that needed the statistics pass */
     int64_t int32_pairs;      /* pairs computed with 32-bit DP words */
-    double ms_total;
-    double ms_stage[8]; /* encode, k-mers, S, SpGEMM, schedule, align, filter, other */
+    double ms_total;    /* host wall time of the call */
+    double ms_stage[8]; /* device time (HIP events on the call's stream) of: encode,
+                           k-mers, S formation, SpGEMM, schedule, alignment pass 1,
+                           alignment pass 2, filter/edges */
 } pastis_run_stats;
 
 typedef struct pastis_ctx pastis_ctx;

@@ -52,6 +52,27 @@ pastis_status ensure_pinned(pastis_ctx *ctx, size_t bytes, void **out) {
     return PASTIS_OK;
 }
 
+hipError_t stage_begin(pastis_ctx *ctx, int stage, hipStream_t s) {
+    ctx->ev_used[stage] = true;
+    return hipEventRecord(ctx->ev[2 * stage], s);
+}
+
+hipError_t stage_end(pastis_ctx *ctx, int stage, hipStream_t s) { return hipEventRecord(ctx->ev[2 * stage + 1], s); }
+
+hipError_t stage_collect(pastis_ctx *ctx, hipStream_t s) {
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    for (int st = 0; st < kNumStages; ++st) {
+        if (!ctx->ev_used[st]) continue;
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, ctx->ev[2 * st], ctx->ev[2 * st + 1]);
+        if (e != hipSuccess) return e;
+        ctx->stats.ms_stage[st] += ms;
+        ctx->ev_used[st] = false;
+    }
+    return hipSuccess;
+}
+
 }  // namespace pastis
 
 namespace {
@@ -169,6 +190,25 @@ pastis_status reset_flags(pastis_ctx *ctx, unsigned long long **d_flags, hipStre
     return PASTIS_OK;
 }
 
+pastis_status make_sw_work(pastis_ctx *ctx, int64_t npairs, int max_len, SwWork &wk) {
+    void *p = nullptr;
+    PASTIS_TRY(ensure(ctx, kBufBinOf, (size_t)std::max<int64_t>(npairs, 1), &p));
+    wk.bin_of = (int8_t *)p;
+    PASTIS_TRY(ensure(ctx, kBufBinMeta, sizeof(int) * 160, &p));
+    wk.counts = (int *)p;
+    wk.starts = wk.counts + 32;
+    wk.starts2 = wk.counts + 64;
+    wk.cursor = wk.counts + 96;
+    PASTIS_TRY(ensure(ctx, kBufIdx, sizeof(int) * (size_t)std::max<int64_t>(npairs, 1), &p));
+    wk.idx = (int *)p;
+    PASTIS_TRY(ensure(ctx, kBufIdx2, sizeof(int) * (size_t)std::max<int64_t>(npairs, 1), &p));
+    wk.idx2 = (int *)p;
+    wk.scratch_per_wave = 6 * (int64_t)std::max(max_len, 1);
+    PASTIS_TRY(ensure(ctx, kBufScratch, sizeof(int) * (size_t)wk.scratch_per_wave * (size_t)sw_scratch_waves(), &p));
+    wk.scratch = (int *)p;
+    return PASTIS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -228,6 +268,12 @@ pastis_status pastis_create(const pastis_params *p, int device, pastis_ctx **out
         delete ctx;
         return PASTIS_E_DEVICE;
     }
+    for (auto &ev : ctx->ev) {
+        if (hipEventCreate(&ev) != hipSuccess) {
+            pastis_destroy(ctx);
+            return PASTIS_E_DEVICE;
+        }
+    }
     *out = ctx;
     return PASTIS_OK;
 }
@@ -239,6 +285,8 @@ void pastis_destroy(pastis_ctx *ctx) {
         if (b.ptr) (void)hipFree(b.ptr);
     if (ctx->d_blosum) (void)hipFree(ctx->d_blosum);
     if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
+    for (auto &ev : ctx->ev)
+        if (ev) (void)hipEventDestroy(ev);
     delete ctx;
 }
 
@@ -294,7 +342,9 @@ pastis_status pastis_align_pairs(pastis_ctx *ctx, const uint8_t *residues, const
     unsigned long long *d_flags = nullptr, h_flags[4];
     PASTIS_TRY(reset_flags(ctx, &d_flags, s));
     uint8_t *codes = nullptr;
+    HIP_TRY(ctx, stage_begin(ctx, kStEncode, s), "event");
     PASTIS_TRY(encode_into(ctx, st.d_res, st.n_res, &codes, d_flags, s));
+    HIP_TRY(ctx, stage_end(ctx, kStEncode, s), "event");
     void *pairs = nullptr;
     PASTIS_TRY(ensure(ctx, kBufPairs, sizeof(PairDesc) * (size_t)std::max<int64_t>(npairs, 1), &pairs));
     HIP_TRY(ctx,
@@ -311,21 +361,19 @@ pastis_status pastis_align_pairs(pastis_ctx *ctx, const uint8_t *residues, const
 
     const pastis_params &P = ctx->params;
     Scoring sc{P.gap_open, P.gap_extend, P.xdrop, P.min_identity_pct, P.min_coverage_pct};
-    void *p1 = nullptr, *scratch = nullptr;
+    void *p1 = nullptr;
     PASTIS_TRY(ensure(ctx, kBufPass1, sizeof(SwPass1Out) * (size_t)npairs, &p1));
-    // whole blocks of four waves; each launched wave owns one scratch slice
-    int waves = (int)((std::min<int64_t>(npairs, 8192) + 3) / 4 * 4);
-    const int64_t per_wave = 8 * (int64_t)std::max(st.max_len, 1);
-    PASTIS_TRY(ensure(ctx, kBufScratch, sizeof(int32_t) * (size_t)per_wave * (size_t)waves, &scratch));
+    SwWork wk;
+    PASTIS_TRY(make_sw_work(ctx, npairs, st.max_len, wk));
     if (P.align_mode == PASTIS_ALIGN_SW) {
         HIP_TRY(ctx,
-                launch_sw(codes, (const PairDesc *)pairs, npairs, ctx->d_blosum, sc, (SwPass1Out *)p1, out,
-                          (int32_t *)scratch, per_wave, P.full_records, waves, s),
+                launch_sw(ctx, codes, (const PairDesc *)pairs, npairs, ctx->d_blosum, sc, (SwPass1Out *)p1, out, wk,
+                          P.full_records, s),
                 "sw kernels");
     } else {
         return set_error(ctx, PASTIS_E_INVAL, "x-drop alignment is not available in this build");
     }
-    HIP_TRY(ctx, hipStreamSynchronize(s), "sync");
+    HIP_TRY(ctx, stage_collect(ctx, s), "sync");
     auto t1 = std::chrono::steady_clock::now();
     ctx->stats.n_sequences = n;
     ctx->stats.n_residues = st.n_res;

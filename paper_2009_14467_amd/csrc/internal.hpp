@@ -42,9 +42,8 @@ struct PairDesc {
     int32_t swapped, pad;
 };
 
-struct RunTimes {
-    double ms[8];
-};
+// Stage timer: HIP events recorded on the call's stream, read after a sync.
+enum Stage { kStEncode = 0, kStKmers, kStSubs, kStSpgemm, kStSched, kStAlign1, kStAlign2, kStFilter, kNumStages };
 
 }  // namespace pastis
 
@@ -59,6 +58,8 @@ struct pastis_ctx {
     pastis::DeviceBuffer buf[32];
     void *h_pinned = nullptr;
     size_t h_pinned_bytes = 0;
+    hipEvent_t ev[2 * 8] = {};
+    bool ev_used[8] = {};
 };
 
 namespace pastis {
@@ -71,6 +72,10 @@ enum BufId {
     kBufPairs,
     kBufPass1,
     kBufScratch,
+    kBufBinOf,
+    kBufBinMeta,
+    kBufIdx,
+    kBufIdx2,
     kBufCount  // first free id
 };
 
@@ -79,6 +84,11 @@ pastis_status hip_error(pastis_ctx *ctx, hipError_t e, const char *what);
 // Make buffer `id` at least `bytes` long (contents not preserved on growth).
 pastis_status ensure(pastis_ctx *ctx, int id, size_t bytes, void **out);
 pastis_status ensure_pinned(pastis_ctx *ctx, size_t bytes, void **out);
+// Record the start / end of a stage on stream s; collect() adds elapsed times
+// of every recorded stage into ctx->stats.ms_stage (after synchronising s).
+hipError_t stage_begin(pastis_ctx *ctx, int stage, hipStream_t s);
+hipError_t stage_end(pastis_ctx *ctx, int stage, hipStream_t s);
+hipError_t stage_collect(pastis_ctx *ctx, hipStream_t s);
 
 // ---- kernels' host launchers (each returns hipGetLastError()) ----
 hipError_t launch_encode(const uint8_t *ascii, int64_t n, uint8_t *codes, unsigned long long *bad, hipStream_t s);
@@ -92,8 +102,22 @@ struct SwPass1Out {
     int32_t pad;
 };
 
-hipError_t launch_sw(const uint8_t *codes, const PairDesc *pairs, int64_t npairs, const int8_t *blosum,
-                     const Scoring &sc, SwPass1Out *p1, pastis_pair_record *out, int32_t *scratch,
-                     int64_t scratch_ints_per_wave, int full, int waves, hipStream_t s);
+// Work buffers of an alignment stage (device): per-pair bin ids, bin counts,
+// bin starts for the two passes, a cursor, the two binned index lists, and
+// boundary-row scratch for pairs taller than one strip (6 planes of max_len
+// ints per wave, for sw_scratch_waves() waves).
+struct SwWork {
+    int8_t *bin_of;
+    int *counts, *starts, *starts2, *cursor;
+    int *idx, *idx2;
+    int *scratch;
+    int64_t scratch_per_wave;
+};
+int sw_num_bins();
+int64_t sw_scratch_waves();
+
+hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pairs, int64_t npairs,
+                     const int8_t *blosum, const Scoring &sc, SwPass1Out *p1, pastis_pair_record *out,
+                     const SwWork &wk, int full, hipStream_t s);
 
 }  // namespace pastis

@@ -1,48 +1,90 @@
-// Smith-Waterman alignment of candidate pairs (Section IV-E), one 64-lane
-// wavefront per pair, 32-bit DP words.
+// Smith-Waterman alignment of candidate pairs (Section IV-E): one 64-lane
+// wavefront per pair, 32-bit DP words, pairs binned by the length of the
+// shorter sequence.
 //
-// Layout: the rows of the shorter sequence a are split into strips of 64*R
-// rows; lane l of the wave owns rows [l*R, l*R + R) of the strip and sweeps
-// the columns of b with a one-column skew per lane (lane l is at column t - l
-// in step t), so all of a lane's DP state lives in registers and only the
-// bottom row of its block crosses to the next lane, once per step.  Between
-// strips the bottom row of the strip goes through a per-wave global buffer.
+// Layout.  The rows of the shorter sequence a are split into strips of 64*R
+// rows; lane l owns rows [l*R, l*R + R) of a strip and sweeps the columns of b
+// one column behind lane l-1 (lane l is at column t - l in step t).  All DP
+// state stays in registers; the bottom row of a lane's block moves to the next
+// lane once per step with a DPP wavefront shift, and the column residue moves
+// with it (lane 0 takes it from a register chunk of b via readlane).  Pairs
+// whose shorter side needs more than one strip pass the strip's bottom row
+// through a per-wave global buffer.  R is chosen per pair (bins R = 1..8, and
+// a multi-strip bin), so few lanes hold padding rows.
 //
-// Substitution scores come from a per-lane profile in LDS: for every column
-// residue code c, the R scores of the lane's rows packed as R int8, read with
-// one 64-bit LDS load per step.
+// Scores.  A per-lane profile in LDS holds, for every column residue code, the
+// R int8 scores of the lane's rows; one LDS load per step serves R cells and
+// the byte selects fold into the adds (SDWA).
 //
-// Pass 1 computes the score and the canonical end (the smallest row, then
-// column, holding the maximum).  Pass 2 recomputes the rectangle
-// [0, end_a] x [0, end_b] carrying, for every cell and state (H, E, F), the
-// start cell, identical pairs and diagonal columns of the canonical path that
-// ends there: the predecessor each cell takes is the one a traceback would
-// take (diagonal before horizontal before vertical gap, extension before
-// opening; a zero cell starts a new path), so the statistics at the end cell
-// are those of the traceback without storing it.
+// Pass 1 computes the score and the canonical end: the smallest row, then the
+// smallest column, holding the maximum.  Each row keeps max((h << 16) |
+// (0xFFFF - column)), which orders by score and then by the earlier column.
+//
+// Pass 2 recomputes the rectangle [0, end_a] x [0, end_b] carrying, for every
+// cell and state (H, E, F), the start cell, identical pairs and diagonal
+// columns of the canonical path ending there.  Each cell takes the predecessor
+// a traceback would take (diagonal before horizontal before vertical gap,
+// extension before opening; a zero diagonal predecessor starts a new path), so
+// by induction the end cell holds the traceback's statistics.  The strip rows
+// are padded at the top so the end cell is always row R-1 of lane 63.
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace pastis {
+
+hipError_t launch_bins(const int8_t *bin_of, int64_t n, int nbins, int *counts, int *starts, int *cursor, int *idx,
+                       hipStream_t s);
+
 namespace {
 
 constexpr int kWave = 64;
 constexpr int kNeg = -(1 << 28);
 constexpr int kWavesPerBlock = 4;
 constexpr int kProfCodes = kAlpha + 1;  // 24 residues + the pad code
+constexpr int kSingleBins = 8;          // bins 0..7: one strip of 64 * (bin + 1) rows
+constexpr int kMultiBin = 8;            // longer: strips of 512 rows
+constexpr int kNumBins = 9;
+constexpr int kDppWaveShr1 = 0x138;
 
-__device__ __forceinline__ int shfl_up1(int v) { return __shfl_up(v, 1, kWave); }
+// lane l receives lane l-1's value; lane 0 receives `lane0`
+__device__ __forceinline__ int shr1(int lane0, int v) {
+    return __builtin_amdgcn_update_dpp(lane0, v, kDppWaveShr1, 0xF, 0xF, false);
+}
 
 template <int R>
-__device__ __forceinline__ void build_profile(uint64_t (*prof)[kWave], const int8_t *sblosum, const uint8_t *a, int la,
-                                              int base, int lane) {
-    uint8_t ar[R];
+using ProfWord = typename std::conditional<(R <= 4), uint32_t, uint2>::type;
+
+template <int R>
+__device__ __forceinline__ int sigma_at(const ProfWord<R> &w, int r) {
+    if constexpr (R <= 4) {
+        return (int)(int8_t)(w >> (8 * r));
+    } else {
+        return r < 4 ? (int)(int8_t)(w.x >> (8 * r)) : (int)(int8_t)(w.y >> (8 * (r - 4)));
+    }
+}
+
+template <int R>
+__device__ __forceinline__ void build_profile(ProfWord<R> (*prof)[kWave], const int8_t *sblosum, const uint8_t *a,
+                                              int la, int base, int lane) {
+    int ar[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) ar[r] = (base + r < la) ? a[base + r] : (uint8_t)kPadCode;
+    for (int r = 0; r < R; ++r) ar[r] = (base + r >= 0 && base + r < la) ? a[base + r] : kPadCode;
     for (int c = 0; c < kProfCodes; ++c) {
-        uint64_t w = 0;
+        uint32_t w0 = 0, w1 = 0;
 #pragma unroll
-        for (int r = 0; r < R; ++r) w |= (uint64_t)(uint8_t)sblosum[ar[r] * kProfCodes + c] << (8 * r);
-        prof[c][lane] = w;
+        for (int r = 0; r < R; ++r) {
+            const uint32_t v = (uint8_t)sblosum[ar[r] * kProfCodes + c];
+            if (r < 4)
+                w0 |= v << (8 * r);
+            else
+                w1 |= v << (8 * (r - 4));
+        }
+        if constexpr (R <= 4) {
+            prof[c][lane] = w0;
+        } else {
+            prof[c][lane] = make_uint2(w0, w1);
+        }
     }
 }
 
@@ -62,92 +104,132 @@ __device__ __forceinline__ void load_blosum(int8_t *sblosum, const int8_t *blosu
     __syncthreads();
 }
 
-template <int R>
+// A load the compiler must issue per lane through the vector memory path (the
+// data was written by another lane of the same wave earlier in the kernel).
+template <typename T>
+__device__ __forceinline__ T vload(const T *p) {
+    return __builtin_nontemporal_load(p);
+}
+
+// ---------------------------------------------------------------- pass 1
+
+template <int R, bool MULTI>
 __global__ __launch_bounds__(256) void sw_pass1_kernel(const uint8_t *__restrict__ codes,
-                                                       const PairDesc *__restrict__ pairs, int64_t npairs,
-                                                       const int8_t *__restrict__ blosum, int go_ge, int ge,
-                                                       SwPass1Out *__restrict__ out, int2 *__restrict__ scratch,
+                                                       const PairDesc *__restrict__ pairs,
+                                                       const int *__restrict__ idx, const int *__restrict__ starts,
+                                                       int bin, const int8_t *__restrict__ blosum, int go_ge, int ge,
+                                                       SwPass1Out *__restrict__ out, int *__restrict__ scratch,
                                                        int64_t scratch_per_wave) {
-    __shared__ uint64_t prof_all[kWavesPerBlock][kProfCodes][kWave];
+    __shared__ ProfWord<R> prof_all[kWavesPerBlock][kProfCodes][kWave];
     __shared__ int8_t sblosum[kProfCodes * kProfCodes];
     load_blosum(sblosum, blosum);
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
-    uint64_t(*prof)[kWave] = prof_all[wave];
+    ProfWord<R>(*prof)[kWave] = prof_all[wave];
     const int64_t gwave = (int64_t)blockIdx.x * kWavesPerBlock + wave;
-    int2 *bnd = scratch + gwave * scratch_per_wave;
+    int *bnd_h = scratch + gwave * scratch_per_wave;  // bottom row H / F of the strip above
+    int *bnd_f = bnd_h + scratch_per_wave / 2;
+    const int item_end = starts[bin + 1];
+    constexpr int RS = kWave * R;
 
-    for (int64_t q = gwave; q < npairs; q += (int64_t)gridDim.x * kWavesPerBlock) {
+    for (int64_t w = starts[bin] + gwave; w < item_end; w += (int64_t)gridDim.x * kWavesPerBlock) {
+        const int q = idx[w];
         const PairDesc pd = pairs[q];
         const uint8_t *a = codes + pd.a_off;
         const uint8_t *b = codes + pd.b_off;
         const int la = pd.la, lb = pd.lb;
         unsigned long long best = 0;  // (score << 32) | ~(row << 16 | col)
-        for (int r0 = 0; r0 < la && lb > 0; r0 += kWave * R) {
-            const int base = r0 + lane * R;
+        const int nstrips = (la > 0 && lb > 0) ? (MULTI ? (la + RS - 1) / RS : 1) : 0;
+        for (int s = 0; s < nstrips; ++s) {
+            const int base = s * RS + lane * R;
             build_profile<R>(prof, sblosum, a, la, base, lane);
-            const bool first = (r0 == 0);
-            const bool has_next = (r0 + kWave * R) < la;
-            int H[R], E[R], rmax[R], rcol[R];
+            const bool from_above = s > 0;
+            const bool to_below = s + 1 < nstrips;
+            int H[R], G[R], E[R];
+            unsigned key[R];  // single strip: (h << 16) | (0xFFFF - col)
+            int rmax[R], rcol[R];  // multi strip: scores may exceed 16 bits
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 H[r] = 0;
+                G[r] = -go_ge;
                 E[r] = kNeg;
+                key[r] = 0;
                 rmax[r] = 0;
                 rcol[r] = 0;
             }
-            int hlast = 0, flast = kNeg, hdiag0 = 0;
-            int cres = kPadCode;  // residue of this lane's current column
-            const int steps = lb + kWave - 1;
-            for (int t = 0; t < steps; ++t) {
-                const int j = t - lane;
-                int rh = shfl_up1(hlast), rf = shfl_up1(flast);
-                int rc = shfl_up1(cres);
-                if (lane == 0) {
-                    rc = (t < lb) ? b[t] : kPadCode;
-                    if (first) {
-                        rh = 0;
-                        rf = kNeg;
-                    } else if (t < lb) {
-                        const int2 v = bnd[t];
-                        rh = v.x;
-                        rf = v.y;
-                    }
+            int hlast = 0, flast = kNeg, hprev = 0, cres = kPadCode;
+            int chunk = kPadCode;
+            // one DP step; in the tail (t >= lb) lanes past the last column
+            // must not touch their running maxima
+            auto step = [&](const int t, auto tail_tag) {
+                constexpr bool kTail = decltype(tail_tag)::value;
+                if ((t & (kWave - 1)) == 0) chunk = (t + lane < lb) ? (int)b[t + lane] : kPadCode;
+                const int bt = __builtin_amdgcn_readlane(chunk, t & (kWave - 1));
+                int in_h = 0, in_f = kNeg;
+                if (MULTI && !kTail && from_above) {
+                    in_h = vload(bnd_h + t);
+                    in_f = vload(bnd_f + t);
                 }
-                cres = rc;
-                const bool valid = (j >= 0) && (j < lb);
-                const uint64_t pw = prof[cres][lane];
-                int hdiag = hdiag0, hup = rh, fup = rf;
+                const int rh = shr1(in_h, hlast);
+                const int rf = shr1(in_f, flast);
+                cres = shr1(bt, cres);
+                const int j = t - lane;
+                const bool valid = j < lb;
+                const ProfWord<R> pw = prof[cres][lane];
+                const unsigned jinv = (unsigned)(0xFFFF - j) & 0xFFFFu;
+                int hd = hprev, gu = rh - go_ge, fu = rf;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const int sigma = (int)(int8_t)(pw >> (8 * r));
-                    const int e = max(E[r] - ge, H[r] - go_ge);
-                    const int f = max(fup - ge, hup - go_ge);
-                    const int h = max(max(hdiag + sigma, 0), max(e, f));
-                    hdiag = H[r];
+                    const int e = max(E[r] - ge, G[r]);
+                    const int f = max(fu - ge, gu);
+                    const int d = hd + sigma_at<R>(pw, r);
+                    const int h = max(max(d, 0), max(e, f));
+                    hd = H[r];
                     H[r] = h;
                     E[r] = e;
-                    hup = h;
-                    fup = f;
-                    if (valid && h > rmax[r]) {
-                        rmax[r] = h;
-                        rcol[r] = j;
+                    const int g = h - go_ge;
+                    G[r] = g;
+                    gu = g;
+                    fu = f;
+                    if constexpr (MULTI) {
+                        if ((!kTail || valid) && h > rmax[r]) {
+                            rmax[r] = h;
+                            rcol[r] = j;
+                        }
+                    } else {
+                        const unsigned k = ((unsigned)h << 16) | jinv;
+                        const unsigned m = k > key[r] ? k : key[r];
+                        key[r] = (!kTail || valid) ? m : key[r];
                     }
                 }
-                hlast = hup;
-                flast = fup;
-                hdiag0 = rh;
-                if (has_next && lane == kWave - 1 && valid) bnd[j] = make_int2(hlast, flast);
-            }
+                hlast = H[R - 1];
+                flast = fu;
+                hprev = rh;
+                if (MULTI && to_below && lane == kWave - 1 && j >= 0 && j < lb) {
+                    bnd_h[j] = hlast;
+                    bnd_f[j] = flast;
+                }
+            };
+            for (int t = 0; t < lb; ++t) step(t, std::false_type{});
+            for (int t = lb; t < lb + kWave - 1; ++t) step(t, std::true_type{});
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                if (base + r < la && rmax[r] > 0) {
-                    const unsigned pos = ((unsigned)(base + r) << 16) | (unsigned)rcol[r];
-                    const unsigned long long key = ((unsigned long long)(unsigned)rmax[r] << 32) | (unsigned)(~pos);
-                    best = key > best ? key : best;
+                const int row = base + r;
+                int sc, col;
+                if constexpr (MULTI) {
+                    sc = rmax[r];
+                    col = rcol[r];
+                } else {
+                    sc = (int)(key[r] >> 16);
+                    col = 0xFFFF - (int)(key[r] & 0xFFFFu);
+                }
+                if (row < la && sc > 0) {
+                    const unsigned pos = ((unsigned)row << 16) | (unsigned)col;
+                    const unsigned long long k = ((unsigned long long)(unsigned)sc << 32) | (unsigned)(~pos);
+                    best = k > best ? k : best;
                 }
             }
-            __threadfence_block();  // the next strip's lane 0 reads what lane 63 wrote
+            if (MULTI) __threadfence_block();  // lane 0 of the next strip reads lane 63's row
         }
         best = wave_max_u64(best);
         if (lane == 0) {
@@ -162,189 +244,293 @@ __global__ __launch_bounds__(256) void sw_pass1_kernel(const uint8_t *__restrict
     }
 }
 
-struct Stat {
-    unsigned beg;  // (row << 16) | col of the first aligned pair
-    unsigned md;   // (identical pairs << 16) | diagonal columns
-};
+// ---------------------------------------------------------------- between the passes
 
-__device__ __forceinline__ Stat shfl_up_stat(Stat s) {
-    Stat o;
-    o.beg = (unsigned)shfl_up1((int)s.beg);
-    o.md = (unsigned)shfl_up1((int)s.md);
-    return o;
+__device__ __forceinline__ int rows_bin(int rows) {
+    if (rows <= 0) return 0;
+    const int r = (rows + kWave - 1) / kWave;
+    return r <= kSingleBins ? r - 1 : kMultiBin;
 }
 
-__device__ __forceinline__ Stat sel(bool c, Stat x, Stat y) { return c ? x : y; }
+__global__ void sw_bin1_kernel(const PairDesc *__restrict__ pairs, int64_t npairs, int8_t *__restrict__ bin_of) {
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < npairs) bin_of[q] = (int8_t)rows_bin(pairs[q].la);
+}
 
-template <int R>
+// Records of pairs that need no statistics pass are final here; the others
+// are binned by the height of their end rectangle.
+__global__ void sw_bin2_kernel(const PairDesc *__restrict__ pairs, const SwPass1Out *__restrict__ p1,
+                               int64_t npairs, int cov_pct, int full, pastis_pair_record *__restrict__ out,
+                               int8_t *__restrict__ bin_of) {
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= npairs) return;
+    const PairDesc pd = pairs[q];
+    const SwPass1Out r1 = p1[q];
+    // coverage needs span_a >= cov% of la, and span_a <= end_a + 1
+    const bool need = r1.score > 0 && (full || 100LL * (r1.end_a + 1) >= (long long)cov_pct * pd.la);
+    if (need) {
+        bin_of[q] = (int8_t)rows_bin(r1.end_a + 1);
+        return;
+    }
+    bin_of[q] = -1;
+    pastis_pair_record rec;
+    rec.score = r1.score;
+    rec.beg_a = rec.beg_b = -1;
+    rec.end_a = r1.end_a;
+    rec.end_b = r1.end_b;
+    rec.matches = rec.columns = 0;
+    rec.seed_used = -1;
+    rec.passed = 0;
+    rec.swapped = pd.swapped;
+    rec.cells = (int64_t)pd.la * pd.lb;
+    out[q] = rec;
+}
+
+// ---------------------------------------------------------------- pass 2
+
+template <int R, bool MULTI>
 __global__ __launch_bounds__(256) void sw_pass2_kernel(const uint8_t *__restrict__ codes,
-                                                       const PairDesc *__restrict__ pairs, int64_t npairs,
-                                                       const int8_t *__restrict__ blosum, int go_ge, int ge,
-                                                       int cov_pct, int id_pct, int full,
-                                                       const SwPass1Out *__restrict__ p1,
+                                                       const PairDesc *__restrict__ pairs,
+                                                       const int *__restrict__ idx, const int *__restrict__ starts,
+                                                       int bin, const int8_t *__restrict__ blosum, int go_ge, int ge,
+                                                       int cov_pct, int id_pct, const SwPass1Out *__restrict__ p1,
                                                        pastis_pair_record *__restrict__ out,
-                                                       int4 *__restrict__ scratch, int64_t scratch_per_wave) {
-    __shared__ uint64_t prof_all[kWavesPerBlock][kProfCodes][kWave];
+                                                       int *__restrict__ scratch, int64_t scratch_per_wave) {
+    __shared__ ProfWord<R> prof_all[kWavesPerBlock][kProfCodes][kWave];
     __shared__ int8_t sblosum[kProfCodes * kProfCodes];
     load_blosum(sblosum, blosum);
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
-    uint64_t(*prof)[kWave] = prof_all[wave];
+    ProfWord<R>(*prof)[kWave] = prof_all[wave];
     const int64_t gwave = (int64_t)blockIdx.x * kWavesPerBlock + wave;
-    // per column: (H, F, H.beg, H.md) and (F.beg, F.md) of the strip's bottom row
-    int4 *bnd_a = scratch + gwave * scratch_per_wave;
-    int2 *bnd_b = (int2 *)(bnd_a + scratch_per_wave / 2);
+    // strip bottom row per column: H, F, H.beg, H.md, F.beg, F.md
+    int *bnd = scratch + gwave * scratch_per_wave;
+    const int64_t plane = scratch_per_wave / 6;
+    const int item_end = starts[bin + 1];
+    constexpr int RS = kWave * R;
 
-    for (int64_t q = gwave; q < npairs; q += (int64_t)gridDim.x * kWavesPerBlock) {
+    for (int64_t w = starts[bin] + gwave; w < item_end; w += (int64_t)gridDim.x * kWavesPerBlock) {
+        const int q = idx[w];
         const PairDesc pd = pairs[q];
         const SwPass1Out r1 = p1[q];
-        const int la_full = pd.la;
-        pastis_pair_record rec;
-        rec.score = r1.score;
-        rec.beg_a = rec.beg_b = -1;
-        rec.end_a = r1.end_a;
-        rec.end_b = r1.end_b;
-        rec.matches = rec.columns = 0;
-        rec.seed_used = -1;
-        rec.passed = 0;
-        rec.swapped = pd.swapped;
-        rec.cells = (int64_t)pd.la * pd.lb;
-        // coverage needs span_a >= cov% of la, and span_a <= end_a + 1
-        const bool need = r1.score > 0 && (full || 100LL * (r1.end_a + 1) >= (long long)cov_pct * la_full);
-        if (!need) {
-            if (lane == 0) out[q] = rec;
-            continue;
-        }
         const uint8_t *a = codes + pd.a_off;
         const uint8_t *b = codes + pd.b_off;
         const int la = r1.end_a + 1, lb = r1.end_b + 1;  // the rectangle ending at the end cell
-        Stat fin = {0u, 0u};
-        for (int r0 = 0; r0 < la; r0 += kWave * R) {
-            const int base = r0 + lane * R;
+        const int nstrips = MULTI ? (la + RS - 1) / RS : 1;
+        const int top = nstrips * RS - la;  // padding rows above row 0
+        unsigned fin_beg = 0, fin_md = 0;
+        for (int s = 0; s < nstrips; ++s) {
+            const int base = s * RS - top + lane * R;
             build_profile<R>(prof, sblosum, a, la, base, lane);
-            uint8_t ar[R];
+            int ar[R];
+            unsigned rowpart[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) ar[r] = (base + r < la) ? a[base + r] : (uint8_t)kPadCode;
-            const bool first = (r0 == 0);
-            const bool has_next = (r0 + kWave * R) < la;
-            int H[R], E[R];
-            Stat sH[R], sE[R];
+            for (int r = 0; r < R; ++r) {
+                ar[r] = (base + r >= 0 && base + r < la) ? (int)a[base + r] : kPadCode;
+                rowpart[r] = (unsigned)(base + r) << 16;
+            }
+            const bool from_above = s > 0;
+            const bool to_below = s + 1 < nstrips;
+            const bool last = s + 1 == nstrips;
+            int H[R], G[R], E[R];
+            unsigned sHb[R], sHm[R], sEb[R], sEm[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 H[r] = 0;
+                G[r] = -go_ge;
                 E[r] = kNeg;
-                sH[r] = Stat{0u, 0u};
-                sE[r] = Stat{0u, 0u};
+                sHb[r] = sHm[r] = sEb[r] = sEm[r] = 0u;
             }
-            int hlast = 0, flast = kNeg, hdiag0 = 0;
-            Stat shlast = {0u, 0u}, sflast = {0u, 0u}, sdiag0 = {0u, 0u};
-            int cres = kPadCode;
+            int hlast = 0, flast = kNeg, hprev = 0, cres = kPadCode, chunk = kPadCode;
+            unsigned hb_last = 0, hm_last = 0, fb_last = 0, fm_last = 0, db_prev = 0, dm_prev = 0;
             const int steps = lb + kWave - 1;
             for (int t = 0; t < steps; ++t) {
-                const int j = t - lane;
-                int rh = shfl_up1(hlast), rf = shfl_up1(flast);
-                Stat rsh = shfl_up_stat(shlast), rsf = shfl_up_stat(sflast);
-                int rc = shfl_up1(cres);
-                if (lane == 0) {
-                    rc = (t < lb) ? b[t] : kPadCode;
-                    if (first) {
-                        rh = 0;
-                        rf = kNeg;
-                        rsh = Stat{0u, 0u};
-                        rsf = Stat{0u, 0u};
-                    } else if (t < lb) {
-                        const int4 v = bnd_a[t];
-                        const int2 w = bnd_b[t];
-                        rh = v.x;
-                        rf = v.y;
-                        rsh = Stat{(unsigned)v.z, (unsigned)v.w};
-                        rsf = Stat{(unsigned)w.x, (unsigned)w.y};
-                    }
+                if ((t & (kWave - 1)) == 0) chunk = (t + lane < lb) ? (int)b[t + lane] : kPadCode;
+                const int bt = __builtin_amdgcn_readlane(chunk, t & (kWave - 1));
+                int in_h = 0, in_f = kNeg;
+                unsigned in_hb = 0, in_hm = 0, in_fb = 0, in_fm = 0;
+                if (MULTI && from_above && t < lb) {
+                    in_h = vload(bnd + t);
+                    in_f = vload(bnd + plane + t);
+                    in_hb = (unsigned)vload(bnd + 2 * plane + t);
+                    in_hm = (unsigned)vload(bnd + 3 * plane + t);
+                    in_fb = (unsigned)vload(bnd + 4 * plane + t);
+                    in_fm = (unsigned)vload(bnd + 5 * plane + t);
                 }
-                cres = rc;
-                const bool valid = (j >= 0) && (j < lb);
-                const uint64_t pw = prof[cres][lane];
-                int hdiag = hdiag0, hup = rh, fup = rf;
-                Stat sdiag = sdiag0, shup = rsh, sfup = rsf;
-                const unsigned here0 = ((unsigned)base << 16) | (unsigned)(j & 0xFFFF);
+                const int rh = shr1(in_h, hlast);
+                const int rf = shr1(in_f, flast);
+                const unsigned rhb = (unsigned)shr1((int)in_hb, (int)hb_last);
+                const unsigned rhm = (unsigned)shr1((int)in_hm, (int)hm_last);
+                const unsigned rfb = (unsigned)shr1((int)in_fb, (int)fb_last);
+                const unsigned rfm = (unsigned)shr1((int)in_fm, (int)fm_last);
+                cres = shr1(bt, cres);
+                const int j = t - lane;
+                const ProfWord<R> pw = prof[cres][lane];
+                const unsigned colpart = (unsigned)j & 0xFFFFu;
+                int hd = hprev, gu = rh - go_ge, fu = rf;
+                unsigned db = db_prev, dm = dm_prev, ub = rhb, um = rhm, fb = rfb, fm = rfm;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const int sigma = (int)(int8_t)(pw >> (8 * r));
-                    // horizontal gap: extend when it is at least as good as opening
-                    const int e_ext = E[r] - ge, e_open = H[r] - go_ge;
-                    const bool e_is_ext = e_ext >= e_open;
-                    const int e = e_is_ext ? e_ext : e_open;
-                    const Stat se = sel(e_is_ext, sE[r], sH[r]);
+                    // horizontal gap: extend when at least as good as opening
+                    const int e_ext = E[r] - ge;
+                    const bool ee = e_ext >= G[r];
+                    const int e = ee ? e_ext : G[r];
+                    const unsigned eb = ee ? sEb[r] : sHb[r];
+                    const unsigned em = ee ? sEm[r] : sHm[r];
                     // vertical gap
-                    const int f_ext = fup - ge, f_open = hup - go_ge;
-                    const bool f_is_ext = f_ext >= f_open;
-                    const int f = f_is_ext ? f_ext : f_open;
-                    const Stat sf = sel(f_is_ext, sfup, shup);
-                    // diagonal: a zero predecessor starts a new path here
-                    const int d = hdiag + sigma;
+                    const int f_ext = fu - ge;
+                    const bool fe = f_ext >= gu;
+                    const int f = fe ? f_ext : gu;
+                    const unsigned nfb = fe ? fb : ub;
+                    const unsigned nfm = fe ? fm : um;
+                    // diagonal; a zero predecessor starts a new path at this cell
+                    const int d = hd + sigma_at<R>(pw, r);
                     const int h = max(max(d, 0), max(e, f));
-                    Stat sd = sel(hdiag == 0, Stat{here0 + ((unsigned)r << 16), 0u}, sdiag);
-                    sd.md += (ar[r] == (uint8_t)cres) ? 0x10001u : 1u;
-                    const Stat sh = sel(h == d, sd, sel(h == e, se, sf));
-                    hdiag = H[r];
-                    sdiag = sH[r];
+                    const bool start = hd == 0;
+                    const unsigned xb = start ? (rowpart[r] | colpart) : db;
+                    const unsigned xm = (start ? 0u : dm) + ((ar[r] == cres) ? 0x10001u : 1u);
+                    const bool is_d = h == d, is_e = h == e;
+                    const unsigned hb = is_d ? xb : (is_e ? eb : nfb);
+                    const unsigned hm = is_d ? xm : (is_e ? em : nfm);
+                    hd = H[r];
+                    db = sHb[r];
+                    dm = sHm[r];
                     H[r] = h;
                     E[r] = e;
-                    sH[r] = sh;
-                    sE[r] = se;
-                    hup = h;
-                    fup = f;
-                    shup = sh;
-                    sfup = sf;
-                    if (valid && j == lb - 1 && base + r == la - 1) fin = sh;
+                    const int g = h - go_ge;
+                    G[r] = g;
+                    sHb[r] = hb;
+                    sHm[r] = hm;
+                    sEb[r] = eb;
+                    sEm[r] = em;
+                    gu = g;
+                    fu = f;
+                    ub = hb;
+                    um = hm;
+                    fb = nfb;
+                    fm = nfm;
                 }
-                hlast = hup;
-                flast = fup;
-                shlast = shup;
-                sflast = sfup;
-                hdiag0 = rh;
-                sdiag0 = rsh;
-                if (has_next && lane == kWave - 1 && valid) {
-                    bnd_a[j] = make_int4(hlast, flast, (int)shlast.beg, (int)shlast.md);
-                    bnd_b[j] = make_int2((int)sflast.beg, (int)sflast.md);
+                hlast = H[R - 1];
+                flast = fu;
+                hb_last = ub;
+                hm_last = um;
+                fb_last = fb;
+                fm_last = fm;
+                hprev = rh;
+                db_prev = rhb;
+                dm_prev = rhm;
+                if (last && lane == kWave - 1 && j == lb - 1) {
+                    fin_beg = hb_last;
+                    fin_md = hm_last;
+                }
+                if (MULTI && to_below && lane == kWave - 1 && j >= 0 && j < lb) {
+                    bnd[j] = hlast;
+                    bnd[plane + j] = flast;
+                    bnd[2 * plane + j] = (int)hb_last;
+                    bnd[3 * plane + j] = (int)hm_last;
+                    bnd[4 * plane + j] = (int)fb_last;
+                    bnd[5 * plane + j] = (int)fm_last;
                 }
             }
-            __threadfence_block();
+            if (MULTI) __threadfence_block();
         }
-        // the end cell belongs to exactly one lane; combine by max (others hold 0)
-        unsigned long long key = ((unsigned long long)fin.beg << 32) | fin.md;
-        key = wave_max_u64(key);
-        if (lane == 0) {
-            const unsigned beg = (unsigned)(key >> 32), md = (unsigned)key;
-            rec.beg_a = (int32_t)(beg >> 16);
-            rec.beg_b = (int32_t)(beg & 0xFFFF);
-            rec.matches = (int32_t)(md >> 16);
-            const int32_t diag = (int32_t)(md & 0xFFFF);
+        if (lane == kWave - 1) {
+            pastis_pair_record rec;
+            rec.score = r1.score;
+            rec.end_a = r1.end_a;
+            rec.end_b = r1.end_b;
+            rec.beg_a = (int32_t)(fin_beg >> 16);
+            rec.beg_b = (int32_t)(fin_beg & 0xFFFF);
+            rec.matches = (int32_t)(fin_md >> 16);
+            const int32_t diag = (int32_t)(fin_md & 0xFFFF);
             rec.columns = (rec.end_a - rec.beg_a + 1) + (rec.end_b - rec.beg_b + 1) - diag;
+            rec.seed_used = -1;
             const long long span = (long long)rec.end_a - rec.beg_a + 1;
             rec.passed = (100LL * rec.matches >= (long long)id_pct * rec.columns) &&
-                         (100LL * span >= (long long)cov_pct * la_full);
+                         (100LL * span >= (long long)cov_pct * pd.la);
+            rec.swapped = pd.swapped;
+            rec.cells = (int64_t)pd.la * pd.lb;
             out[q] = rec;
         }
     }
 }
 
+template <int R>
+hipError_t launch_p1(int bin, int blocks, const uint8_t *codes, const PairDesc *pairs, const int *idx,
+                     const int *starts, const int8_t *blosum, int go_ge, int ge, SwPass1Out *p1, int *scratch,
+                     int64_t spw, hipStream_t s) {
+    if (bin == kMultiBin)
+        sw_pass1_kernel<R, true><<<blocks, 256, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, p1, scratch,
+                                                        spw);
+    else
+        sw_pass1_kernel<R, false><<<blocks, 256, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, p1,
+                                                         scratch, spw);
+    return hipGetLastError();
+}
+
+template <int R>
+hipError_t launch_p2(int bin, int blocks, const uint8_t *codes, const PairDesc *pairs, const int *idx,
+                     const int *starts, const int8_t *blosum, int go_ge, int ge, int cov, int id,
+                     const SwPass1Out *p1, pastis_pair_record *out, int *scratch, int64_t spw, hipStream_t s) {
+    if (bin == kMultiBin)
+        sw_pass2_kernel<R, true><<<blocks, 256, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, cov, id, p1,
+                                                        out, scratch, spw);
+    else
+        sw_pass2_kernel<R, false><<<blocks, 256, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, cov, id,
+                                                         p1, out, scratch, spw);
+    return hipGetLastError();
+}
+
+typedef hipError_t (*P1Fn)(int, int, const uint8_t *, const PairDesc *, const int *, const int *, const int8_t *, int,
+                           int, SwPass1Out *, int *, int64_t, hipStream_t);
+typedef hipError_t (*P2Fn)(int, int, const uint8_t *, const PairDesc *, const int *, const int *, const int8_t *, int,
+                           int, int, int, const SwPass1Out *, pastis_pair_record *, int *, int64_t, hipStream_t);
+
+const P1Fn kP1[kNumBins] = {launch_p1<1>, launch_p1<2>, launch_p1<3>, launch_p1<4>, launch_p1<5>,
+                            launch_p1<6>, launch_p1<7>, launch_p1<8>, launch_p1<8>};
+const P2Fn kP2[kNumBins] = {launch_p2<1>, launch_p2<2>, launch_p2<3>, launch_p2<4>, launch_p2<5>,
+                            launch_p2<6>, launch_p2<7>, launch_p2<8>, launch_p2<8>};
+
 }  // namespace
 
-hipError_t launch_sw(const uint8_t *codes, const PairDesc *pairs, int64_t npairs, const int8_t *blosum,
-                     const Scoring &sc, SwPass1Out *p1, pastis_pair_record *out, int32_t *scratch,
-                     int64_t scratch_ints_per_wave, int full, int waves, hipStream_t s) {
+int sw_num_bins() { return kNumBins; }
+
+// Blocks per bin launch: enough resident waves to fill 256 CUs for the bin's
+// LDS footprint (the grid-stride loop reads the bin size on the device).
+static int blocks_for_bin(int bin) { return bin < 4 ? 256 * 6 : 256 * 3; }
+
+// Only the multi-strip bin uses the boundary buffers.
+int64_t sw_scratch_waves() { return (int64_t)blocks_for_bin(kMultiBin) * kWavesPerBlock; }
+
+hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pairs, int64_t npairs,
+                     const int8_t *blosum, const Scoring &sc, SwPass1Out *p1, pastis_pair_record *out,
+                     const SwWork &wk, int full, hipStream_t s) {
     if (npairs <= 0) return hipSuccess;
     const int go_ge = sc.gap_open + sc.gap_extend, ge = sc.gap_extend;
-    int blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
-    if (blocks < 1) blocks = 1;
-    sw_pass1_kernel<8><<<blocks, 256, 0, s>>>(codes, pairs, npairs, blosum, go_ge, ge, p1, (int2 *)scratch,
-                                              scratch_ints_per_wave / 2);
-    hipError_t e = hipGetLastError();
+    const int nb = (int)((npairs + 255) / 256);
+    hipError_t e = stage_begin(ctx, kStSched, s);
     if (e != hipSuccess) return e;
-    sw_pass2_kernel<8><<<blocks, 256, 0, s>>>(codes, pairs, npairs, blosum, go_ge, ge, sc.cov_pct, sc.id_pct, full,
-                                              p1, out, (int4 *)scratch, scratch_ints_per_wave / 4);
-    return hipGetLastError();
+    sw_bin1_kernel<<<nb, 256, 0, s>>>(pairs, npairs, wk.bin_of);
+    if ((e = launch_bins(wk.bin_of, npairs, kNumBins, wk.counts, wk.starts, wk.cursor, wk.idx, s)) != hipSuccess)
+        return e;
+    if ((e = stage_end(ctx, kStSched, s)) != hipSuccess || (e = stage_begin(ctx, kStAlign1, s)) != hipSuccess)
+        return e;
+    for (int bin = 0; bin < kNumBins; ++bin) {
+        e = kP1[bin](bin, blocks_for_bin(bin), codes, pairs, wk.idx, wk.starts, blosum, go_ge, ge, p1, wk.scratch,
+                     wk.scratch_per_wave, s);
+        if (e != hipSuccess) return e;
+    }
+    if ((e = stage_end(ctx, kStAlign1, s)) != hipSuccess || (e = stage_begin(ctx, kStAlign2, s)) != hipSuccess)
+        return e;
+    sw_bin2_kernel<<<nb, 256, 0, s>>>(pairs, p1, npairs, sc.cov_pct, full, out, wk.bin_of);
+    if ((e = launch_bins(wk.bin_of, npairs, kNumBins, wk.counts, wk.starts2, wk.cursor, wk.idx2, s)) != hipSuccess)
+        return e;
+    for (int bin = 0; bin < kNumBins; ++bin) {
+        e = kP2[bin](bin, blocks_for_bin(bin), codes, pairs, wk.idx2, wk.starts2, blosum, go_ge, ge, sc.cov_pct,
+                     sc.id_pct, p1, out, wk.scratch, wk.scratch_per_wave, s);
+        if (e != hipSuccess) return e;
+    }
+    return stage_end(ctx, kStAlign2, s);
 }
 
 }  // namespace pastis

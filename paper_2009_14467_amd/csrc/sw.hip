@@ -158,17 +158,38 @@ __global__ __launch_bounds__(256) void sw_pass1_kernel(const uint8_t *__restrict
                 rcol[r] = 0;
             }
             int hlast = 0, flast = kNeg, hprev = 0, cres = kPadCode;
-            int chunk = kPadCode;
+            // column residues and the strip boundary row arrive in coalesced
+            // chunks of 64 columns, fetched one chunk ahead; lane 0 reads its
+            // value for step t with readlane
+            int chunk = kPadCode, ch_h = 0, ch_f = kNeg;
+            int nx = (lane < lb) ? (int)b[lane] : kPadCode;
+            int nx_h = 0, nx_f = kNeg;
+            if (MULTI && from_above && lane < lb) {
+                nx_h = vload(bnd_h + lane);
+                nx_f = vload(bnd_f + lane);
+            }
             // one DP step; in the tail (t >= lb) lanes past the last column
             // must not touch their running maxima
             auto step = [&](const int t, auto tail_tag) {
                 constexpr bool kTail = decltype(tail_tag)::value;
-                if ((t & (kWave - 1)) == 0) chunk = (t + lane < lb) ? (int)b[t + lane] : kPadCode;
+                if ((t & (kWave - 1)) == 0) {
+                    chunk = nx;
+                    const int c = t + kWave + lane;
+                    nx = (c < lb) ? (int)b[c] : kPadCode;
+                    if (MULTI && from_above) {
+                        ch_h = nx_h;
+                        ch_f = nx_f;
+                        if (c < lb) {
+                            nx_h = vload(bnd_h + c);
+                            nx_f = vload(bnd_f + c);
+                        }
+                    }
+                }
                 const int bt = __builtin_amdgcn_readlane(chunk, t & (kWave - 1));
                 int in_h = 0, in_f = kNeg;
                 if (MULTI && !kTail && from_above) {
-                    in_h = vload(bnd_h + t);
-                    in_f = vload(bnd_f + t);
+                    in_h = __builtin_amdgcn_readlane(ch_h, t & (kWave - 1));
+                    in_f = __builtin_amdgcn_readlane(ch_f, t & (kWave - 1));
                 }
                 const int rh = shr1(in_h, hlast);
                 const int rf = shr1(in_f, flast);
@@ -343,19 +364,39 @@ __global__ __launch_bounds__(256) void sw_pass2_kernel(const uint8_t *__restrict
             }
             int hlast = 0, flast = kNeg, hprev = 0, cres = kPadCode, chunk = kPadCode;
             unsigned hb_last = 0, hm_last = 0, fb_last = 0, fm_last = 0, db_prev = 0, dm_prev = 0;
+            // chunked, one-ahead prefetch of residues and boundary planes (see pass 1)
+            int nx = (lane < lb) ? (int)b[lane] : kPadCode;
+            int cb[6] = {0, kNeg, 0, 0, 0, 0}, nb[6] = {0, kNeg, 0, 0, 0, 0};
+            if (MULTI && from_above && lane < lb) {
+#pragma unroll
+                for (int p = 0; p < 6; ++p) nb[p] = vload(bnd + p * plane + lane);
+            }
             const int steps = lb + kWave - 1;
             for (int t = 0; t < steps; ++t) {
-                if ((t & (kWave - 1)) == 0) chunk = (t + lane < lb) ? (int)b[t + lane] : kPadCode;
+                if ((t & (kWave - 1)) == 0) {
+                    chunk = nx;
+                    const int c = t + kWave + lane;
+                    nx = (c < lb) ? (int)b[c] : kPadCode;
+                    if (MULTI && from_above) {
+#pragma unroll
+                        for (int p = 0; p < 6; ++p) cb[p] = nb[p];
+                        if (c < lb) {
+#pragma unroll
+                            for (int p = 0; p < 6; ++p) nb[p] = vload(bnd + p * plane + c);
+                        }
+                    }
+                }
                 const int bt = __builtin_amdgcn_readlane(chunk, t & (kWave - 1));
                 int in_h = 0, in_f = kNeg;
                 unsigned in_hb = 0, in_hm = 0, in_fb = 0, in_fm = 0;
                 if (MULTI && from_above && t < lb) {
-                    in_h = vload(bnd + t);
-                    in_f = vload(bnd + plane + t);
-                    in_hb = (unsigned)vload(bnd + 2 * plane + t);
-                    in_hm = (unsigned)vload(bnd + 3 * plane + t);
-                    in_fb = (unsigned)vload(bnd + 4 * plane + t);
-                    in_fm = (unsigned)vload(bnd + 5 * plane + t);
+                    const int tt = t & (kWave - 1);
+                    in_h = __builtin_amdgcn_readlane(cb[0], tt);
+                    in_f = __builtin_amdgcn_readlane(cb[1], tt);
+                    in_hb = (unsigned)__builtin_amdgcn_readlane(cb[2], tt);
+                    in_hm = (unsigned)__builtin_amdgcn_readlane(cb[3], tt);
+                    in_fb = (unsigned)__builtin_amdgcn_readlane(cb[4], tt);
+                    in_fm = (unsigned)__builtin_amdgcn_readlane(cb[5], tt);
                 }
                 const int rh = shr1(in_h, hlast);
                 const int rf = shr1(in_f, flast);

@@ -14,5 +14,6 @@ from .families import (  # noqa: F401
     FamilySet,
     background_frequencies,
     make_family_set,
+    pair_list,
     workload,
 )

@@ -259,3 +259,33 @@ def workload(name: str, *, seed: int = 0, **overrides) -> FamilySet:
     cfg = dict(WORKLOADS[name])
     cfg.update(overrides)
     return make_family_set(seed=seed, name=name, **cfg)
+
+
+def pair_list(fs: FamilySet, *, random_per_seq: float = 10.0, seed: int = 0, stream: int = 100):
+    """A seeded pair list over a family set: every within-family pair plus
+    about ``random_per_seq * n`` uniformly random unrelated pairs (i < j).
+    Input generation only (no k-mers, no scoring): it stands in for a
+    candidate list when a stage is timed on its own."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed, spawn_key=(stream,)))
+    lab = fs.labels
+    order = np.argsort(lab, kind="stable")
+    fam_pairs = []
+    sl = lab[order]
+    bounds = np.flatnonzero(np.diff(np.concatenate([[-2], sl, [-3]])))
+    for s0, s1 in zip(bounds[:-1], bounds[1:]):
+        if sl[s0] < 0 or s1 - s0 < 2:
+            continue
+        members = order[s0:s1]
+        a, b = np.triu_indices(members.size, 1)
+        fam_pairs.append(np.stack([members[a], members[b]], 1))
+    fam = np.concatenate(fam_pairs) if fam_pairs else np.zeros((0, 2), np.int64)
+    m = int(random_per_seq * fs.n)
+    x = rng.integers(0, fs.n, m)
+    y = rng.integers(0, fs.n, m)
+    keep = (x != y) & ((lab[x] != lab[y]) | (lab[x] < 0))
+    rnd = np.stack([x[keep], y[keep]], 1)
+    allp = np.concatenate([fam, rnd])
+    lo = np.minimum(allp[:, 0], allp[:, 1]).astype(np.uint32)
+    hi = np.maximum(allp[:, 0], allp[:, 1]).astype(np.uint32)
+    key = np.unique((lo.astype(np.uint64) << np.uint64(32)) | hi.astype(np.uint64))
+    return (key >> np.uint64(32)).astype(np.uint32), (key & np.uint64(0xFFFFFFFF)).astype(np.uint32)

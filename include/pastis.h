@@ -161,6 +161,48 @@ pastis_status pastis_align_pairs(pastis_ctx *ctx, const uint8_t *residues, const
                                  int input_on_device, const uint32_t *pi, const uint32_t *pj, const uint32_t *seed1,
                                  const uint32_t *seed2, int64_t npairs, pastis_pair_record *out, void *stream);
 
+/* Candidate discovery (Sections IV-A to IV-C, threshold of Section VI): k-mers
+ * of every sequence (A), the m nearest substitutes of every distinct k-mer
+ * when n_subs > 0 (S), the sparse product A A^T or (A S) A^T under the count +
+ * seed semiring, the common-k-mer threshold ck_min and, with substitutes,
+ * symmetrisation (each pair keeps the direction with the larger count; the
+ * lower-numbered sequence's direction on a tie).  Candidates stay in ctx;
+ * *n_candidates receives their number.  Inputs as for pastis_align_pairs.
+ * Errors: PASTIS_E_INVAL, PASTIS_E_BAD_RESIDUE, PASTIS_E_NOMEM, PASTIS_E_DEVICE. */
+pastis_status pastis_discover(pastis_ctx *ctx, const uint8_t *residues, const int64_t *offsets, int64_t n,
+                              int input_on_device, void *stream, int64_t *n_candidates);
+
+/* Copy the last discovery's candidates, sorted by (lo, hi), lo < hi:
+ * count = shared (substitute) k-mers, seed1 / seed2 = the two smallest keys
+ * (pos_in_lo << 16 | pos_in_hi), 0xFFFFFFFF when absent.  Any destination may
+ * be NULL (skipped).  PASTIS_E_CAPACITY if cap < count (nothing written);
+ * PASTIS_E_STATE if there was no discovery. */
+pastis_status pastis_candidates_copy(pastis_ctx *ctx, uint32_t *lo, uint32_t *hi, uint32_t *count, uint32_t *seed1,
+                                     uint32_t *seed2, int64_t cap, int dst_on_device, void *stream);
+
+/* The ctx's n_subs nearest substitutes (Section IV-B) of n k-mer ids (radix
+ * 24 over the context's k), all device arrays: out_ids / out_dist [n][n_subs],
+ * out_count [n] = entries written per k-mer (n_subs unless the k-mer space is
+ * smaller).  Within a k-mer the entries are not ordered.
+ * Errors: PASTIS_E_INVAL (n_subs == 0 or bad arguments), PASTIS_E_DEVICE. */
+pastis_status pastis_subkmers(pastis_ctx *ctx, const uint32_t *kmer_ids, int64_t n, uint32_t *out_ids,
+                              int32_t *out_dist, int32_t *out_count, void *stream);
+
+/* Sequences in, weighted similarity edges out (Section II problem, Section IV
+ * pipeline): discovery, alignment of every candidate with the context's
+ * align_mode, then the Section IV-F cut (weight_mode ANI) or no cut
+ * (weight_mode NS, every positive score).  *out owns the edges until
+ * pastis_result_free.  Errors as for pastis_discover. */
+pastis_status pastis_search(pastis_ctx *ctx, const uint8_t *residues, const int64_t *offsets, int64_t n,
+                            int input_on_device, void *stream, pastis_result **out);
+pastis_status pastis_result_count(const pastis_result *r, int64_t *n_edges);
+/* Device pointer to the result's edges (owned by the result). */
+const pastis_edge *pastis_result_device_ptr(const pastis_result *r);
+/* Copy all edges to dst (host or device); PASTIS_E_CAPACITY if cap is too small. */
+pastis_status pastis_result_copy(const pastis_result *r, pastis_edge *dst, int64_t cap, int dst_on_device,
+                                 void *stream);
+void pastis_result_free(pastis_result *r);
+
 /* Counters and per-stage times of the last pastis_search / pastis_align_pairs. */
 pastis_status pastis_stats(const pastis_ctx *ctx, pastis_run_stats *out);
 

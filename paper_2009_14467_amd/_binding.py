@@ -151,6 +151,14 @@ _SIGNATURES = [
     ("pastis_align_pairs", ctypes.c_int,
      [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_int, _VP, _VP, _VP, _VP, ctypes.c_int64, _VP, _VP]),
     ("pastis_stats", ctypes.c_int, [_VP, ctypes.POINTER(_Stats)]),
+    ("pastis_discover", ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_int, _VP, ctypes.POINTER(ctypes.c_int64)]),
+    ("pastis_candidates_copy", ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_int64, ctypes.c_int, _VP]),
+    ("pastis_subkmers", ctypes.c_int, [_VP, _VP, ctypes.c_int64, _VP, _VP, _VP, _VP]),
+    ("pastis_search", ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_int, _VP, ctypes.POINTER(_VP)]),
+    ("pastis_result_count", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int64)]),
+    ("pastis_result_device_ptr", _VP, [_VP]),
+    ("pastis_result_copy", ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int, _VP]),
+    ("pastis_result_free", None, [_VP]),
 ]
 
 
@@ -254,6 +262,57 @@ class Context:
                                              _dev_ptr(pi), _dev_ptr(pj), _dev_ptr(seed1), _dev_ptr(seed2), npairs,
                                              _dev_ptr(out), _stream_ptr(stream)))
         return out[: npairs * RECORD_DTYPE.itemsize]
+
+
+    def discover(self, residues, offsets, stream=None) -> int:
+        """Candidate discovery; returns the number of candidates (kept in ctx)."""
+        n = offsets.numel() - 1
+        on_dev = int(residues.is_cuda)
+        nc = ctypes.c_int64(0)
+        self._check(lib().pastis_discover(self._ctx, _dev_ptr(residues), _dev_ptr(offsets), n, on_dev,
+                                          _stream_ptr(stream), ctypes.byref(nc)))
+        return int(nc.value)
+
+    def candidates(self, n_candidates: int, stream=None) -> dict:
+        """Device tensors (int32 views of uint32) of the last discovery's candidates."""
+        torch = _torch()
+        dev = f"cuda:{self.device}"
+        out = {k: torch.empty(max(n_candidates, 1), dtype=torch.int32, device=dev)
+               for k in ("lo", "hi", "count", "seed1", "seed2")}
+        self._check(lib().pastis_candidates_copy(self._ctx, *(_dev_ptr(out[k]) for k in
+                                                            ("lo", "hi", "count", "seed1", "seed2")),
+                                                 n_candidates, 1, _stream_ptr(stream)))
+        return {k: v[:n_candidates] for k, v in out.items()}
+
+    def subkmers(self, kmer_ids, stream=None):
+        """kmer_ids: int32 device tensor of radix-24 ids -> (ids [n, m], dist [n, m], count [n])."""
+        torch = _torch()
+        n = kmer_ids.numel()
+        m = self.params.n_subs
+        dev = f"cuda:{self.device}"
+        ids = torch.empty((max(n, 1), m), dtype=torch.int32, device=dev)
+        dist = torch.empty((max(n, 1), m), dtype=torch.int32, device=dev)
+        cnt = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        self._check(lib().pastis_subkmers(self._ctx, _dev_ptr(kmer_ids), n, _dev_ptr(ids), _dev_ptr(dist),
+                                          _dev_ptr(cnt), _stream_ptr(stream)))
+        return ids[:n], dist[:n], cnt[:n]
+
+    def search(self, residues, offsets, stream=None) -> np.ndarray:
+        """Sequences in, edges out (host numpy array of EDGE_DTYPE)."""
+        n = offsets.numel() - 1
+        on_dev = int(residues.is_cuda)
+        res = _VP()
+        self._check(lib().pastis_search(self._ctx, _dev_ptr(residues), _dev_ptr(offsets), n, on_dev,
+                                        _stream_ptr(stream), ctypes.byref(res)))
+        try:
+            ne = ctypes.c_int64(0)
+            self._check(lib().pastis_result_count(res, ctypes.byref(ne)))
+            out = np.zeros(ne.value, dtype=EDGE_DTYPE)
+            if ne.value:
+                self._check(lib().pastis_result_copy(res, out.ctypes.data, ne.value, 0, _stream_ptr(stream)))
+            return out
+        finally:
+            lib().pastis_result_free(res)
 
 
 def records_to_numpy(t) -> np.ndarray:

@@ -3,6 +3,7 @@
 #include <chrono>
 
 #include "internal.hpp"
+#include "prim.hpp"
 
 using namespace pastis;
 
@@ -77,18 +78,6 @@ hipError_t stage_collect(pastis_ctx *ctx, hipStream_t s) {
 
 namespace {
 
-#define PASTIS_TRY(expr)                     \
-    do {                                     \
-        pastis_status _s = (expr);           \
-        if (_s != PASTIS_OK) return _s;      \
-    } while (0)
-
-#define HIP_TRY(ctx, expr, what)                          \
-    do {                                                  \
-        hipError_t _e = (expr);                           \
-        if (_e != hipSuccess) return hip_error(ctx, _e, what); \
-    } while (0)
-
 pastis_status validate(const pastis_params *p, std::string &why) {
     if (p->k < 1 || p->k > 6) return why = "k must be in 1..6", PASTIS_E_INVAL;
     if (p->n_subs < 0 || p->n_subs > 64) return why = "n_subs must be in 0..64", PASTIS_E_INVAL;
@@ -112,14 +101,9 @@ pastis_status validate(const pastis_params *p, std::string &why) {
     return PASTIS_OK;
 }
 
-// Host copy of the offsets plus the device residues/offsets of a call.
-struct Staged {
-    const uint8_t *d_res = nullptr;
-    const int64_t *d_off = nullptr;
-    std::vector<int64_t> h_off;
-    int64_t n_res = 0;
-    int max_len = 0;
-};
+}  // namespace
+
+namespace pastis {
 
 pastis_status stage_sequences(pastis_ctx *ctx, const uint8_t *residues, const int64_t *offsets, int64_t n,
                               int on_device, hipStream_t s, Staged &st) {
@@ -172,6 +156,12 @@ pastis_status encode_into(pastis_ctx *ctx, const uint8_t *d_res, int64_t n_res, 
     return PASTIS_OK;
 }
 
+pastis_status read_device(pastis_ctx *ctx, const void *d, void *h, size_t bytes, hipStream_t s) {
+    HIP_TRY(ctx, hipMemcpyAsync(h, d, bytes, hipMemcpyDeviceToHost, s), "read device");
+    HIP_TRY(ctx, hipStreamSynchronize(s), "sync");
+    return PASTIS_OK;
+}
+
 pastis_status read_flags(pastis_ctx *ctx, unsigned long long *d_flags, unsigned long long *h_flags, int count,
                          hipStream_t s) {
     HIP_TRY(ctx, hipMemcpyAsync(h_flags, d_flags, sizeof(unsigned long long) * count, hipMemcpyDeviceToHost, s),
@@ -194,8 +184,9 @@ pastis_status make_sw_work(pastis_ctx *ctx, int64_t npairs, int max_len, SwWork 
     void *p = nullptr;
     PASTIS_TRY(ensure(ctx, kBufBinOf, (size_t)std::max<int64_t>(npairs, 1), &p));
     wk.bin_of = (int8_t *)p;
-    PASTIS_TRY(ensure(ctx, kBufBinMeta, sizeof(int) * 160, &p));
+    PASTIS_TRY(ensure(ctx, kBufBinMeta, sizeof(int) * 160 + sizeof(unsigned long long) * 8, &p));
     wk.counts = (int *)p;
+    wk.counters = (unsigned long long *)((int *)p + 160);
     wk.starts = wk.counts + 32;
     wk.starts2 = wk.counts + 64;
     wk.cursor = wk.counts + 96;
@@ -209,7 +200,60 @@ pastis_status make_sw_work(pastis_ctx *ctx, int64_t npairs, int max_len, SwWork 
     return PASTIS_OK;
 }
 
-}  // namespace
+// Orient the pairs, then run the context's alignment mode; `out` gets one
+// record per pair.  Validates pair indices (PASTIS_E_INVAL).
+pastis_status align_core(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, int64_t n, const uint32_t *pi,
+                         const uint32_t *pj, const uint32_t *seed1, const uint32_t *seed2, int64_t npairs,
+                         pastis_pair_record *out, hipStream_t s) {
+    ctx->stats.n_aligned = npairs;
+    if (npairs == 0) return PASTIS_OK;
+    unsigned long long *d_flags = nullptr, h_flags[4];
+    PASTIS_TRY(reset_flags(ctx, &d_flags, s));
+    void *pairs = nullptr;
+    PASTIS_TRY(ensure(ctx, kBufPairs, sizeof(PairDesc) * (size_t)npairs, &pairs));
+    HIP_TRY(ctx,
+            launch_orient_pairs(st.d_off, n, pi, pj, seed1, seed2, npairs, ctx->params.k, (PairDesc *)pairs,
+                                d_flags + 1, s),
+            "orient kernel");
+    PASTIS_TRY(read_flags(ctx, d_flags, h_flags, 2, s));
+    if (h_flags[1] & 1ull) return set_error(ctx, PASTIS_E_INVAL, "pair index out of range or pi == pj");
+    const pastis_params &P = ctx->params;
+    Scoring sc{P.gap_open, P.gap_extend, P.xdrop, P.min_identity_pct, P.min_coverage_pct};
+    void *p1 = nullptr;
+    PASTIS_TRY(ensure(ctx, kBufPass1, sizeof(SwPass1Out) * (size_t)npairs, &p1));
+    SwWork wk;
+    PASTIS_TRY(make_sw_work(ctx, npairs, st.max_len, wk));
+    HIP_TRY(ctx, fill<unsigned long long>(wk.counters, 4, 0ull, s), "reset");
+    // traceback statistics: every pair on request; none for the normalised
+    // score weight; otherwise only where the coverage cut can still hold
+    const int stats_mode = P.full_records ? 1 : (P.weight_mode == PASTIS_WEIGHT_NS ? 2 : 0);
+    if (P.align_mode == PASTIS_ALIGN_SW) {
+        HIP_TRY(ctx,
+                launch_sw(ctx, codes, (const PairDesc *)pairs, npairs, ctx->d_blosum, sc, (SwPass1Out *)p1, out, wk,
+                          stats_mode, s),
+                "sw kernels");
+    } else {
+        return set_error(ctx, PASTIS_E_INVAL, "x-drop alignment is not available in this build");
+    }
+    unsigned long long c[4];
+    PASTIS_TRY(read_device(ctx, wk.counters, c, sizeof(c), s));
+    ctx->stats.cells = (int64_t)c[0];
+    ctx->stats.stats_pass_pairs = (int64_t)c[1];
+    return PASTIS_OK;
+}
+
+pastis_status align_candidates(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, int64_t n, hipStream_t s,
+                               pastis_pair_record **rec_out) {
+    const int64_t nc = ctx->n_candidates;
+    void *rec = nullptr;
+    PASTIS_TRY(ensure(ctx, kBufRecords, sizeof(pastis_pair_record) * (size_t)std::max<int64_t>(nc, 1), &rec));
+    *rec_out = (pastis_pair_record *)rec;
+    return align_core(ctx, st, codes, n, (const uint32_t *)ctx->buf[kBufCandLo].ptr,
+                      (const uint32_t *)ctx->buf[kBufCandHi].ptr, (const uint32_t *)ctx->buf[kBufCandS1].ptr,
+                      (const uint32_t *)ctx->buf[kBufCandS2].ptr, nc, (pastis_pair_record *)rec, s);
+}
+
+}  // namespace pastis
 
 extern "C" {
 
@@ -345,39 +389,16 @@ pastis_status pastis_align_pairs(pastis_ctx *ctx, const uint8_t *residues, const
     HIP_TRY(ctx, stage_begin(ctx, kStEncode, s), "event");
     PASTIS_TRY(encode_into(ctx, st.d_res, st.n_res, &codes, d_flags, s));
     HIP_TRY(ctx, stage_end(ctx, kStEncode, s), "event");
-    void *pairs = nullptr;
-    PASTIS_TRY(ensure(ctx, kBufPairs, sizeof(PairDesc) * (size_t)std::max<int64_t>(npairs, 1), &pairs));
-    HIP_TRY(ctx,
-            launch_orient_pairs(st.d_off, n, pi, pj, seed1, seed2, npairs, ctx->params.k, (PairDesc *)pairs,
-                                d_flags + 1, s),
-            "orient kernel");
-    PASTIS_TRY(read_flags(ctx, d_flags, h_flags, 2, s));
+    PASTIS_TRY(read_flags(ctx, d_flags, h_flags, 1, s));
     if (h_flags[0] != ~0ull) {
         ctx->bad_residue = (int64_t)h_flags[0];
         return set_error(ctx, PASTIS_E_BAD_RESIDUE, "bad residue at index " + std::to_string(h_flags[0]));
     }
-    if (h_flags[1] & 1ull) return set_error(ctx, PASTIS_E_INVAL, "pair index out of range or pi == pj");
-    if (npairs == 0) return PASTIS_OK;
-
-    const pastis_params &P = ctx->params;
-    Scoring sc{P.gap_open, P.gap_extend, P.xdrop, P.min_identity_pct, P.min_coverage_pct};
-    void *p1 = nullptr;
-    PASTIS_TRY(ensure(ctx, kBufPass1, sizeof(SwPass1Out) * (size_t)npairs, &p1));
-    SwWork wk;
-    PASTIS_TRY(make_sw_work(ctx, npairs, st.max_len, wk));
-    if (P.align_mode == PASTIS_ALIGN_SW) {
-        HIP_TRY(ctx,
-                launch_sw(ctx, codes, (const PairDesc *)pairs, npairs, ctx->d_blosum, sc, (SwPass1Out *)p1, out, wk,
-                          P.full_records, s),
-                "sw kernels");
-    } else {
-        return set_error(ctx, PASTIS_E_INVAL, "x-drop alignment is not available in this build");
-    }
+    PASTIS_TRY(align_core(ctx, st, codes, n, pi, pj, seed1, seed2, npairs, out, s));
     HIP_TRY(ctx, stage_collect(ctx, s), "sync");
     auto t1 = std::chrono::steady_clock::now();
     ctx->stats.n_sequences = n;
     ctx->stats.n_residues = st.n_res;
-    ctx->stats.n_aligned = npairs;
     ctx->stats.ms_total = std::chrono::duration<double, std::milli>(t1 - t0).count();
     return PASTIS_OK;
 }

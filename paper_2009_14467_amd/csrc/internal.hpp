@@ -45,6 +45,43 @@ struct PairDesc {
 // Stage timer: HIP events recorded on the call's stream, read after a sync.
 enum Stage { kStEncode = 0, kStKmers, kStSubs, kStSpgemm, kStSched, kStAlign1, kStAlign2, kStFilter, kNumStages };
 
+#define PASTIS_TRY(expr)                \
+    do {                                \
+        pastis_status _s = (expr);      \
+        if (_s != PASTIS_OK) return _s; \
+    } while (0)
+
+#define HIP_TRY(ctx, expr, what)                                        \
+    do {                                                                \
+        hipError_t _e = (expr);                                         \
+        if (_e != hipSuccess) return pastis::hip_error(ctx, _e, what);  \
+    } while (0)
+
+struct SwWork;
+
+// Host copy of the offsets plus the device residues/offsets of a call.
+struct Staged {
+    const uint8_t *d_res = nullptr;
+    const int64_t *d_off = nullptr;
+    std::vector<int64_t> h_off;
+    int64_t n_res = 0;
+    int max_len = 0;
+};
+
+pastis_status stage_sequences(pastis_ctx *ctx, const uint8_t *residues, const int64_t *offsets, int64_t n,
+                              int on_device, hipStream_t s, Staged &st);
+pastis_status encode_into(pastis_ctx *ctx, const uint8_t *d_res, int64_t n_res, uint8_t **codes_out,
+                          unsigned long long *flag, hipStream_t s);
+pastis_status read_flags(pastis_ctx *ctx, unsigned long long *d_flags, unsigned long long *h_flags, int count,
+                         hipStream_t s);
+pastis_status reset_flags(pastis_ctx *ctx, unsigned long long **d_flags, hipStream_t s);
+pastis_status make_sw_work(pastis_ctx *ctx, int64_t npairs, int max_len, SwWork &wk);
+pastis_status align_core(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, int64_t n, const uint32_t *pi,
+                         const uint32_t *pj, const uint32_t *seed1, const uint32_t *seed2, int64_t npairs,
+                         pastis_pair_record *out, hipStream_t s);
+// Read `count` device words into host memory (synchronises the stream).
+pastis_status read_device(pastis_ctx *ctx, const void *d, void *h, size_t bytes, hipStream_t s);
+
 }  // namespace pastis
 
 struct pastis_ctx {
@@ -55,7 +92,11 @@ struct pastis_ctx {
     pastis_run_stats stats{};
     int8_t *d_blosum = nullptr;  // 24 x 24 int8 + pad row (25 x 25 when padded)
     // grow-only device buffers, reused across calls
-    pastis::DeviceBuffer buf[32];
+    pastis::DeviceBuffer buf[96];
+    // discovery results kept for the align stage / candidate copies
+    int64_t n_candidates = 0;
+    int64_t n_seqs_last = 0;
+    bool have_candidates = false;
     void *h_pinned = nullptr;
     size_t h_pinned_bytes = 0;
     hipEvent_t ev[2 * 8] = {};
@@ -76,8 +117,15 @@ enum BufId {
     kBufBinMeta,
     kBufIdx,
     kBufIdx2,
-    kBufCount  // first free id
+    kBufCandLo,
+    kBufCandHi,
+    kBufCandCnt,
+    kBufCandS1,
+    kBufCandS2,
+    kBufRecords,
+    kBufCount  // first id used by the discovery stage
 };
+constexpr int kNumBufs = 96;
 
 pastis_status set_error(pastis_ctx *ctx, pastis_status s, const std::string &msg);
 pastis_status hip_error(pastis_ctx *ctx, hipError_t e, const char *what);
@@ -107,6 +155,7 @@ struct SwPass1Out {
 // boundary-row scratch for pairs taller than one strip (6 planes of max_len
 // ints per wave, for sw_scratch_waves() waves).
 struct SwWork {
+    unsigned long long *counters;  // [0] cells, [1] statistics-pass pairs, [2] their cells
     int8_t *bin_of;
     int *counts, *starts, *starts2, *cursor;
     int *idx, *idx2;
@@ -118,6 +167,6 @@ int64_t sw_scratch_waves();
 
 hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pairs, int64_t npairs,
                      const int8_t *blosum, const Scoring &sc, SwPass1Out *p1, pastis_pair_record *out,
-                     const SwWork &wk, int full, hipStream_t s);
+                     const SwWork &wk, int stats_mode, hipStream_t s);
 
 }  // namespace pastis

@@ -1,0 +1,525 @@
+// The whole pipeline (Section IV): encode -> k-mers -> [S, A S] -> sparse
+// product + threshold + symmetrisation -> candidates -> alignment -> filter
+// -> edges.  Host orchestration of the stage kernels, plus the C ABI calls of
+// the discovery stage and the result handle.
+#include <algorithm>
+#include <chrono>
+
+#include "internal.hpp"
+#include "kmers.hpp"
+#include "prim.hpp"
+#include "spgemm.hpp"
+#include "subs.hpp"
+
+struct pastis_result {
+    pastis_edge *d_edges = nullptr;
+    int64_t n = 0;
+    int device = 0;
+};
+
+namespace pastis {
+namespace {
+
+enum DiscBuf {
+    kDKCounts = kBufCount,
+    kDPostSeq,
+    kDPostPos,
+    kDPostU,
+    kDUkId,
+    kDUkStart,
+    kDRowCnt,
+    kDRowStart,
+    kDRowU,
+    kDRowPos,
+    kDKmap,
+    kDTemp,
+    kDSu,
+    kDSd,
+    kDScnt,
+    kDStmpIds,
+    kDStmpD,
+    kDAsUb,
+    kDAsStart,
+    kDAsLen,
+    kDAsS,
+    kDAsDp,
+    kDAsGtab,
+    kDMisc,
+    kDWork,
+    kDBigRows,
+    kDDirKey,
+    kDDirCnt,
+    kDDirS1,
+    kDDirS2,
+    kDDirDir,
+    kDDirKeyAlt,
+    kDPerm,
+    kDPermAlt,
+    kDFlag,
+    kDPick,
+    kDOpos,
+    kDGtab,
+    kDGcand,
+    kDEdgeFlag,
+    kDEdgePos,
+    kDSubIn,
+    kDSubIds,
+    kDSubD,
+    kDSubN,
+    kDEnd
+};
+static_assert(kDEnd <= kNumBufs, "buffer ids");
+
+template <typename T>
+pastis_status get(pastis_ctx *ctx, int id, size_t count, T **out) {
+    void *p = nullptr;
+    PASTIS_TRY(ensure(ctx, id, sizeof(T) * (count > 0 ? count : 1), &p));
+    *out = (T *)p;
+    return PASTIS_OK;
+}
+
+inline uint32_t next_pow2(uint64_t x) {
+    uint64_t p = 1;
+    while (p < x) p <<= 1;
+    return (uint32_t)p;
+}
+
+// Misc device words: [0..3] k-mer counts (in KmerTables), the rest below.
+struct Misc {
+    unsigned long long *max_ub;   // 1
+    unsigned long long *max_big;  // 1
+    uint32_t *n_big;              // 2
+    uint32_t *d_count;            // 1
+    uint32_t *d_overflow;         // 1
+    uint32_t *n_cand;             // 1
+    uint32_t *n_edges;            // 1
+    int *bin_meta;                // 160
+};
+
+pastis_status misc(pastis_ctx *ctx, Misc &m) {
+    unsigned long long *base = nullptr;
+    PASTIS_TRY(get(ctx, kDMisc, 128, &base));
+    m.max_ub = base;
+    m.max_big = base + 1;
+    uint32_t *w = (uint32_t *)(base + 2);
+    m.n_big = w;
+    m.d_count = w + 2;
+    m.d_overflow = w + 3;
+    m.n_cand = w + 4;
+    m.n_edges = w + 5;
+    m.bin_meta = (int *)(base + 8);
+    return PASTIS_OK;
+}
+
+// Edges of aligned candidates (sorted by (lo, hi) since the candidates are).
+__global__ void edge_flag_kernel(const pastis_pair_record *__restrict__ rec, int64_t n, int ns_mode,
+                                 uint8_t *__restrict__ flag) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+        flag[q] = ns_mode ? (rec[q].score > 0) : (rec[q].passed != 0);
+}
+
+__global__ void edge_write_kernel(const pastis_pair_record *__restrict__ rec, const uint8_t *__restrict__ flag,
+                                  const uint32_t *__restrict__ pos, int64_t n, const uint32_t *__restrict__ lo,
+                                  const uint32_t *__restrict__ hi, const uint32_t *__restrict__ count,
+                                  const int64_t *__restrict__ offsets, int ns_mode, pastis_edge *__restrict__ out) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        if (!flag[q]) continue;
+        const pastis_pair_record r = rec[q];
+        pastis_edge e;
+        const uint32_t i = lo[q], j = hi[q];
+        // rows a are sequence i unless the pair was swapped (then a = j)
+        const bool a_is_i = r.swapped == 0;
+        e.i = i;
+        e.j = j;
+        e.score = r.score;
+        e.matches = (uint32_t)r.matches;
+        e.columns = (uint32_t)r.columns;
+        e.beg_i = (uint32_t)(a_is_i ? r.beg_a : r.beg_b);
+        e.end_i = (uint32_t)(a_is_i ? r.end_a : r.end_b);
+        e.beg_j = (uint32_t)(a_is_i ? r.beg_b : r.beg_a);
+        e.end_j = (uint32_t)(a_is_i ? r.end_b : r.end_a);
+        e.shared_kmers = (uint16_t)(count[q] > 65535u ? 65535u : count[q]);
+        e.seed_used = r.seed_used < 0 ? (uint8_t)255 : (uint8_t)r.seed_used;
+        e.flags = (uint8_t)(r.swapped & 1);
+        e.identity = __fdiv_rn((float)r.matches, (float)(r.columns > 0 ? r.columns : 1));
+        const int64_t li = offsets[i + 1] - offsets[i], lj = offsets[j + 1] - offsets[j];
+        e.ns_weight = __fdiv_rn((float)r.score, (float)(li < lj ? li : lj));
+        if (ns_mode) {
+            // the normalised score needs no traceback: its statistics are not computed
+            e.beg_i = e.beg_j = 0xFFFFFFFFu;
+            e.matches = e.columns = 0;
+            e.identity = 0.0f;
+        }
+        out[pos[q]] = e;
+    }
+}
+
+inline unsigned grid_for(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    if (b > 16384) b = 16384;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
+// Discovery: candidates into kDCand*; returns their count.
+pastis_status discover(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, int64_t n, hipStream_t s,
+                       int64_t *n_cand_out) {
+    const pastis_params &P = ctx->params;
+    const int64_t m = st.n_res;
+    const bool subs = P.n_subs > 0;
+    Misc M;
+    PASTIS_TRY(misc(ctx, M));
+
+    // ---- k-mers
+    HIP_TRY(ctx, stage_begin(ctx, kStKmers, s), "event");
+    KmerTables kt;
+    PASTIS_TRY(get(ctx, kDKCounts, 4, &kt.counts));
+    PASTIS_TRY(get(ctx, kDPostSeq, m, &kt.post_seq));
+    PASTIS_TRY(get(ctx, kDPostPos, m, &kt.post_pos));
+    PASTIS_TRY(get(ctx, kDPostU, m, &kt.post_u));
+    PASTIS_TRY(get(ctx, kDUkId, m, &kt.uk_id));
+    PASTIS_TRY(get(ctx, kDUkStart, m + 1, &kt.uk_start));
+    PASTIS_TRY(get(ctx, kDRowCnt, n + 1, &kt.row_cnt));
+    PASTIS_TRY(get(ctx, kDRowStart, n + 1, &kt.row_start));
+    PASTIS_TRY(get(ctx, kDRowU, m, &kt.row_u));
+    PASTIS_TRY(get(ctx, kDRowPos, m, &kt.row_pos));
+    kt.kmap = nullptr;
+    if (subs) PASTIS_TRY(get(ctx, kDKmap, (size_t)kmap_entries(P.k), &kt.kmap));
+    char *temp = nullptr;
+    PASTIS_TRY(get(ctx, kDTemp, kmers_temp_bytes(m, n), &temp));
+    HIP_TRY(ctx, build_kmers(codes, st.d_off, n, m, P.k, subs, kt, temp, s), "k-mer kernels");
+    HIP_TRY(ctx, stage_end(ctx, kStKmers, s), "event");
+    uint32_t kc[4];
+    PASTIS_TRY(read_device(ctx, kt.counts, kc, sizeof(kc), s));
+    const int64_t nnz = kc[0], nu = kc[1];
+    ctx->stats.n_kmers = nnz;
+
+    // ---- substitute rows and A S
+    SpgemmArgs sp{};
+    sp.kt = &kt;
+    sp.n = n;
+    sp.ck = P.ck_min;
+    sp.exact = subs ? 0 : 1;
+    if (subs) {
+        HIP_TRY(ctx, stage_begin(ctx, kStSubs, s), "event");
+        const int W = P.n_subs + 1;
+        uint32_t *s_u, *s_cnt, *tmp_ids;
+        int8_t *s_d, *tmp_d;
+        PASTIS_TRY(get(ctx, kDSu, (size_t)nu * W, &s_u));
+        PASTIS_TRY(get(ctx, kDSd, (size_t)nu * W, &s_d));
+        PASTIS_TRY(get(ctx, kDScnt, (size_t)nu, &s_cnt));
+        PASTIS_TRY(get(ctx, kDStmpIds, (size_t)s_rows_threads() * P.n_subs, &tmp_ids));
+        PASTIS_TRY(get(ctx, kDStmpD, (size_t)s_rows_threads() * P.n_subs, &tmp_d));
+        HIP_TRY(ctx,
+                launch_s_rows(kt.uk_id, kt.counts + 1, kt.kmap, ctx->d_blosum, P.k, P.n_subs, P.sub_alphabet, s_u, s_d,
+                              s_cnt, tmp_ids, tmp_d, s),
+                "S kernel");
+        AsArgs as{};
+        as.kt = &kt;
+        as.s_u = s_u;
+        as.s_d = s_d;
+        as.s_cnt = s_cnt;
+        as.W = W;
+        as.n = n;
+        PASTIS_TRY(get(ctx, kDAsUb, n, &as.ub));
+        PASTIS_TRY(get(ctx, kDAsStart, n + 1, &as.as_start));
+        PASTIS_TRY(get(ctx, kDAsLen, n, &as.as_len));
+        PASTIS_TRY(get(ctx, kBufBinOf, n, &as.bin_of));
+        as.bins = BinBufs{M.bin_meta, M.bin_meta + 32, M.bin_meta + 64, nullptr};
+        PASTIS_TRY(get(ctx, kBufIdx, n, &as.bins.idx));
+        as.max_ub = M.max_ub;
+        as.scan_temp = temp;
+        HIP_TRY(ctx, as_stage(as, s), "A S plan");
+        uint64_t tot = 0;
+        unsigned long long mx = 0;
+        PASTIS_TRY(read_device(ctx, as.as_start + n, &tot, sizeof(tot), s));
+        PASTIS_TRY(read_device(ctx, M.max_ub, &mx, sizeof(mx), s));
+        PASTIS_TRY(get(ctx, kDAsS, tot, &as.as_s));
+        PASTIS_TRY(get(ctx, kDAsDp, tot, &as.as_dp));
+        uint32_t gcap = 0;
+        as.global_blocks = 256;
+        if (mx > 0) {
+            gcap = next_pow2(2 * mx);
+            as.global_blocks = (int)std::max<int64_t>(8, std::min<int64_t>(256, (int64_t)(2ll << 30) / (8ll * gcap)));
+            PASTIS_TRY(get(ctx, kDAsGtab, (size_t)as.global_blocks * 2 * gcap, &as.gtables));
+        }
+        HIP_TRY(ctx, as_run(as, gcap, s), "A S kernels");
+        HIP_TRY(ctx, stage_end(ctx, kStSubs, s), "event");
+        sp.row_start64 = as.as_start;
+        sp.row_len = as.as_len;
+        sp.ent_s = as.as_s;
+        sp.ent_dp = as.as_dp;
+    } else {
+        sp.row_start32 = kt.row_start;
+        sp.ent_s = kt.row_u;
+        sp.ent_pos16 = kt.row_pos;
+    }
+
+    // ---- sparse product
+    HIP_TRY(ctx, stage_begin(ctx, kStSpgemm, s), "event");
+    PASTIS_TRY(get(ctx, kDWork, n, &sp.work));
+    PASTIS_TRY(get(ctx, kBufBinOf, n, &sp.bin_of));
+    sp.bins = BinBufs{M.bin_meta, M.bin_meta + 32, M.bin_meta + 64, nullptr};
+    PASTIS_TRY(get(ctx, kBufIdx, n, &sp.bins.idx));
+    sp.max_big = M.max_big;
+    PASTIS_TRY(get(ctx, kDBigRows, n, &sp.big_rows));
+    sp.n_big = M.n_big;
+    sp.d_count = M.d_count;
+    sp.d_overflow = M.d_overflow;
+    sp.nbits = key_bits(n);
+    HIP_TRY(ctx, spgemm_plan(sp, s), "product plan");
+    unsigned long long mxw = 0;
+    PASTIS_TRY(read_device(ctx, M.max_big, &mxw, sizeof(mxw), s));
+    const uint32_t gcap = next_pow2(2 * std::max<unsigned long long>(mxw, 12288ull));
+    sp.global_blocks = (int)std::max<int64_t>(8, std::min<int64_t>(256, (int64_t)(2ll << 30) / (16ll * gcap)));
+    PASTIS_TRY(get(ctx, kDGtab, (size_t)sp.global_blocks * gcap, &sp.gtables));
+    PASTIS_TRY(get(ctx, kDGcand, (size_t)sp.global_blocks * 2 * gcap, &sp.gcand));
+    uint32_t cap = (uint32_t)std::min<int64_t>(std::max<int64_t>(4 * n, 1 << 20), (int64_t)1 << 31);
+    for (;;) {
+        sp.cap = cap;
+        PASTIS_TRY(get(ctx, kDDirKey, cap, &sp.d_key));
+        PASTIS_TRY(get(ctx, kDDirCnt, cap, &sp.d_cnt));
+        PASTIS_TRY(get(ctx, kDDirS1, cap, &sp.d_s1));
+        PASTIS_TRY(get(ctx, kDDirS2, cap, &sp.d_s2));
+        PASTIS_TRY(get(ctx, kDDirDir, cap, &sp.d_dir));
+        // the spill counter (second word) is reset so each attempt starts clean
+        HIP_TRY(ctx, fill<uint32_t>(sp.n_big + 1, 1, 0u, s), "reset");
+        uint32_t nb0 = 0;
+        PASTIS_TRY(read_device(ctx, sp.n_big, &nb0, sizeof(nb0), s));
+        HIP_TRY(ctx, spgemm_run(sp, gcap, s), "product kernels");
+        uint32_t got[2];
+        PASTIS_TRY(read_device(ctx, M.d_count, got, sizeof(got), s));
+        if (!got[1]) break;
+        cap = (uint32_t)std::min<uint64_t>((uint64_t)got[0] + got[0] / 4 + 1024, 0xFFFFFFF0ull);
+        // redo from the planned state: restore the big-row count of the plan
+        HIP_TRY(ctx, fill<uint32_t>(sp.n_big, 1, nb0, s), "reset");
+    }
+    uint32_t n_dir = 0;
+    PASTIS_TRY(read_device(ctx, M.d_count, &n_dir, sizeof(n_dir), s));
+
+    // ---- symmetrise, sort, threshold already applied
+    SymArgs sy{};
+    sy.n_dir = n_dir;
+    sy.d_ndir = M.d_count;
+    sy.key = sp.d_key;
+    PASTIS_TRY(get(ctx, kDDirKeyAlt, n_dir, &sy.key_alt));
+    PASTIS_TRY(get(ctx, kDPerm, n_dir, &sy.perm));
+    PASTIS_TRY(get(ctx, kDPermAlt, n_dir, &sy.perm_alt));
+    sy.cnt = sp.d_cnt;
+    sy.s1 = sp.d_s1;
+    sy.s2 = sp.d_s2;
+    sy.dir = sp.d_dir;
+    PASTIS_TRY(get(ctx, kDFlag, n_dir, &sy.flag));
+    PASTIS_TRY(get(ctx, kDPick, n_dir, &sy.pick));
+    PASTIS_TRY(get(ctx, kDOpos, n_dir, &sy.opos));
+    sy.d_ncand = M.n_cand;
+    sy.nbits = sp.nbits;
+    PASTIS_TRY(get(ctx, kDTemp, std::max(kmers_temp_bytes(m, n), radix_temp_bytes(n_dir) + scan_temp_bytes(n_dir)),
+                   (char **)&sy.sort_temp));
+    PASTIS_TRY(get(ctx, kBufCandLo, n_dir, &sy.out.lo));
+    PASTIS_TRY(get(ctx, kBufCandHi, n_dir, &sy.out.hi));
+    PASTIS_TRY(get(ctx, kBufCandCnt, n_dir, &sy.out.count));
+    PASTIS_TRY(get(ctx, kBufCandS1, n_dir, &sy.out.seed1));
+    PASTIS_TRY(get(ctx, kBufCandS2, n_dir, &sy.out.seed2));
+    if (n_dir > 0) {
+        HIP_TRY(ctx, symmetrise(sy, s), "symmetrise");
+    } else {
+        HIP_TRY(ctx, fill<uint32_t>(M.n_cand, 1, 0u, s), "reset");
+    }
+    HIP_TRY(ctx, stage_end(ctx, kStSpgemm, s), "event");
+    uint32_t nc = 0;
+    PASTIS_TRY(read_device(ctx, M.n_cand, &nc, sizeof(nc), s));
+    *n_cand_out = nc;
+    ctx->stats.n_candidates = nc;
+    ctx->n_candidates = nc;
+    ctx->n_seqs_last = n;
+    ctx->have_candidates = true;
+    return PASTIS_OK;
+}
+
+pastis_status begin_call(pastis_ctx *ctx) {
+    HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    ctx->bad_residue = -1;
+    ctx->stats = pastis_run_stats{};
+    ctx->last_error.clear();
+    return PASTIS_OK;
+}
+
+pastis_status stage_and_encode(pastis_ctx *ctx, const uint8_t *residues, const int64_t *offsets, int64_t n,
+                               int on_device, hipStream_t s, Staged &st, uint8_t **codes) {
+    PASTIS_TRY(stage_sequences(ctx, residues, offsets, n, on_device, s, st));
+    unsigned long long *d_flags = nullptr, h_flags[4];
+    PASTIS_TRY(reset_flags(ctx, &d_flags, s));
+    HIP_TRY(ctx, stage_begin(ctx, kStEncode, s), "event");
+    PASTIS_TRY(encode_into(ctx, st.d_res, st.n_res, codes, d_flags, s));
+    HIP_TRY(ctx, stage_end(ctx, kStEncode, s), "event");
+    PASTIS_TRY(read_flags(ctx, d_flags, h_flags, 1, s));
+    if (h_flags[0] != ~0ull) {
+        ctx->bad_residue = (int64_t)h_flags[0];
+        return set_error(ctx, PASTIS_E_BAD_RESIDUE, "bad residue at index " + std::to_string(h_flags[0]));
+    }
+    ctx->stats.n_sequences = n;
+    ctx->stats.n_residues = st.n_res;
+    return PASTIS_OK;
+}
+
+}  // namespace
+
+// Align the ctx's current candidates; records into kDRecords.
+pastis_status align_candidates(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, int64_t n, hipStream_t s,
+                               pastis_pair_record **rec_out);
+
+}  // namespace pastis
+
+using namespace pastis;
+
+extern "C" {
+
+pastis_status pastis_discover(pastis_ctx *ctx, const uint8_t *residues, const int64_t *offsets, int64_t n,
+                              int input_on_device, void *stream, int64_t *n_candidates) {
+    if (!ctx || !n_candidates) return PASTIS_E_INVAL;
+    hipStream_t s = (hipStream_t)stream;
+    auto t0 = std::chrono::steady_clock::now();
+    PASTIS_TRY(begin_call(ctx));
+    ctx->have_candidates = false;
+    Staged st;
+    uint8_t *codes = nullptr;
+    PASTIS_TRY(stage_and_encode(ctx, residues, offsets, n, input_on_device, s, st, &codes));
+    PASTIS_TRY(discover(ctx, st, codes, n, s, n_candidates));
+    HIP_TRY(ctx, stage_collect(ctx, s), "sync");
+    ctx->stats.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return PASTIS_OK;
+}
+
+pastis_status pastis_candidates_copy(pastis_ctx *ctx, uint32_t *lo, uint32_t *hi, uint32_t *count, uint32_t *seed1,
+                                     uint32_t *seed2, int64_t cap, int dst_on_device, void *stream) {
+    if (!ctx) return PASTIS_E_INVAL;
+    if (!ctx->have_candidates) return set_error(ctx, PASTIS_E_STATE, "no candidates: call pastis_discover first");
+    const int64_t nc = ctx->n_candidates;
+    if (cap < nc) return set_error(ctx, PASTIS_E_CAPACITY, "candidate buffers too small");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    const hipMemcpyKind kind = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    const int ids[5] = {kBufCandLo, kBufCandHi, kBufCandCnt, kBufCandS1, kBufCandS2};
+    uint32_t *dst[5] = {lo, hi, count, seed1, seed2};
+    for (int f = 0; f < 5; ++f) {
+        if (!dst[f] || nc == 0) continue;
+        HIP_TRY(ctx, hipMemcpyAsync(dst[f], ctx->buf[ids[f]].ptr, sizeof(uint32_t) * nc, kind, s), "copy");
+    }
+    HIP_TRY(ctx, hipStreamSynchronize(s), "sync");
+    return PASTIS_OK;
+}
+
+pastis_status pastis_subkmers(pastis_ctx *ctx, const uint32_t *kmer_ids, int64_t n, uint32_t *out_ids,
+                              int32_t *out_dist, int32_t *out_count, void *stream) {
+    if (!ctx || n < 0 || (n > 0 && (!kmer_ids || !out_ids || !out_dist || !out_count))) return PASTIS_E_INVAL;
+    const pastis_params &P = ctx->params;
+    if (P.n_subs <= 0) return set_error(ctx, PASTIS_E_INVAL, "n_subs must be > 0");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    if (n == 0) return PASTIS_OK;
+    int8_t *d8 = nullptr;
+    PASTIS_TRY(get(ctx, kDSubD, (size_t)n * P.n_subs, &d8));
+    HIP_TRY(ctx, launch_nearest_ids(kmer_ids, n, ctx->d_blosum, P.k, P.n_subs, P.sub_alphabet, out_ids, d8, out_count, s),
+            "neighbourhood kernel");
+    // widen distances to int32 on the host side of the copy
+    std::vector<int8_t> h8((size_t)n * P.n_subs);
+    PASTIS_TRY(read_device(ctx, d8, h8.data(), h8.size(), s));
+    std::vector<int32_t> h32(h8.begin(), h8.end());
+    HIP_TRY(ctx, hipMemcpyAsync(out_dist, h32.data(), sizeof(int32_t) * h32.size(), hipMemcpyHostToDevice, s), "copy");
+    HIP_TRY(ctx, hipStreamSynchronize(s), "sync");
+    return PASTIS_OK;
+}
+
+pastis_status pastis_search(pastis_ctx *ctx, const uint8_t *residues, const int64_t *offsets, int64_t n,
+                            int input_on_device, void *stream, pastis_result **out) {
+    if (!ctx || !out) return PASTIS_E_INVAL;
+    *out = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    auto t0 = std::chrono::steady_clock::now();
+    PASTIS_TRY(begin_call(ctx));
+    ctx->have_candidates = false;
+    Staged st;
+    uint8_t *codes = nullptr;
+    PASTIS_TRY(stage_and_encode(ctx, residues, offsets, n, input_on_device, s, st, &codes));
+    int64_t nc = 0;
+    PASTIS_TRY(discover(ctx, st, codes, n, s, &nc));
+    pastis_pair_record *rec = nullptr;
+    PASTIS_TRY(align_candidates(ctx, st, codes, n, s, &rec));
+    // edges
+    Misc M;
+    PASTIS_TRY(misc(ctx, M));
+    HIP_TRY(ctx, stage_begin(ctx, kStFilter, s), "event");
+    uint8_t *flag = nullptr;
+    uint32_t *pos = nullptr;
+    PASTIS_TRY(get(ctx, kDEdgeFlag, nc, &flag));
+    PASTIS_TRY(get(ctx, kDEdgePos, nc, &pos));
+    char *temp = nullptr;
+    PASTIS_TRY(get(ctx, kDTemp, scan_temp_bytes(nc) + 4096, &temp));
+    const int ns = ctx->params.weight_mode == PASTIS_WEIGHT_NS;
+    if (nc > 0) {
+        edge_flag_kernel<<<grid_for(nc), 256, 0, s>>>(rec, nc, ns, flag);
+        HIP_TRY(ctx, hipGetLastError(), "edge kernel");
+    }
+    HIP_TRY(ctx, (exclusive_scan<uint8_t, uint32_t>(flag, nc, pos, M.n_edges, temp, s)), "scan");
+    uint32_t ne = 0;
+    PASTIS_TRY(read_device(ctx, M.n_edges, &ne, sizeof(ne), s));
+    pastis_result *res = new pastis_result();
+    res->device = ctx->device;
+    res->n = ne;
+    if (ne > 0) {
+        if (hipMalloc(&res->d_edges, sizeof(pastis_edge) * ne) != hipSuccess) {
+            (void)hipGetLastError();
+            delete res;
+            return set_error(ctx, PASTIS_E_NOMEM, "edge allocation failed");
+        }
+        edge_write_kernel<<<grid_for(nc), 256, 0, s>>>(rec, flag, pos, nc, (const uint32_t *)ctx->buf[kBufCandLo].ptr,
+                                                        (const uint32_t *)ctx->buf[kBufCandHi].ptr,
+                                                        (const uint32_t *)ctx->buf[kBufCandCnt].ptr, st.d_off, ns,
+                                                        res->d_edges);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) {
+            (void)hipFree(res->d_edges);
+            delete res;
+            return hip_error(ctx, e, "edge kernel");
+        }
+    }
+    HIP_TRY(ctx, stage_end(ctx, kStFilter, s), "event");
+    HIP_TRY(ctx, stage_collect(ctx, s), "sync");
+    ctx->stats.n_edges = ne;
+    ctx->stats.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = res;
+    return PASTIS_OK;
+}
+
+pastis_status pastis_result_count(const pastis_result *r, int64_t *n_edges) {
+    if (!r || !n_edges) return PASTIS_E_INVAL;
+    *n_edges = r->n;
+    return PASTIS_OK;
+}
+
+const pastis_edge *pastis_result_device_ptr(const pastis_result *r) { return r ? r->d_edges : nullptr; }
+
+pastis_status pastis_result_copy(const pastis_result *r, pastis_edge *dst, int64_t cap, int dst_on_device,
+                                 void *stream) {
+    if (!r || (r->n > 0 && !dst)) return PASTIS_E_INVAL;
+    if (cap < r->n) return PASTIS_E_CAPACITY;
+    if (r->n == 0) return PASTIS_OK;
+    if (hipSetDevice(r->device) != hipSuccess) return PASTIS_E_DEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(dst, r->d_edges, sizeof(pastis_edge) * r->n,
+                       dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s) != hipSuccess)
+        return PASTIS_E_DEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return PASTIS_E_DEVICE;
+    return PASTIS_OK;
+}
+
+void pastis_result_free(pastis_result *r) {
+    if (!r) return;
+    if (r->d_edges) {
+        (void)hipSetDevice(r->device);
+        (void)hipFree(r->d_edges);
+    }
+    delete r;
+}
+
+}  // extern "C"

@@ -1,0 +1,664 @@
+// Candidate discovery: the sparse products A A^T and (A S) A^T under the
+// count + seed semiring (Sections IV-A and IV-C), the common-k-mer threshold
+// (Section VI) and symmetrisation.
+//
+// Row i of the product visits, for every entry (s, pos_i) of its row (a k-mer
+// of A_i, or a substitute of (A S)_i), every posting (j, pos_j) of s, and adds
+// one to entry j with seed key (pos_lo << 16 | pos_hi), keeping the two
+// smallest keys.  Exact k-mers give a symmetric B, so only j > i is visited.
+// Substitutes give a directional count c(i -> j); both directions are made and
+// each pair keeps the larger count (lo -> hi on a tie), which equals B when
+// m = 0.
+//
+// One workgroup owns one row.  Entries are expanded in chunks: the posting
+// lengths of a chunk are prefix-summed in LDS and every thread takes products
+// by binary search, so a long posting list is shared by the whole group.
+// Phase 1 counts into an LDS hash whose 32-bit slots pack (j << 14 | count);
+// entries reaching the threshold get a candidate slot; phase 2 replays the
+// products and keeps the two smallest seed keys of candidates only (lock-free:
+// the key displaced from the first slot falls to the second).  Rows too large
+// for LDS use the same scheme with 64-bit slots in global memory.
+#include "internal.hpp"
+#include "kmers.hpp"
+#include "prim.hpp"
+#include "spgemm.hpp"
+
+namespace pastis {
+
+hipError_t launch_bins(const int8_t *bin_of, int64_t n, int nbins, int *counts, int *starts, int *cursor, int *idx,
+                       hipStream_t s);
+
+namespace {
+
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+constexpr int kChunk = 512;
+constexpr int kCandCap = 512;
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ uint32_t hash32(uint32_t x) { return x * 0x9E3779B1u; }
+
+// A row's entries: exact (A_i: k-mer index + position) or substitute
+// ((A S)_i: substitute index + (distance, position)).
+struct RowView {
+    const uint32_t *start32;  // exact: row_start [n+1]
+    const uint64_t *start64;  // substitutes: as_start [n+1]
+    const uint32_t *len;      // substitutes: as_len [n]
+    const uint32_t *ent_s;
+    const uint16_t *ent_pos16;  // exact
+    const uint32_t *ent_dp;     // substitutes: ((d + 128) << 16) | pos
+    int exact;
+
+    __device__ __forceinline__ void bounds(uint32_t i, uint64_t &b, uint64_t &e) const {
+        if (exact) {
+            b = start32[i];
+            e = start32[i + 1];
+        } else {
+            b = start64[i];
+            e = b + len[i];
+        }
+    }
+    __device__ __forceinline__ uint32_t pos(uint64_t x) const {
+        return exact ? (uint32_t)ent_pos16[x] : (ent_dp[x] & 0xFFFFu);
+    }
+};
+
+struct Postings {
+    const uint32_t *uk_start;
+    const uint32_t *seq;
+    const uint16_t *pos;
+};
+
+struct Emit {
+    uint32_t *count;  // device counter
+    uint32_t *overflow;
+    uint64_t *key;
+    uint32_t *cnt, *s1, *s2, *dir;
+    uint32_t cap;
+    int nbits;  // key = lo << nbits | hi
+};
+
+__device__ __forceinline__ void seed_min2(uint32_t *s1, uint32_t *s2, uint32_t key) {
+    const uint32_t old = atomicMin(s1, key);
+    if (old == kEmpty) return;
+    atomicMin(s2, key < old ? old : key);
+}
+
+__device__ __forceinline__ uint32_t seed_key(uint32_t i, uint32_t j, uint32_t pi, uint32_t pj) {
+    return i < j ? ((pi << 16) | pj) : ((pj << 16) | pi);
+}
+
+__device__ __forceinline__ void emit(const Emit &em, uint32_t i, uint32_t j, uint32_t c, uint32_t a, uint32_t b) {
+    const uint32_t slot = atomicAdd(em.count, 1u);
+    if (slot >= em.cap) {
+        atomicOr(em.overflow, 1u);
+        return;
+    }
+    const uint32_t lo = i < j ? i : j, hi = i < j ? j : i;
+    em.key[slot] = ((uint64_t)lo << em.nbits) | hi;
+    em.cnt[slot] = c;
+    em.s1[slot] = a;
+    em.s2[slot] = b;
+    em.dir[slot] = i < j ? 0u : 1u;
+}
+
+// Chunk expansion shared by both phases and both table kinds: calls
+// f(pos_i, j, pos_j) for every product of entries [c0, c0 + ce) of row i.
+struct ChunkLds {
+    uint32_t pref[kChunk + 1];
+    uint32_t pbeg[kChunk];
+    uint32_t epos[kChunk];
+    uint32_t wsum[kThreads / 64];
+};
+
+template <typename F>
+__device__ __forceinline__ void expand_row(const RowView &rv, const Postings &P, uint32_t i, ChunkLds &C, F &&f) {
+    uint64_t b, e;
+    rv.bounds(i, b, e);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (uint64_t c0 = b; c0 < e; c0 += kChunk) {
+        const int ce = (int)((e - c0) < (uint64_t)kChunk ? (e - c0) : (uint64_t)kChunk);
+        // lengths of this chunk's posting lists, prefix-summed over the block
+        uint32_t len0 = 0, len1 = 0;
+        const int t0 = threadIdx.x * 2, t1 = t0 + 1;
+        if (t0 < ce) {
+            const uint32_t s = rv.ent_s[c0 + t0];
+            const uint32_t pb = P.uk_start[s];
+            len0 = P.uk_start[s + 1] - pb;
+            C.pbeg[t0] = pb;
+            C.epos[t0] = rv.pos(c0 + t0);
+        }
+        if (t1 < ce) {
+            const uint32_t s = rv.ent_s[c0 + t1];
+            const uint32_t pb = P.uk_start[s];
+            len1 = P.uk_start[s + 1] - pb;
+            C.pbeg[t1] = pb;
+            C.epos[t1] = rv.pos(c0 + t1);
+        }
+        uint32_t v = len0 + len1, inc = v;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t o = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += o;
+        }
+        if (lane == 63) C.wsum[wave] = inc;
+        __syncthreads();
+        uint32_t add = 0;
+        for (int w = 0; w < wave; ++w) add += C.wsum[w];
+        const uint32_t excl = inc - v + add;
+        if (t0 < ce) C.pref[t0] = excl;
+        if (t1 < ce) C.pref[t1] = excl + len0;
+        if (threadIdx.x == kThreads - 1) C.pref[ce] = excl + v;
+        __syncthreads();
+        const uint32_t total = C.pref[ce];
+        for (uint32_t p = threadIdx.x; p < total; p += kThreads) {
+            // entry x with pref[x] <= p < pref[x + 1]
+            int lo = 0, hi = ce;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (C.pref[mid] <= p)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            const uint32_t z = C.pbeg[lo] + (p - C.pref[lo]);
+            f(C.epos[lo], P.seq[z], (uint32_t)P.pos[z]);
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ LDS kernel
+
+template <int CAP>
+struct RowLds {
+    uint32_t slot[CAP];  // (j << 14) | count, then (j << 14) | (candidate + 1)
+    uint32_t cj[kCandCap], cc[kCandCap], c1[kCandCap], c2[kCandCap];
+    ChunkLds chunk;
+    uint32_t ncand;
+    uint32_t spill;
+};
+
+template <int CAP>
+__global__ __launch_bounds__(kThreads) void spgemm_lds_kernel(RowView rv, Postings P, const int *__restrict__ idx,
+                                                              const int *__restrict__ starts, int bin, int ck,
+                                                              Emit em, uint32_t *__restrict__ spill_rows,
+                                                              uint32_t *__restrict__ spill_count) {
+    __shared__ RowLds<CAP> L;
+    constexpr uint32_t mask = CAP - 1;
+    for (int t = threadIdx.x; t < CAP; t += kThreads) L.slot[t] = kEmpty;
+    if (threadIdx.x == 0) {
+        L.ncand = 0;
+        L.spill = 0;
+    }
+    __syncthreads();
+    const int end = starts[bin + 1];
+    for (int w = starts[bin] + blockIdx.x; w < end; w += gridDim.x) {
+        const uint32_t i = (uint32_t)idx[w];
+        const bool exact = rv.exact;
+        // phase 1: counts
+        expand_row(rv, P, i, L.chunk, [&](uint32_t, uint32_t j, uint32_t) {
+            if (j == i || (exact && j < i)) return;
+            uint32_t h = hash32(j) & mask;
+            for (;;) {
+                uint32_t v = L.slot[h];
+                if (v == kEmpty) {
+                    const uint32_t old = atomicCAS(&L.slot[h], kEmpty, (j << 14) | 1u);
+                    if (old == kEmpty) return;
+                    v = old;
+                }
+                if ((v >> 14) == j) {
+                    atomicAdd(&L.slot[h], 1u);
+                    return;
+                }
+                h = (h + 1) & mask;
+            }
+        });
+        __syncthreads();
+        for (int t = threadIdx.x; t < CAP; t += kThreads) {
+            const uint32_t v = L.slot[t];
+            if (v == kEmpty) continue;
+            const uint32_t c = v & 0x3FFFu, j = v >> 14;
+            uint32_t tag = 0;
+            if (c >= (uint32_t)ck) {
+                const uint32_t q = atomicAdd(&L.ncand, 1u);
+                if (q < kCandCap) {
+                    L.cj[q] = j;
+                    L.cc[q] = c;
+                    L.c1[q] = kEmpty;
+                    L.c2[q] = kEmpty;
+                    tag = q + 1;
+                } else {
+                    L.spill = 1;
+                }
+            }
+            L.slot[t] = (j << 14) | tag;
+        }
+        __syncthreads();
+        if (L.spill) {
+            // too many candidates for this table: the global path redoes the row
+            if (threadIdx.x == 0) spill_rows[atomicAdd(spill_count, 1u)] = i;
+        } else if (L.ncand > 0) {
+            // phase 2: seeds of candidate entries
+            expand_row(rv, P, i, L.chunk, [&](uint32_t pi, uint32_t j, uint32_t pj) {
+                if (j == i || (exact && j < i)) return;
+                uint32_t h = hash32(j) & mask;
+                uint32_t v = L.slot[h];
+                while ((v >> 14) != j) {
+                    h = (h + 1) & mask;
+                    v = L.slot[h];
+                }
+                const uint32_t tag = v & 0x3FFFu;
+                if (tag) seed_min2(&L.c1[tag - 1], &L.c2[tag - 1], seed_key(i, j, pi, pj));
+            });
+            __syncthreads();
+            for (uint32_t q = threadIdx.x; q < L.ncand; q += kThreads) emit(em, i, L.cj[q], L.cc[q], L.c1[q], L.c2[q]);
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < CAP; t += kThreads) L.slot[t] = kEmpty;
+        if (threadIdx.x == 0) {
+            L.ncand = 0;
+            L.spill = 0;
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ global kernel
+
+// Rows listed in rows[0..*nrows) with a per-block table of cap 64-bit slots
+// (j << 32 | count, later j << 32 | candidate + 1) and cap / 2 candidates.
+__global__ __launch_bounds__(kThreads) void spgemm_global_kernel(RowView rv, Postings P, const uint32_t *__restrict__ rows,
+                                                                 const uint32_t *__restrict__ nrows_p, int ck, Emit em,
+                                                                 unsigned long long *__restrict__ tables, uint32_t cap,
+                                                                 uint32_t *__restrict__ cand) {
+    __shared__ ChunkLds C;
+    __shared__ uint32_t ncand;
+    const uint32_t mask = cap - 1;
+    unsigned long long *slot = tables + (size_t)blockIdx.x * cap;
+    uint32_t *cj = cand + (size_t)blockIdx.x * 2 * cap;  // cap/2 entries x 4 arrays
+    uint32_t *cc = cj + cap / 2, *c1 = cc + cap / 2, *c2 = c1 + cap / 2;
+    const unsigned long long empty = ~0ull;
+    for (uint32_t t = threadIdx.x; t < cap; t += kThreads) slot[t] = empty;
+    if (threadIdx.x == 0) ncand = 0;
+    __threadfence_block();
+    __syncthreads();
+    const uint32_t nrows = *nrows_p;
+    for (uint32_t w = blockIdx.x; w < nrows; w += gridDim.x) {
+        const uint32_t i = rows[w];
+        const bool exact = rv.exact;
+        expand_row(rv, P, i, C, [&](uint32_t, uint32_t j, uint32_t) {
+            if (j == i || (exact && j < i)) return;
+            uint32_t h = hash32(j) & mask;
+            for (;;) {
+                unsigned long long v = slot[h];
+                if (v == empty) {
+                    const unsigned long long old = atomicCAS(&slot[h], empty, ((unsigned long long)j << 32) | 1ull);
+                    if (old == empty) return;
+                    v = old;
+                }
+                if ((uint32_t)(v >> 32) == j) {
+                    atomicAdd(&slot[h], 1ull);
+                    return;
+                }
+                h = (h + 1) & mask;
+            }
+        });
+        __threadfence_block();
+        __syncthreads();
+        for (uint32_t t = threadIdx.x; t < cap; t += kThreads) {
+            const unsigned long long v = slot[t];
+            if (v == empty) continue;
+            const uint32_t c = (uint32_t)v, j = (uint32_t)(v >> 32);
+            uint32_t tag = 0;
+            if (c >= (uint32_t)ck) {
+                const uint32_t q = atomicAdd(&ncand, 1u);
+                cj[q] = j;
+                cc[q] = c;
+                c1[q] = kEmpty;
+                c2[q] = kEmpty;
+                tag = q + 1;
+            }
+            slot[t] = ((unsigned long long)j << 32) | tag;
+        }
+        __threadfence_block();
+        __syncthreads();
+        if (ncand > 0) {
+            expand_row(rv, P, i, C, [&](uint32_t pi, uint32_t j, uint32_t pj) {
+                if (j == i || (exact && j < i)) return;
+                uint32_t h = hash32(j) & mask;
+                unsigned long long v = slot[h];
+                while ((uint32_t)(v >> 32) != j) {
+                    h = (h + 1) & mask;
+                    v = slot[h];
+                }
+                const uint32_t tag = (uint32_t)v;
+                if (tag) seed_min2(&c1[tag - 1], &c2[tag - 1], seed_key(i, j, pi, pj));
+            });
+            __threadfence_block();
+            __syncthreads();
+            for (uint32_t q = threadIdx.x; q < ncand; q += kThreads) emit(em, i, cj[q], cc[q], c1[q], c2[q]);
+        }
+        __syncthreads();
+        for (uint32_t t = threadIdx.x; t < cap; t += kThreads) slot[t] = empty;
+        if (threadIdx.x == 0) ncand = 0;
+        __threadfence_block();
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ A S rows
+
+constexpr int kAsCap = 8192;
+
+struct AsIn {
+    const uint32_t *row_start;  // A rows
+    const uint32_t *row_u;
+    const uint16_t *row_pos;
+    const uint32_t *s_u;  // S rows, m + 1 slots each
+    const int8_t *s_d;
+    const uint32_t *s_cnt;
+    int W;  // m + 1
+};
+
+// (A S)_{i,s}: the closest k-mer of row i reaching s, then the smaller
+// position (Section IV-C), reduced with atomicMin on ((d + 128) << 16 | pos).
+template <typename Slots>
+__device__ __forceinline__ void as_reduce(const AsIn &in, uint32_t i, Slots &tab, uint32_t mask) {
+    const uint32_t b = in.row_start[i], e = in.row_start[i + 1];
+    const uint32_t total = (e - b) * (uint32_t)in.W;
+    for (uint32_t p = threadIdx.x; p < total; p += kThreads) {
+        const uint32_t x = b + p / in.W, q = p % in.W;
+        const uint32_t u = in.row_u[x];
+        if (q >= in.s_cnt[u]) continue;
+        const uint32_t s = in.s_u[(size_t)u * in.W + q];
+        const uint32_t dp = ((uint32_t)(in.s_d[(size_t)u * in.W + q] + 128) << 16) | in.row_pos[x];
+        uint32_t h = hash32(s) & mask;
+        for (;;) {
+            uint32_t k = tab.key(h);
+            if (k == kEmpty) {
+                const uint32_t old = tab.cas(h, s);
+                if (old == kEmpty || old == s) {
+                    tab.vmin(h, dp);
+                    break;
+                }
+                k = old;
+            }
+            if (k == s) {
+                tab.vmin(h, dp);
+                break;
+            }
+            h = (h + 1) & mask;
+        }
+    }
+}
+
+struct LdsSlots {
+    uint32_t *k, *v;
+    __device__ uint32_t key(uint32_t h) { return k[h]; }
+    __device__ uint32_t cas(uint32_t h, uint32_t s) { return atomicCAS(&k[h], kEmpty, s); }
+    __device__ void vmin(uint32_t h, uint32_t dp) { atomicMin(&v[h], dp); }
+};
+
+__global__ __launch_bounds__(kThreads) void as_lds_kernel(AsIn in, const int *__restrict__ idx,
+                                                          const int *__restrict__ starts, int bin,
+                                                          const uint64_t *__restrict__ as_start,
+                                                          uint32_t *__restrict__ as_len, uint32_t *__restrict__ as_s,
+                                                          uint32_t *__restrict__ as_dp) {
+    __shared__ uint32_t K[kAsCap], V[kAsCap];
+    __shared__ uint32_t n_out;
+    LdsSlots tab{K, V};
+    for (int t = threadIdx.x; t < kAsCap; t += kThreads) {
+        K[t] = kEmpty;
+        V[t] = kEmpty;
+    }
+    if (threadIdx.x == 0) n_out = 0;
+    __syncthreads();
+    const int end = starts[bin + 1];
+    for (int w = starts[bin] + blockIdx.x; w < end; w += gridDim.x) {
+        const uint32_t i = (uint32_t)idx[w];
+        as_reduce(in, i, tab, kAsCap - 1);
+        __syncthreads();
+        const uint64_t base = as_start[i];
+        for (int t = threadIdx.x; t < kAsCap; t += kThreads) {
+            if (K[t] == kEmpty) continue;
+            const uint32_t q = atomicAdd(&n_out, 1u);
+            as_s[base + q] = K[t];
+            as_dp[base + q] = V[t];
+            K[t] = kEmpty;
+            V[t] = kEmpty;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            as_len[i] = n_out;
+            n_out = 0;
+        }
+        __syncthreads();
+    }
+}
+
+struct GlobalSlots {
+    uint32_t *k, *v;
+    __device__ uint32_t key(uint32_t h) { return __builtin_nontemporal_load(&k[h]); }
+    __device__ uint32_t cas(uint32_t h, uint32_t s) { return atomicCAS(&k[h], kEmpty, s); }
+    __device__ void vmin(uint32_t h, uint32_t dp) { atomicMin(&v[h], dp); }
+};
+
+__global__ __launch_bounds__(kThreads) void as_global_kernel(AsIn in, const int *__restrict__ idx,
+                                                             const int *__restrict__ starts, int bin,
+                                                             const uint64_t *__restrict__ as_start,
+                                                             uint32_t *__restrict__ as_len,
+                                                             uint32_t *__restrict__ as_s, uint32_t *__restrict__ as_dp,
+                                                             uint32_t *__restrict__ tables, uint32_t cap) {
+    __shared__ uint32_t n_out;
+    uint32_t *K = tables + (size_t)blockIdx.x * 2 * cap, *V = K + cap;
+    GlobalSlots tab{K, V};
+    for (uint32_t t = threadIdx.x; t < cap; t += kThreads) {
+        K[t] = kEmpty;
+        V[t] = kEmpty;
+    }
+    if (threadIdx.x == 0) n_out = 0;
+    __threadfence_block();
+    __syncthreads();
+    const int end = starts[bin + 1];
+    for (int w = starts[bin] + blockIdx.x; w < end; w += gridDim.x) {
+        const uint32_t i = (uint32_t)idx[w];
+        as_reduce(in, i, tab, cap - 1);
+        __threadfence_block();
+        __syncthreads();
+        const uint64_t base = as_start[i];
+        for (uint32_t t = threadIdx.x; t < cap; t += kThreads) {
+            if (K[t] == kEmpty) continue;
+            const uint32_t q = atomicAdd(&n_out, 1u);
+            as_s[base + q] = K[t];
+            as_dp[base + q] = V[t];
+            K[t] = kEmpty;
+            V[t] = kEmpty;
+        }
+        __threadfence_block();
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            as_len[i] = n_out;
+            n_out = 0;
+        }
+        __syncthreads();
+    }
+}
+
+// upper bound of (A S)_i entries = sum of present S-row sizes of i's k-mers;
+// every row's length starts at 0 (rows without k-mers are never filled)
+__global__ void as_ub_kernel(AsIn in, int64_t n, uint32_t *__restrict__ ub, uint32_t *__restrict__ as_len,
+                             int8_t *__restrict__ bin_of, unsigned long long *__restrict__ max_ub) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t s = 0;
+        for (uint32_t x = in.row_start[i]; x < in.row_start[i + 1]; ++x) s += in.s_cnt[in.row_u[x]];
+        ub[i] = s;
+        as_len[i] = 0;
+        bin_of[i] = s == 0 ? (int8_t)-1 : (s * 4u <= (uint32_t)kAsCap * 3u ? (int8_t)0 : (int8_t)1);
+        if (s * 4u > (uint32_t)kAsCap * 3u) atomicMax(max_ub, (unsigned long long)s);
+    }
+}
+
+// products of row i (postings visited), and the row's bin
+__global__ void work_kernel(RowView rv, Postings P, int64_t n, int n_big_ok, uint64_t *__restrict__ work,
+                            int8_t *__restrict__ bin_of, unsigned long long *__restrict__ max_big,
+                            uint32_t *__restrict__ big_rows, uint32_t *__restrict__ n_big) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t b, e;
+        rv.bounds((uint32_t)i, b, e);
+        uint64_t w = 0;
+        for (uint64_t x = b; x < e; ++x) {
+            const uint32_t s = rv.ent_s[x];
+            w += P.uk_start[s + 1] - P.uk_start[s];
+        }
+        work[i] = w;
+        int8_t bin;
+        if (w == 0)
+            bin = -1;
+        else if (n_big_ok && w <= 6144)
+            bin = 0;  // 8192 slots
+        else if (n_big_ok && w <= 12288)
+            bin = 1;  // 16384 slots
+        else
+            bin = -1;
+        bin_of[i] = bin;
+        if (w > 0 && (!n_big_ok || w > 12288)) {
+            big_rows[atomicAdd(n_big, 1u)] = (uint32_t)i;
+            atomicMax(max_big, (unsigned long long)w);
+        }
+    }
+}
+
+// ------------------------------------------------------------ symmetrise
+
+// entries sorted by key; each (lo, hi) keeps the larger direction (lo -> hi on
+// a tie); out_flag marks the kept representative
+__global__ void merge_flag_kernel(const uint64_t *__restrict__ skey, const uint32_t *__restrict__ perm,
+                                  const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ dir,
+                                  const uint32_t *__restrict__ n_p, uint8_t *__restrict__ flag,
+                                  uint32_t *__restrict__ pick) {
+    const uint32_t n = *n_p;
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x) {
+        if (x > 0 && skey[x - 1] == skey[x]) {
+            flag[x] = 0;
+            continue;
+        }
+        flag[x] = 1;
+        uint32_t best = perm[x];
+        if (x + 1 < n && skey[x + 1] == skey[x]) {
+            const uint32_t o = perm[x + 1];
+            const bool take_o = cnt[o] > cnt[best] || (cnt[o] == cnt[best] && dir[o] < dir[best]);
+            if (take_o) best = o;
+        }
+        pick[x] = best;
+    }
+}
+
+__global__ void merge_write_kernel(const uint64_t *__restrict__ skey, const uint8_t *__restrict__ flag,
+                                   const uint32_t *__restrict__ pick, const uint32_t *__restrict__ opos,
+                                   const uint32_t *__restrict__ n_p, const uint32_t *__restrict__ cnt,
+                                   const uint32_t *__restrict__ s1, const uint32_t *__restrict__ s2, int nbits,
+                                   Candidates out) {
+    const uint32_t n = *n_p;
+    const uint64_t hmask = (1ull << nbits) - 1ull;
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x) {
+        if (!flag[x]) continue;
+        const uint32_t q = opos[x], b = pick[x];
+        out.lo[q] = (uint32_t)(skey[x] >> nbits);
+        out.hi[q] = (uint32_t)(skey[x] & hmask);
+        out.count[q] = cnt[b];
+        out.seed1[q] = s1[b];
+        out.seed2[q] = s2[b];
+    }
+}
+
+inline unsigned grid_for(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    if (b > 16384) b = 16384;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+int key_bits(int64_t n) {
+    int b = 1;
+    while (b < 32 && (1ll << b) < n) ++b;
+    return b;
+}
+
+hipError_t as_stage(const AsArgs &a, hipStream_t s) {
+    AsIn in{a.kt->row_start, a.kt->row_u, a.kt->row_pos, a.s_u, a.s_d, a.s_cnt, a.W};
+    hipError_t e;
+    if ((e = fill<unsigned long long>(a.max_ub, 1, 0ull, s)) != hipSuccess) return e;
+    as_ub_kernel<<<grid_for(a.n), 256, 0, s>>>(in, a.n, a.ub, a.as_len, a.bin_of, a.max_ub);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    e = exclusive_scan<uint32_t, uint64_t>(a.ub, a.n, a.as_start, a.as_start + a.n, a.scan_temp, s);
+    if (e != hipSuccess) return e;
+    return launch_bins(a.bin_of, a.n, 2, a.bins.counts, a.bins.starts, a.bins.cursor, a.bins.idx, s);
+}
+
+hipError_t as_run(const AsArgs &a, uint32_t gcap, hipStream_t s) {
+    AsIn in{a.kt->row_start, a.kt->row_u, a.kt->row_pos, a.s_u, a.s_d, a.s_cnt, a.W};
+    as_lds_kernel<<<512, kThreads, 0, s>>>(in, a.bins.idx, a.bins.starts, 0, a.as_start, a.as_len, a.as_s, a.as_dp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (gcap > 0) {
+        as_global_kernel<<<a.global_blocks, kThreads, 0, s>>>(in, a.bins.idx, a.bins.starts, 1, a.as_start, a.as_len,
+                                                               a.as_s, a.as_dp, a.gtables, gcap);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+hipError_t spgemm_plan(const SpgemmArgs &a, hipStream_t s) {
+    RowView rv{a.row_start32, a.row_start64, a.row_len, a.ent_s, a.ent_pos16, a.ent_dp, a.exact};
+    Postings P{a.kt->uk_start, a.kt->post_seq, a.kt->post_pos};
+    hipError_t e;
+    if ((e = fill<unsigned long long>(a.max_big, 1, 0ull, s)) != hipSuccess) return e;
+    if ((e = fill<uint32_t>(a.n_big, 2, 0u, s)) != hipSuccess) return e;
+    work_kernel<<<grid_for(a.n), 256, 0, s>>>(rv, P, a.n, a.n < (1ll << 18) ? 1 : 0, a.work, a.bin_of, a.max_big,
+                                               a.big_rows, a.n_big);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return launch_bins(a.bin_of, a.n, 2, a.bins.counts, a.bins.starts, a.bins.cursor, a.bins.idx, s);
+}
+
+hipError_t spgemm_run(const SpgemmArgs &a, uint32_t gcap, hipStream_t s) {
+    RowView rv{a.row_start32, a.row_start64, a.row_len, a.ent_s, a.ent_pos16, a.ent_dp, a.exact};
+    Postings P{a.kt->uk_start, a.kt->post_seq, a.kt->post_pos};
+    Emit em{a.d_count, a.d_overflow, a.d_key, a.d_cnt, a.d_s1, a.d_s2, a.d_dir, a.cap, a.nbits};
+    hipError_t e;
+    if ((e = fill<uint32_t>(a.d_count, 1, 0u, s)) != hipSuccess) return e;
+    if ((e = fill<uint32_t>(a.d_overflow, 1, 0u, s)) != hipSuccess) return e;
+    // spilled rows (too many candidates for LDS) join the big-row list
+    spgemm_lds_kernel<8192><<<768, kThreads, 0, s>>>(rv, P, a.bins.idx, a.bins.starts, 0, a.ck, em, a.big_rows,
+                                                      a.n_big);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    spgemm_lds_kernel<16384><<<512, kThreads, 0, s>>>(rv, P, a.bins.idx, a.bins.starts, 1, a.ck, em, a.big_rows,
+                                                       a.n_big);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (gcap > 0) {
+        spgemm_global_kernel<<<a.global_blocks, kThreads, 0, s>>>(rv, P, a.big_rows, a.n_big, a.ck, em, a.gtables,
+                                                                   gcap, a.gcand);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+hipError_t symmetrise(const SymArgs &a, hipStream_t s) {
+    hipError_t e;
+    bool alt = false;
+    if ((e = iota(a.perm, a.n_dir, s)) != hipSuccess) return e;
+    if ((e = radix_sort(a.key, a.perm, a.key_alt, a.perm_alt, a.n_dir, 2 * a.nbits, a.sort_temp, s, &alt)) !=
+        hipSuccess)
+        return e;
+    const uint64_t *sk = alt ? a.key_alt : a.key;
+    const uint32_t *pm = alt ? a.perm_alt : a.perm;
+    merge_flag_kernel<<<grid_for(a.n_dir), 256, 0, s>>>(sk, pm, a.cnt, a.dir, a.d_ndir, a.flag, a.pick);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = exclusive_scan<uint8_t, uint32_t>(a.flag, a.n_dir, a.opos, a.d_ncand, a.sort_temp, s)) != hipSuccess)
+        return e;
+    merge_write_kernel<<<grid_for(a.n_dir), 256, 0, s>>>(sk, a.flag, a.pick, a.opos, a.d_ndir, a.cnt, a.s1, a.s2,
+                                                          a.nbits, a.out);
+    return hipGetLastError();
+}
+
+}  // namespace pastis

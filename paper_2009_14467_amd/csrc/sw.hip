@@ -273,24 +273,40 @@ __device__ __forceinline__ int rows_bin(int rows) {
     return r <= kSingleBins ? r - 1 : kMultiBin;
 }
 
-__global__ void sw_bin1_kernel(const PairDesc *__restrict__ pairs, int64_t npairs, int8_t *__restrict__ bin_of) {
+// Bins by rows per lane; counters[0] += DP cells of the pairs.
+__global__ void sw_bin1_kernel(const PairDesc *__restrict__ pairs, int64_t npairs, int8_t *__restrict__ bin_of,
+                               unsigned long long *__restrict__ counters) {
+    __shared__ unsigned long long cells;
+    if (threadIdx.x == 0) cells = 0;
+    __syncthreads();
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < npairs) bin_of[q] = (int8_t)rows_bin(pairs[q].la);
+    if (q < npairs) {
+        const PairDesc pd = pairs[q];
+        bin_of[q] = (int8_t)rows_bin(pd.la);
+        atomicAdd(&cells, (unsigned long long)pd.la * (unsigned long long)pd.lb);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && cells) atomicAdd(&counters[0], cells);
 }
 
 // Records of pairs that need no statistics pass are final here; the others
 // are binned by the height of their end rectangle.
+// stats_mode: 0 = only pairs whose coverage cut can hold, 1 = every aligned
+// pair, 2 = none (the normalised-score weight needs no traceback).
 __global__ void sw_bin2_kernel(const PairDesc *__restrict__ pairs, const SwPass1Out *__restrict__ p1,
-                               int64_t npairs, int cov_pct, int full, pastis_pair_record *__restrict__ out,
-                               int8_t *__restrict__ bin_of) {
+                               int64_t npairs, int cov_pct, int stats_mode, pastis_pair_record *__restrict__ out,
+                               int8_t *__restrict__ bin_of, unsigned long long *__restrict__ counters) {
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= npairs) return;
     const PairDesc pd = pairs[q];
     const SwPass1Out r1 = p1[q];
     // coverage needs span_a >= cov% of la, and span_a <= end_a + 1
-    const bool need = r1.score > 0 && (full || 100LL * (r1.end_a + 1) >= (long long)cov_pct * pd.la);
+    const bool need = r1.score > 0 && stats_mode != 2 &&
+                      (stats_mode == 1 || 100LL * (r1.end_a + 1) >= (long long)cov_pct * pd.la);
     if (need) {
         bin_of[q] = (int8_t)rows_bin(r1.end_a + 1);
+        atomicAdd(&counters[1], 1ull);
+        atomicAdd(&counters[2], (unsigned long long)(r1.end_a + 1) * (unsigned long long)(r1.end_b + 1));
         return;
     }
     bin_of[q] = -1;
@@ -545,13 +561,13 @@ int64_t sw_scratch_waves() { return (int64_t)blocks_for_bin(kMultiBin) * kWavesP
 
 hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pairs, int64_t npairs,
                      const int8_t *blosum, const Scoring &sc, SwPass1Out *p1, pastis_pair_record *out,
-                     const SwWork &wk, int full, hipStream_t s) {
+                     const SwWork &wk, int stats_mode, hipStream_t s) {
     if (npairs <= 0) return hipSuccess;
     const int go_ge = sc.gap_open + sc.gap_extend, ge = sc.gap_extend;
     const int nb = (int)((npairs + 255) / 256);
     hipError_t e = stage_begin(ctx, kStSched, s);
     if (e != hipSuccess) return e;
-    sw_bin1_kernel<<<nb, 256, 0, s>>>(pairs, npairs, wk.bin_of);
+    sw_bin1_kernel<<<nb, 256, 0, s>>>(pairs, npairs, wk.bin_of, wk.counters);
     if ((e = launch_bins(wk.bin_of, npairs, kNumBins, wk.counts, wk.starts, wk.cursor, wk.idx, s)) != hipSuccess)
         return e;
     if ((e = stage_end(ctx, kStSched, s)) != hipSuccess || (e = stage_begin(ctx, kStAlign1, s)) != hipSuccess)
@@ -563,7 +579,7 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
     }
     if ((e = stage_end(ctx, kStAlign1, s)) != hipSuccess || (e = stage_begin(ctx, kStAlign2, s)) != hipSuccess)
         return e;
-    sw_bin2_kernel<<<nb, 256, 0, s>>>(pairs, p1, npairs, sc.cov_pct, full, out, wk.bin_of);
+    sw_bin2_kernel<<<nb, 256, 0, s>>>(pairs, p1, npairs, sc.cov_pct, stats_mode, out, wk.bin_of, wk.counters);
     if ((e = launch_bins(wk.bin_of, npairs, kNumBins, wk.counts, wk.starts2, wk.cursor, wk.idx2, s)) != hipSuccess)
         return e;
     for (int bin = 0; bin < kNumBins; ++bin) {

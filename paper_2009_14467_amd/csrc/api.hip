@@ -233,7 +233,15 @@ pastis_status align_core(pastis_ctx *ctx, const Staged &st, const uint8_t *codes
                           stats_mode, s),
                 "sw kernels");
     } else {
-        return set_error(ctx, PASTIS_E_INVAL, "x-drop alignment is not available in this build");
+        void *redo = nullptr, *ring = nullptr;
+        PASTIS_TRY(ensure(ctx, kBufXdRedo, sizeof(uint32_t) * (size_t)(npairs + 4), &redo));
+        PASTIS_TRY(ensure(ctx, kBufXdRing, (size_t)xd_global_waves() * xd_ring_bytes_per_wave(), &ring));
+        uint32_t *n_redo = (uint32_t *)redo + npairs;
+        HIP_TRY(ctx, fill<uint32_t>(n_redo, 1, 0u, s), "reset");
+        HIP_TRY(ctx,
+                launch_xd(ctx, codes, (const PairDesc *)pairs, npairs, ctx->d_blosum, sc, P.k, out, (uint32_t *)redo,
+                          n_redo, (int *)ring, wk.counters, s),
+                "xd kernels");
     }
     unsigned long long c[4];
     PASTIS_TRY(read_device(ctx, wk.counters, c, sizeof(c), s));

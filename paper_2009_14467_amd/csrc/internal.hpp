@@ -123,6 +123,8 @@ enum BufId {
     kBufCandS1,
     kBufCandS2,
     kBufRecords,
+    kBufXdRedo,
+    kBufXdRing,
     kBufCount  // first id used by the discovery stage
 };
 constexpr int kNumBufs = 96;
@@ -163,6 +165,14 @@ struct SwWork {
     int64_t scratch_per_wave;
 };
 int sw_num_bins();
+int64_t xd_global_waves();
+size_t xd_ring_bytes_per_wave();
+// XD alignment of every pair; bands wider than the LDS ring are redone from
+// redo[] (device list, count in *n_redo, which must start at 0) with rings in
+// gring (xd_global_waves() * xd_ring_bytes_per_wave() bytes).
+hipError_t launch_xd(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pairs, int64_t npairs,
+                     const int8_t *blosum, const Scoring &sc, int k, pastis_pair_record *out, uint32_t *redo,
+                     uint32_t *n_redo, int *gring, unsigned long long *counters, hipStream_t s);
 int64_t sw_scratch_waves();
 
 hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pairs, int64_t npairs,

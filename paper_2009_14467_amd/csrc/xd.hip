@@ -1,0 +1,378 @@
+// Seed-and-extend with gapped x-drop (Section IV-E, XD), one 64-lane
+// wavefront per candidate pair.
+//
+// For each stored seed (at most two), the k seed columns are scored, then the
+// alignment is extended to the right of the seed and, on reversed prefixes,
+// to the left.  An extension is an anchored affine-gap DP (no zero floor)
+// processed by anti-diagonals d = u + v: a cell with no live predecessor is
+// not computed; a computed cell is live when its score is at least
+// (best score of earlier anti-diagonals) - X; the extension stops at the first
+// anti-diagonal without a live cell.  Its end is the best live cell, the
+// earliest anti-diagonal and then the smallest row winning ties.  The pair
+// keeps the best-scoring seed among those that pass the identity / coverage
+// cut (the first seed on a tie), or the best-scoring seed when none passes.
+//
+// Layout.  The live band of an anti-diagonal is spread over the lanes (cell u
+// at lane (u - lo) mod 64).  The last three anti-diagonals live in a ring in
+// LDS indexed by u mod 256, holding H, E, F and, for each state, the packed
+// (identical pairs << 16 | diagonal columns) of the canonical path reaching
+// it: each cell takes the predecessor a traceback would take (diagonal, then
+// horizontal, then vertical gap; extension before opening), and since every
+// extension path starts at the anchor, columns = u + v - diagonal columns.
+// Bands wider than the LDS ring are redone with a ring in global memory.
+#include <climits>
+
+#include "internal.hpp"
+
+namespace pastis {
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kWavesPerBlock = 4;
+constexpr int kNeg = -(1 << 28);
+constexpr int kLdsCap = 256;
+constexpr int kGlobalCap = 65536;
+constexpr int kProfCodes = kAlpha + 1;
+
+struct Ring {
+    int *H, *E, *F;
+    unsigned *SH, *SE, *SF;  // 3 slots of `cap` entries each
+    int cap;
+};
+
+struct Ext {
+    int score, u, v;
+    unsigned md;
+    int cells;
+    bool overflow;
+};
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
+        unsigned olo = __shfl_xor(lo, off, kWave), ohi = __shfl_xor(hi, off, kWave);
+        unsigned long long o = ((unsigned long long)ohi << 32) | olo;
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int wave_min_i(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+__device__ __forceinline__ int wave_sum_i(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// One extension from the anchor over a'[t] = a0[t * adir], b'[t] = b0[t * bdir].
+template <bool GLOBAL>
+__device__ Ext extend(const uint8_t *a0, int la, int adir, const uint8_t *b0, int lb, int bdir, const int8_t *sbl,
+                      int o, int e, int X, const Ring &R, int lane) {
+    const int oe = o + e;
+    const int mask = R.cap - 1;
+    if (lane == 0) {  // anti-diagonal 0: the anchor, slot 0
+        R.H[0] = 0;
+        R.E[0] = kNeg;
+        R.F[0] = kNeg;
+        R.SH[0] = 0u;
+        R.SE[0] = 0u;
+        R.SF[0] = 0u;
+    }
+    if (GLOBAL) __threadfence_block();
+    int clo1 = 0, chi1 = 0, llo1 = 0, lhi1 = 0;  // anti-diagonal d-1: computed / live ranges
+    int clo2 = 1, chi2 = 0, llo2 = 1, lhi2 = 0;  // d-2 (none yet)
+    int best = 0, bu = 0, bv = 0;
+    unsigned bmd = 0u;
+    int cells = 0;
+    bool overflow = false;
+    const int dmax = la + lb;
+    for (int d = 1; d <= dmax; ++d) {
+        int lo = INT_MAX, hi = -1;
+        if (llo1 <= lhi1) {
+            lo = llo1;
+            hi = lhi1 + 1;
+        }
+        if (llo2 <= lhi2) {
+            lo = min(lo, llo2 + 1);
+            hi = max(hi, lhi2 + 1);
+        }
+        lo = max(lo, max(0, d - lb));
+        hi = min(hi, min(d, la));
+        if (lo > hi) break;
+        if (hi - lo + 1 > R.cap) {
+            overflow = true;
+            break;
+        }
+        const int s0 = (d % 3) * R.cap, s1 = ((d + 2) % 3) * R.cap, s2 = ((d + 1) % 3) * R.cap;
+        const int floor_ = best - X;
+        int lbest = INT_MIN, lbu = 0;
+        unsigned lbmd = 0u;
+        int lmin = INT_MAX, lmax = -1;
+        for (int u0 = lo; u0 <= hi; u0 += kWave) {
+            const int u = u0 + lane;
+            if (u > hi) continue;
+            const int v = d - u;
+            int Hu = kNeg, Fu = kNeg, Hl = kNeg, El = kNeg, Hd = kNeg;
+            unsigned sHu = 0u, sFu = 0u, sHl = 0u, sEl = 0u, sHd = 0u;
+            if (u - 1 >= clo1 && u - 1 <= chi1) {  // (u-1, v): vertical
+                const int x = s1 + ((u - 1) & mask);
+                Hu = R.H[x];
+                Fu = R.F[x];
+                sHu = R.SH[x];
+                sFu = R.SF[x];
+            }
+            if (v >= 1 && u >= clo1 && u <= chi1) {  // (u, v-1): horizontal
+                const int x = s1 + (u & mask);
+                Hl = R.H[x];
+                El = R.E[x];
+                sHl = R.SH[x];
+                sEl = R.SE[x];
+            }
+            if (u >= 1 && v >= 1 && u - 1 >= clo2 && u - 1 <= chi2) {  // (u-1, v-1)
+                const int x = s2 + ((u - 1) & mask);
+                Hd = R.H[x];
+                sHd = R.SH[x];
+            }
+            const bool lu = Hu > kNeg / 2, ll = Hl > kNeg / 2, ld = Hd > kNeg / 2;
+            const bool any = lu || ll || ld;
+            const int e_ext = El - e, e_open = Hl - oe;
+            const bool ee = e_ext >= e_open;
+            const int E_ = ee ? e_ext : e_open;
+            const int f_ext = Fu - e, f_open = Hu - oe;
+            const bool fe = f_ext >= f_open;
+            const int F_ = fe ? f_ext : f_open;
+            int D_ = kNeg;
+            unsigned sD = 0u;
+            if (ld) {
+                const int ca = a0[(u - 1) * adir], cb = b0[(v - 1) * bdir];
+                D_ = Hd + sbl[ca * kProfCodes + cb];
+                sD = sHd + (ca == cb ? 0x10001u : 1u);
+            }
+            const int H_ = max(D_, max(E_, F_));
+            const unsigned sE_ = ee ? sEl : sHl;
+            const unsigned sF_ = fe ? sFu : sHu;
+            const unsigned sH_ = (ld && H_ == D_) ? sD : (H_ == E_ ? sE_ : sF_);
+            const bool live = any && H_ >= floor_;
+            cells += any ? 1 : 0;
+            const int x = s0 + (u & mask);
+            R.H[x] = live ? H_ : kNeg;
+            R.E[x] = live ? E_ : kNeg;
+            R.F[x] = live ? F_ : kNeg;
+            R.SH[x] = sH_;
+            R.SE[x] = sE_;
+            R.SF[x] = sF_;
+            if (live) {
+                lmin = min(lmin, u);
+                lmax = max(lmax, u);
+                if (H_ > lbest) {  // u increases along a lane: the first maximum wins
+                    lbest = H_;
+                    lbu = u;
+                    lbmd = sH_;
+                }
+            }
+        }
+        if (GLOBAL) __threadfence_block();
+        // best live cell of this anti-diagonal: highest score, then smallest u
+        unsigned long long key = 0ull;
+        if (lbest != INT_MIN)
+            key = ((unsigned long long)(unsigned)(lbest + (1 << 30)) << 32) | (0xFFFFFFFFu - (unsigned)lbu);
+        const unsigned long long wkey = wave_max_u64(key);
+        const int wmin = wave_min_i(lmin), wmax = wave_max_i(lmax);
+        clo2 = clo1;
+        chi2 = chi1;
+        llo2 = llo1;
+        lhi2 = lhi1;
+        clo1 = lo;
+        chi1 = hi;
+        if (wkey == 0ull) {
+            llo1 = 1;
+            lhi1 = 0;
+            break;
+        }
+        llo1 = wmin;
+        lhi1 = wmax;
+        const int dbest = (int)(unsigned)(wkey >> 32) - (1 << 30);
+        if (dbest > best) {
+            const unsigned long long hit = __ballot(key == wkey);
+            const int winner = __ffsll((long long)hit) - 1;
+            best = dbest;
+            bu = (int)(0xFFFFFFFFu - (unsigned)wkey);
+            bv = d - bu;
+            bmd = (unsigned)__builtin_amdgcn_readlane((int)lbmd, winner);
+        }
+    }
+    Ext r;
+    r.score = best;
+    r.u = bu;
+    r.v = bv;
+    r.md = bmd;
+    r.cells = wave_sum_i(cells);
+    r.overflow = overflow;
+    return r;
+}
+
+struct SeedAln {
+    int score, beg_a, end_a, beg_b, end_b, matches, columns, cells;
+    bool overflow;
+};
+
+template <bool GLOBAL>
+__device__ SeedAln align_seed(const uint8_t *a, int la, const uint8_t *b, int lb, int pa, int pb, int k,
+                              const int8_t *sbl, int o, int e, int X, const Ring &R, int lane) {
+    int sc = 0, sm = 0;
+    for (int t = 0; t < k; ++t) {
+        const int ca = a[pa + t], cb = b[pb + t];
+        sc += sbl[ca * kProfCodes + cb];
+        sm += ca == cb;
+    }
+    const Ext rt = extend<GLOBAL>(a + pa + k, la - pa - k, 1, b + pb + k, lb - pb - k, 1, sbl, o, e, X, R, lane);
+    const Ext lf = extend<GLOBAL>(a + pa - 1, pa, -1, b + pb - 1, pb, -1, sbl, o, e, X, R, lane);
+    SeedAln s;
+    s.score = lf.score + sc + rt.score;
+    s.beg_a = pa - lf.u;
+    s.beg_b = pb - lf.v;
+    s.end_a = pa + k - 1 + rt.u;
+    s.end_b = pb + k - 1 + rt.v;
+    s.matches = (int)(lf.md >> 16) + sm + (int)(rt.md >> 16);
+    s.columns = (lf.u + lf.v - (int)(lf.md & 0xFFFFu)) + k + (rt.u + rt.v - (int)(rt.md & 0xFFFFu));
+    s.cells = lf.cells + rt.cells;
+    s.overflow = lf.overflow || rt.overflow;
+    return s;
+}
+
+__device__ __forceinline__ bool passes(const SeedAln &s, int la, int id_pct, int cov_pct) {
+    if (s.score <= 0 || s.columns <= 0) return false;
+    const long long span = (long long)s.end_a - s.beg_a + 1;
+    return 100LL * s.matches >= (long long)id_pct * s.columns && 100LL * span >= (long long)cov_pct * la;
+}
+
+// GLOBAL = false: every pair of [0, npairs), LDS ring; pairs whose band
+// outgrows it are listed in redo[] and left for GLOBAL = true, which walks
+// that list with rings in global memory.
+template <bool GLOBAL>
+__global__ __launch_bounds__(256) void xd_kernel(const uint8_t *__restrict__ codes, const PairDesc *__restrict__ pairs,
+                                                 int64_t npairs, const int8_t *__restrict__ blosum, int k, int o, int e,
+                                                 int X, int id_pct, int cov_pct, pastis_pair_record *__restrict__ out,
+                                                 uint32_t *__restrict__ redo, uint32_t *__restrict__ n_redo,
+                                                 int *__restrict__ gring, unsigned long long *__restrict__ counters) {
+    __shared__ int8_t sbl[kProfCodes * kProfCodes];
+    for (int t = threadIdx.x; t < kProfCodes * kProfCodes; t += blockDim.x) sbl[t] = blosum[t];
+    __shared__ int lds_int[GLOBAL ? 1 : kWavesPerBlock * 9 * kLdsCap];
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int64_t gwave = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+    Ring R;
+    int *base;
+    if constexpr (GLOBAL) {
+        R.cap = kGlobalCap;
+        base = gring + gwave * (int64_t)18 * kGlobalCap;
+    } else {
+        R.cap = kLdsCap;
+        base = lds_int + wave * 9 * kLdsCap;  // 3 int planes + 3 unsigned planes of 3 slots... see below
+    }
+    // planes of 3 * cap entries: H, E, F, SH, SE, SF
+    if constexpr (GLOBAL) {
+        R.H = base;
+        R.E = base + 3 * R.cap;
+        R.F = base + 6 * R.cap;
+        R.SH = (unsigned *)(base + 9 * R.cap);
+        R.SE = (unsigned *)(base + 12 * R.cap);
+        R.SF = (unsigned *)(base + 15 * R.cap);
+    }
+    __shared__ unsigned lds_u[GLOBAL ? 1 : kWavesPerBlock * 9 * kLdsCap];
+    if constexpr (!GLOBAL) {
+        R.H = base;
+        R.E = base + 3 * R.cap;
+        R.F = base + 6 * R.cap;
+        unsigned *ub = lds_u + wave * 9 * kLdsCap;
+        R.SH = ub;
+        R.SE = ub + 3 * R.cap;
+        R.SF = ub + 6 * R.cap;
+    }
+    const int64_t count = GLOBAL ? (int64_t)*n_redo : npairs;
+    unsigned long long my_cells = 0;
+    for (int64_t w = gwave; w < count; w += (int64_t)gridDim.x * kWavesPerBlock) {
+        const int64_t q = GLOBAL ? (int64_t)redo[w] : w;
+        const PairDesc pd = pairs[q];
+        const uint8_t *a = codes + pd.a_off;
+        const uint8_t *b = codes + pd.b_off;
+        const int pa[2] = {pd.pa1, pd.pa2}, pb[2] = {pd.pb1, pd.pb2};
+        pastis_pair_record rec;
+        rec.score = 0;
+        rec.beg_a = rec.end_a = rec.beg_b = rec.end_b = -1;
+        rec.matches = rec.columns = 0;
+        rec.seed_used = -1;
+        rec.passed = 0;
+        rec.swapped = pd.swapped;
+        bool have = false, best_pass = false, overflow = false;
+        int cells = 0;
+        for (int s = 0; s < 2; ++s) {
+            if (pa[s] < 0) continue;
+            const SeedAln t = align_seed<GLOBAL>(a, pd.la, b, pd.lb, pa[s], pb[s], k, sbl, o, e, X, R, lane);
+            overflow |= t.overflow;
+            cells += t.cells;
+            const bool pass = passes(t, pd.la, id_pct, cov_pct);
+            if (!have || (pass && !best_pass) || (pass == best_pass && t.score > rec.score)) {
+                rec.score = t.score;
+                rec.beg_a = t.beg_a;
+                rec.end_a = t.end_a;
+                rec.beg_b = t.beg_b;
+                rec.end_b = t.end_b;
+                rec.matches = t.matches;
+                rec.columns = t.columns;
+                rec.seed_used = s;
+                best_pass = pass;
+                have = true;
+            }
+        }
+        rec.passed = best_pass ? 1 : 0;
+        rec.cells = cells;
+        if (!GLOBAL && overflow) {
+            if (lane == 0) redo[atomicAdd(n_redo, 1u)] = (uint32_t)q;
+            continue;
+        }
+        my_cells += (unsigned long long)cells;
+        if (lane == 0) out[q] = rec;
+    }
+    if (lane == 0 && my_cells) atomicAdd(&counters[0], my_cells);
+}
+
+}  // namespace
+
+int64_t xd_global_waves() { return 64 * kWavesPerBlock; }
+size_t xd_ring_bytes_per_wave() { return sizeof(int) * 18 * (size_t)kGlobalCap; }
+
+hipError_t launch_xd(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pairs, int64_t npairs,
+                     const int8_t *blosum, const Scoring &sc, int k, pastis_pair_record *out, uint32_t *redo,
+                     uint32_t *n_redo, int *gring, unsigned long long *counters, hipStream_t s) {
+    if (npairs <= 0) return hipSuccess;
+    hipError_t e = stage_begin(ctx, kStAlign1, s);
+    if (e != hipSuccess) return e;
+    int64_t blocks = (npairs + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (blocks > 4096) blocks = 4096;
+    xd_kernel<false><<<(unsigned)blocks, 256, 0, s>>>(codes, pairs, npairs, blosum, k, sc.gap_open, sc.gap_extend,
+                                                       sc.xdrop, sc.id_pct, sc.cov_pct, out, redo, n_redo, gring,
+                                                       counters);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = stage_end(ctx, kStAlign1, s)) != hipSuccess || (e = stage_begin(ctx, kStAlign2, s)) != hipSuccess)
+        return e;
+    xd_kernel<true><<<(unsigned)(xd_global_waves() / kWavesPerBlock), 256, 0, s>>>(
+        codes, pairs, npairs, blosum, k, sc.gap_open, sc.gap_extend, sc.xdrop, sc.id_pct, sc.cov_pct, out, redo,
+        n_redo, gring, counters);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return stage_end(ctx, kStAlign2, s);
+}
+
+}  // namespace pastis

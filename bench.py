@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--workload", default="mid", choices=["tiny", "mid", "large", "heavy"])
     ap.add_argument("--families", type=int, default=None, help="scale the workload down (tests)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mlp", action="store_true", help="skip the learned-filter leg")
+    ap.add_argument("--mlp-epochs", type=int, default=4)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     return ap.parse_args()
 
@@ -91,6 +93,61 @@ def cpu_baseline(fs, lo, hi, target_s):
     }
 
 
+def mlp_leg(P, args, params, over, res, off, edges, plain_ms):
+    """Train the learned pre-alignment filter on another seed of the same
+    workload recipe (labels from exact alignment), then time the filtered
+    search on the bench workload and measure its recall of the exact edges."""
+    import numpy as np
+    import torch
+
+    from paper_2009_14467_amd import learned_filter as LF
+    from synth import workload
+
+    fs_tr = workload(args.workload, seed=1, **over)
+    dev = res.device
+    tf = LF.train(P.Params(**params), torch.from_numpy(fs_tr.residues).to(dev),
+                  torch.from_numpy(fs_tr.offsets).to(dev), epochs=args.mlp_epochs)
+    torch.cuda.empty_cache()
+    ctx = P.Context(P.Params(filter_mode="mlp", **params))
+    tf.install(ctx)
+    for _ in range(args.warmup):
+        ctx.search(res, off)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fstage = [0.0] * 9
+    for _ in range(args.steps):
+        fedges = ctx.search(res, off)
+        st = ctx.stats()
+        fstage = [a + b for a, b in zip(fstage, st["ms_stage"])]
+    torch.cuda.synchronize()
+    fms = (time.perf_counter() - t0) * 1e3 / args.steps
+
+    def keys(e):
+        return (e["i"].astype(np.uint64) << np.uint64(32)) | e["j"].astype(np.uint64)
+
+    found = np.isin(keys(edges), keys(fedges)).sum()
+    return {
+        "recall": float(found / max(edges.size, 1)),
+        "edges": int(fedges.size),
+        "aligned_frac": st["n_aligned"] / max(st["n_candidates"], 1),
+        "ms_per_step": fms,
+        "speedup": plain_ms / fms,
+        "filter_ms": fstage[8] / args.steps,
+        "align_ms": (fstage[5] + fstage[6]) / args.steps,
+        "train": {
+            "workload": f"same recipe, seed 1: {fs_tr.n} sequences",
+            "examples": tf.n_examples,
+            "positive_frac": tf.positive_frac,
+            "epochs": args.mlp_epochs,
+            "seconds": tf.seconds,
+            "losses": tf.losses,
+            "heldout_recall": tf.heldout_recall,
+            "heldout_kept_frac": tf.heldout_kept_frac,
+            "tau": tf.tau,
+        },
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -114,7 +171,7 @@ def main():
     for _ in range(args.warmup):
         ctx.search(res, off)
     torch.cuda.synchronize()
-    stage = [0.0] * 8
+    stage = [0.0] * 9
     t0 = time.perf_counter()
     for _ in range(args.steps):
         edges = ctx.search(res, off)
@@ -128,7 +185,7 @@ def main():
     pass1_ms = stage[5] / args.steps
 
     achieved = cells * OPS_PER_SW_CELL / (pass1_ms * 1e-3) / 1e12
-    names = ["encode", "kmers", "subs_AS", "spgemm", "schedule", "sw_pass1", "sw_pass2", "edges"]
+    names = ["encode", "kmers", "subs_AS", "spgemm", "schedule", "sw_pass1", "sw_pass2", "edges", "mlp_filter"]
     line = {
         "metric": METRIC,
         "value": cells / (ms_step * 1e-3) / 1e9,
@@ -165,8 +222,30 @@ def main():
             "traffic": None,
         },
     }
+    # the same workload with x-drop seed extension from the stored seeds (X = 49)
+    ctx_xd = P.Context(P.Params(align_mode="xd", **params))
+    for _ in range(args.warmup):
+        ctx_xd.search(res, off)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xstage = [0.0] * 9
+    for _ in range(args.steps):
+        xedges = ctx_xd.search(res, off)
+        xst = ctx_xd.stats()
+        xstage = [a + b for a, b in zip(xstage, xst["ms_stage"])]
+    torch.cuda.synchronize()
+    xms = (time.perf_counter() - t0) * 1e3 / args.steps
+    line["xd"] = {
+        "ms_per_step": xms,
+        "pairs_per_s": n_cand / (xms * 1e-3),
+        "live_cells": float(xst["cells"]),
+        "align_ms": (xstage[5] + xstage[6]) / args.steps,
+        "align_pairs_per_s": n_cand / ((xstage[5] + xstage[6]) / args.steps * 1e-3),
+        "edges": int(xedges.size),
+    }
+    if not args.no_mlp:
+        line["mlp_filter"] = mlp_leg(P, args, params, over, res, off, edges, ms_step)
     if not args.no_cpu_baseline:
-        import numpy as np
 
         c = ctx.candidates(n_cand)
         lo = c["lo"].cpu().numpy().view(np.uint32)

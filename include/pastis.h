@@ -78,7 +78,9 @@ typedef struct pastis_params {
     int32_t full_records;     /* 1: traceback statistics (beg, matches, columns) for every
                                  aligned pair; 0: only for pairs whose coverage cut can
                                  still hold (the others report beg = -1, passed = 0) */
-    int32_t reserved[7];      /* must be zero */
+    int32_t filter_mode;      /* 0: align every candidate; 1: align only candidates the
+                                 learned filter keeps (pastis_mlp_set first) */
+    int32_t reserved[6];      /* must be zero */
 } pastis_params;
 
 /* One similarity edge, 48 bytes.  i < j; edges are sorted by (i, j).
@@ -120,9 +122,10 @@ typedef struct pastis_run_stats {
     int64_t stats_pass_pairs; /* pairs that needed the statistics pass */
     int64_t int32_pairs;      /* pairs computed with 32-bit DP words */
     double ms_total;    /* host wall time of the call */
-    double ms_stage[8]; /* device time (HIP events on the call's stream) of: encode,
+    double ms_stage[9]; /* device time (HIP events on the call's stream) of: encode,
                            k-mers, S formation, SpGEMM, schedule, alignment pass 1,
-                           alignment pass 2, filter/edges */
+                           alignment pass 2, identity/coverage cut and edges, learned
+                           pre-alignment filter */
 } pastis_run_stats;
 
 typedef struct pastis_ctx pastis_ctx;
@@ -202,6 +205,52 @@ const pastis_edge *pastis_result_device_ptr(const pastis_result *r);
 pastis_status pastis_result_copy(const pastis_result *r, pastis_edge *dst, int64_t cap, int dst_on_device,
                                  void *stream);
 void pastis_result_free(pastis_result *r);
+
+/* ---- learned pre-alignment filter (not part of the paper) ----
+ * A 16-128-128-1 MLP (ReLU, sigmoid output) scores each candidate from 16
+ * features: shared-k-mer count; seed-1 diagonal (pos_b - pos_a) / Lb;
+ * |diag2 - diag1| / Lb; ln La; ln Lb; La / Lb; |composition difference| over
+ * the residue groups {AG}{ST}{DE}{NQ}{KRH}{IV}{LM}{FYW}{C}{P} (a = shorter
+ * sequence).  Inputs are z-scored and cast to bf16; weights and activations
+ * are bf16 copies with fp32 accumulation on matrix cores; biases stay fp32.
+ * Parameters: one fp32 vector of PASTIS_MLP_PARAMS values, W1 [128][16],
+ * b1 [128], W2 [128][128], b2 [128], w3 [128], b3 [1].  A candidate is kept
+ * when its logit >= tau (the logit threshold). */
+#define PASTIS_MLP_FEATURES 16
+#define PASTIS_MLP_PARAMS 18817
+
+/* Raw features [n_candidates][16] (device, fp32) of the last discovery's
+ * candidates over the given sequences (same as that discovery's).
+ * PASTIS_E_STATE without a discovery; PASTIS_E_CAPACITY if cap < count. */
+pastis_status pastis_mlp_features(pastis_ctx *ctx, const uint8_t *residues, const int64_t *offsets, int64_t n,
+                                  int input_on_device, float *features, int64_t cap, void *stream);
+/* Set the network (host arrays): params [PASTIS_MLP_PARAMS], feature mean and
+ * std [16], logit threshold tau.  Resets the optimiser state. */
+pastis_status pastis_mlp_set(pastis_ctx *ctx, const float *params, const float *mean, const float *stdv, float tau);
+/* Read the network back (host arrays; any may be NULL). */
+pastis_status pastis_mlp_get(pastis_ctx *ctx, float *params, float *mean, float *stdv, float *tau);
+/* mean / std of each feature column of X [n][16] (device) become the
+ * network's normalisation. */
+pastis_status pastis_mlp_fit_normalizer(pastis_ctx *ctx, const float *X, int64_t n, void *stream);
+/* logits [n] (device) of raw features X [n][16] (device). */
+pastis_status pastis_mlp_forward(pastis_ctx *ctx, const float *X, int64_t n, float *logits, void *stream);
+/* Gradient (host [PASTIS_MLP_PARAMS]) and value (host) of the mean weighted
+ * binary cross-entropy over X [n][16] with labels [n] (device, 0/1):
+ * loss = mean(pos_weight * t * softplus(-y) + (1 - t) * softplus(y)). */
+pastis_status pastis_mlp_grad(pastis_ctx *ctx, const float *X, const uint8_t *labels, int64_t n, float pos_weight,
+                              float *grad, float *loss, void *stream);
+/* One pass over the examples order[0..n) (device int32 indices into the
+ * n_examples rows of X / labels, checked before any update: PASTIS_E_INVAL if
+ * one is out of range) in minibatches of `batch` (multiple of 16, <= 65536):
+ * gradient, then an Adam step (beta 0.9 / 0.999, eps 1e-8) on the fp32
+ * masters.  *mean_loss (host, may be NULL) gets the mean minibatch loss. */
+pastis_status pastis_mlp_train_epoch(pastis_ctx *ctx, const float *X, const uint8_t *labels, int64_t n_examples,
+                                     const int32_t *order, int64_t n, int32_t batch, float lr, float pos_weight,
+                                     float *mean_loss, void *stream);
+/* Logit threshold keeping at least target_recall of the positive examples of
+ * X / labels (device); also stored as the network's tau. */
+pastis_status pastis_mlp_calibrate(pastis_ctx *ctx, const float *X, const uint8_t *labels, int64_t n,
+                                   double target_recall, float *tau, void *stream);
 
 /* Counters and per-stage times of the last pastis_search / pastis_align_pairs. */
 pastis_status pastis_stats(const pastis_ctx *ctx, pastis_run_stats *out);

@@ -8,6 +8,8 @@ This package is the thin Python binding; it needs the built library.
 
 from ._binding import (  # noqa: F401
     EDGE_DTYPE,
+    MLP_FEATURES,
+    MLP_PARAMS,
     RECORD_DTYPE,
     Context,
     Params,

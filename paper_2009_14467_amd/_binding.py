@@ -80,7 +80,8 @@ class _Params(ctypes.Structure):
         ("weight_mode", ctypes.c_int32),
         ("score_width", ctypes.c_int32),
         ("full_records", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 7),
+        ("filter_mode", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 6),
     ]
 
 
@@ -96,7 +97,7 @@ class _Stats(ctypes.Structure):
         ("stats_pass_pairs", ctypes.c_int64),
         ("int32_pairs", ctypes.c_int64),
         ("ms_total", ctypes.c_double),
-        ("ms_stage", ctypes.c_double * 8),
+        ("ms_stage", ctypes.c_double * 9),
     ]
 
 
@@ -117,6 +118,7 @@ class Params:
     weight_mode: str = "ani"  # "ani" | "ns"
     score_width: int = 0
     full_records: bool = False
+    filter_mode: str = "none"  # "none" | "mlp" (the learned filter, set with Context.mlp_set)
 
     def to_c(self) -> _Params:
         p = _Params()
@@ -133,6 +135,7 @@ class Params:
         p.weight_mode = {"ani": 0, "ns": 1}[self.weight_mode]
         p.score_width = self.score_width
         p.full_records = int(self.full_records)
+        p.filter_mode = {"none": 0, "mlp": 1}[self.filter_mode]
         return p
 
 
@@ -159,7 +162,19 @@ _SIGNATURES = [
     ("pastis_result_device_ptr", _VP, [_VP]),
     ("pastis_result_copy", ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int, _VP]),
     ("pastis_result_free", None, [_VP]),
+    ("pastis_mlp_features", ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_int, _VP, ctypes.c_int64, _VP]),
+    ("pastis_mlp_set", ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_float]),
+    ("pastis_mlp_get", ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.POINTER(ctypes.c_float)]),
+    ("pastis_mlp_fit_normalizer", ctypes.c_int, [_VP, _VP, ctypes.c_int64, _VP]),
+    ("pastis_mlp_forward", ctypes.c_int, [_VP, _VP, ctypes.c_int64, _VP, _VP]),
+    ("pastis_mlp_grad", ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_float, _VP, _VP, _VP]),
+    ("pastis_mlp_train_epoch", ctypes.c_int,
+     [_VP, _VP, _VP, ctypes.c_int64, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_float, ctypes.c_float, _VP, _VP]),
+    ("pastis_mlp_calibrate", ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_double, _VP, _VP]),
 ]
+
+MLP_FEATURES = 16
+MLP_PARAMS = 18817
 
 
 def lib():
@@ -313,6 +328,71 @@ class Context:
             return out
         finally:
             lib().pastis_result_free(res)
+
+    # ---- learned pre-alignment filter ----
+
+    def mlp_features(self, residues, offsets, n_candidates: int, stream=None):
+        """Raw features [n_candidates, 16] (device fp32) of the last discovery's candidates."""
+        torch = _torch()
+        n = offsets.numel() - 1
+        out = torch.empty((max(n_candidates, 1), MLP_FEATURES), dtype=torch.float32, device=f"cuda:{self.device}")
+        self._check(lib().pastis_mlp_features(self._ctx, _dev_ptr(residues), _dev_ptr(offsets), n,
+                                              int(residues.is_cuda), _dev_ptr(out), n_candidates,
+                                              _stream_ptr(stream)))
+        return out[:n_candidates]
+
+    def mlp_set(self, params, mean, std, tau: float = 0.0):
+        """Install a network (host arrays, fp32): params [MLP_PARAMS], mean / std [16]."""
+        th = np.ascontiguousarray(params, np.float32)
+        mu = np.ascontiguousarray(mean, np.float32)
+        sd = np.ascontiguousarray(std, np.float32)
+        if th.size != MLP_PARAMS or mu.size != MLP_FEATURES or sd.size != MLP_FEATURES:
+            raise ValueError("network arrays have the wrong size")
+        self._check(lib().pastis_mlp_set(self._ctx, th.ctypes.data, mu.ctypes.data, sd.ctypes.data, float(tau)))
+
+    def mlp_get(self) -> dict:
+        th = np.zeros(MLP_PARAMS, np.float32)
+        mu = np.zeros(MLP_FEATURES, np.float32)
+        sd = np.zeros(MLP_FEATURES, np.float32)
+        tau = ctypes.c_float(0.0)
+        self._check(lib().pastis_mlp_get(self._ctx, th.ctypes.data, mu.ctypes.data, sd.ctypes.data,
+                                         ctypes.byref(tau)))
+        return {"params": th, "mean": mu, "std": sd, "tau": float(tau.value)}
+
+    def mlp_fit_normalizer(self, X, stream=None):
+        self._check(lib().pastis_mlp_fit_normalizer(self._ctx, _dev_ptr(X), X.shape[0], _stream_ptr(stream)))
+
+    def mlp_forward(self, X, stream=None):
+        """Logits [n] (device fp32) of raw features X [n, 16] (device fp32)."""
+        torch = _torch()
+        out = torch.empty(max(X.shape[0], 1), dtype=torch.float32, device=f"cuda:{self.device}")
+        self._check(lib().pastis_mlp_forward(self._ctx, _dev_ptr(X), X.shape[0], _dev_ptr(out),
+                                             _stream_ptr(stream)))
+        return out[: X.shape[0]]
+
+    def mlp_grad(self, X, labels, pos_weight: float = 1.0, stream=None):
+        """(loss, gradient [MLP_PARAMS]) of the weighted BCE over X / labels (device)."""
+        g = np.zeros(MLP_PARAMS, np.float32)
+        loss = np.zeros(1, np.float32)
+        self._check(lib().pastis_mlp_grad(self._ctx, _dev_ptr(X), _dev_ptr(labels), X.shape[0], float(pos_weight),
+                                          g.ctypes.data, loss.ctypes.data, _stream_ptr(stream)))
+        return float(loss[0]), g
+
+    def mlp_train_epoch(self, X, labels, order, batch: int = 4096, lr: float = 1e-3, pos_weight: float = 1.0,
+                        stream=None) -> float:
+        """One Adam pass over order (device int32 example indices); returns the mean batch loss."""
+        loss = np.zeros(1, np.float32)
+        self._check(lib().pastis_mlp_train_epoch(self._ctx, _dev_ptr(X), _dev_ptr(labels), X.shape[0],
+                                                 _dev_ptr(order), order.numel(), int(batch), float(lr), float(pos_weight),
+                                                 loss.ctypes.data, _stream_ptr(stream)))
+        return float(loss[0])
+
+    def mlp_calibrate(self, X, labels, target_recall: float, stream=None) -> float:
+        """Set (and return) the logit threshold keeping >= target_recall of the positives."""
+        tau = np.zeros(1, np.float32)
+        self._check(lib().pastis_mlp_calibrate(self._ctx, _dev_ptr(X), _dev_ptr(labels), X.shape[0],
+                                               float(target_recall), tau.ctypes.data, _stream_ptr(stream)))
+        return float(tau[0])
 
 
 def records_to_numpy(t) -> np.ndarray:

@@ -96,7 +96,8 @@ pastis_status validate(const pastis_params *p, std::string &why) {
     if (p->score_width != 0 && p->score_width != 16 && p->score_width != 32)
         return why = "score_width must be 0, 16 or 32", PASTIS_E_INVAL;
     if (p->full_records != 0 && p->full_records != 1) return why = "full_records must be 0 or 1", PASTIS_E_INVAL;
-    for (int t = 0; t < 7; ++t)
+    if (p->filter_mode != 0 && p->filter_mode != 1) return why = "filter_mode must be 0 or 1", PASTIS_E_INVAL;
+    for (int t = 0; t < 6; ++t)
         if (p->reserved[t] != 0) return why = "reserved fields must be zero", PASTIS_E_INVAL;
     return PASTIS_OK;
 }
@@ -202,6 +203,8 @@ pastis_status make_sw_work(pastis_ctx *ctx, int64_t npairs, int max_len, SwWork 
 
 // Orient the pairs, then run the context's alignment mode; `out` gets one
 // record per pair.  Validates pair indices (PASTIS_E_INVAL).
+void mlp_free(pastis_ctx *ctx);
+
 pastis_status align_core(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, int64_t n, const uint32_t *pi,
                          const uint32_t *pj, const uint32_t *seed1, const uint32_t *seed2, int64_t npairs,
                          pastis_pair_record *out, hipStream_t s) {
@@ -333,6 +336,7 @@ pastis_status pastis_create(const pastis_params *p, int device, pastis_ctx **out
 void pastis_destroy(pastis_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
+    mlp_free(ctx);
     for (auto &b : ctx->buf)
         if (b.ptr) (void)hipFree(b.ptr);
     if (ctx->d_blosum) (void)hipFree(ctx->d_blosum);

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/pastis.h"
+#include "mlp.hpp"
 
 namespace pastis {
 
@@ -43,7 +44,7 @@ struct PairDesc {
 };
 
 // Stage timer: HIP events recorded on the call's stream, read after a sync.
-enum Stage { kStEncode = 0, kStKmers, kStSubs, kStSpgemm, kStSched, kStAlign1, kStAlign2, kStFilter, kNumStages };
+enum Stage { kStEncode = 0, kStKmers, kStSubs, kStSpgemm, kStSched, kStAlign1, kStAlign2, kStFilter, kStLearned, kNumStages };
 
 #define PASTIS_TRY(expr)                \
     do {                                \
@@ -97,10 +98,15 @@ struct pastis_ctx {
     int64_t n_candidates = 0;
     int64_t n_seqs_last = 0;
     bool have_candidates = false;
+    // learned filter
+    pastis::MlpState mlp{};
+    bool mlp_alloc = false, mlp_set = false;
+    float mlp_tau = 0.f;
+    int mlp_step = 0;
     void *h_pinned = nullptr;
     size_t h_pinned_bytes = 0;
-    hipEvent_t ev[2 * 8] = {};
-    bool ev_used[8] = {};
+    hipEvent_t ev[2 * 9] = {};
+    bool ev_used[9] = {};
 };
 
 namespace pastis {
@@ -125,6 +131,13 @@ enum BufId {
     kBufRecords,
     kBufXdRedo,
     kBufXdRing,
+    kBufMlpComp,
+    kBufMlpFeat,
+    kBufMlpLogit,
+    kBufMlpKeep,
+    kBufMlpPos,
+    kBufMlpTmp,
+    kBufMlpOrder,
     kBufCount  // first id used by the discovery stage
 };
 constexpr int kNumBufs = 96;

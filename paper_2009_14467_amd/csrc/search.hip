@@ -364,6 +364,9 @@ pastis_status stage_and_encode(pastis_ctx *ctx, const uint8_t *residues, const i
 
 }  // namespace
 
+pastis_status mlp_filter_candidates(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, int64_t n,
+                                   hipStream_t s);
+
 // Align the ctx's current candidates; records into kDRecords.
 pastis_status align_candidates(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, int64_t n, hipStream_t s,
                                pastis_pair_record **rec_out);
@@ -443,6 +446,10 @@ pastis_status pastis_search(pastis_ctx *ctx, const uint8_t *residues, const int6
     PASTIS_TRY(stage_and_encode(ctx, residues, offsets, n, input_on_device, s, st, &codes));
     int64_t nc = 0;
     PASTIS_TRY(discover(ctx, st, codes, n, s, &nc));
+    if (ctx->params.filter_mode == 1) {
+        PASTIS_TRY(mlp_filter_candidates(ctx, st, codes, n, s));
+        nc = ctx->n_candidates;
+    }
     pastis_pair_record *rec = nullptr;
     PASTIS_TRY(align_candidates(ctx, st, codes, n, s, &rec));
     // edges

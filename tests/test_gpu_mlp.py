@@ -1,0 +1,209 @@
+"""Parity of the learned pre-alignment filter's HIP kernels with the CPU
+oracle (oracle/mlp.py): features, bf16 MFMA forward, gradients, an Adam
+step, calibration, and the filtered search."""
+
+import numpy as np
+import pytest
+
+from oracle import mlp as M
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(x, gpu):
+    import torch
+
+    a = np.ascontiguousarray(x)
+    if a.dtype == np.uint32:
+        a = a.view(np.int32)
+    return torch.from_numpy(a).to(gpu)
+
+
+def _key(lo, hi):
+    return (np.asarray(lo, np.uint64) << np.uint64(32)) | np.asarray(hi, np.uint64)
+
+
+def _net(seed=0, scale_b=0.1):
+    theta = M.init_params(seed)
+    rng = np.random.default_rng(seed + 100)
+    p = M.unpack(theta)
+    p["b1"] = rng.normal(0, scale_b, M.N_H)
+    p["b2"] = rng.normal(0, scale_b, M.N_H)
+    p["b3"] = np.array([0.2])
+    return M.pack(p).astype(np.float32).astype(np.float64)
+
+
+def _features(n, seed):
+    """Seeded feature-like rows: counts, diagonals, log lengths, ratios, composition gaps."""
+    rng = np.random.default_rng(seed)
+    X = np.zeros((n, M.N_IN), np.float32)
+    X[:, 0] = rng.integers(1, 40, n)
+    X[:, 1] = rng.normal(0, 0.2, n)
+    X[:, 2] = np.abs(rng.normal(0, 0.05, n))
+    la = rng.lognormal(np.log(300), 0.5, n)
+    lb = la * rng.uniform(1, 3, n)
+    X[:, 3], X[:, 4], X[:, 5] = np.log(la), np.log(lb), la / lb
+    X[:, 6:] = np.abs(rng.normal(0, 0.03, (n, 10)))
+    return X
+
+
+@pytest.mark.parametrize("n_subs,ck", [(0, 1), (25, 2)])
+def test_features_match_oracle(gpu, orc, n_subs, ck):
+    import paper_2009_14467_amd as P
+    from synth import workload
+
+    s = workload("tiny", n_families=12)
+    codes = orc.encode(s.residues)
+    c = orc.candidates(codes, s.offsets, 6, ck_min=ck, n_subs=n_subs)
+    want = M.features(codes, s.offsets, c["lo"], c["hi"], c["count"], c["seed1"], c["seed2"])
+    ctx = P.Context(P.Params(k=6, n_subs=n_subs, ck_min=ck))
+    res, off = _dev(s.residues, gpu), _dev(s.offsets, gpu)
+    nc = ctx.discover(res, off)
+    assert nc == c["lo"].size
+    g = ctx.candidates(nc)
+    F = ctx.mlp_features(res, off, nc).cpu().numpy().astype(np.float64)
+    kg = _key(g["lo"].cpu().numpy().view(np.uint32), g["hi"].cpu().numpy().view(np.uint32))
+    kw = _key(c["lo"], c["hi"])
+    F = F[np.argsort(kg)]
+    want = want[np.argsort(kw)]
+    # fp32 on the GPU: logs and quotients to a few float32 ulps
+    np.testing.assert_allclose(F, want, rtol=4e-7, atol=1e-6)
+
+
+@pytest.mark.parametrize("n", [1, 17, 1000, 70001])
+def test_forward_matches_oracle(gpu, n):
+    import paper_2009_14467_amd as P
+
+    theta = _net(1)
+    X = _features(n, seed=n)
+    mean, std = X.mean(0), X.std(0) + 1e-3
+    ctx = P.Context()
+    ctx.mlp_set(theta, mean, std)
+    y = ctx.mlp_forward(_dev(X, gpu)).cpu().numpy().astype(np.float64)
+    want, _ = M.forward(theta, M.normalise(X, mean, std))
+    err = np.abs(y - want)
+    # fp32 accumulation against fp64: ~1e-6 relative, plus a rare one-ulp
+    # difference of a bf16 activation rounded from a value on a rounding tie
+    assert np.median(err) <= 1e-5 * (1 + np.median(np.abs(want)))
+    assert (err <= 2e-2 * (1 + np.abs(want))).all(), err.max()
+
+
+@pytest.mark.parametrize("n,pw", [(16, 1.0), (999, 3.0), (4096, 10.0)])
+def test_gradient_matches_oracle(gpu, n, pw):
+    import paper_2009_14467_amd as P
+
+    theta = _net(2)
+    X = _features(n, seed=7 + n)
+    rng = np.random.default_rng(n)
+    t = (rng.random(n) < 0.3).astype(np.uint8)
+    mean, std = X.mean(0), X.std(0) + 1e-3
+    ctx = P.Context()
+    ctx.mlp_set(theta, mean, std)
+    loss, g = ctx.mlp_grad(_dev(X, gpu), _dev(t, gpu), pos_weight=pw)
+    wl, wg = M.backward(theta, M.normalise(X, mean, std), t, pw)
+    assert loss == pytest.approx(wl, rel=1e-5)
+    o = 0
+    for name, shape in M.SHAPES:
+        sz = int(np.prod(shape))
+        a, b = g[o : o + sz].astype(np.float64), wg[o : o + sz]
+        o += sz
+        scale = max(np.abs(b).max(), 1e-12)
+        assert np.linalg.norm(a - b) <= 1e-3 * np.linalg.norm(b) + 1e-7 * scale, name
+        assert (np.abs(a - b) <= 1e-2 * scale).all(), name
+
+
+def test_adam_step_matches_oracle(gpu):
+    import torch
+
+    import paper_2009_14467_amd as P
+
+    n = 2048
+    theta = _net(3)
+    X = _features(n, seed=3)
+    t = (np.random.default_rng(3).random(n) < 0.5).astype(np.uint8)
+    mean, std = X.mean(0), X.std(0) + 1e-3
+    ctx = P.Context()
+    ctx.mlp_set(theta, mean, std)
+    order = torch.arange(n, dtype=torch.int32, device=gpu)
+    ctx.mlp_train_epoch(_dev(X, gpu), _dev(t, gpu), order, batch=n, lr=1e-3)
+    got = ctx.mlp_get()["params"].astype(np.float64)
+    _, wg = M.backward(theta, M.normalise(X, mean, std), t, 1.0)
+    want = M.Adam(M.N_PARAMS, lr=1e-3).step(theta, wg)
+    # the first Adam step moves each weight by lr * g / (|g| + eps): compare
+    # where the gradient is well above float32 noise
+    big = np.abs(wg) > 1e-4 * np.abs(wg).max()
+    assert big.mean() > 0.3
+    np.testing.assert_allclose(got[big], want[big], rtol=0, atol=2e-5)
+    # no step exceeds lr (plus the float32 rounding of the stored weight)
+    assert (np.abs(got - theta) <= 1e-3 + 2e-7).all()
+
+
+def test_training_learns_and_calibration_holds_recall(gpu):
+    import torch
+
+    import paper_2009_14467_amd as P
+
+    n = 20000
+    X = _features(n, seed=21)
+    t = ((X[:, 5] > 0.55) & (X[:, 0] > 8)).astype(np.uint8)
+    ctx = P.Context()
+    ctx.mlp_set(M.init_params(4), np.zeros(16), np.ones(16))
+    Xd, td = _dev(X, gpu), _dev(t, gpu)
+    ctx.mlp_fit_normalizer(Xd)
+    net = ctx.mlp_get()
+    np.testing.assert_allclose(net["mean"], X.astype(np.float64).mean(0), rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(net["std"], X.astype(np.float64).std(0), rtol=1e-4)
+    g = torch.Generator().manual_seed(0)
+    losses = []
+    for ep in range(15):
+        order = torch.randperm(n, generator=g).to(torch.int32).to(gpu)
+        losses.append(ctx.mlp_train_epoch(Xd, td, order, batch=1024, lr=2e-3, pos_weight=2.0))
+    assert losses[-1] < 0.5 * losses[0]
+    tau = ctx.mlp_calibrate(Xd, td, 0.99)
+    y = ctx.mlp_forward(Xd).cpu().numpy()
+    recall = (y[t == 1] >= tau).mean()
+    assert recall >= 0.99
+    assert (y[t == 0] >= tau).mean() < 0.3  # it does discriminate
+    assert ctx.mlp_get()["tau"] == tau
+
+
+def test_filtered_search_aligns_exactly_the_kept_pairs(gpu):
+    import paper_2009_14467_amd as P
+    from synth import workload
+
+    s = workload("tiny")
+    res, off = _dev(s.residues, gpu), _dev(s.offsets, gpu)
+    plain = P.Context(P.Params(k=6, ck_min=1))
+    want = plain.search(res, off)
+    nc = plain.discover(res, off)
+    c = plain.candidates(nc)
+    F = plain.mlp_features(res, off, nc)
+
+    ctx = P.Context(P.Params(k=6, ck_min=1, filter_mode="mlp"))
+    theta = _net(5)
+    Fh = F.cpu().numpy()
+    ctx.mlp_set(theta, Fh.mean(0), Fh.std(0) + 1e-3, tau=-np.inf)
+    got = ctx.search(res, off)  # keeps everything
+    from test_gpu_search import _compare_edges
+
+    _compare_edges(got, want)
+    y = ctx.mlp_forward(F).cpu().numpy()
+    tau = float(np.median(y))
+    ctx.mlp_set(theta, Fh.mean(0), Fh.std(0) + 1e-3, tau=tau)
+    got = ctx.search(res, off)
+    st = ctx.stats()
+    keep = y >= tau
+    assert st["n_candidates"] == nc and st["n_aligned"] == int(keep.sum())
+    kept = set(_key(c["lo"].cpu().numpy().view(np.uint32)[keep], c["hi"].cpu().numpy().view(np.uint32)[keep]))
+    sel = np.array([k in kept for k in _key(want["i"], want["j"])], bool)
+    _compare_edges(got, want[sel])
+
+
+def test_filter_needs_a_network(gpu):
+    import paper_2009_14467_amd as P
+    from synth import workload
+
+    s = workload("tiny", n_families=3)
+    ctx = P.Context(P.Params(k=6, ck_min=1, filter_mode="mlp"))
+    with pytest.raises(P.PastisError, match="network"):
+        ctx.search(_dev(s.residues, gpu), _dev(s.offsets, gpu))

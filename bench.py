@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-filter leg")
     ap.add_argument("--mlp-epochs", type=int, default=4)
+    ap.add_argument("--no-xd", action="store_true", help="skip the x-drop leg")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one 1 GiB device-to-device copy (a reference for HBM byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     return ap.parse_args()
 
@@ -90,6 +93,32 @@ def cpu_baseline(fs, lo, hi, target_s):
         "cores": oracle.num_threads(),
         "kind": "oracle",
         "sample": f"{n1} random candidate pairs of the step ({cells:.3e} cells), SW with full traceback, {dt:.1f} s",
+    }
+
+
+def xd_leg(P, args, params, res, off, n_cand):
+    """The same workload with x-drop seed extension from the stored seeds (X = 49)."""
+    import torch
+
+    ctx_xd = P.Context(P.Params(align_mode="xd", **params))
+    for _ in range(args.warmup):
+        ctx_xd.search(res, off)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xstage = [0.0] * 9
+    for _ in range(args.steps):
+        xedges = ctx_xd.search(res, off)
+        xst = ctx_xd.stats()
+        xstage = [a + b for a, b in zip(xstage, xst["ms_stage"])]
+    torch.cuda.synchronize()
+    xms = (time.perf_counter() - t0) * 1e3 / args.steps
+    return {
+        "ms_per_step": xms,
+        "pairs_per_s": n_cand / (xms * 1e-3),
+        "live_cells": float(xst["cells"]),
+        "align_ms": (xstage[5] + xstage[6]) / args.steps,
+        "align_pairs_per_s": n_cand / ((xstage[5] + xstage[6]) / args.steps * 1e-3),
+        "edges": int(xedges.size),
     }
 
 
@@ -164,6 +193,12 @@ def main():
     params = dict(WORKLOAD_PARAMS[args.workload])
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     res = torch.from_numpy(fs.residues).to(dev)
     off = torch.from_numpy(fs.offsets).to(dev)
     ctx = P.Context(P.Params(**params))
@@ -184,7 +219,12 @@ def main():
     n_cand = int(st["n_candidates"])
     pass1_ms = stage[5] / args.steps
 
-    achieved = cells * OPS_PER_SW_CELL / (pass1_ms * 1e-3) / 1e12
+    # the dominant kernel: the pass-1 length bin with the most device time
+    # (one launch per step), its own cells over its own HIP-event time
+    dom = max(st["sw_bins"], key=lambda b: b["ms"])
+    dom_name = "sw_pass1_kernel<%d, %s>" % (dom["rows_per_lane"], "true" if dom["multi_strip"] else "false")
+    achieved = dom["cells"] * OPS_PER_SW_CELL / (dom["ms"] * 1e-3) / 1e12
+    pass1_tops = cells * OPS_PER_SW_CELL / (pass1_ms * 1e-3) / 1e12
     names = ["encode", "kmers", "subs_AS", "spgemm", "schedule", "sw_pass1", "sw_pass2", "edges", "mlp_filter"]
     line = {
         "metric": METRIC,
@@ -213,40 +253,24 @@ def main():
         "stage_ms": {k: v / args.steps for k, v in zip(names, stage)},
         "align_gcups": cells / ((stage[5] + stage[6]) / args.steps * 1e-3) / 1e9,
         "roofline": {
-            "kernel": "sw_pass1_kernel (all length bins)",
+            "kernel": dom_name,
             "bound": "alu",
             "achieved": achieved,
             "peak": PEAK_INT32_TOPS,
             "unit": "Tops/s",
             "frac": achieved / PEAK_INT32_TOPS,
             "traffic": None,
+            "kernel_ms": dom["ms"],
+            "kernel_cells": dom["cells"],
+            "all_pass1_bins": {"achieved": pass1_tops, "frac": pass1_tops / PEAK_INT32_TOPS},
         },
+        "sw_bins": [dict(b, gcups=b["cells"] / max(b["ms"], 1e-9) / 1e6) for b in st["sw_bins"] if b["pairs"]],
     }
-    # the same workload with x-drop seed extension from the stored seeds (X = 49)
-    ctx_xd = P.Context(P.Params(align_mode="xd", **params))
-    for _ in range(args.warmup):
-        ctx_xd.search(res, off)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    xstage = [0.0] * 9
-    for _ in range(args.steps):
-        xedges = ctx_xd.search(res, off)
-        xst = ctx_xd.stats()
-        xstage = [a + b for a, b in zip(xstage, xst["ms_stage"])]
-    torch.cuda.synchronize()
-    xms = (time.perf_counter() - t0) * 1e3 / args.steps
-    line["xd"] = {
-        "ms_per_step": xms,
-        "pairs_per_s": n_cand / (xms * 1e-3),
-        "live_cells": float(xst["cells"]),
-        "align_ms": (xstage[5] + xstage[6]) / args.steps,
-        "align_pairs_per_s": n_cand / ((xstage[5] + xstage[6]) / args.steps * 1e-3),
-        "edges": int(xedges.size),
-    }
+    if not args.no_xd:
+        line["xd"] = xd_leg(P, args, params, res, off, n_cand)
     if not args.no_mlp:
         line["mlp_filter"] = mlp_leg(P, args, params, over, res, off, edges, ms_step)
     if not args.no_cpu_baseline:
-
         c = ctx.candidates(n_cand)
         lo = c["lo"].cpu().numpy().view(np.uint32)
         hi = c["hi"].cpu().numpy().view(np.uint32)

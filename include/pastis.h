@@ -126,6 +126,16 @@ typedef struct pastis_run_stats {
                            k-mers, S formation, SpGEMM, schedule, alignment pass 1,
                            alignment pass 2, identity/coverage cut and edges, learned
                            pre-alignment filter */
+    /* Smith-Waterman pass 1 per length bin (one kernel launch each): rows per
+     * lane R, whether the bin's pairs span several strips of 64 * R rows, and
+     * the bin's pairs, DP cells and device time (HIP events around the launch,
+     * on the call's stream).  sw_bins = 0 after an x-drop call. */
+    int32_t sw_bins;
+    int32_t sw_bin_rows[16];
+    int32_t sw_bin_multi[16];
+    int64_t sw_bin_pairs[16];
+    int64_t sw_bin_cells[16];
+    double sw_bin_ms[16];
 } pastis_run_stats;
 
 typedef struct pastis_ctx pastis_ctx;

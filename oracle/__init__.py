@@ -103,6 +103,9 @@ def lib():
         L.orc_candidates_index.argtypes = [_u8p, _i64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                            ctypes.c_int, _i64p, ctypes.c_int64, ctypes.c_int64, _u32p, _u32p,
                                            _u32p, _u32p, _u32p]
+        L.orc_pair_counts.restype = ctypes.c_int64
+        L.orc_pair_counts.argtypes = [_u8p, _i64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _u32p,
+                                      _u32p, ctypes.c_int64, _u32p, _u32p, _u32p]
         aln_p = np.ctypeslib.ndpointer(dtype=ALN_DTYPE, flags="C_CONTIGUOUS")
         L.orc_sw.restype = None
         L.orc_sw.argtypes = [_u8p, ctypes.c_int, _u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, aln_p]
@@ -213,6 +216,27 @@ def candidates(codes, offsets, k: int, ck_min: int = 1, n_subs: int = 0, alpha: 
         if got >= 0:
             return dict(lo=lo[:got], hi=hi[:got], count=cnt[:got], seed1=s1[:got], seed2=s2[:got])
         cap *= 4
+
+
+def pair_counts(codes, offsets, lo, hi, k: int, n_subs: int = 0, alpha: int = 20) -> dict:
+    """Shared (substitute) k-mer count and seeds of the listed pairs lo < hi,
+    as candidate discovery defines them, without the threshold (count 0 when
+    the pair shares nothing).  Needs only the listed pairs' sequences."""
+    codes = np.ascontiguousarray(codes, dtype=np.uint8)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    lo = np.ascontiguousarray(lo, dtype=np.uint32)
+    hi = np.ascontiguousarray(hi, dtype=np.uint32)
+    if codes.size == 0:
+        codes = np.zeros(1, np.uint8)
+    m = lo.size
+    cnt = np.zeros(max(m, 1), np.uint32)
+    s1 = np.zeros(max(m, 1), np.uint32)
+    s2 = np.zeros(max(m, 1), np.uint32)
+    got = lib().orc_pair_counts(codes, offsets, offsets.size - 1, k, n_subs, alpha, lo if m else np.zeros(1, np.uint32),
+                                hi if m else np.zeros(1, np.uint32), m, cnt, s1, s2)
+    if got < 0:
+        raise ValueError("pairs must satisfy lo < hi < n")
+    return dict(count=cnt[:m], seed1=s1[:m], seed2=s2[:m])
 
 
 # ---------------------------------------------------------------- alignment

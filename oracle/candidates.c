@@ -375,3 +375,139 @@ int orc_num_threads(void) {
     return 1;
 #endif
 }
+
+/* Row i of A S as a list sorted by substitute id: for every k-mer s reached
+ * from a k-mer of i, the closest such k-mer's position (smaller position on
+ * equal distance).  Exact mode (n_subs = 0) gives K(i) itself. */
+static int64_t as_row(const kmer_sets *ks, int64_t i, int k, int n_subs, int alpha, asent **buf, int64_t *cap) {
+    int64_t kb = ks->off[i], ke = ks->off[i + 1];
+    int64_t need = (ke - kb) * (int64_t)(n_subs + 1);
+    if (need > *cap) {
+        *cap = need;
+        *buf = (asent *)realloc(*buf, (size_t)(need > 0 ? need : 1) * sizeof(asent));
+    }
+    asent *as = *buf;
+    int64_t *nb_id = (int64_t *)malloc((size_t)(n_subs + 1) * sizeof(int64_t));
+    int32_t *nb_d = (int32_t *)malloc((size_t)(n_subs + 1) * sizeof(int32_t));
+    int64_t na = 0;
+    for (int64_t q = kb; q < ke; ++q) {
+        as[na].s = ks->id[q];
+        as[na].dist = 0;
+        as[na].pos = ks->pos[q];
+        ++na;
+        if (n_subs > 0) {
+            int got = orc_subk_bounded(ks->id[q], k, n_subs, alpha, nb_id, nb_d);
+            for (int g = 0; g < got; ++g) {
+                as[na].s = nb_id[g];
+                as[na].dist = nb_d[g];
+                as[na].pos = ks->pos[q];
+                ++na;
+            }
+        }
+    }
+    free(nb_id);
+    free(nb_d);
+    qsort(as, (size_t)na, sizeof(asent), cmp_asent);
+    int64_t w = 0;
+    for (int64_t q = 0; q < na; ++q)
+        if (q == 0 || as[q].s != as[q - 1].s) as[w++] = as[q];
+    return w;
+}
+
+int64_t orc_pair_counts(const uint8_t *codes, const int64_t *offsets, int64_t n, int k, int n_subs, int alpha,
+                        const uint32_t *lo, const uint32_t *hi, int64_t npairs, uint32_t *count, uint32_t *seed1,
+                        uint32_t *seed2) {
+    /* only the sequences of the listed pairs are needed */
+    unsigned char *used = (unsigned char *)calloc((size_t)(n > 0 ? n : 1), 1);
+    for (int64_t q = 0; q < npairs; ++q) {
+        if (lo[q] >= hi[q] || hi[q] >= (uint64_t)n) {
+            free(used);
+            return -1;
+        }
+        used[lo[q]] = used[hi[q]] = 1;
+    }
+    int64_t nu = 0;
+    int64_t *slot = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i) slot[i] = used[i] ? nu++ : -1;
+    int64_t *seqs = (int64_t *)malloc((size_t)(nu > 0 ? nu : 1) * sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i)
+        if (used[i]) seqs[slot[i]] = i;
+    /* k-mer sets of the used sequences only (others left empty) */
+    kmer_sets ks;
+    ks.off = (int64_t *)malloc((size_t)(n + 1) * sizeof(int64_t));
+    ks.off[0] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t len = offsets[i + 1] - offsets[i];
+        ks.off[i + 1] = ks.off[i] + ((used[i] && len >= k) ? len - k + 1 : 0);
+    }
+    int64_t tot = ks.off[n] > 0 ? ks.off[n] : 1;
+    ks.id = (int64_t *)malloc((size_t)tot * sizeof(int64_t));
+    ks.pos = (int32_t *)malloc((size_t)tot * sizeof(int32_t));
+    int64_t *kcount = (int64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t u = 0; u < nu; ++u) {
+        int64_t i = seqs[u];
+        kcount[i] = orc_kmer_set(codes + offsets[i], offsets[i + 1] - offsets[i], k, ks.id + ks.off[i],
+                                 ks.pos + ks.off[i]);
+    }
+    /* the rows of A S of the used sequences */
+    asent **rows = (asent **)calloc((size_t)(nu > 0 ? nu : 1), sizeof(asent *));
+    int64_t *rlen = (int64_t *)calloc((size_t)(nu > 0 ? nu : 1), sizeof(int64_t));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t u = 0; u < nu; ++u) {
+        int64_t i = seqs[u];
+        int64_t off2[2] = {ks.off[i], ks.off[i] + kcount[i]};
+        kmer_sets view;
+        view.off = off2;
+        view.id = ks.id;
+        view.pos = ks.pos;
+        asent *buf = NULL;
+        int64_t cap = 0;
+        rlen[u] = as_row(&view, 0, k, n_subs, alpha, &buf, &cap);
+        rows[u] = buf;
+    }
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < npairs; ++q) {
+        uint32_t best_c = 0, best_s1 = NO_SEED, best_s2 = NO_SEED;
+        for (int dir = 0; dir < 2; ++dir) {
+            uint32_t r = dir == 0 ? lo[q] : hi[q], c = dir == 0 ? hi[q] : lo[q];
+            const asent *ar = rows[slot[r]];
+            int64_t na = rlen[slot[r]];
+            int64_t b = ks.off[c], be = ks.off[c] + kcount[c];
+            int64_t a = 0;
+            uint32_t cnt = 0, s1 = NO_SEED, s2 = NO_SEED;
+            /* c(r -> c): the k-mers s of c with (A S)_{r,s} defined */
+            while (a < na && b < be) {
+                if (ar[a].s < ks.id[b]) {
+                    ++a;
+                } else if (ar[a].s > ks.id[b]) {
+                    ++b;
+                } else {
+                    ++cnt;
+                    seed_insert(seed_key(r, c, ar[a].pos, ks.pos[b]), &s1, &s2);
+                    ++a;
+                    ++b;
+                }
+            }
+            if (dir == 0 || cnt > best_c) {
+                best_c = cnt;
+                best_s1 = s1;
+                best_s2 = s2;
+            }
+        }
+        count[q] = best_c;
+        seed1[q] = best_s1;
+        seed2[q] = best_s2;
+    }
+    for (int64_t u = 0; u < nu; ++u) free(rows[u]);
+    free(rows);
+    free(rlen);
+    free(kcount);
+    free(ks.off);
+    free(ks.id);
+    free(ks.pos);
+    free(seqs);
+    free(slot);
+    free(used);
+    return npairs;
+}

@@ -69,6 +69,13 @@ int64_t orc_candidates_bruteforce(const uint8_t *codes, const int64_t *offsets, 
 int64_t orc_candidates_index(const uint8_t *codes, const int64_t *offsets, int64_t n, int k, int n_subs,
                              int alpha, int ck_min, const int64_t *rows, int64_t nrows, int64_t cap, uint32_t *lo,
                              uint32_t *hi, uint32_t *count, uint32_t *seed1, uint32_t *seed2);
+/* The same quantities for a given list of pairs lo < hi only (both
+ * directions of the substitute product, the larger kept, lo -> hi on a tie):
+ * count = 0 when the pair shares nothing.  Needs only the sequences of the
+ * pairs, so it runs at any set size.  Returns npairs, or -1 on a bad pair. */
+int64_t orc_pair_counts(const uint8_t *codes, const int64_t *offsets, int64_t n, int k, int n_subs, int alpha,
+                        const uint32_t *lo, const uint32_t *hi, int64_t npairs, uint32_t *count, uint32_t *seed1,
+                        uint32_t *seed2);
 
 /* ---- alignment (Section IV-E) and similarity filter (Section IV-F) ---- */
 typedef struct {

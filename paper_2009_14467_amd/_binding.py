@@ -98,6 +98,12 @@ class _Stats(ctypes.Structure):
         ("int32_pairs", ctypes.c_int64),
         ("ms_total", ctypes.c_double),
         ("ms_stage", ctypes.c_double * 9),
+        ("sw_bins", ctypes.c_int32),
+        ("sw_bin_rows", ctypes.c_int32 * 16),
+        ("sw_bin_multi", ctypes.c_int32 * 16),
+        ("sw_bin_pairs", ctypes.c_int64 * 16),
+        ("sw_bin_cells", ctypes.c_int64 * 16),
+        ("sw_bin_ms", ctypes.c_double * 16),
     ]
 
 
@@ -250,8 +256,15 @@ class Context:
     def stats(self) -> dict:
         s = _Stats()
         self._check(lib().pastis_stats(self._ctx, ctypes.byref(s)))
-        out = {f: getattr(s, f) for f, _ in _Stats._fields_ if f != "ms_stage"}
+        arrays = ("ms_stage", "sw_bin_rows", "sw_bin_multi", "sw_bin_pairs", "sw_bin_cells", "sw_bin_ms")
+        out = {f: getattr(s, f) for f, _ in _Stats._fields_ if f not in arrays}
         out["ms_stage"] = list(s.ms_stage)
+        nb = s.sw_bins
+        out["sw_bins"] = [
+            {"rows_per_lane": s.sw_bin_rows[b], "multi_strip": bool(s.sw_bin_multi[b]), "pairs": s.sw_bin_pairs[b],
+             "cells": s.sw_bin_cells[b], "ms": s.sw_bin_ms[b]}
+            for b in range(nb)
+        ]
         return out
 
     def encode(self, residues, stream=None):

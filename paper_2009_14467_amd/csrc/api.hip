@@ -185,7 +185,7 @@ pastis_status make_sw_work(pastis_ctx *ctx, int64_t npairs, int max_len, SwWork 
     void *p = nullptr;
     PASTIS_TRY(ensure(ctx, kBufBinOf, (size_t)std::max<int64_t>(npairs, 1), &p));
     wk.bin_of = (int8_t *)p;
-    PASTIS_TRY(ensure(ctx, kBufBinMeta, sizeof(int) * 160 + sizeof(unsigned long long) * 8, &p));
+    PASTIS_TRY(ensure(ctx, kBufBinMeta, sizeof(int) * 160 + sizeof(unsigned long long) * kNumCounters, &p));
     wk.counts = (int *)p;
     wk.counters = (unsigned long long *)((int *)p + 160);
     wk.starts = wk.counts + 32;
@@ -226,7 +226,8 @@ pastis_status align_core(pastis_ctx *ctx, const Staged &st, const uint8_t *codes
     PASTIS_TRY(ensure(ctx, kBufPass1, sizeof(SwPass1Out) * (size_t)npairs, &p1));
     SwWork wk;
     PASTIS_TRY(make_sw_work(ctx, npairs, st.max_len, wk));
-    HIP_TRY(ctx, fill<unsigned long long>(wk.counters, 4, 0ull, s), "reset");
+    HIP_TRY(ctx, fill<unsigned long long>(wk.counters, kNumCounters, 0ull, s), "reset");
+    ctx->stats.sw_bins = 0;
     // traceback statistics: every pair on request; none for the normalised
     // score weight; otherwise only where the coverage cut can still hold
     const int stats_mode = P.full_records ? 1 : (P.weight_mode == PASTIS_WEIGHT_NS ? 2 : 0);
@@ -246,10 +247,24 @@ pastis_status align_core(pastis_ctx *ctx, const Staged &st, const uint8_t *codes
                           n_redo, (int *)ring, wk.counters, s),
                 "xd kernels");
     }
-    unsigned long long c[4];
+    unsigned long long c[kNumCounters];
     PASTIS_TRY(read_device(ctx, wk.counters, c, sizeof(c), s));
     ctx->stats.cells = (int64_t)c[0];
     ctx->stats.stats_pass_pairs = (int64_t)c[1];
+    if (P.align_mode == PASTIS_ALIGN_SW) {
+        int starts[33];  // pass-1 bin bounds (the pass-2 binning reuses the counts)
+        PASTIS_TRY(read_device(ctx, wk.starts, starts, sizeof(starts), s));
+        const int nb = sw_num_bins();
+        ctx->stats.sw_bins = nb;
+        for (int b = 0; b < nb; ++b) {
+            sw_bin_shape(b, &ctx->stats.sw_bin_rows[b], &ctx->stats.sw_bin_multi[b]);
+            ctx->stats.sw_bin_pairs[b] = starts[b + 1] - starts[b];
+            ctx->stats.sw_bin_cells[b] = (int64_t)c[kCounterBinCells + b];
+            float ms = 0.f;
+            HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->bin_ev[2 * b], ctx->bin_ev[2 * b + 1]), "event time");
+            ctx->stats.sw_bin_ms[b] = ms;
+        }
+    }
     return PASTIS_OK;
 }
 
@@ -329,6 +344,12 @@ pastis_status pastis_create(const pastis_params *p, int device, pastis_ctx **out
             return PASTIS_E_DEVICE;
         }
     }
+    for (auto &ev : ctx->bin_ev) {
+        if (hipEventCreate(&ev) != hipSuccess) {
+            pastis_destroy(ctx);
+            return PASTIS_E_DEVICE;
+        }
+    }
     *out = ctx;
     return PASTIS_OK;
 }
@@ -342,6 +363,8 @@ void pastis_destroy(pastis_ctx *ctx) {
     if (ctx->d_blosum) (void)hipFree(ctx->d_blosum);
     if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
     for (auto &ev : ctx->ev)
+        if (ev) (void)hipEventDestroy(ev);
+    for (auto &ev : ctx->bin_ev)
         if (ev) (void)hipEventDestroy(ev);
     delete ctx;
 }

@@ -106,6 +106,7 @@ struct pastis_ctx {
     void *h_pinned = nullptr;
     size_t h_pinned_bytes = 0;
     hipEvent_t ev[2 * 9] = {};
+    hipEvent_t bin_ev[2 * 16] = {};  // around each SW pass-1 bin launch
     bool ev_used[9] = {};
 };
 
@@ -169,8 +170,13 @@ struct SwPass1Out {
 // bin starts for the two passes, a cursor, the two binned index lists, and
 // boundary-row scratch for pairs taller than one strip (6 planes of max_len
 // ints per wave, for sw_scratch_waves() waves).
+// counters: [0] cells, [1] statistics-pass pairs, [2] their cells,
+// [kCounterBinCells + b] pass-1 cells of SW bin b
+constexpr int kCounterBinCells = 8;
+constexpr int kNumCounters = kCounterBinCells + 16;
+
 struct SwWork {
-    unsigned long long *counters;  // [0] cells, [1] statistics-pass pairs, [2] their cells
+    unsigned long long *counters;
     int8_t *bin_of;
     int *counts, *starts, *starts2, *cursor;
     int *idx, *idx2;
@@ -178,6 +184,7 @@ struct SwWork {
     int64_t scratch_per_wave;
 };
 int sw_num_bins();
+void sw_bin_shape(int bin, int32_t *rows_per_lane, int32_t *multi);
 int64_t xd_global_waves();
 size_t xd_ring_bytes_per_wave();
 // XD alignment of every pair; bands wider than the LDS ring are redone from

@@ -9,8 +9,9 @@
 // lane once per step with a DPP wavefront shift, and the column residue moves
 // with it (lane 0 takes it from a register chunk of b via readlane).  Pairs
 // whose shorter side needs more than one strip pass the strip's bottom row
-// through a per-wave global buffer.  R is chosen per pair (bins R = 1..8, and
-// a multi-strip bin), so few lanes hold padding rows.
+// through a per-wave global buffer.  R is chosen per pair (one-strip bins
+// R = 1..8; multi-strip bins R = 5..8 with the fewest strips of at most 512
+// rows), so few lanes hold padding rows.
 //
 // Scores.  A per-lane profile in LDS holds, for every column residue code, the
 // R int8 scores of the lane's rows; one LDS load per step serves R cells and
@@ -43,8 +44,9 @@ constexpr int kNeg = -(1 << 28);
 constexpr int kWavesPerBlock = 4;
 constexpr int kProfCodes = kAlpha + 1;  // 24 residues + the pad code
 constexpr int kSingleBins = 8;          // bins 0..7: one strip of 64 * (bin + 1) rows
-constexpr int kMultiBin = 8;            // longer: strips of 512 rows
-constexpr int kNumBins = 9;
+constexpr int kMultiBin = 8;            // bins 8..11: several strips of 64 * R rows, R = bin - 3
+constexpr int kMultiMinR = 5;
+constexpr int kNumBins = 12;
 constexpr int kDppWaveShr1 = 0x138;
 
 // lane l receives lane l-1's value; lane 0 receives `lane0`
@@ -267,26 +269,37 @@ __global__ __launch_bounds__(256) void sw_pass1_kernel(const uint8_t *__restrict
 
 // ---------------------------------------------------------------- between the passes
 
+// Rows up to 512 take one strip of 64 * R rows with the smallest R; longer
+// ones take the fewest strips of at most 512 rows, with R as small as that
+// strip count allows (so padding stays under one row per lane and strip).
 __device__ __forceinline__ int rows_bin(int rows) {
     if (rows <= 0) return 0;
     const int r = (rows + kWave - 1) / kWave;
-    return r <= kSingleBins ? r - 1 : kMultiBin;
+    if (r <= kSingleBins) return r - 1;
+    const int strips = (rows + kWave * kSingleBins - 1) / (kWave * kSingleBins);
+    const int rm = (rows + kWave * strips - 1) / (kWave * strips);  // in [5, 8]
+    return kMultiBin + rm - kMultiMinR;
 }
 
-// Bins by rows per lane; counters[0] += DP cells of the pairs.
+// Bins by rows per lane; counters[0] += DP cells of the pairs, and
+// counters[kCounterBinCells + bin] += those of each bin.
 __global__ void sw_bin1_kernel(const PairDesc *__restrict__ pairs, int64_t npairs, int8_t *__restrict__ bin_of,
                                unsigned long long *__restrict__ counters) {
-    __shared__ unsigned long long cells;
-    if (threadIdx.x == 0) cells = 0;
+    __shared__ unsigned long long cells[kNumBins];
+    if (threadIdx.x < kNumBins) cells[threadIdx.x] = 0;
     __syncthreads();
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q < npairs) {
         const PairDesc pd = pairs[q];
-        bin_of[q] = (int8_t)rows_bin(pd.la);
-        atomicAdd(&cells, (unsigned long long)pd.la * (unsigned long long)pd.lb);
+        const int bin = rows_bin(pd.la);
+        bin_of[q] = (int8_t)bin;
+        atomicAdd(&cells[bin], (unsigned long long)pd.la * (unsigned long long)pd.lb);
     }
     __syncthreads();
-    if (threadIdx.x == 0 && cells) atomicAdd(&counters[0], cells);
+    if (threadIdx.x < kNumBins && cells[threadIdx.x]) {
+        atomicAdd(&counters[0], cells[threadIdx.x]);
+        atomicAdd(&counters[kCounterBinCells + threadIdx.x], cells[threadIdx.x]);
+    }
 }
 
 // Records of pairs that need no statistics pass are final here; the others
@@ -516,7 +529,7 @@ template <int R>
 hipError_t launch_p1(int bin, int blocks, const uint8_t *codes, const PairDesc *pairs, const int *idx,
                      const int *starts, const int8_t *blosum, int go_ge, int ge, SwPass1Out *p1, int *scratch,
                      int64_t spw, hipStream_t s) {
-    if (bin == kMultiBin)
+    if (bin >= kMultiBin)
         sw_pass1_kernel<R, true><<<blocks, 256, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, p1, scratch,
                                                         spw);
     else
@@ -529,7 +542,7 @@ template <int R>
 hipError_t launch_p2(int bin, int blocks, const uint8_t *codes, const PairDesc *pairs, const int *idx,
                      const int *starts, const int8_t *blosum, int go_ge, int ge, int cov, int id,
                      const SwPass1Out *p1, pastis_pair_record *out, int *scratch, int64_t spw, hipStream_t s) {
-    if (bin == kMultiBin)
+    if (bin >= kMultiBin)
         sw_pass2_kernel<R, true><<<blocks, 256, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, cov, id, p1,
                                                         out, scratch, spw);
     else
@@ -543,20 +556,25 @@ typedef hipError_t (*P1Fn)(int, int, const uint8_t *, const PairDesc *, const in
 typedef hipError_t (*P2Fn)(int, int, const uint8_t *, const PairDesc *, const int *, const int *, const int8_t *, int,
                            int, int, int, const SwPass1Out *, pastis_pair_record *, int *, int64_t, hipStream_t);
 
-const P1Fn kP1[kNumBins] = {launch_p1<1>, launch_p1<2>, launch_p1<3>, launch_p1<4>, launch_p1<5>,
-                            launch_p1<6>, launch_p1<7>, launch_p1<8>, launch_p1<8>};
-const P2Fn kP2[kNumBins] = {launch_p2<1>, launch_p2<2>, launch_p2<3>, launch_p2<4>, launch_p2<5>,
-                            launch_p2<6>, launch_p2<7>, launch_p2<8>, launch_p2<8>};
+const P1Fn kP1[kNumBins] = {launch_p1<1>, launch_p1<2>, launch_p1<3>, launch_p1<4>, launch_p1<5>, launch_p1<6>,
+                            launch_p1<7>, launch_p1<8>, launch_p1<5>, launch_p1<6>, launch_p1<7>, launch_p1<8>};
+const P2Fn kP2[kNumBins] = {launch_p2<1>, launch_p2<2>, launch_p2<3>, launch_p2<4>, launch_p2<5>, launch_p2<6>,
+                            launch_p2<7>, launch_p2<8>, launch_p2<5>, launch_p2<6>, launch_p2<7>, launch_p2<8>};
 
 }  // namespace
 
 int sw_num_bins() { return kNumBins; }
 
+void sw_bin_shape(int bin, int32_t *rows_per_lane, int32_t *multi) {
+    *multi = bin >= kMultiBin;
+    *rows_per_lane = bin >= kMultiBin ? bin - kMultiBin + kMultiMinR : bin + 1;
+}
+
 // Blocks per bin launch: enough resident waves to fill 256 CUs for the bin's
 // LDS footprint (the grid-stride loop reads the bin size on the device).
 static int blocks_for_bin(int bin) { return bin < 4 ? 256 * 6 : 256 * 3; }
 
-// Only the multi-strip bin uses the boundary buffers.
+// Only the multi-strip bins use the boundary buffers.
 int64_t sw_scratch_waves() { return (int64_t)blocks_for_bin(kMultiBin) * kWavesPerBlock; }
 
 hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pairs, int64_t npairs,
@@ -573,9 +591,11 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
     if ((e = stage_end(ctx, kStSched, s)) != hipSuccess || (e = stage_begin(ctx, kStAlign1, s)) != hipSuccess)
         return e;
     for (int bin = 0; bin < kNumBins; ++bin) {
+        if ((e = hipEventRecord(ctx->bin_ev[2 * bin], s)) != hipSuccess) return e;
         e = kP1[bin](bin, blocks_for_bin(bin), codes, pairs, wk.idx, wk.starts, blosum, go_ge, ge, p1, wk.scratch,
                      wk.scratch_per_wave, s);
         if (e != hipSuccess) return e;
+        if ((e = hipEventRecord(ctx->bin_ev[2 * bin + 1], s)) != hipSuccess) return e;
     }
     if ((e = stage_end(ctx, kStAlign1, s)) != hipSuccess || (e = stage_begin(ctx, kStAlign2, s)) != hipSuccess)
         return e;

@@ -63,10 +63,11 @@ def initial_params(seed: int = 0) -> np.ndarray:
 
 
 def train(params: Params, residues, offsets, epochs: int = 4, batch: int = 8192, lr: float = 2e-3,
-          pos_weight: float = 8.0, target_recall: float = 0.995, heldout: float = 0.2, seed: int = 0,
+          pos_weight: float | None = None, target_recall: float = 0.995, heldout: float = 0.2, seed: int = 0,
           device: int = 0) -> TrainedFilter:
     """Train a filter on the candidates of one sequence set (device tensors)
-    and calibrate its threshold on a held-out fraction of them."""
+    and calibrate its threshold on a held-out fraction of them.  The
+    positive class weight defaults to the negative / positive ratio."""
     import torch
 
     t0 = time.perf_counter()
@@ -80,6 +81,9 @@ def train(params: Params, residues, offsets, epochs: int = 4, batch: int = 8192,
     n_hold = max(16, int(heldout * n))
     hold = perm[:n_hold].to(X.device, torch.int64)
     train_idx = perm[n_hold:]
+    if pos_weight is None:
+        n_pos = max(int(y.sum()), 1)
+        pos_weight = float(n - n_pos) / n_pos
     ctx.mlp_set(initial_params(seed), np.zeros(MLP_FEATURES), np.ones(MLP_FEATURES), 0.0)
     ctx.mlp_fit_normalizer(X[train_idx.to(X.device, torch.int64)].contiguous())
     losses = []

@@ -126,3 +126,36 @@ def test_sw_rejects_bad_input(gpu):
         _gpu_records(gpu, s, np.array([0], np.uint32), np.array([2], np.uint32))
     with pytest.raises(P.PastisError, match="INVAL"):
         _gpu_records(gpu, s, np.array([1], np.uint32), np.array([1], np.uint32))
+
+
+def test_sw_every_length_bin(gpu, orc):
+    """One pair per side of every bin boundary (64 R rows in one strip; 2, 3
+    and 4 strips of 64 R rows, R = 5..8), against the oracle."""
+    from synth.families import FamilySet
+
+    rng = np.random.default_rng(5)
+    lens = [1, 64, 65, 128, 129, 448, 449, 512, 513, 640, 641, 768, 769, 896, 897, 1024, 1025, 1152, 1153, 1344,
+            1345, 1536, 1537, 1792, 2048, 2049, 2500]
+    seqs = []
+    for L in lens:
+        a = rng.integers(0, 20, L)
+        b = a.copy()
+        sub = rng.random(L) < 0.25
+        b[sub] = rng.integers(0, 20, int(sub.sum()))
+        b = np.concatenate([rng.integers(0, 20, 7), b, rng.integers(0, 20, 11)])
+        seqs += [a, b]
+    letters = np.frombuffer(b"ARNDCQEGHILKMFPSTWYV", np.uint8)
+    res = np.concatenate([letters[x] for x in seqs]).astype(np.uint8)
+    off = np.zeros(len(seqs) + 1, np.int64)
+    np.cumsum([len(x) for x in seqs], out=off[1:])
+    s = FamilySet(res, off, np.zeros(len(seqs), np.int32), {})
+    codes = orc.encode(s.residues)
+    lo = np.arange(0, len(seqs), 2, dtype=np.uint32)
+    hi = lo + 1
+    want = orc.align_pairs(codes, s.offsets, lo, hi, mode="sw")
+    for full in (True, False):
+        got = _gpu_records(gpu, s, lo, hi, full_records=full)
+        if full:
+            _compare(got, want)
+        else:
+            _compare(got, want, ("score", "end_a", "end_b", "passed", "swapped", "cells"))

@@ -158,3 +158,22 @@ def test_family_workload_candidates_are_mostly_family_pairs(orc):
     same = s.labels[c["lo"]] == s.labels[c["hi"]]
     assert same.mean() > 0.9
     assert (c["lo"] < c["hi"]).all() and (c["count"] >= 1).all()
+
+
+@pytest.mark.parametrize("m,ck", [(0, 1), (6, 2)])
+def test_pair_counts_match_python_definition_on_every_pair(orc, m, ck):
+    """The per-pair route (used at full size on sampled pairs) against the
+    plain-Python definition over all pairs of a small random set."""
+    rng = np.random.default_rng(24 + m)
+    codes, off = _random_set(rng, 14, 0, 25, [0, 15, 16, 4, 7])
+    want = _py_subs(orc, codes, off, 3, m, ck) if m else _as_tuples(orc.candidates(codes, off, 3, ck_min=ck,
+                                                                                    method="brute"))
+    lo, hi = np.triu_indices(off.size - 1, 1)
+    p = orc.pair_counts(codes, off, lo, hi, 3, n_subs=m)
+    keep = p["count"] >= ck
+    got = _as_tuples(dict(lo=lo[keep], hi=hi[keep], count=p["count"][keep], seed1=p["seed1"][keep],
+                          seed2=p["seed2"][keep]))
+    assert got == want
+    assert (p["count"][~keep] < ck).all()
+    with pytest.raises(ValueError):
+        orc.pair_counts(codes, off, [3], [3], 3)

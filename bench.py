@@ -250,6 +250,9 @@ def main():
         "cells": cells,
         "edges": int(edges.size),
         "stats_pass_pairs": int(st["stats_pass_pairs"]),
+        "stats_pass_cells": int(st["stats_pass_cells"]),
+        "bound_pass_pairs": int(st["bound_pass_pairs"]),
+        "bound_pass_cells": int(st["bound_pass_cells"]),
         "stage_ms": {k: v / args.steps for k, v in zip(names, stage)},
         "align_gcups": cells / ((stage[5] + stage[6]) / args.steps * 1e-3) / 1e9,
         "roofline": {

@@ -131,11 +131,16 @@ typedef struct pastis_run_stats {
      * the bin's pairs, DP cells and device time (HIP events around the launch,
      * on the call's stream).  sw_bins = 0 after an x-drop call. */
     int32_t sw_bins;
-    int32_t sw_bin_rows[16];
-    int32_t sw_bin_multi[16];
-    int64_t sw_bin_pairs[16];
-    int64_t sw_bin_cells[16];
-    double sw_bin_ms[16];
+    int32_t sw_bin_rows[32];
+    int32_t sw_bin_multi[32];
+    int64_t sw_bin_pairs[32];
+    int64_t sw_bin_cells[32];
+    double sw_bin_ms[32];
+    /* Smith-Waterman pairs (and their end-rectangle cells) that took the
+     * start-bound pass, and cells of the statistics pass. */
+    int64_t bound_pass_pairs;
+    int64_t bound_pass_cells;
+    int64_t stats_pass_cells;
 } pastis_run_stats;
 
 typedef struct pastis_ctx pastis_ctx;

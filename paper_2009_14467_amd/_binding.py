@@ -99,11 +99,14 @@ class _Stats(ctypes.Structure):
         ("ms_total", ctypes.c_double),
         ("ms_stage", ctypes.c_double * 9),
         ("sw_bins", ctypes.c_int32),
-        ("sw_bin_rows", ctypes.c_int32 * 16),
-        ("sw_bin_multi", ctypes.c_int32 * 16),
-        ("sw_bin_pairs", ctypes.c_int64 * 16),
-        ("sw_bin_cells", ctypes.c_int64 * 16),
-        ("sw_bin_ms", ctypes.c_double * 16),
+        ("sw_bin_rows", ctypes.c_int32 * 32),
+        ("sw_bin_multi", ctypes.c_int32 * 32),
+        ("sw_bin_pairs", ctypes.c_int64 * 32),
+        ("sw_bin_cells", ctypes.c_int64 * 32),
+        ("sw_bin_ms", ctypes.c_double * 32),
+        ("bound_pass_pairs", ctypes.c_int64),
+        ("bound_pass_cells", ctypes.c_int64),
+        ("stats_pass_cells", ctypes.c_int64),
     ]
 
 

@@ -251,6 +251,9 @@ pastis_status align_core(pastis_ctx *ctx, const Staged &st, const uint8_t *codes
     PASTIS_TRY(read_device(ctx, wk.counters, c, sizeof(c), s));
     ctx->stats.cells = (int64_t)c[0];
     ctx->stats.stats_pass_pairs = (int64_t)c[1];
+    ctx->stats.stats_pass_cells = (int64_t)c[2];
+    ctx->stats.bound_pass_pairs = (int64_t)c[3];
+    ctx->stats.bound_pass_cells = (int64_t)c[4];
     if (P.align_mode == PASTIS_ALIGN_SW) {
         int starts[33];  // pass-1 bin bounds (the pass-2 binning reuses the counts)
         PASTIS_TRY(read_device(ctx, wk.starts, starts, sizeof(starts), s));

@@ -106,7 +106,7 @@ struct pastis_ctx {
     void *h_pinned = nullptr;
     size_t h_pinned_bytes = 0;
     hipEvent_t ev[2 * 9] = {};
-    hipEvent_t bin_ev[2 * 16] = {};  // around each SW pass-1 bin launch
+    hipEvent_t bin_ev[2 * 32] = {};  // around each SW pass-1 bin launch
     bool ev_used[9] = {};
 };
 
@@ -173,7 +173,7 @@ struct SwPass1Out {
 // counters: [0] cells, [1] statistics-pass pairs, [2] their cells,
 // [kCounterBinCells + b] pass-1 cells of SW bin b
 constexpr int kCounterBinCells = 8;
-constexpr int kNumCounters = kCounterBinCells + 16;
+constexpr int kNumCounters = kCounterBinCells + 32;
 
 struct SwWork {
     unsigned long long *counters;

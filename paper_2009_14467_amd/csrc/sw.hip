@@ -10,8 +10,8 @@
 // with it (lane 0 takes it from a register chunk of b via readlane).  Pairs
 // whose shorter side needs more than one strip pass the strip's bottom row
 // through a per-wave global buffer.  R is chosen per pair (one-strip bins
-// R = 1..8; multi-strip bins R = 5..8 with the fewest strips of at most 512
-// rows), so few lanes hold padding rows.
+// R = 1..16; multi-strip bins R = 9..16 with the fewest strips of at most
+// 1024 rows), so few lanes hold padding rows.
 //
 // Scores.  A per-lane profile in LDS holds, for every column residue code, the
 // R int8 scores of the lane's rows; one LDS load per step serves R cells and
@@ -28,6 +28,7 @@
 // extension before opening; a zero diagonal predecessor starts a new path), so
 // by induction the end cell holds the traceback's statistics.  The strip rows
 // are padded at the top so the end cell is always row R-1 of lane 63.
+#include <algorithm>
 #include <type_traits>
 
 #include "internal.hpp"
@@ -43,10 +44,16 @@ constexpr int kWave = 64;
 constexpr int kNeg = -(1 << 28);
 constexpr int kWavesPerBlock = 4;
 constexpr int kProfCodes = kAlpha + 1;  // 24 residues + the pad code
-constexpr int kSingleBins = 8;          // bins 0..7: one strip of 64 * (bin + 1) rows
-constexpr int kMultiBin = 8;            // bins 8..11: several strips of 64 * R rows, R = bin - 3
-constexpr int kMultiMinR = 5;
-constexpr int kNumBins = 12;
+constexpr int kMaxR = 16;               // rows per lane
+constexpr int kSingleBins = kMaxR;      // bins 0..15: one strip of 64 * (bin + 1) rows
+constexpr int kMultiBin = kSingleBins;  // bins 16..23: several strips of 64 * R rows, R = bin - 7
+constexpr int kMultiMinR = kMaxR / 2 + 1;
+constexpr int kNumBins = kMultiBin + kMaxR - kMultiMinR + 1;
+static_assert(kNumBins <= 32, "bin tables hold 32 entries");
+
+__host__ __device__ constexpr int rows_of_bin(int bin) {
+    return bin >= kMultiBin ? bin - kMultiBin + kMultiMinR : bin + 1;
+}
 constexpr int kDppWaveShr1 = 0x138;
 
 // lane l receives lane l-1's value; lane 0 receives `lane0`
@@ -55,14 +62,18 @@ __device__ __forceinline__ int shr1(int lane0, int v) {
 }
 
 template <int R>
-using ProfWord = typename std::conditional<(R <= 4), uint32_t, uint2>::type;
+using ProfWord =
+    typename std::conditional<(R <= 4), uint32_t, typename std::conditional<(R <= 8), uint2, uint4>::type>::type;
 
 template <int R>
 __device__ __forceinline__ int sigma_at(const ProfWord<R> &w, int r) {
     if constexpr (R <= 4) {
         return (int)(int8_t)(w >> (8 * r));
-    } else {
+    } else if constexpr (R <= 8) {
         return r < 4 ? (int)(int8_t)(w.x >> (8 * r)) : (int)(int8_t)(w.y >> (8 * (r - 4)));
+    } else {
+        const uint32_t x = r < 4 ? w.x : r < 8 ? w.y : r < 12 ? w.z : w.w;
+        return (int)(int8_t)(x >> (8 * (r & 3)));
     }
 }
 
@@ -73,19 +84,15 @@ __device__ __forceinline__ void build_profile(ProfWord<R> (*prof)[kWave], const 
 #pragma unroll
     for (int r = 0; r < R; ++r) ar[r] = (base + r >= 0 && base + r < la) ? a[base + r] : kPadCode;
     for (int c = 0; c < kProfCodes; ++c) {
-        uint32_t w0 = 0, w1 = 0;
+        uint32_t w[4] = {0, 0, 0, 0};
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const uint32_t v = (uint8_t)sblosum[ar[r] * kProfCodes + c];
-            if (r < 4)
-                w0 |= v << (8 * r);
-            else
-                w1 |= v << (8 * (r - 4));
-        }
+        for (int r = 0; r < R; ++r) w[r >> 2] |= (uint32_t)(uint8_t)sblosum[ar[r] * kProfCodes + c] << (8 * (r & 3));
         if constexpr (R <= 4) {
-            prof[c][lane] = w0;
+            prof[c][lane] = w[0];
+        } else if constexpr (R <= 8) {
+            prof[c][lane] = make_uint2(w[0], w[1]);
         } else {
-            prof[c][lane] = make_uint2(w0, w1);
+            prof[c][lane] = make_uint4(w[0], w[1], w[2], w[3]);
         }
     }
 }
@@ -269,15 +276,15 @@ __global__ __launch_bounds__(256) void sw_pass1_kernel(const uint8_t *__restrict
 
 // ---------------------------------------------------------------- between the passes
 
-// Rows up to 512 take one strip of 64 * R rows with the smallest R; longer
-// ones take the fewest strips of at most 512 rows, with R as small as that
-// strip count allows (so padding stays under one row per lane and strip).
+// Rows up to 64 * kMaxR take one strip of 64 * R rows with the smallest R;
+// longer ones take the fewest strips of at most 64 * kMaxR rows, with R as
+// small as that strip count allows (padding under one row per lane and strip).
 __device__ __forceinline__ int rows_bin(int rows) {
     if (rows <= 0) return 0;
     const int r = (rows + kWave - 1) / kWave;
     if (r <= kSingleBins) return r - 1;
     const int strips = (rows + kWave * kSingleBins - 1) / (kWave * kSingleBins);
-    const int rm = (rows + kWave * strips - 1) / (kWave * strips);  // in [5, 8]
+    const int rm = (rows + kWave * strips - 1) / (kWave * strips);  // in [kMultiMinR, kMaxR]
     return kMultiBin + rm - kMultiMinR;
 }
 
@@ -303,7 +310,8 @@ __global__ void sw_bin1_kernel(const PairDesc *__restrict__ pairs, int64_t npair
 }
 
 // Records of pairs that need no statistics pass are final here; the others
-// are binned by the height of their end rectangle.
+// are binned by the height of their end rectangle (counters[3], [4]: pairs
+// and cells of the start-bound pass; counters[1], [2] in full-records mode).
 // stats_mode: 0 = only pairs whose coverage cut can hold, 1 = every aligned
 // pair, 2 = none (the normalised-score weight needs no traceback).
 __global__ void sw_bin2_kernel(const PairDesc *__restrict__ pairs, const SwPass1Out *__restrict__ p1,
@@ -318,6 +326,168 @@ __global__ void sw_bin2_kernel(const PairDesc *__restrict__ pairs, const SwPass1
                       (stats_mode == 1 || 100LL * (r1.end_a + 1) >= (long long)cov_pct * pd.la);
     if (need) {
         bin_of[q] = (int8_t)rows_bin(r1.end_a + 1);
+        if (stats_mode == 1) {  // no start bound: every such pair takes pass 2
+            atomicAdd(&counters[1], 1ull);
+            atomicAdd(&counters[2], (unsigned long long)(r1.end_a + 1) * (unsigned long long)(r1.end_b + 1));
+        } else {
+            atomicAdd(&counters[3], 1ull);
+            atomicAdd(&counters[4], (unsigned long long)(r1.end_a + 1) * (unsigned long long)(r1.end_b + 1));
+        }
+        return;
+    }
+    bin_of[q] = -1;
+    pastis_pair_record rec;
+    rec.score = r1.score;
+    rec.beg_a = rec.beg_b = -1;
+    rec.end_a = r1.end_a;
+    rec.end_b = r1.end_b;
+    rec.matches = rec.columns = 0;
+    rec.seed_used = -1;
+    rec.passed = 0;
+    rec.swapped = pd.swapped;
+    rec.cells = (int64_t)pd.la * pd.lb;
+    out[q] = rec;
+}
+
+// ---------------------------------------------------------------- start bound
+
+// Scores of the packed recomputation must fit 15 bits; a local alignment
+// gains at most 11 per row, so rectangles up to this many rows qualify.
+constexpr int kBoundMaxRows = 32000 / 11;
+
+// For a pair that still needs the statistics pass, recompute its end
+// rectangle [0, end_a] x [0, end_b] with every DP value packed as
+// score * 65536 + (65535 - start row).  Each max then keeps the higher score
+// and, between equal scores, the smaller start row, so by induction a cell
+// holds the smallest start row over all optimal local alignments ending in
+// it (an empty alignment ending at row i starts the next path at row i + 1).
+// The canonical alignment is one of those ending at the end cell, so its
+// coverage of a is at most end_a - bound + 1.  The bound goes to p1[q].pad.
+// Taller rectangles keep bound 0 (no pruning).
+template <int R, bool MULTI>
+__global__ __launch_bounds__(256) void sw_bound_kernel(const uint8_t *__restrict__ codes,
+                                                       const PairDesc *__restrict__ pairs,
+                                                       const int *__restrict__ idx, const int *__restrict__ starts,
+                                                       int bin, const int8_t *__restrict__ blosum, int go_ge, int ge,
+                                                       SwPass1Out *__restrict__ p1, int *__restrict__ scratch,
+                                                       int64_t scratch_per_wave) {
+    __shared__ ProfWord<R> prof_all[kWavesPerBlock][kProfCodes][kWave];
+    __shared__ int8_t sblosum[kProfCodes * kProfCodes];
+    load_blosum(sblosum, blosum);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    ProfWord<R>(*prof)[kWave] = prof_all[wave];
+    const int64_t gwave = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+    int *bnd_h = scratch + gwave * scratch_per_wave;
+    int *bnd_f = bnd_h + scratch_per_wave / 2;
+    const int item_end = starts[bin + 1];
+    constexpr int RS = kWave * R;
+    constexpr int kNegP = -(1 << 30);
+    constexpr int kZero = 0xFFFF;  // score 0, start row 0
+    const int GO = go_ge * 65536, GE = ge * 65536;
+
+    for (int64_t w = starts[bin] + gwave; w < item_end; w += (int64_t)gridDim.x * kWavesPerBlock) {
+        const int q = idx[w];
+        const PairDesc pd = pairs[q];
+        const SwPass1Out r1 = p1[q];
+        const int la = r1.end_a + 1, lb = r1.end_b + 1;
+        if (la > kBoundMaxRows) {
+            if (lane == 0) p1[q].pad = 0;
+            continue;
+        }
+        const uint8_t *a = codes + pd.a_off;
+        const uint8_t *b = codes + pd.b_off;
+        const int nstrips = MULTI ? (la + RS - 1) / RS : 1;
+        const int top = nstrips * RS - la;  // padding rows above row 0
+        int fin = 0;
+        for (int s = 0; s < nstrips; ++s) {
+            const int base = s * RS - top + lane * R;
+            build_profile<R>(prof, sblosum, a, la, base, lane);
+            const bool from_above = s > 0;
+            const bool to_below = s + 1 < nstrips;
+            const bool last = s + 1 == nstrips;
+            int H[R], G[R], E[R], Z[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                Z[r] = 0xFFFF - max(base + r + 1, 0);  // empty alignment ending in row base + r
+                H[r] = Z[r];                           // column -1
+                G[r] = Z[r] - GO;
+                E[r] = kNegP;
+            }
+            int hlast = kZero, flast = kNegP, hprev = kZero, cres = kPadCode, chunk = kPadCode;
+            int nx = (lane < lb) ? (int)b[lane] : kPadCode;
+            int ch_h = kZero, ch_f = kNegP, nx_h = kZero, nx_f = kNegP;
+            if (MULTI && from_above && lane < lb) {
+                nx_h = vload(bnd_h + lane);
+                nx_f = vload(bnd_f + lane);
+            }
+            const int steps = lb + kWave - 1;
+            for (int t = 0; t < steps; ++t) {
+                if ((t & (kWave - 1)) == 0) {
+                    chunk = nx;
+                    const int c = t + kWave + lane;
+                    nx = (c < lb) ? (int)b[c] : kPadCode;
+                    if (MULTI && from_above) {
+                        ch_h = nx_h;
+                        ch_f = nx_f;
+                        if (c < lb) {
+                            nx_h = vload(bnd_h + c);
+                            nx_f = vload(bnd_f + c);
+                        }
+                    }
+                }
+                const int bt = __builtin_amdgcn_readlane(chunk, t & (kWave - 1));
+                int in_h = kZero, in_f = kNegP;
+                if (MULTI && from_above && t < lb) {
+                    in_h = __builtin_amdgcn_readlane(ch_h, t & (kWave - 1));
+                    in_f = __builtin_amdgcn_readlane(ch_f, t & (kWave - 1));
+                }
+                const int rh = shr1(in_h, hlast);
+                const int rf = shr1(in_f, flast);
+                cres = shr1(bt, cres);
+                const int j = t - lane;
+                const ProfWord<R> pw = prof[cres][lane];
+                int hd = hprev, gu = rh - GO, fu = rf;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int e = max(E[r] - GE, G[r]);
+                    const int f = max(fu - GE, gu);
+                    const int d = hd + sigma_at<R>(pw, r) * 65536;
+                    const int h = max(max(d, Z[r]), max(e, f));
+                    hd = H[r];
+                    H[r] = h;
+                    E[r] = e;
+                    const int g = h - GO;
+                    G[r] = g;
+                    gu = g;
+                    fu = f;
+                }
+                hlast = H[R - 1];
+                flast = fu;
+                hprev = rh;
+                if (last && lane == kWave - 1 && j == lb - 1) fin = hlast;
+                if (MULTI && to_below && lane == kWave - 1 && j >= 0 && j < lb) {
+                    bnd_h[j] = hlast;
+                    bnd_f[j] = flast;
+                }
+            }
+            if (MULTI) __threadfence_block();
+        }
+        if (lane == kWave - 1) p1[q].pad = 0xFFFF - (fin & 0xFFFF);
+    }
+}
+
+// Pairs binned for the statistics pass whose coverage bound already fails
+// get their final record here; the rest keep their bin.  counters[1] and [2]
+// count the pairs and cells left for pass 2.
+__global__ void sw_bin3_kernel(const PairDesc *__restrict__ pairs, const SwPass1Out *__restrict__ p1,
+                               int64_t npairs, int cov_pct, pastis_pair_record *__restrict__ out,
+                               int8_t *__restrict__ bin_of, unsigned long long *__restrict__ counters) {
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= npairs || bin_of[q] < 0) return;
+    const PairDesc pd = pairs[q];
+    const SwPass1Out r1 = p1[q];
+    if (100LL * (r1.end_a - r1.pad + 1) >= (long long)cov_pct * pd.la) {
         atomicAdd(&counters[1], 1ull);
         atomicAdd(&counters[2], (unsigned long long)(r1.end_a + 1) * (unsigned long long)(r1.end_b + 1));
         return;
@@ -551,15 +721,36 @@ hipError_t launch_p2(int bin, int blocks, const uint8_t *codes, const PairDesc *
     return hipGetLastError();
 }
 
+template <int R>
+hipError_t launch_pb(int bin, int blocks, const uint8_t *codes, const PairDesc *pairs, const int *idx,
+                     const int *starts, const int8_t *blosum, int go_ge, int ge, SwPass1Out *p1, int *scratch,
+                     int64_t spw, hipStream_t s) {
+    if (bin >= kMultiBin)
+        sw_bound_kernel<R, true><<<blocks, 256, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, p1, scratch,
+                                                        spw);
+    else
+        sw_bound_kernel<R, false><<<blocks, 256, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, p1,
+                                                         scratch, spw);
+    return hipGetLastError();
+}
+
 typedef hipError_t (*P1Fn)(int, int, const uint8_t *, const PairDesc *, const int *, const int *, const int8_t *, int,
                            int, SwPass1Out *, int *, int64_t, hipStream_t);
 typedef hipError_t (*P2Fn)(int, int, const uint8_t *, const PairDesc *, const int *, const int *, const int8_t *, int,
                            int, int, int, const SwPass1Out *, pastis_pair_record *, int *, int64_t, hipStream_t);
 
-const P1Fn kP1[kNumBins] = {launch_p1<1>, launch_p1<2>, launch_p1<3>, launch_p1<4>, launch_p1<5>, launch_p1<6>,
-                            launch_p1<7>, launch_p1<8>, launch_p1<5>, launch_p1<6>, launch_p1<7>, launch_p1<8>};
-const P2Fn kP2[kNumBins] = {launch_p2<1>, launch_p2<2>, launch_p2<3>, launch_p2<4>, launch_p2<5>, launch_p2<6>,
-                            launch_p2<7>, launch_p2<8>, launch_p2<5>, launch_p2<6>, launch_p2<7>, launch_p2<8>};
+const P1Fn kP1[kNumBins] = {launch_p1<1>,  launch_p1<2>,  launch_p1<3>,  launch_p1<4>,  launch_p1<5>,  launch_p1<6>,
+                            launch_p1<7>,  launch_p1<8>,  launch_p1<9>,  launch_p1<10>, launch_p1<11>, launch_p1<12>,
+                            launch_p1<13>, launch_p1<14>, launch_p1<15>, launch_p1<16>, launch_p1<9>,  launch_p1<10>,
+                            launch_p1<11>, launch_p1<12>, launch_p1<13>, launch_p1<14>, launch_p1<15>, launch_p1<16>};
+const P1Fn kPB[kNumBins] = {launch_pb<1>,  launch_pb<2>,  launch_pb<3>,  launch_pb<4>,  launch_pb<5>,  launch_pb<6>,
+                            launch_pb<7>,  launch_pb<8>,  launch_pb<9>,  launch_pb<10>, launch_pb<11>, launch_pb<12>,
+                            launch_pb<13>, launch_pb<14>, launch_pb<15>, launch_pb<16>, launch_pb<9>,  launch_pb<10>,
+                            launch_pb<11>, launch_pb<12>, launch_pb<13>, launch_pb<14>, launch_pb<15>, launch_pb<16>};
+const P2Fn kP2[kNumBins] = {launch_p2<1>,  launch_p2<2>,  launch_p2<3>,  launch_p2<4>,  launch_p2<5>,  launch_p2<6>,
+                            launch_p2<7>,  launch_p2<8>,  launch_p2<9>,  launch_p2<10>, launch_p2<11>, launch_p2<12>,
+                            launch_p2<13>, launch_p2<14>, launch_p2<15>, launch_p2<16>, launch_p2<9>,  launch_p2<10>,
+                            launch_p2<11>, launch_p2<12>, launch_p2<13>, launch_p2<14>, launch_p2<15>, launch_p2<16>};
 
 }  // namespace
 
@@ -567,15 +758,23 @@ int sw_num_bins() { return kNumBins; }
 
 void sw_bin_shape(int bin, int32_t *rows_per_lane, int32_t *multi) {
     *multi = bin >= kMultiBin;
-    *rows_per_lane = bin >= kMultiBin ? bin - kMultiBin + kMultiMinR : bin + 1;
+    *rows_per_lane = rows_of_bin(bin);
 }
 
-// Blocks per bin launch: enough resident waves to fill 256 CUs for the bin's
-// LDS footprint (the grid-stride loop reads the bin size on the device).
-static int blocks_for_bin(int bin) { return bin < 4 ? 256 * 6 : 256 * 3; }
+// Blocks per bin launch: the blocks of the bin's LDS footprint (25 codes x
+// 64 lanes x 4, 8 or 16 profile bytes per wave) resident on 256 CUs at once;
+// the grid-stride loop reads the bin size on the device.
+static int blocks_for_bin(int bin) {
+    const int r = rows_of_bin(bin);
+    return r <= 4 ? 256 * 6 : r <= 8 ? 256 * 3 : 256;
+}
 
 // Only the multi-strip bins use the boundary buffers.
-int64_t sw_scratch_waves() { return (int64_t)blocks_for_bin(kMultiBin) * kWavesPerBlock; }
+int64_t sw_scratch_waves() {
+    int64_t w = 0;
+    for (int b = kMultiBin; b < kNumBins; ++b) w = std::max<int64_t>(w, (int64_t)blocks_for_bin(b) * kWavesPerBlock);
+    return w;
+}
 
 hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pairs, int64_t npairs,
                      const int8_t *blosum, const Scoring &sc, SwPass1Out *p1, pastis_pair_record *out,
@@ -602,6 +801,18 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
     sw_bin2_kernel<<<nb, 256, 0, s>>>(pairs, p1, npairs, sc.cov_pct, stats_mode, out, wk.bin_of, wk.counters);
     if ((e = launch_bins(wk.bin_of, npairs, kNumBins, wk.counts, wk.starts2, wk.cursor, wk.idx2, s)) != hipSuccess)
         return e;
+    if (stats_mode == 0) {
+        // start bound, then only the pairs whose coverage can still hold
+        for (int bin = 0; bin < kNumBins; ++bin) {
+            e = kPB[bin](bin, blocks_for_bin(bin), codes, pairs, wk.idx2, wk.starts2, blosum, go_ge, ge, p1,
+                         wk.scratch, wk.scratch_per_wave, s);
+            if (e != hipSuccess) return e;
+        }
+        sw_bin3_kernel<<<nb, 256, 0, s>>>(pairs, p1, npairs, sc.cov_pct, out, wk.bin_of, wk.counters);
+        if ((e = launch_bins(wk.bin_of, npairs, kNumBins, wk.counts, wk.starts2, wk.cursor, wk.idx2, s)) !=
+            hipSuccess)
+            return e;
+    }
     for (int bin = 0; bin < kNumBins; ++bin) {
         e = kP2[bin](bin, blocks_for_bin(bin), codes, pairs, wk.idx2, wk.starts2, blosum, go_ge, ge, sc.cov_pct,
                      sc.id_pct, p1, out, wk.scratch, wk.scratch_per_wave, s);

@@ -117,6 +117,8 @@ def xd_leg(P, args, params, res, off, n_cand):
         "pairs_per_s": n_cand / (xms * 1e-3),
         "live_cells": float(xst["cells"]),
         "align_ms": (xstage[5] + xstage[6]) / args.steps,
+        "register_band_ms": xstage[5] / args.steps,
+        "wide_band_redo_ms": xstage[6] / args.steps,
         "align_pairs_per_s": n_cand / ((xstage[5] + xstage[6]) / args.steps * 1e-3),
         "edges": int(xedges.size),
     }

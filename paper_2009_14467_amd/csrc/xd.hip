@@ -12,14 +12,15 @@
 // keeps the best-scoring seed among those that pass the identity / coverage
 // cut (the first seed on a tie), or the best-scoring seed when none passes.
 //
-// Layout.  The live band of an anti-diagonal is spread over the lanes (cell u
-// at lane (u - lo) mod 64).  The last three anti-diagonals live in a ring in
-// LDS indexed by u mod 256, holding H, E, F and, for each state, the packed
+// Layout.  Every cell carries, for each state (H, E, F), the packed
 // (identical pairs << 16 | diagonal columns) of the canonical path reaching
 // it: each cell takes the predecessor a traceback would take (diagonal, then
 // horizontal, then vertical gap; extension before opening), and since every
 // extension path starts at the anchor, columns = u + v - diagonal columns.
-// Bands wider than the LDS ring are redone with a ring in global memory.
+// The first pass keeps the band of an anti-diagonal in registers (cell u in
+// lane u mod 64, see extend_reg); pairs with a band wider than 64 rows are
+// redone by a second kernel that keeps the last three anti-diagonals in a
+// ring in global memory indexed by u.
 #include <climits>
 
 #include "internal.hpp"
@@ -30,7 +31,6 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;
 constexpr int kNeg = -(1 << 28);
-constexpr int kLdsCap = 256;
 constexpr int kGlobalCap = 65536;
 constexpr int kProfCodes = kAlpha + 1;
 
@@ -223,22 +223,211 @@ __device__ Ext extend(const uint8_t *a0, int la, int adir, const uint8_t *b0, in
     return r;
 }
 
+
+// ---------------------------------------------------------------- register band
+//
+// The same extension with the band in registers: cell u of an anti-diagonal
+// lives in lane u mod 64 (the computed range [lo, hi] must fit 64 rows, else
+// the pair is redone with a ring in global memory).  Predecessors come from
+// the lane itself (horizontal, d-1) and, by a one-lane wave rotation, from
+// lane u-1 (vertical at d-1; diagonal at d-2, the rotation kept from the step
+// before).  A predecessor counts only if its row was in the computed range of
+// its anti-diagonal, so stale lanes never leak in.  Residues stream through
+// 256-entry LDS rings per sequence, filled in 64-entry chunks one chunk ahead
+// of the largest index the band can reach (the band moves at most one row and
+// one column per anti-diagonal).
+
+constexpr int kDppWaveRor1 = 0x13C;  // lane l receives lane l-1 (lane 0 from 63)
+
+__device__ __forceinline__ int ror1(int v) { return __builtin_amdgcn_update_dpp(0, v, kDppWaveRor1, 0xF, 0xF, false); }
+
+struct Stream {
+    const uint8_t *p;
+    int len, dir;
+    uint8_t *ring;  // 256 entries, index & 255
+    int next;       // chunks [0, next) are in the ring
+    int pending;    // this lane's element of chunk `next`, loaded ahead
+};
+
+__device__ __forceinline__ int stream_elem(const Stream &w, int c, int lane) {
+    const int t = c * kWave + lane;
+    return t < w.len ? (int)w.p[(int64_t)t * w.dir] : kPadCode;
+}
+
+__device__ __forceinline__ void stream_init(Stream &w, int lane) {
+    w.ring[lane] = (uint8_t)stream_elem(w, 0, lane);
+    w.ring[kWave + lane] = (uint8_t)stream_elem(w, 1, lane);
+    w.pending = stream_elem(w, 2, lane);
+    w.next = 2;
+}
+
+// make every index <= frontier + 64 readable
+__device__ __forceinline__ void stream_ensure(Stream &w, int frontier, int lane) {
+    while ((frontier >> 6) + 1 >= w.next) {
+        w.ring[(w.next & 3) * kWave + lane] = (uint8_t)w.pending;
+        ++w.next;
+        w.pending = stream_elem(w, w.next, lane);
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ unsigned long long rotr64(unsigned long long m, int s) {
+    return s == 0 ? m : (m >> s) | (m << (64 - s));
+}
+
+__device__ __forceinline__ int wave_max_dpp(int v) {
+    // within rows of 16, then across rows; lane 63 ends with the maximum
+    v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x111, 0xF, 0xF, false));  // row_shr:1
+    v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x112, 0xF, 0xF, false));  // row_shr:2
+    v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x114, 0xF, 0xF, false));  // row_shr:4
+    v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x118, 0xF, 0xF, false));  // row_shr:8
+    v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x142, 0xA, 0xF, false));  // row_bcast:15
+    v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x143, 0xC, 0xF, false));  // row_bcast:31
+    return __builtin_amdgcn_readlane(v, kWave - 1);
+}
+
+__device__ Ext extend_reg(const uint8_t *a0, int la, int adir, const uint8_t *b0, int lb, int bdir,
+                          const int8_t *sbl, int o, int e, int X, uint8_t *ring_a, uint8_t *ring_b, int lane) {
+    const int oe = o + e;
+    Stream sa{a0, la, adir, ring_a, 0, 0}, sb{b0, lb, bdir, ring_b, 0, 0};
+    stream_init(sa, lane);
+    stream_init(sb, lane);
+    // anti-diagonal 0: the anchor in lane 0
+    int H1 = lane == 0 ? 0 : kNeg, E1 = kNeg, F1 = kNeg;
+    unsigned SH1 = 0u, SE1 = 0u, SF1 = 0u;
+    int VH = kNeg;  // lane u-1's H two anti-diagonals back (rotated one step ago)
+    unsigned VSH = 0u;
+    int clo1 = 0, chi1 = 0, llo1 = 0, lhi1 = 0;
+    int clo2 = 1, chi2 = 0, llo2 = 1, lhi2 = 0;
+    int best = 0, bu = 0, bv = 0;
+    unsigned bmd = 0u;
+    int cells = 0;
+    bool overflow = false;
+    const int dmax = la + lb;
+    for (int d = 1; d <= dmax; ++d) {
+        int lo = INT_MAX, hi = -1;
+        if (llo1 <= lhi1) {
+            lo = llo1;
+            hi = lhi1 + 1;
+        }
+        if (llo2 <= lhi2) {
+            lo = min(lo, llo2 + 1);
+            hi = max(hi, lhi2 + 1);
+        }
+        lo = max(lo, max(0, d - lb));
+        hi = min(hi, min(d, la));
+        if (lo > hi) break;
+        if (hi - lo + 1 > kWave) {
+            overflow = true;
+            break;
+        }
+        const int u = lo + ((lane - lo) & (kWave - 1));
+        const int v = d - u;
+        const bool inband = u <= hi;
+        // predecessors
+        const int rH = ror1(H1), rF = ror1(F1);
+        const unsigned rSH = (unsigned)ror1((int)SH1), rSF = (unsigned)ror1((int)SF1);
+        const bool okv = u - 1 >= clo1 && u - 1 <= chi1;             // (u-1, v) at d-1
+        const bool okh = v >= 1 && u >= clo1 && u <= chi1;           // (u, v-1) at d-1
+        const bool okd = u >= 1 && v >= 1 && u - 1 >= clo2 && u - 1 <= chi2;  // (u-1, v-1) at d-2
+        const int Hu = okv ? rH : kNeg, Fu = okv ? rF : kNeg;
+        const int Hl = okh ? H1 : kNeg, El = okh ? E1 : kNeg;
+        const int Hd = okd ? VH : kNeg;
+        const unsigned sHd = VSH;
+        VH = rH;
+        VSH = rSH;
+        // residues of the diagonal move
+        if (hi >= 1) stream_ensure(sa, hi - 1, lane);
+        if (d - lo - 1 >= 0) stream_ensure(sb, d - lo - 1, lane);
+        const bool ld = inband && Hd > kNeg / 2;
+        int sig = 0, same = 0;
+        if (ld) {
+            const int ca = ring_a[(u - 1) & 255], cb = ring_b[(v - 1) & 255];
+            sig = sbl[ca * kProfCodes + cb];
+            same = ca == cb;
+        }
+        const bool any = inband && (Hu > kNeg / 2 || Hl > kNeg / 2 || ld);
+        const int e_ext = El - e, e_open = Hl - oe;
+        const bool ee = e_ext >= e_open;
+        const int E_ = ee ? e_ext : e_open;
+        const int f_ext = Fu - e, f_open = Hu - oe;
+        const bool fe = f_ext >= f_open;
+        const int F_ = fe ? f_ext : f_open;
+        const int D_ = ld ? Hd + sig : kNeg;
+        const unsigned sD = sHd + (same ? 0x10001u : 1u);
+        const int H_ = max(D_, max(E_, F_));
+        const unsigned sE_ = ee ? SE1 : SH1;
+        const unsigned sF_ = fe ? rSF : rSH;
+        const unsigned sH_ = (ld && H_ == D_) ? sD : (H_ == E_ ? sE_ : sF_);
+        const bool live = any && H_ >= best - X;
+        cells += any ? 1 : 0;
+        H1 = live ? H_ : kNeg;
+        E1 = live ? E_ : kNeg;
+        F1 = live ? F_ : kNeg;
+        SH1 = sH_;
+        SE1 = sE_;
+        SF1 = sF_;
+        // live range and best cell of this anti-diagonal (u = lo + rotated lane)
+        const unsigned long long lm = rotr64(__ballot(live), lo & (kWave - 1));
+        clo2 = clo1;
+        chi2 = chi1;
+        llo2 = llo1;
+        lhi2 = lhi1;
+        clo1 = lo;
+        chi1 = hi;
+        if (lm == 0ull) {
+            llo1 = 1;
+            lhi1 = 0;
+            break;
+        }
+        llo1 = lo + __ffsll((long long)lm) - 1;
+        lhi1 = lo + 63 - __clzll((long long)lm);
+        const int dbest = wave_max_dpp(live ? H_ : INT_MIN);
+        if (dbest > best) {
+            const unsigned long long hit = rotr64(__ballot(live && H_ == dbest), lo & (kWave - 1));
+            const int off = __ffsll((long long)hit) - 1;
+            best = dbest;
+            bu = lo + off;
+            bv = d - bu;
+            bmd = (unsigned)__builtin_amdgcn_readlane((int)sH_, bu & (kWave - 1));
+        }
+    }
+    Ext r;
+    r.score = best;
+    r.u = bu;
+    r.v = bv;
+    r.md = bmd;
+    r.cells = wave_sum_i(cells);
+    r.overflow = overflow;
+    return r;
+}
+
 struct SeedAln {
     int score, beg_a, end_a, beg_b, end_b, matches, columns, cells;
     bool overflow;
 };
 
+// GLOBAL = false: the register band (rings = two 256-entry LDS rings);
+// GLOBAL = true: the ring in global memory.
 template <bool GLOBAL>
 __device__ SeedAln align_seed(const uint8_t *a, int la, const uint8_t *b, int lb, int pa, int pb, int k,
-                              const int8_t *sbl, int o, int e, int X, const Ring &R, int lane) {
+                              const int8_t *sbl, int o, int e, int X, const Ring &R, uint8_t *rings, int lane) {
     int sc = 0, sm = 0;
     for (int t = 0; t < k; ++t) {
         const int ca = a[pa + t], cb = b[pb + t];
         sc += sbl[ca * kProfCodes + cb];
         sm += ca == cb;
     }
-    const Ext rt = extend<GLOBAL>(a + pa + k, la - pa - k, 1, b + pb + k, lb - pb - k, 1, sbl, o, e, X, R, lane);
-    const Ext lf = extend<GLOBAL>(a + pa - 1, pa, -1, b + pb - 1, pb, -1, sbl, o, e, X, R, lane);
+    Ext rt, lf;
+    if constexpr (GLOBAL) {
+        rt = extend<true>(a + pa + k, la - pa - k, 1, b + pb + k, lb - pb - k, 1, sbl, o, e, X, R, lane);
+        lf = extend<true>(a + pa - 1, pa, -1, b + pb - 1, pb, -1, sbl, o, e, X, R, lane);
+    } else {
+        rt = extend_reg(a + pa + k, la - pa - k, 1, b + pb + k, lb - pb - k, 1, sbl, o, e, X, rings, rings + 256,
+                        lane);
+        lf = rt.overflow ? rt
+                         : extend_reg(a + pa - 1, pa, -1, b + pb - 1, pb, -1, sbl, o, e, X, rings, rings + 256, lane);
+    }
     SeedAln s;
     s.score = lf.score + sc + rt.score;
     s.beg_a = pa - lf.u;
@@ -269,37 +458,23 @@ __global__ __launch_bounds__(256) void xd_kernel(const uint8_t *__restrict__ cod
                                                  int *__restrict__ gring, unsigned long long *__restrict__ counters) {
     __shared__ int8_t sbl[kProfCodes * kProfCodes];
     for (int t = threadIdx.x; t < kProfCodes * kProfCodes; t += blockDim.x) sbl[t] = blosum[t];
-    __shared__ int lds_int[GLOBAL ? 1 : kWavesPerBlock * 9 * kLdsCap];
+    __shared__ uint8_t lds_rings[GLOBAL ? 1 : kWavesPerBlock * 512];
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int64_t gwave = (int64_t)blockIdx.x * kWavesPerBlock + wave;
-    Ring R;
-    int *base;
+    Ring R{};
+    uint8_t *rings = nullptr;
     if constexpr (GLOBAL) {
+        int *base = gring + gwave * (int64_t)18 * kGlobalCap;
         R.cap = kGlobalCap;
-        base = gring + gwave * (int64_t)18 * kGlobalCap;
-    } else {
-        R.cap = kLdsCap;
-        base = lds_int + wave * 9 * kLdsCap;  // 3 int planes + 3 unsigned planes of 3 slots... see below
-    }
-    // planes of 3 * cap entries: H, E, F, SH, SE, SF
-    if constexpr (GLOBAL) {
         R.H = base;
         R.E = base + 3 * R.cap;
         R.F = base + 6 * R.cap;
         R.SH = (unsigned *)(base + 9 * R.cap);
         R.SE = (unsigned *)(base + 12 * R.cap);
         R.SF = (unsigned *)(base + 15 * R.cap);
-    }
-    __shared__ unsigned lds_u[GLOBAL ? 1 : kWavesPerBlock * 9 * kLdsCap];
-    if constexpr (!GLOBAL) {
-        R.H = base;
-        R.E = base + 3 * R.cap;
-        R.F = base + 6 * R.cap;
-        unsigned *ub = lds_u + wave * 9 * kLdsCap;
-        R.SH = ub;
-        R.SE = ub + 3 * R.cap;
-        R.SF = ub + 6 * R.cap;
+    } else {
+        rings = lds_rings + wave * 512;
     }
     const int64_t count = GLOBAL ? (int64_t)*n_redo : npairs;
     unsigned long long my_cells = 0;
@@ -320,7 +495,8 @@ __global__ __launch_bounds__(256) void xd_kernel(const uint8_t *__restrict__ cod
         int cells = 0;
         for (int s = 0; s < 2; ++s) {
             if (pa[s] < 0) continue;
-            const SeedAln t = align_seed<GLOBAL>(a, pd.la, b, pd.lb, pa[s], pb[s], k, sbl, o, e, X, R, lane);
+            const SeedAln t =
+                align_seed<GLOBAL>(a, pd.la, b, pd.lb, pa[s], pb[s], k, sbl, o, e, X, R, rings, lane);
             overflow |= t.overflow;
             cells += t.cells;
             const bool pass = passes(t, pd.la, id_pct, cov_pct);
@@ -339,7 +515,7 @@ __global__ __launch_bounds__(256) void xd_kernel(const uint8_t *__restrict__ cod
         }
         rec.passed = best_pass ? 1 : 0;
         rec.cells = cells;
-        if (!GLOBAL && overflow) {
+        if (!GLOBAL && overflow) {  // a band wider than 64 rows
             if (lane == 0) redo[atomicAdd(n_redo, 1u)] = (uint32_t)q;
             continue;
         }

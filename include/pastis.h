@@ -74,7 +74,13 @@ typedef struct pastis_params {
     int32_t min_identity_pct; /* ANI cut: 100 * matches >= pct * columns */
     int32_t min_coverage_pct; /* ANI cut: 100 * aligned span >= pct * shorter length */
     int32_t weight_mode;      /* pastis_weight_mode */
-    int32_t score_width;      /* 0 = automatic, 16 or 32: DP word width request */
+    int32_t score_width;      /* DP word width of Smith-Waterman pass 1: 16 runs pairs
+                                 whose shorter side fits one strip of 512 rows two
+                                 per wave in 16-bit lanes (records of pairs without
+                                 the statistics pass then carry end_b = -1); 32 runs
+                                 every pair in 32-bit lanes; 0 (automatic) takes 16
+                                 inside pastis_search with identity weights and 32
+                                 elsewhere.  16 needs gap_open + gap_extend >= 4. */
     int32_t full_records;     /* 1: traceback statistics (beg, matches, columns) for every
                                  aligned pair; 0: only for pairs whose coverage cut can
                                  still hold (the others report beg = -1, passed = 0) */
@@ -133,6 +139,7 @@ typedef struct pastis_run_stats {
     int32_t sw_bins;
     int32_t sw_bin_rows[32];
     int32_t sw_bin_multi[32];
+    int32_t sw_bin_bits[32]; /* 16: two pairs per wave in 16-bit lanes; 32: one pair */
     int64_t sw_bin_pairs[32];
     int64_t sw_bin_cells[32];
     double sw_bin_ms[32];

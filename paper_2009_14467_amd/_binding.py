@@ -101,6 +101,7 @@ class _Stats(ctypes.Structure):
         ("sw_bins", ctypes.c_int32),
         ("sw_bin_rows", ctypes.c_int32 * 32),
         ("sw_bin_multi", ctypes.c_int32 * 32),
+        ("sw_bin_bits", ctypes.c_int32 * 32),
         ("sw_bin_pairs", ctypes.c_int64 * 32),
         ("sw_bin_cells", ctypes.c_int64 * 32),
         ("sw_bin_ms", ctypes.c_double * 32),
@@ -259,12 +260,14 @@ class Context:
     def stats(self) -> dict:
         s = _Stats()
         self._check(lib().pastis_stats(self._ctx, ctypes.byref(s)))
-        arrays = ("ms_stage", "sw_bin_rows", "sw_bin_multi", "sw_bin_pairs", "sw_bin_cells", "sw_bin_ms")
+        arrays = ("ms_stage", "sw_bin_rows", "sw_bin_multi", "sw_bin_bits", "sw_bin_pairs", "sw_bin_cells",
+                  "sw_bin_ms")
         out = {f: getattr(s, f) for f, _ in _Stats._fields_ if f not in arrays}
         out["ms_stage"] = list(s.ms_stage)
         nb = s.sw_bins
         out["sw_bins"] = [
-            {"rows_per_lane": s.sw_bin_rows[b], "multi_strip": bool(s.sw_bin_multi[b]), "pairs": s.sw_bin_pairs[b],
+            {"rows_per_lane": s.sw_bin_rows[b], "multi_strip": bool(s.sw_bin_multi[b]), "bits": s.sw_bin_bits[b],
+             "pairs": s.sw_bin_pairs[b],
              "cells": s.sw_bin_cells[b], "ms": s.sw_bin_ms[b]}
             for b in range(nb)
         ]

@@ -201,6 +201,20 @@ pastis_status make_sw_work(pastis_ctx *ctx, int64_t npairs, int max_len, SwWork 
     return PASTIS_OK;
 }
 
+static pastis_status make_sort_work(pastis_ctx *ctx, int64_t npairs, SwWork &wk) {
+    const size_t n = (size_t)std::max<int64_t>(npairs, 1);
+    void *p = nullptr;
+    PASTIS_TRY(ensure(ctx, kBufSortKeys, sizeof(uint64_t) * n, &p));
+    wk.sort_keys = (uint64_t *)p;
+    PASTIS_TRY(ensure(ctx, kBufSortKeysAlt, sizeof(uint64_t) * n, &p));
+    wk.sort_keys_alt = (uint64_t *)p;
+    PASTIS_TRY(ensure(ctx, kBufSortValsAlt, sizeof(uint32_t) * n, &p));
+    wk.sort_vals_alt = (uint32_t *)p;
+    PASTIS_TRY(ensure(ctx, kBufSortTemp, radix_temp_bytes(npairs) + 256, &p));
+    wk.sort_temp = p;
+    return PASTIS_OK;
+}
+
 // Orient the pairs, then run the context's alignment mode; `out` gets one
 // record per pair.  Validates pair indices (PASTIS_E_INVAL).
 void mlp_free(pastis_ctx *ctx);
@@ -228,13 +242,21 @@ pastis_status align_core(pastis_ctx *ctx, const Staged &st, const uint8_t *codes
     PASTIS_TRY(make_sw_work(ctx, npairs, st.max_len, wk));
     HIP_TRY(ctx, fill<unsigned long long>(wk.counters, kNumCounters, 0ull, s), "reset");
     ctx->stats.sw_bins = 0;
+    ctx->stats.int32_pairs = 0;
+    ctx->last_use16 = false;
     // traceback statistics: every pair on request; none for the normalised
     // score weight; otherwise only where the coverage cut can still hold
     const int stats_mode = P.full_records ? 1 : (P.weight_mode == PASTIS_WEIGHT_NS ? 2 : 0);
     if (P.align_mode == PASTIS_ALIGN_SW) {
+        // 16-bit pass 1 on request, or by default where its records stay
+        // inside the search (they omit end_b of pairs without statistics)
+        const bool use16 = sw16_supported(sc) && stats_mode == 0 &&
+                           (P.score_width == 16 || (P.score_width == 0 && ctx->records_internal));
+        if (use16) PASTIS_TRY(make_sort_work(ctx, npairs, wk));
+        ctx->last_use16 = use16;
         HIP_TRY(ctx,
                 launch_sw(ctx, codes, (const PairDesc *)pairs, npairs, ctx->d_blosum, sc, (SwPass1Out *)p1, out, wk,
-                          stats_mode, s),
+                          stats_mode, use16, s),
                 "sw kernels");
     } else {
         void *redo = nullptr, *ring = nullptr;
@@ -261,6 +283,9 @@ pastis_status align_core(pastis_ctx *ctx, const Staged &st, const uint8_t *codes
         ctx->stats.sw_bins = nb;
         for (int b = 0; b < nb; ++b) {
             sw_bin_shape(b, &ctx->stats.sw_bin_rows[b], &ctx->stats.sw_bin_multi[b]);
+            const bool b16 = ctx->last_use16 && sw_bin_is16(b);
+            ctx->stats.sw_bin_bits[b] = b16 ? 16 : 32;
+            if (!b16) ctx->stats.int32_pairs += starts[b + 1] - starts[b];
             ctx->stats.sw_bin_pairs[b] = starts[b + 1] - starts[b];
             ctx->stats.sw_bin_cells[b] = (int64_t)c[kCounterBinCells + b];
             float ms = 0.f;
@@ -277,6 +302,11 @@ pastis_status align_candidates(pastis_ctx *ctx, const Staged &st, const uint8_t 
     void *rec = nullptr;
     PASTIS_TRY(ensure(ctx, kBufRecords, sizeof(pastis_pair_record) * (size_t)std::max<int64_t>(nc, 1), &rec));
     *rec_out = (pastis_pair_record *)rec;
+    ctx->records_internal = true;
+    struct Reset {
+        pastis_ctx *c;
+        ~Reset() { c->records_internal = false; }
+    } reset{ctx};
     return align_core(ctx, st, codes, n, (const uint32_t *)ctx->buf[kBufCandLo].ptr,
                       (const uint32_t *)ctx->buf[kBufCandHi].ptr, (const uint32_t *)ctx->buf[kBufCandS1].ptr,
                       (const uint32_t *)ctx->buf[kBufCandS2].ptr, nc, (pastis_pair_record *)rec, s);

@@ -98,6 +98,8 @@ struct pastis_ctx {
     int64_t n_candidates = 0;
     int64_t n_seqs_last = 0;
     bool have_candidates = false;
+    bool records_internal = false;
+    bool last_use16 = false;  // the last SW call ran 16-bit pass-1 bins  // the current alignment's records feed edges only
     // learned filter
     pastis::MlpState mlp{};
     bool mlp_alloc = false, mlp_set = false;
@@ -139,6 +141,10 @@ enum BufId {
     kBufMlpPos,
     kBufMlpTmp,
     kBufMlpOrder,
+    kBufSortKeys,
+    kBufSortKeysAlt,
+    kBufSortValsAlt,
+    kBufSortTemp,
     kBufCount  // first id used by the discovery stage
 };
 constexpr int kNumBufs = 96;
@@ -182,6 +188,10 @@ struct SwWork {
     int *idx, *idx2;
     int *scratch;
     int64_t scratch_per_wave;
+    // pairing of the 16-bit pass (pairs sorted by bin, then longer b first)
+    uint64_t *sort_keys = nullptr, *sort_keys_alt = nullptr;
+    uint32_t *sort_vals_alt = nullptr;
+    void *sort_temp = nullptr;
 };
 int sw_num_bins();
 void sw_bin_shape(int bin, int32_t *rows_per_lane, int32_t *multi);
@@ -195,8 +205,13 @@ hipError_t launch_xd(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
                      uint32_t *n_redo, int *gring, unsigned long long *counters, hipStream_t s);
 int64_t sw_scratch_waves();
 
+// use16: pass 1 of one-strip pairs in 16-bit lanes, two pairs per wave; its
+// records leave end_b = -1 for pairs that skip the statistics pass.
 hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pairs, int64_t npairs,
                      const int8_t *blosum, const Scoring &sc, SwPass1Out *p1, pastis_pair_record *out,
-                     const SwWork &wk, int stats_mode, hipStream_t s);
+                     const SwWork &wk, int stats_mode, bool use16, hipStream_t s);
+// 16-bit pass 1 needs o + e >= 4 (biased scores stay non-negative).
+bool sw16_supported(const Scoring &sc);
+bool sw_bin_is16(int bin);
 
 }  // namespace pastis

@@ -257,13 +257,16 @@ __device__ __forceinline__ int stream_elem(const Stream &w, int c, int lane) {
 __device__ __forceinline__ void stream_init(Stream &w, int lane) {
     w.ring[lane] = (uint8_t)stream_elem(w, 0, lane);
     w.ring[kWave + lane] = (uint8_t)stream_elem(w, 1, lane);
+    w.ring[2 * kWave + lane] = (uint8_t)kPadCode;  // every ring byte is a valid code
+    w.ring[3 * kWave + lane] = (uint8_t)kPadCode;
     w.pending = stream_elem(w, 2, lane);
     w.next = 2;
 }
 
-// make every index <= frontier + 64 readable
+// make every index <= frontier + 64 readable; frontier (wave-uniform) grows
+// by at most one per call, so one chunk at a time suffices
 __device__ __forceinline__ void stream_ensure(Stream &w, int frontier, int lane) {
-    while ((frontier >> 6) + 1 >= w.next) {
+    if ((frontier >> 6) + 1 >= w.next) {
         w.ring[(w.next & 3) * kWave + lane] = (uint8_t)w.pending;
         ++w.next;
         w.pending = stream_elem(w, w.next, lane);
@@ -286,6 +289,11 @@ __device__ __forceinline__ int wave_max_dpp(int v) {
     return __builtin_amdgcn_readlane(v, kWave - 1);
 }
 
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// (unsigned)(x - base) < len: x in [base, base + len) with one compare
+__device__ __forceinline__ bool in_range(int x, int base, int len) { return (unsigned)(x - base) < (unsigned)len; }
+
 __device__ Ext extend_reg(const uint8_t *a0, int la, int adir, const uint8_t *b0, int lb, int bdir,
                           const int8_t *sbl, int o, int e, int X, uint8_t *ring_a, uint8_t *ring_b, int lane) {
     const int oe = o + e;
@@ -297,8 +305,10 @@ __device__ Ext extend_reg(const uint8_t *a0, int la, int adir, const uint8_t *b0
     unsigned SH1 = 0u, SE1 = 0u, SF1 = 0u;
     int VH = kNeg;  // lane u-1's H two anti-diagonals back (rotated one step ago)
     unsigned VSH = 0u;
-    int clo1 = 0, chi1 = 0, llo1 = 0, lhi1 = 0;
-    int clo2 = 1, chi2 = 0, llo2 = 1, lhi2 = 0;
+    // computed (c) and live (l) row ranges of anti-diagonals d-1 and d-2 as
+    // (first row, count); count 0 = empty
+    int c1 = 0, n1 = 1, l1 = 0, m1 = 1;
+    int c2 = 0, n2 = 0, l2 = 0, m2 = 0;
     int best = 0, bu = 0, bv = 0;
     unsigned bmd = 0u;
     int cells = 0;
@@ -306,16 +316,16 @@ __device__ Ext extend_reg(const uint8_t *a0, int la, int adir, const uint8_t *b0
     const int dmax = la + lb;
     for (int d = 1; d <= dmax; ++d) {
         int lo = INT_MAX, hi = -1;
-        if (llo1 <= lhi1) {
-            lo = llo1;
-            hi = lhi1 + 1;
+        if (m1 > 0) {
+            lo = l1;
+            hi = l1 + m1;
         }
-        if (llo2 <= lhi2) {
-            lo = min(lo, llo2 + 1);
-            hi = max(hi, lhi2 + 1);
+        if (m2 > 0) {
+            lo = min(lo, l2 + 1);
+            hi = max(hi, l2 + m2);
         }
-        lo = max(lo, max(0, d - lb));
-        hi = min(hi, min(d, la));
+        lo = uni(max(lo, max(0, d - lb)));
+        hi = uni(min(hi, min(d, la)));
         if (lo > hi) break;
         if (hi - lo + 1 > kWave) {
             overflow = true;
@@ -323,42 +333,38 @@ __device__ Ext extend_reg(const uint8_t *a0, int la, int adir, const uint8_t *b0
         }
         const int u = lo + ((lane - lo) & (kWave - 1));
         const int v = d - u;
-        const bool inband = u <= hi;
-        // predecessors
+        // predecessors: (u-1, v) and (u, v-1) at d-1, (u-1, v-1) at d-2; v >= 1
+        // means u <= d-1, and rows of d-2 are <= d-2
         const int rH = ror1(H1), rF = ror1(F1);
         const unsigned rSH = (unsigned)ror1((int)SH1), rSF = (unsigned)ror1((int)SF1);
-        const bool okv = u - 1 >= clo1 && u - 1 <= chi1;             // (u-1, v) at d-1
-        const bool okh = v >= 1 && u >= clo1 && u <= chi1;           // (u, v-1) at d-1
-        const bool okd = u >= 1 && v >= 1 && u - 1 >= clo2 && u - 1 <= chi2;  // (u-1, v-1) at d-2
+        const int nh = uni(max(min(c1 + n1, d) - c1, 0));  // rows of d-1 in [c1, d-1]
+        const bool okv = in_range(u, c1 + 1, n1);
+        const bool okh = in_range(u, c1, nh);
+        const bool okd = in_range(u, c2 + 1, n2);
         const int Hu = okv ? rH : kNeg, Fu = okv ? rF : kNeg;
         const int Hl = okh ? H1 : kNeg, El = okh ? E1 : kNeg;
         const int Hd = okd ? VH : kNeg;
         const unsigned sHd = VSH;
         VH = rH;
         VSH = rSH;
-        // residues of the diagonal move
-        if (hi >= 1) stream_ensure(sa, hi - 1, lane);
-        if (d - lo - 1 >= 0) stream_ensure(sb, d - lo - 1, lane);
-        const bool ld = inband && Hd > kNeg / 2;
-        int sig = 0, same = 0;
-        if (ld) {
-            const int ca = ring_a[(u - 1) & 255], cb = ring_b[(v - 1) & 255];
-            sig = sbl[ca * kProfCodes + cb];
-            same = ca == cb;
-        }
-        const bool any = inband && (Hu > kNeg / 2 || Hl > kNeg / 2 || ld);
+        // residues of the diagonal move (ring indices always in range)
+        stream_ensure(sa, hi - 1, lane);
+        stream_ensure(sb, d - lo - 1, lane);
+        const int ca = ring_a[(u - 1) & 255], cb = ring_b[(v - 1) & 255];
+        const int sig = sbl[ca * kProfCodes + cb];
         const int e_ext = El - e, e_open = Hl - oe;
         const bool ee = e_ext >= e_open;
-        const int E_ = ee ? e_ext : e_open;
+        const int E_ = max(e_ext, e_open);
         const int f_ext = Fu - e, f_open = Hu - oe;
         const bool fe = f_ext >= f_open;
-        const int F_ = fe ? f_ext : f_open;
-        const int D_ = ld ? Hd + sig : kNeg;
-        const unsigned sD = sHd + (same ? 0x10001u : 1u);
+        const int F_ = max(f_ext, f_open);
+        const int D_ = Hd + sig;  // dead predecessors stay far below kNeg / 2
+        const unsigned sD = sHd + (ca == cb ? 0x10001u : 1u);
         const int H_ = max(D_, max(E_, F_));
         const unsigned sE_ = ee ? SE1 : SH1;
         const unsigned sF_ = fe ? rSF : rSH;
-        const unsigned sH_ = (ld && H_ == D_) ? sD : (H_ == E_ ? sE_ : sF_);
+        const unsigned sH_ = H_ == D_ ? sD : (H_ == E_ ? sE_ : sF_);
+        const bool any = u <= hi && max(Hd, max(Hu, Hl)) > kNeg / 2;
         const bool live = any && H_ >= best - X;
         cells += any ? 1 : 0;
         H1 = live ? H_ : kNeg;
@@ -368,23 +374,21 @@ __device__ Ext extend_reg(const uint8_t *a0, int la, int adir, const uint8_t *b0
         SE1 = sE_;
         SF1 = sF_;
         // live range and best cell of this anti-diagonal (u = lo + rotated lane)
-        const unsigned long long lm = rotr64(__ballot(live), lo & (kWave - 1));
-        clo2 = clo1;
-        chi2 = chi1;
-        llo2 = llo1;
-        lhi2 = lhi1;
-        clo1 = lo;
-        chi1 = hi;
-        if (lm == 0ull) {
-            llo1 = 1;
-            lhi1 = 0;
-            break;
-        }
-        llo1 = lo + __ffsll((long long)lm) - 1;
-        lhi1 = lo + 63 - __clzll((long long)lm);
-        const int dbest = wave_max_dpp(live ? H_ : INT_MIN);
-        if (dbest > best) {
-            const unsigned long long hit = rotr64(__ballot(live && H_ == dbest), lo & (kWave - 1));
+        const int sh = lo & (kWave - 1);
+        const unsigned long long lm = rotr64(__ballot(live), sh);
+        c2 = c1;
+        n2 = n1;
+        l2 = l1;
+        m2 = m1;
+        c1 = lo;
+        n1 = hi - lo + 1;
+        if (lm == 0ull) break;
+        l1 = lo + __ffsll((long long)lm) - 1;
+        m1 = lo + 64 - __clzll((long long)lm) - l1;
+        const unsigned long long up = __ballot(live && H_ > best);
+        if (up != 0ull) {
+            const int dbest = wave_max_dpp(live ? H_ : INT_MIN);
+            const unsigned long long hit = rotr64(__ballot(live && H_ == dbest), sh);
             const int off = __ffsll((long long)hit) - 1;
             best = dbest;
             bu = lo + off;

@@ -159,3 +159,68 @@ def test_sw_every_length_bin(gpu, orc):
             _compare(got, want)
         else:
             _compare(got, want, ("score", "end_a", "end_b", "passed", "swapped", "cells"))
+
+
+def _check16(got, want):
+    """16-bit pass 1: score, end row and the cut are exact for every pair; the
+    end column and statistics exist where the statistics pass ran, and every
+    pair without them fails the cut."""
+    _compare(got, want, ("score", "end_a", "passed", "swapped", "cells"))
+    have = got["beg_a"] >= 0
+    assert (want["passed"][~have] == 0).all()
+    _compare(got, want, ("beg_a", "beg_b", "matches", "columns"), mask=have)
+    _compare(got, want, ("end_b",), mask=got["end_b"] != -1)
+    assert (got["end_b"][have] >= 0).all()
+    return have
+
+
+def test_sw16_records_tiny(gpu, tiny):
+    s, cand, want = tiny
+    got = _gpu_records(gpu, s, cand["lo"], cand["hi"], score_width=16)
+    have = _check16(got, want)
+    assert have.sum() >= (want["passed"] == 1).sum() > 0
+
+
+def test_sw16_every_one_strip_bin_and_odd_counts(gpu, orc):
+    """Rows 1..512 (bins R = 1..8) with odd pair counts per bin, so the last
+    wave of a bin carries one pair."""
+    from synth.families import FamilySet
+
+    rng = np.random.default_rng(8)
+    lens = [1, 2, 63, 64, 65, 100, 128, 129, 191, 192, 193, 255, 256, 257, 320, 321, 383, 384, 385, 448, 449, 511,
+            512]
+    seqs = []
+    for L in lens:
+        a = rng.integers(0, 20, L)
+        b = a.copy()
+        sub = rng.random(L) < 0.3
+        b[sub] = rng.integers(0, 20, int(sub.sum()))
+        b = np.concatenate([rng.integers(0, 20, int(rng.integers(0, 40))), b, rng.integers(0, 20, 5)])
+        seqs += [a, b]
+    letters = np.frombuffer(b"ARNDCQEGHILKMFPSTWYV", np.uint8)
+    res = np.concatenate([letters[x] for x in seqs]).astype(np.uint8)
+    off = np.zeros(len(seqs) + 1, np.int64)
+    np.cumsum([len(x) for x in seqs], out=off[1:])
+    s = FamilySet(res, off, np.zeros(len(seqs), np.int32), {})
+    codes = orc.encode(s.residues)
+    lo = np.arange(0, len(seqs), 2, dtype=np.uint32)
+    hi = lo + 1
+    # plus every cross pair among the first 16 sequences: many pairs per bin
+    a, b = np.triu_indices(16, 1)
+    lo = np.concatenate([lo, a.astype(np.uint32)])
+    hi = np.concatenate([hi, b.astype(np.uint32)])
+    want = orc.align_pairs(codes, s.offsets, lo, hi, mode="sw")
+    got = _gpu_records(gpu, s, lo, hi, score_width=16)
+    _check16(got, want)
+
+
+def test_search_same_edges_in_16_and_32_bits(gpu):
+    import paper_2009_14467_amd as P
+    from synth import workload
+
+    s = workload("tiny", n_families=15)
+    res, off = _to_dev(s.residues, gpu), _to_dev(s.offsets, gpu)
+    e16 = P.Context(P.Params(k=6, ck_min=1, score_width=16)).search(res, off)
+    e32 = P.Context(P.Params(k=6, ck_min=1, score_width=32)).search(res, off)
+    assert e16.size == e32.size > 0
+    assert e16.tobytes() == e32.tobytes()

@@ -235,7 +235,7 @@ pastis_status align_core(pastis_ctx *ctx, const Staged &st, const uint8_t *codes
     PASTIS_TRY(read_flags(ctx, d_flags, h_flags, 2, s));
     if (h_flags[1] & 1ull) return set_error(ctx, PASTIS_E_INVAL, "pair index out of range or pi == pj");
     const pastis_params &P = ctx->params;
-    Scoring sc{P.gap_open, P.gap_extend, P.xdrop, P.min_identity_pct, P.min_coverage_pct};
+    Scoring sc{P.gap_open, P.gap_extend, P.xdrop, P.min_identity_pct, P.min_coverage_pct, ctx->sw_direct_pct};
     void *p1 = nullptr;
     PASTIS_TRY(ensure(ctx, kBufPass1, sizeof(SwPass1Out) * (size_t)npairs, &p1));
     SwWork wk;

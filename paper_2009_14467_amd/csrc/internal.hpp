@@ -33,6 +33,9 @@ struct DeviceBuffer {
 
 struct Scoring {
     int gap_open, gap_extend, xdrop, id_pct, cov_pct;
+    // pairs with 100 * score >= direct_pct * la skip the start-bound pass
+    // (likely to pass the cut); exact either way, only the cost moves
+    int direct_pct = 50;
 };
 
 // Oriented pair descriptor: rows a = shorter sequence (first on a tie).
@@ -98,8 +101,9 @@ struct pastis_ctx {
     int64_t n_candidates = 0;
     int64_t n_seqs_last = 0;
     bool have_candidates = false;
-    bool records_internal = false;
-    bool last_use16 = false;  // the last SW call ran 16-bit pass-1 bins  // the current alignment's records feed edges only
+    bool records_internal = false;  // the current alignment's records feed edges only
+    bool last_use16 = false;        // the last SW call ran 16-bit pass-1 bins
+    int sw_direct_pct = 50;         // see Scoring::direct_pct
     // learned filter
     pastis::MlpState mlp{};
     bool mlp_alloc = false, mlp_set = false;

@@ -493,8 +493,8 @@ __global__ void sw_bin1_kernel(const PairDesc *__restrict__ pairs, int64_t npair
 // and cells of the start-bound pass; counters[1], [2] in full-records mode).
 // stats_mode: 0 = only pairs whose coverage cut can hold, 1 = every aligned
 // pair, 2 = none (the normalised-score weight needs no traceback).
-__global__ void sw_bin2_kernel(const PairDesc *__restrict__ pairs, const SwPass1Out *__restrict__ p1,
-                               int64_t npairs, int cov_pct, int stats_mode, pastis_pair_record *__restrict__ out,
+__global__ void sw_bin2_kernel(const PairDesc *__restrict__ pairs, SwPass1Out *__restrict__ p1, int64_t npairs,
+                               int cov_pct, int stats_mode, int direct_pct, pastis_pair_record *__restrict__ out,
                                int8_t *__restrict__ bin_of, unsigned long long *__restrict__ counters) {
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= npairs) return;
@@ -508,6 +508,8 @@ __global__ void sw_bin2_kernel(const PairDesc *__restrict__ pairs, const SwPass1
         if (stats_mode == 1) {  // no start bound: every such pair takes pass 2
             atomicAdd(&counters[1], 1ull);
             atomicAdd(&counters[2], (unsigned long long)(r1.end_a + 1) * (unsigned long long)(r1.end_b + 1));
+        } else if (100LL * r1.score >= (long long)direct_pct * pd.la) {
+            p1[q].pad = -1;  // likely to pass: no start bound
         } else {
             const int cols = r1.end_b >= 0 ? r1.end_b + 1 : pd.lb;
             atomicAdd(&counters[3], 1ull);
@@ -570,6 +572,7 @@ __global__ __launch_bounds__(256) void sw_bound_kernel(const uint8_t *__restrict
         const int q = idx[w];
         const PairDesc pd = pairs[q];
         const SwPass1Out r1 = p1[q];
+        if (r1.pad < 0) continue;  // sent straight to the statistics pass
         // end_b < 0: unknown (16-bit pass 1); the end column is then the first
         // one where row end_a reaches the score
         const bool search = r1.end_b < 0;
@@ -682,9 +685,12 @@ __global__ void sw_bin3_kernel(const PairDesc *__restrict__ pairs, const SwPass1
     if (q >= npairs || bin_of[q] < 0) return;
     const PairDesc pd = pairs[q];
     const SwPass1Out r1 = p1[q];
-    if (100LL * (r1.end_a - r1.pad + 1) >= (long long)cov_pct * pd.la) {
+    // pad < 0: sent straight here (bound 0 in effect: the coverage test of
+    // the first binning already holds)
+    if (r1.pad < 0 || 100LL * (r1.end_a - r1.pad + 1) >= (long long)cov_pct * pd.la) {
+        const int cols = r1.end_b >= 0 ? r1.end_b + 1 : pd.lb;
         atomicAdd(&counters[1], 1ull);
-        atomicAdd(&counters[2], (unsigned long long)(r1.end_a + 1) * (unsigned long long)(r1.end_b + 1));
+        atomicAdd(&counters[2], (unsigned long long)(r1.end_a + 1) * (unsigned long long)cols);
         return;
     }
     bin_of[q] = -1;
@@ -730,10 +736,14 @@ __global__ __launch_bounds__(256) void sw_pass2_kernel(const uint8_t *__restrict
         const SwPass1Out r1 = p1[q];
         const uint8_t *a = codes + pd.a_off;
         const uint8_t *b = codes + pd.b_off;
-        const int la = r1.end_a + 1, lb = r1.end_b + 1;  // the rectangle ending at the end cell
+        // the rectangle ending at the end cell; with the end column unknown
+        // (16-bit pass 1), the full width until row end_a first reaches the score
+        const bool search = r1.end_b < 0;
+        const int la = r1.end_a + 1, lb = search ? pd.lb : r1.end_b + 1;
         const int nstrips = MULTI ? (la + RS - 1) / RS : 1;
         const int top = nstrips * RS - la;  // padding rows above row 0
         unsigned fin_beg = 0, fin_md = 0;
+        int fend = -1;
         for (int s = 0; s < nstrips; ++s) {
             const int base = s * RS - top + lane * R;
             build_profile<R>(prof, sblosum, a, la, base, lane);
@@ -854,9 +864,11 @@ __global__ __launch_bounds__(256) void sw_pass2_kernel(const uint8_t *__restrict
                 hprev = rh;
                 db_prev = rhb;
                 dm_prev = rhm;
-                if (last && lane == kWave - 1 && j == lb - 1) {
+                if (last && lane == kWave - 1 && j >= 0 && j < lb &&
+                    (search ? (fend < 0 && hlast == r1.score) : j == lb - 1)) {
                     fin_beg = hb_last;
                     fin_md = hm_last;
+                    fend = j;
                 }
                 if (MULTI && to_below && lane == kWave - 1 && j >= 0 && j < lb) {
                     bnd[j] = hlast;
@@ -866,6 +878,7 @@ __global__ __launch_bounds__(256) void sw_pass2_kernel(const uint8_t *__restrict
                     bnd[4 * plane + j] = (int)fb_last;
                     bnd[5 * plane + j] = (int)fm_last;
                 }
+                if (search && last && __builtin_amdgcn_readlane(fend, kWave - 1) >= 0) break;
             }
             if (MULTI) __threadfence_block();
         }
@@ -873,7 +886,7 @@ __global__ __launch_bounds__(256) void sw_pass2_kernel(const uint8_t *__restrict
             pastis_pair_record rec;
             rec.score = r1.score;
             rec.end_a = r1.end_a;
-            rec.end_b = r1.end_b;
+            rec.end_b = fend;
             rec.beg_a = (int32_t)(fin_beg >> 16);
             rec.beg_b = (int32_t)(fin_beg & 0xFFFF);
             rec.matches = (int32_t)(fin_md >> 16);
@@ -1022,7 +1035,8 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
     }
     if ((e = stage_end(ctx, kStAlign1, s)) != hipSuccess || (e = stage_begin(ctx, kStAlign2, s)) != hipSuccess)
         return e;
-    sw_bin2_kernel<<<nb, 256, 0, s>>>(pairs, p1, npairs, sc.cov_pct, stats_mode, out, wk.bin_of, wk.counters);
+    sw_bin2_kernel<<<nb, 256, 0, s>>>(pairs, p1, npairs, sc.cov_pct, stats_mode, sc.direct_pct, out, wk.bin_of,
+                                      wk.counters);
     if ((e = launch_bins(wk.bin_of, npairs, kNumBins, wk.counts, wk.starts2, wk.cursor, wk.idx2, s)) != hipSuccess)
         return e;
     if (stats_mode == 0) {

@@ -43,7 +43,8 @@ struct PairDesc {
     int64_t a_off, b_off;
     int32_t la, lb;
     int32_t pa1, pb1, pa2, pb2;  // oriented seeds (-1 when absent)
-    int32_t swapped, pad;
+    int32_t swapped;
+    int32_t a_seq;  // index of sequence a
 };
 
 // Stage timer: HIP events recorded on the call's stream, read after a sync.

@@ -89,7 +89,7 @@ __global__ void orient_kernel(const int64_t *__restrict__ offsets, int64_t n, co
     d.la = (int32_t)(swapped ? lj : li);
     d.lb = (int32_t)(swapped ? li : lj);
     d.swapped = swapped ? 1 : 0;
-    d.pad = 0;
+    d.a_seq = (int32_t)(swapped ? j : i);
     int32_t pa[2] = {-1, -1}, pb[2] = {-1, -1};
     for (int s = 0; s < 2; ++s) {
         const uint32_t *src = s == 0 ? seed1 : seed2;

@@ -278,17 +278,19 @@ __global__ __launch_bounds__(256) void sw_pass1_kernel(const uint8_t *__restrict
 // ---------------------------------------------------------------- pass 1, 16-bit lanes
 
 // Two pairs per wave in the 16-bit halves of every DP word (pair P low, Q
-// high), same lane layout as the 32-bit pass, one strip (R <= 8).  Only G =
-// H - (o + e) is kept per row: the diagonal term H(i-1, j-1) + s becomes
-// G(i-1, j-1) + (s + o + e), and the biased scores s + o + e >= 0 sit in an
-// int8 profile per pair (each row's two bytes are spread into the halves by
-// one byte permute).  Padding residues score -(o + e).  Each row keeps only
-// its maximum: cells outside the pair (padding rows and columns, columns
-// before the first) score strictly below the best real cell, so the score
-// and the first row holding it are exact; the end column is found later, by
-// the start-bound pass, for the pairs that need it (end_b = -1 here).
-// Scores stay below 11 * 512, far from the 16-bit limit.
-constexpr int kMax16R = 8;
+// high), same lane layout as the 32-bit pass, one strip (R <= 16).  The two
+// pairs share their shorter sequence a (pairs are sorted by bin, then a, then
+// the longer b first), so one int8 profile serves both; a wave whose two
+// items differ in a runs them one after the other.  Only G = H - (o + e) is
+// kept per row: the diagonal term H(i-1, j-1) + s becomes G(i-1, j-1) +
+// (s + o + e), with the biased scores s + o + e >= 0 in the profile (each
+// row's two bytes are spread into the halves by one byte permute).  Padding
+// residues score -(o + e).  Each row keeps only its maximum: cells outside a
+// pair (padding rows and columns, columns before the first) score strictly
+// below its best real cell, so the score and the first row holding it are
+// exact; the end column is found later, for the pairs that need it (end_b =
+// -1 here).  Scores stay below 11 * 1024, far from the 16-bit limit.
+constexpr int kMax16R = kMaxR;
 
 typedef short short2_t __attribute__((ext_vector_type(2)));
 
@@ -304,7 +306,7 @@ __device__ __forceinline__ void build_profile16(ProfWord<R> (*prof)[kWave], cons
 #pragma unroll
     for (int r = 0; r < R; ++r) ar[r] = (lane * R + r < la) ? a[lane * R + r] : kPadCode;
     for (int c = 0; c < kProfCodes; ++c) {
-        uint32_t w[2] = {0, 0};
+        uint32_t w[4] = {0, 0, 0, 0};
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int sc = max((int)sblosum[ar[r] * kProfCodes + c], -oe) + oe;
@@ -312,8 +314,10 @@ __device__ __forceinline__ void build_profile16(ProfWord<R> (*prof)[kWave], cons
         }
         if constexpr (R <= 4) {
             prof[c][lane] = w[0];
-        } else {
+        } else if constexpr (R <= 8) {
             prof[c][lane] = make_uint2(w[0], w[1]);
+        } else {
+            prof[c][lane] = make_uint4(w[0], w[1], w[2], w[3]);
         }
     }
 }
@@ -322,8 +326,10 @@ template <int R>
 __device__ __forceinline__ uint32_t prof_word(const ProfWord<R> &w, int r) {
     if constexpr (R <= 4) {
         return w;
-    } else {
+    } else if constexpr (R <= 8) {
         return r < 4 ? w.x : w.y;
+    } else {
+        return r < 4 ? w.x : r < 8 ? w.y : r < 12 ? w.z : w.w;
     }
 }
 
@@ -340,116 +346,124 @@ __global__ __launch_bounds__(64 * WPB) void sw16_pass1_kernel(const uint8_t *__r
                                                               const int *__restrict__ starts, int bin,
                                                               const int8_t *__restrict__ blosum, int go_ge, int ge,
                                                               SwPass1Out *__restrict__ out) {
-    static_assert(R <= kMax16R, "one strip of at most 512 rows");
-    __shared__ ProfWord<R> prof_all[WPB][2][kProfCodes][kWave];
+    static_assert(R <= kMax16R, "one strip");
+    __shared__ ProfWord<R> prof_all[WPB][kProfCodes][kWave];
     __shared__ int8_t sblosum[kProfCodes * kProfCodes];
     load_blosum(sblosum, blosum);
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
-    ProfWord<R>(*profP)[kWave] = prof_all[wave][0];
-    ProfWord<R>(*profQ)[kWave] = prof_all[wave][1];
+    ProfWord<R>(*prof)[kWave] = prof_all[wave];
     const int64_t gwave = (int64_t)blockIdx.x * WPB + wave;
     const int item_end = starts[bin + 1];
     const uint32_t OE2 = (uint32_t)go_ge * 0x10001u, GE2 = (uint32_t)ge * 0x10001u;
     const uint32_t NEG2 = 0xC000C000u;  // -16384 in both halves
-    const uint32_t BORDER = (uint32_t)(-go_ge) & 0xFFFFu;
-    const uint32_t G0 = BORDER * 0x10001u;  // G of an H = 0 cell, both halves
+    const uint32_t G0 = ((uint32_t)(-go_ge) & 0xFFFFu) * 0x10001u;  // G of an H = 0 cell
 
     for (int64_t w = starts[bin] + 2 * gwave; w < item_end; w += 2 * (int64_t)gridDim.x * WPB) {
-        const bool hasQ = w + 1 < item_end;
-        const int qP = idx[w], qQ = hasQ ? idx[w + 1] : qP;
-        const PairDesc pP = pairs[qP], pQ = pairs[qQ];
-        const int laP = pP.la, lbP = pP.lb;
-        const int laQ = hasQ ? pQ.la : 0, lbQ = hasQ ? pQ.lb : 0;
-        const uint8_t *aP = codes + pP.a_off, *bP = codes + pP.b_off;
-        const uint8_t *aQ = codes + pQ.a_off, *bQ = codes + pQ.b_off;
-        build_profile16<R>(profP, sblosum, aP, laP, lane, go_ge);
-        build_profile16<R>(profQ, sblosum, aQ, laQ, lane, go_ge);
-        const int lb = max(lbP, lbQ);
-        uint32_t G[R], E[R], M[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            G[r] = G0;
-            E[r] = NEG2;
-            M[r] = 0u;
-        }
-        uint32_t glast = G0, flast = NEG2, gprev = G0;
-        int cres = kPadCode | (kPadCode << 8);
-        auto col = [&](int c) {
-            const int x = c < lbP ? (int)bP[c] : kPadCode;
-            const int y = c < lbQ ? (int)bQ[c] : kPadCode;
-            return x | (y << 8);
-        };
-        int chunk = cres;
-        int nx = col(lane);
-        const int steps = lb > 0 ? lb + kWave - 1 : 0;
-        for (int t = 0; t < steps; ++t) {
-            if ((t & (kWave - 1)) == 0) {
-                chunk = nx;
-                nx = col(t + kWave + lane);
-            }
-            const int bt = __builtin_amdgcn_readlane(chunk, t & (kWave - 1));
-            const uint32_t rg = (uint32_t)shr1u(G0, glast);
-            const uint32_t rf = (uint32_t)shr1u(NEG2, flast);
-            cres = shr1(bt, cres);
-            const ProfWord<R> wP = profP[cres & 0xFF][lane];
-            const ProfWord<R> wQ = profQ[(cres >> 8) & 0xFF][lane];
-            short2_t gd = s2(gprev), gu = s2(rg), fu = s2(rf);
+        const bool two = w + 1 < item_end;
+        const int q0 = idx[w], q1 = two ? idx[w + 1] : q0;
+        const PairDesc d0 = pairs[q0], d1 = pairs[q1];
+        const bool same = two && d0.a_seq == d1.a_seq;
+        const int rounds = (two && !same) ? 2 : 1;
+        for (int round = 0; round < rounds; ++round) {
+            const PairDesc pP = round == 0 ? d0 : d1;
+            const int qP = round == 0 ? q0 : q1;
+            const bool hasQ = same;
+            const int laP = pP.la, lbP = pP.lb, lbQ = hasQ ? d1.lb : 0;
+            const uint8_t *bP = codes + pP.b_off, *bQ = codes + d1.b_off;
+            build_profile16<R>(prof, sblosum, codes + pP.a_off, laP, lane, go_ge);
+            const int lb = max(lbP, lbQ);
+            uint32_t G[R], E[R], M[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                // byte r of P's and Q's words into the two halves
-                const uint32_t sel = (uint32_t)(r & 3) | 0x0C00u | ((uint32_t)(4 + (r & 3)) << 16) | 0x0C000000u;
-                const short2_t sig = s2(__builtin_amdgcn_perm(prof_word<R>(wQ, r), prof_word<R>(wP, r), sel));
-                const short2_t e = pmax(s2(E[r]) - s2(GE2), s2(G[r]));
-                const short2_t f = pmax(fu - s2(GE2), gu);
-                const short2_t d = gd + sig;
-                const short2_t h = pmax(pmax(d, s2(0u)), pmax(e, f));
-                gd = s2(G[r]);
-                const short2_t g = h - s2(OE2);
-                G[r] = u2(g);
-                E[r] = u2(e);
-                M[r] = u2(pmax(s2(M[r]), h));
-                gu = g;
-                fu = f;
+                G[r] = G0;
+                E[r] = NEG2;
+                M[r] = 0u;
             }
-            glast = G[R - 1];
-            flast = u2(fu);
-            gprev = rg;
-        }
-        // best row of each pair: (score << 16) | (0xFFFF - row), maximised
-        unsigned kp = 0u, kq = 0u;
+            uint32_t glast = G0, flast = NEG2, gprev = G0;
+            int cres = kPadCode | (kPadCode << 8);
+            auto col = [&](int c) {
+                const int x = c < lbP ? (int)bP[c] : kPadCode;
+                const int y = c < lbQ ? (int)bQ[c] : kPadCode;
+                return x | (y << 8);
+            };
+            int chunk = cres;
+            int nx = col(lane);
+            const int steps = lb > 0 ? lb + kWave - 1 : 0;
+            for (int t = 0; t < steps; ++t) {
+                if ((t & (kWave - 1)) == 0) {
+                    chunk = nx;
+                    nx = col(t + kWave + lane);
+                }
+                const int bt = __builtin_amdgcn_readlane(chunk, t & (kWave - 1));
+                const uint32_t rg = (uint32_t)shr1u(G0, glast);
+                const uint32_t rf = (uint32_t)shr1u(NEG2, flast);
+                cres = shr1(bt, cres);
+                const ProfWord<R> wP = prof[cres & 0xFF][lane];
+                const ProfWord<R> wQ = prof[(cres >> 8) & 0xFF][lane];
+                short2_t gd = s2(gprev), gu = s2(rg), fu = s2(rf);
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int row = lane * R + r;
-            const unsigned sp = M[r] & 0xFFFFu, sq = M[r] >> 16;
-            const unsigned rk = 0xFFFFu - (unsigned)row;
-            if (row < laP) kp = max(kp, (sp << 16) | rk);
-            if (row < laQ) kq = max(kq, (sq << 16) | rk);
-        }
-        kp = wave_max_u32(kp);
-        kq = wave_max_u32(kq);
-        if (lane == 0) {
-            SwPass1Out o;
-            o.score = (int32_t)(kp >> 16);
-            o.end_a = o.score > 0 ? (int32_t)(0xFFFFu - (kp & 0xFFFFu)) : -1;
-            o.end_b = -1;
-            o.pad = 0;
-            out[qP] = o;
-            if (hasQ) {
-                o.score = (int32_t)(kq >> 16);
-                o.end_a = o.score > 0 ? (int32_t)(0xFFFFu - (kq & 0xFFFFu)) : -1;
-                out[qQ] = o;
+                for (int r = 0; r < R; ++r) {
+                    // byte r of P's and Q's words into the two halves
+                    const uint32_t sel =
+                        (uint32_t)(r & 3) | 0x0C00u | ((uint32_t)(4 + (r & 3)) << 16) | 0x0C000000u;
+                    const short2_t sig = s2(__builtin_amdgcn_perm(prof_word<R>(wQ, r), prof_word<R>(wP, r), sel));
+                    const short2_t e = pmax(s2(E[r]) - s2(GE2), s2(G[r]));
+                    const short2_t f = pmax(fu - s2(GE2), gu);
+                    const short2_t d = gd + sig;
+                    const short2_t h = pmax(pmax(d, s2(0u)), pmax(e, f));
+                    gd = s2(G[r]);
+                    const short2_t g = h - s2(OE2);
+                    G[r] = u2(g);
+                    E[r] = u2(e);
+                    M[r] = u2(pmax(s2(M[r]), h));
+                    gu = g;
+                    fu = f;
+                }
+                glast = G[R - 1];
+                flast = u2(fu);
+                gprev = rg;
+            }
+            // best row of each pair: (score << 16) | (0xFFFF - row), maximised
+            unsigned kp = 0u, kq = 0u;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int row = lane * R + r;
+                const unsigned rk = 0xFFFFu - (unsigned)row;
+                if (row < laP) {
+                    kp = max(kp, ((M[r] & 0xFFFFu) << 16) | rk);
+                    kq = max(kq, (M[r] & 0xFFFF0000u) | rk);
+                }
+            }
+            kp = wave_max_u32(kp);
+            kq = wave_max_u32(kq);
+            if (lane == 0) {
+                SwPass1Out o;
+                o.score = (int32_t)(kp >> 16);
+                o.end_a = o.score > 0 ? (int32_t)(0xFFFFu - (kp & 0xFFFFu)) : -1;
+                o.end_b = -1;
+                o.pad = 0;
+                out[qP] = o;
+                if (hasQ) {
+                    o.score = (int32_t)(kq >> 16);
+                    o.end_a = o.score > 0 ? (int32_t)(0xFFFFu - (kq & 0xFFFFu)) : -1;
+                    out[q1] = o;
+                }
             }
         }
     }
 }
 
-// sort keys of the pairing: bin, then the longer b first
+// sort keys of the pairing: bin, then sequence a (low 24 bits of its index;
+// the kernel checks equality itself), then the longer b first
+constexpr int kPairKeyBits = 48;
 __global__ void sw_pair_keys_kernel(const PairDesc *__restrict__ pairs, const int8_t *__restrict__ bin_of,
                                     int64_t npairs, uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= npairs) return;
-    keys[q] = ((uint64_t)(uint8_t)bin_of[q] << 16) | (uint64_t)(0xFFFF - pairs[q].lb);
+    const PairDesc pd = pairs[q];
+    keys[q] = ((uint64_t)(uint8_t)bin_of[q] << 40) | ((uint64_t)((uint32_t)pd.a_seq & 0xFFFFFFu) << 16) |
+              (uint64_t)(0xFFFF - pd.lb);
     vals[q] = (uint32_t)q;
 }
 
@@ -942,11 +956,16 @@ hipError_t launch_pb(int bin, int blocks, const uint8_t *codes, const PairDesc *
     return hipGetLastError();
 }
 
+// waves per block of the 16-bit pass: one int8 profile of 25 x 64 x R bytes
+// per wave, blocks of at most ~51 KB of LDS
+constexpr int wpb16(int R) { return R <= 8 ? 4 : 2; }
+static int blocks16(int R) { return R <= 4 ? 256 * 6 : 256 * 3; }
+
 template <int R>
 hipError_t launch_p16(int bin, int blocks, const uint8_t *codes, const PairDesc *pairs, const int *idx,
                       const int *starts, const int8_t *blosum, int go_ge, int ge, SwPass1Out *p1, int *, int64_t,
                       hipStream_t s) {
-    constexpr int WPB = R <= 4 ? 4 : 2;  // LDS: two int8 profiles of 25 x 64 x R bytes per wave
+    constexpr int WPB = wpb16(R);
     sw16_pass1_kernel<R, WPB><<<blocks, 64 * WPB, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, p1);
     return hipGetLastError();
 }
@@ -960,8 +979,10 @@ const P1Fn kP1[kNumBins] = {launch_p1<1>,  launch_p1<2>,  launch_p1<3>,  launch_
                             launch_p1<7>,  launch_p1<8>,  launch_p1<9>,  launch_p1<10>, launch_p1<11>, launch_p1<12>,
                             launch_p1<13>, launch_p1<14>, launch_p1<15>, launch_p1<16>, launch_p1<9>,  launch_p1<10>,
                             launch_p1<11>, launch_p1<12>, launch_p1<13>, launch_p1<14>, launch_p1<15>, launch_p1<16>};
-const P1Fn kP16[kMax16R] = {launch_p16<1>, launch_p16<2>, launch_p16<3>, launch_p16<4>,
-                            launch_p16<5>, launch_p16<6>, launch_p16<7>, launch_p16<8>};
+const P1Fn kP16[kMax16R] = {launch_p16<1>,  launch_p16<2>,  launch_p16<3>,  launch_p16<4>,
+                            launch_p16<5>,  launch_p16<6>,  launch_p16<7>,  launch_p16<8>,
+                            launch_p16<9>,  launch_p16<10>, launch_p16<11>, launch_p16<12>,
+                            launch_p16<13>, launch_p16<14>, launch_p16<15>, launch_p16<16>};
 const P1Fn kPB[kNumBins] = {launch_pb<1>,  launch_pb<2>,  launch_pb<3>,  launch_pb<4>,  launch_pb<5>,  launch_pb<6>,
                             launch_pb<7>,  launch_pb<8>,  launch_pb<9>,  launch_pb<10>, launch_pb<11>, launch_pb<12>,
                             launch_pb<13>, launch_pb<14>, launch_pb<15>, launch_pb<16>, launch_pb<9>,  launch_pb<10>,
@@ -997,7 +1018,7 @@ int64_t sw_scratch_waves() {
 
 bool sw16_supported(const Scoring &sc) { return sc.gap_open + sc.gap_extend >= 4; }
 
-bool sw_bin_is16(int bin) { return bin < kMax16R; }
+bool sw_bin_is16(int bin) { return bin < kSingleBins; }
 
 hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pairs, int64_t npairs,
                      const int8_t *blosum, const Scoring &sc, SwPass1Out *p1, pastis_pair_record *out,
@@ -1012,12 +1033,12 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
         return e;
     const int *idx1 = wk.idx;
     if (use16) {
-        // pair up similar columns counts: bin order, then the longer b first
+        // pair up pairs of one sequence a with similar column counts
         sw_pair_keys_kernel<<<nb, 256, 0, s>>>(pairs, wk.bin_of, npairs, wk.sort_keys, (uint32_t *)wk.idx);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         bool alt = false;
-        if ((e = radix_sort(wk.sort_keys, (uint32_t *)wk.idx, wk.sort_keys_alt, wk.sort_vals_alt, npairs, 24,
-                            wk.sort_temp, s, &alt)) != hipSuccess)
+        if ((e = radix_sort(wk.sort_keys, (uint32_t *)wk.idx, wk.sort_keys_alt, wk.sort_vals_alt, npairs,
+                            kPairKeyBits, wk.sort_temp, s, &alt)) != hipSuccess)
             return e;
         if (alt) idx1 = (const int *)wk.sort_vals_alt;
     }
@@ -1026,7 +1047,8 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
     for (int bin = 0; bin < kNumBins; ++bin) {
         if ((e = hipEventRecord(ctx->bin_ev[2 * bin], s)) != hipSuccess) return e;
         if (use16 && sw_bin_is16(bin))
-            e = kP16[bin](bin, 256 * 3, codes, pairs, idx1, wk.starts, blosum, go_ge, ge, p1, nullptr, 0, s);
+            e = kP16[bin](bin, blocks16(rows_of_bin(bin)), codes, pairs, idx1, wk.starts, blosum, go_ge, ge, p1, nullptr,
+                          0, s);
         else
             e = kP1[bin](bin, blocks_for_bin(bin), codes, pairs, idx1, wk.starts, blosum, go_ge, ge, p1, wk.scratch,
                          wk.scratch_per_wave, s);

@@ -182,13 +182,14 @@ def test_sw16_records_tiny(gpu, tiny):
 
 
 def test_sw16_every_one_strip_bin_and_odd_counts(gpu, orc):
-    """Rows 1..512 (bins R = 1..8) with odd pair counts per bin, so the last
-    wave of a bin carries one pair."""
+    """Rows 1..1024 (one-strip bins R = 1..16) with odd pair counts per bin,
+    so the last wave of a bin carries one pair, and several pairs sharing
+    their shorter sequence (the 16-bit pass pairs those in one wave)."""
     from synth.families import FamilySet
 
     rng = np.random.default_rng(8)
     lens = [1, 2, 63, 64, 65, 100, 128, 129, 191, 192, 193, 255, 256, 257, 320, 321, 383, 384, 385, 448, 449, 511,
-            512]
+            512, 513, 640, 641, 768, 769, 896, 897, 1023, 1024]
     seqs = []
     for L in lens:
         a = rng.integers(0, 20, L)

@@ -43,7 +43,9 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kNeg = -(1 << 28);
-constexpr int kWavesPerBlock = 4;
+// waves per block of the 32-bit kernels: one int8 profile of 25 x 64 x R
+// bytes per wave, blocks of at most ~51 KB of LDS (three per CU)
+__host__ __device__ constexpr int wpb32(int R) { return R <= 8 ? 4 : 2; }
 constexpr int kProfCodes = kAlpha + 1;  // 24 residues + the pad code
 constexpr int kMaxR = 16;               // rows per lane
 constexpr int kSingleBins = kMaxR;      // bins 0..15: one strip of 64 * (bin + 1) rows
@@ -62,20 +64,41 @@ __device__ __forceinline__ int shr1(int lane0, int v) {
     return __builtin_amdgcn_update_dpp(lane0, v, kDppWaveShr1, 0xF, 0xF, false);
 }
 
+// R int8 scores per lane and residue code, in ceil(R / 4) words
 template <int R>
-using ProfWord =
-    typename std::conditional<(R <= 4), uint32_t, typename std::conditional<(R <= 8), uint2, uint4>::type>::type;
+using ProfWord = typename std::conditional<
+    (R <= 4), uint32_t,
+    typename std::conditional<(R <= 8), uint2, typename std::conditional<(R <= 12), uint3, uint4>::type>::type>::type;
+
+template <int R>
+__device__ __forceinline__ uint32_t word_of(const ProfWord<R> &w, int k) {
+    if constexpr (R <= 4) {
+        return w;
+    } else if constexpr (R <= 8) {
+        return k == 0 ? w.x : w.y;
+    } else if constexpr (R <= 12) {
+        return k == 0 ? w.x : k == 1 ? w.y : w.z;
+    } else {
+        return k == 0 ? w.x : k == 1 ? w.y : k == 2 ? w.z : w.w;
+    }
+}
+
+template <int R>
+__device__ __forceinline__ ProfWord<R> make_word(const uint32_t (&w)[4]) {
+    if constexpr (R <= 4) {
+        return w[0];
+    } else if constexpr (R <= 8) {
+        return make_uint2(w[0], w[1]);
+    } else if constexpr (R <= 12) {
+        return make_uint3(w[0], w[1], w[2]);
+    } else {
+        return make_uint4(w[0], w[1], w[2], w[3]);
+    }
+}
 
 template <int R>
 __device__ __forceinline__ int sigma_at(const ProfWord<R> &w, int r) {
-    if constexpr (R <= 4) {
-        return (int)(int8_t)(w >> (8 * r));
-    } else if constexpr (R <= 8) {
-        return r < 4 ? (int)(int8_t)(w.x >> (8 * r)) : (int)(int8_t)(w.y >> (8 * (r - 4)));
-    } else {
-        const uint32_t x = r < 4 ? w.x : r < 8 ? w.y : r < 12 ? w.z : w.w;
-        return (int)(int8_t)(x >> (8 * (r & 3)));
-    }
+    return (int)(int8_t)(word_of<R>(w, r >> 2) >> (8 * (r & 3)));
 }
 
 template <int R>
@@ -88,13 +111,7 @@ __device__ __forceinline__ void build_profile(ProfWord<R> (*prof)[kWave], const 
         uint32_t w[4] = {0, 0, 0, 0};
 #pragma unroll
         for (int r = 0; r < R; ++r) w[r >> 2] |= (uint32_t)(uint8_t)sblosum[ar[r] * kProfCodes + c] << (8 * (r & 3));
-        if constexpr (R <= 4) {
-            prof[c][lane] = w[0];
-        } else if constexpr (R <= 8) {
-            prof[c][lane] = make_uint2(w[0], w[1]);
-        } else {
-            prof[c][lane] = make_uint4(w[0], w[1], w[2], w[3]);
-        }
+        prof[c][lane] = make_word<R>(w);
     }
 }
 
@@ -124,25 +141,26 @@ __device__ __forceinline__ T vload(const T *p) {
 // ---------------------------------------------------------------- pass 1
 
 template <int R, bool MULTI>
-__global__ __launch_bounds__(256) void sw_pass1_kernel(const uint8_t *__restrict__ codes,
+__global__ __launch_bounds__(64 * wpb32(R)) void sw_pass1_kernel(const uint8_t *__restrict__ codes,
                                                        const PairDesc *__restrict__ pairs,
                                                        const int *__restrict__ idx, const int *__restrict__ starts,
                                                        int bin, const int8_t *__restrict__ blosum, int go_ge, int ge,
                                                        SwPass1Out *__restrict__ out, int *__restrict__ scratch,
                                                        int64_t scratch_per_wave) {
-    __shared__ ProfWord<R> prof_all[kWavesPerBlock][kProfCodes][kWave];
+    constexpr int WPB = wpb32(R);
+    __shared__ ProfWord<R> prof_all[WPB][kProfCodes][kWave];
     __shared__ int8_t sblosum[kProfCodes * kProfCodes];
     load_blosum(sblosum, blosum);
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
     ProfWord<R>(*prof)[kWave] = prof_all[wave];
-    const int64_t gwave = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+    const int64_t gwave = (int64_t)blockIdx.x * WPB + wave;
     int *bnd_h = scratch + gwave * scratch_per_wave;  // bottom row H / F of the strip above
     int *bnd_f = bnd_h + scratch_per_wave / 2;
     const int item_end = starts[bin + 1];
     constexpr int RS = kWave * R;
 
-    for (int64_t w = starts[bin] + gwave; w < item_end; w += (int64_t)gridDim.x * kWavesPerBlock) {
+    for (int64_t w = starts[bin] + gwave; w < item_end; w += (int64_t)gridDim.x * WPB) {
         const int q = idx[w];
         const PairDesc pd = pairs[q];
         const uint8_t *a = codes + pd.a_off;
@@ -312,25 +330,13 @@ __device__ __forceinline__ void build_profile16(ProfWord<R> (*prof)[kWave], cons
             const int sc = max((int)sblosum[ar[r] * kProfCodes + c], -oe) + oe;
             w[r >> 2] |= (uint32_t)sc << (8 * (r & 3));
         }
-        if constexpr (R <= 4) {
-            prof[c][lane] = w[0];
-        } else if constexpr (R <= 8) {
-            prof[c][lane] = make_uint2(w[0], w[1]);
-        } else {
-            prof[c][lane] = make_uint4(w[0], w[1], w[2], w[3]);
-        }
+        prof[c][lane] = make_word<R>(w);
     }
 }
 
 template <int R>
 __device__ __forceinline__ uint32_t prof_word(const ProfWord<R> &w, int r) {
-    if constexpr (R <= 4) {
-        return w;
-    } else if constexpr (R <= 8) {
-        return r < 4 ? w.x : w.y;
-    } else {
-        return r < 4 ? w.x : r < 8 ? w.y : r < 12 ? w.z : w.w;
-    }
+    return word_of<R>(w, r >> 2);
 }
 
 __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
@@ -390,7 +396,7 @@ __global__ __launch_bounds__(64 * WPB) void sw16_pass1_kernel(const uint8_t *__r
             int chunk = cres;
             int nx = col(lane);
             const int steps = lb > 0 ? lb + kWave - 1 : 0;
-            for (int t = 0; t < steps; ++t) {
+            auto step = [&](const int t) {
                 if ((t & (kWave - 1)) == 0) {
                     chunk = nx;
                     nx = col(t + kWave + lane);
@@ -423,7 +429,15 @@ __global__ __launch_bounds__(64 * WPB) void sw16_pass1_kernel(const uint8_t *__r
                 glast = G[R - 1];
                 flast = u2(fu);
                 gprev = rg;
+            };
+            // two steps per iteration, so the old and new G registers can swap
+            // roles instead of being copied back every step
+            int t = 0;
+            for (; t + 1 < steps; t += 2) {
+                step(t);
+                step(t + 1);
             }
+            if (t < steps) step(t);
             // best row of each pair: (score << 16) | (0xFFFF - row), maximised
             unsigned kp = 0u, kq = 0u;
 #pragma unroll
@@ -561,19 +575,20 @@ constexpr int kBoundMaxRows = 32000 / 11;
 // coverage of a is at most end_a - bound + 1.  The bound goes to p1[q].pad.
 // Taller rectangles keep bound 0 (no pruning).
 template <int R, bool MULTI>
-__global__ __launch_bounds__(256) void sw_bound_kernel(const uint8_t *__restrict__ codes,
+__global__ __launch_bounds__(64 * wpb32(R)) void sw_bound_kernel(const uint8_t *__restrict__ codes,
                                                        const PairDesc *__restrict__ pairs,
                                                        const int *__restrict__ idx, const int *__restrict__ starts,
                                                        int bin, const int8_t *__restrict__ blosum, int go_ge, int ge,
                                                        SwPass1Out *__restrict__ p1, int *__restrict__ scratch,
                                                        int64_t scratch_per_wave) {
-    __shared__ ProfWord<R> prof_all[kWavesPerBlock][kProfCodes][kWave];
+    constexpr int WPB = wpb32(R);
+    __shared__ ProfWord<R> prof_all[WPB][kProfCodes][kWave];
     __shared__ int8_t sblosum[kProfCodes * kProfCodes];
     load_blosum(sblosum, blosum);
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
     ProfWord<R>(*prof)[kWave] = prof_all[wave];
-    const int64_t gwave = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+    const int64_t gwave = (int64_t)blockIdx.x * WPB + wave;
     int *bnd_h = scratch + gwave * scratch_per_wave;
     int *bnd_f = bnd_h + scratch_per_wave / 2;
     const int item_end = starts[bin + 1];
@@ -582,7 +597,7 @@ __global__ __launch_bounds__(256) void sw_bound_kernel(const uint8_t *__restrict
     constexpr int kZero = 0xFFFF;  // score 0, start row 0
     const int GO = go_ge * 65536, GE = ge * 65536;
 
-    for (int64_t w = starts[bin] + gwave; w < item_end; w += (int64_t)gridDim.x * kWavesPerBlock) {
+    for (int64_t w = starts[bin] + gwave; w < item_end; w += (int64_t)gridDim.x * WPB) {
         const int q = idx[w];
         const PairDesc pd = pairs[q];
         const SwPass1Out r1 = p1[q];
@@ -724,27 +739,28 @@ __global__ void sw_bin3_kernel(const PairDesc *__restrict__ pairs, const SwPass1
 // ---------------------------------------------------------------- pass 2
 
 template <int R, bool MULTI>
-__global__ __launch_bounds__(256) void sw_pass2_kernel(const uint8_t *__restrict__ codes,
+__global__ __launch_bounds__(64 * wpb32(R)) void sw_pass2_kernel(const uint8_t *__restrict__ codes,
                                                        const PairDesc *__restrict__ pairs,
                                                        const int *__restrict__ idx, const int *__restrict__ starts,
                                                        int bin, const int8_t *__restrict__ blosum, int go_ge, int ge,
                                                        int cov_pct, int id_pct, const SwPass1Out *__restrict__ p1,
                                                        pastis_pair_record *__restrict__ out,
                                                        int *__restrict__ scratch, int64_t scratch_per_wave) {
-    __shared__ ProfWord<R> prof_all[kWavesPerBlock][kProfCodes][kWave];
+    constexpr int WPB = wpb32(R);
+    __shared__ ProfWord<R> prof_all[WPB][kProfCodes][kWave];
     __shared__ int8_t sblosum[kProfCodes * kProfCodes];
     load_blosum(sblosum, blosum);
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
     ProfWord<R>(*prof)[kWave] = prof_all[wave];
-    const int64_t gwave = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+    const int64_t gwave = (int64_t)blockIdx.x * WPB + wave;
     // strip bottom row per column: H, F, H.beg, H.md, F.beg, F.md
     int *bnd = scratch + gwave * scratch_per_wave;
     const int64_t plane = scratch_per_wave / 6;
     const int item_end = starts[bin + 1];
     constexpr int RS = kWave * R;
 
-    for (int64_t w = starts[bin] + gwave; w < item_end; w += (int64_t)gridDim.x * kWavesPerBlock) {
+    for (int64_t w = starts[bin] + gwave; w < item_end; w += (int64_t)gridDim.x * WPB) {
         const int q = idx[w];
         const PairDesc pd = pairs[q];
         const SwPass1Out r1 = p1[q];
@@ -922,10 +938,10 @@ hipError_t launch_p1(int bin, int blocks, const uint8_t *codes, const PairDesc *
                      const int *starts, const int8_t *blosum, int go_ge, int ge, SwPass1Out *p1, int *scratch,
                      int64_t spw, hipStream_t s) {
     if (bin >= kMultiBin)
-        sw_pass1_kernel<R, true><<<blocks, 256, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, p1, scratch,
+        sw_pass1_kernel<R, true><<<blocks, 64 * wpb32(R), 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, p1, scratch,
                                                         spw);
     else
-        sw_pass1_kernel<R, false><<<blocks, 256, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, p1,
+        sw_pass1_kernel<R, false><<<blocks, 64 * wpb32(R), 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, p1,
                                                          scratch, spw);
     return hipGetLastError();
 }
@@ -935,10 +951,10 @@ hipError_t launch_p2(int bin, int blocks, const uint8_t *codes, const PairDesc *
                      const int *starts, const int8_t *blosum, int go_ge, int ge, int cov, int id,
                      const SwPass1Out *p1, pastis_pair_record *out, int *scratch, int64_t spw, hipStream_t s) {
     if (bin >= kMultiBin)
-        sw_pass2_kernel<R, true><<<blocks, 256, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, cov, id, p1,
+        sw_pass2_kernel<R, true><<<blocks, 64 * wpb32(R), 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, cov, id, p1,
                                                         out, scratch, spw);
     else
-        sw_pass2_kernel<R, false><<<blocks, 256, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, cov, id,
+        sw_pass2_kernel<R, false><<<blocks, 64 * wpb32(R), 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, cov, id,
                                                          p1, out, scratch, spw);
     return hipGetLastError();
 }
@@ -948,10 +964,10 @@ hipError_t launch_pb(int bin, int blocks, const uint8_t *codes, const PairDesc *
                      const int *starts, const int8_t *blosum, int go_ge, int ge, SwPass1Out *p1, int *scratch,
                      int64_t spw, hipStream_t s) {
     if (bin >= kMultiBin)
-        sw_bound_kernel<R, true><<<blocks, 256, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, p1, scratch,
+        sw_bound_kernel<R, true><<<blocks, 64 * wpb32(R), 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, p1, scratch,
                                                         spw);
     else
-        sw_bound_kernel<R, false><<<blocks, 256, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, p1,
+        sw_bound_kernel<R, false><<<blocks, 64 * wpb32(R), 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, p1,
                                                          scratch, spw);
     return hipGetLastError();
 }
@@ -959,7 +975,7 @@ hipError_t launch_pb(int bin, int blocks, const uint8_t *codes, const PairDesc *
 // waves per block of the 16-bit pass: one int8 profile of 25 x 64 x R bytes
 // per wave, blocks of at most ~51 KB of LDS
 constexpr int wpb16(int R) { return R <= 8 ? 4 : 2; }
-static int blocks16(int R) { return R <= 4 ? 256 * 6 : 256 * 3; }
+static int blocks16(int R) { return R <= 4 ? 256 * 6 : (R > 8 && R <= 12) ? 256 * 4 : 256 * 3; }
 
 template <int R>
 hipError_t launch_p16(int bin, int blocks, const uint8_t *codes, const PairDesc *pairs, const int *idx,
@@ -1006,13 +1022,14 @@ void sw_bin_shape(int bin, int32_t *rows_per_lane, int32_t *multi) {
 // the grid-stride loop reads the bin size on the device.
 static int blocks_for_bin(int bin) {
     const int r = rows_of_bin(bin);
-    return r <= 4 ? 256 * 6 : r <= 8 ? 256 * 3 : 256;
+    return r <= 4 ? 256 * 6 : (r > 8 && r <= 12) ? 256 * 4 : 256 * 3;
 }
 
 // Only the multi-strip bins use the boundary buffers.
 int64_t sw_scratch_waves() {
     int64_t w = 0;
-    for (int b = kMultiBin; b < kNumBins; ++b) w = std::max<int64_t>(w, (int64_t)blocks_for_bin(b) * kWavesPerBlock);
+    for (int b = kMultiBin; b < kNumBins; ++b)
+        w = std::max<int64_t>(w, (int64_t)blocks_for_bin(b) * wpb32(rows_of_bin(b)));
     return w;
 }
 

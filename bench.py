@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-filter leg")
     ap.add_argument("--mlp-epochs", type=int, default=4)
     ap.add_argument("--no-xd", action="store_true", help="skip the x-drop leg")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default alignment schedule")
+    ap.add_argument("--tune-pairs", type=int, default=2_000_000, help="candidate sample size of the autotuner")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one 1 GiB device-to-device copy (a reference for HBM byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
@@ -214,6 +216,12 @@ def main():
     res = torch.from_numpy(fs.residues).to(dev)
     off = torch.from_numpy(fs.offsets).to(dev)
     ctx = P.Context(P.Params(**params))
+    tuning = None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        tuning = ctx.autotune(res, off, max_pairs=args.tune_pairs)
+        torch.cuda.synchronize()
+        tuning = dict(tuning, seconds=time.perf_counter() - t0, sample_pairs=args.tune_pairs)
 
     for _ in range(args.warmup):
         ctx.search(res, off)
@@ -290,6 +298,7 @@ def main():
             "all_pass1_bins": {"achieved": pass1_tops, "frac_of_mix_peak": mix_peak_s / (pass1_ms * 1e-3)},
         },
         "sw_bins": [dict(b, gcups=b["cells"] / max(b["ms"], 1e-9) / 1e6) for b in st["sw_bins"] if b["pairs"]],
+        "schedule": tuning if tuning is not None else "default",
     }
     if not args.no_xd:
         line["xd"] = xd_leg(P, args, params, res, off, n_cand)

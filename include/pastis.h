@@ -274,6 +274,32 @@ pastis_status pastis_mlp_train_epoch(pastis_ctx *ctx, const float *X, const uint
 pastis_status pastis_mlp_calibrate(pastis_ctx *ctx, const float *X, const uint8_t *labels, int64_t n,
                                    double target_recall, float *tau, void *stream);
 
+/* ---- schedule of the Smith-Waterman stage ----
+ * Knobs of the length-binned launches (every setting gives the same results;
+ * only the time changes).  pastis_autotune times candidate settings on a
+ * sample of the given sequences' own candidate pairs and keeps the fastest. */
+typedef struct pastis_tuning {
+    int32_t sw16_max_rows; /* one-strip bins with at most this many rows per lane run two
+                              pairs per wave in 16-bit lanes (0: none; at most 16), where
+                              16-bit lanes are in use (see score_width) */
+    int32_t sw_direct_pct; /* pairs with 100 * score >= this * (shorter length) skip the
+                              start-bound pass and go straight to the statistics pass */
+    int32_t sw_grid_scale; /* pass-1 launches get this many times the blocks that fit on
+                              the device at once (1..4) */
+    int32_t reserved[5];
+} pastis_tuning;
+
+pastis_status pastis_get_tuning(const pastis_ctx *ctx, pastis_tuning *out);
+/* PASTIS_E_INVAL for values out of range. */
+pastis_status pastis_set_tuning(pastis_ctx *ctx, const pastis_tuning *t);
+/* Discovery on the given sequences, then for each knob in turn (16-bit rows,
+ * start-bound routing, grid scale) the alignment of up to max_pairs of the
+ * candidates (an even stride through them) under each candidate value, twice,
+ * timed with HIP events on the stream; the fastest setting is kept in ctx and
+ * written to *out (may be NULL).  The discovery's candidates stay in ctx. */
+pastis_status pastis_autotune(pastis_ctx *ctx, const uint8_t *residues, const int64_t *offsets, int64_t n,
+                              int input_on_device, int64_t max_pairs, void *stream, pastis_tuning *out);
+
 /* Counters and per-stage times of the last pastis_search / pastis_align_pairs. */
 pastis_status pastis_stats(const pastis_ctx *ctx, pastis_run_stats *out);
 

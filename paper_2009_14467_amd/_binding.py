@@ -85,6 +85,15 @@ class _Params(ctypes.Structure):
     ]
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [
+        ("sw16_max_rows", ctypes.c_int32),
+        ("sw_direct_pct", ctypes.c_int32),
+        ("sw_grid_scale", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 5),
+    ]
+
+
 class _Stats(ctypes.Structure):
     _fields_ = [
         ("n_sequences", ctypes.c_int64),
@@ -181,6 +190,10 @@ _SIGNATURES = [
     ("pastis_mlp_train_epoch", ctypes.c_int,
      [_VP, _VP, _VP, ctypes.c_int64, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_float, ctypes.c_float, _VP, _VP]),
     ("pastis_mlp_calibrate", ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_double, _VP, _VP]),
+    ("pastis_get_tuning", ctypes.c_int, [_VP, ctypes.POINTER(_Tuning)]),
+    ("pastis_set_tuning", ctypes.c_int, [_VP, ctypes.POINTER(_Tuning)]),
+    ("pastis_autotune", ctypes.c_int,
+     [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_int, ctypes.c_int64, _VP, ctypes.POINTER(_Tuning)]),
 ]
 
 MLP_FEATURES = 16
@@ -347,6 +360,26 @@ class Context:
             return out
         finally:
             lib().pastis_result_free(res)
+
+    # ---- schedule of the alignment stage ----
+
+    def get_tuning(self) -> dict:
+        t = _Tuning()
+        self._check(lib().pastis_get_tuning(self._ctx, ctypes.byref(t)))
+        return {"sw16_max_rows": t.sw16_max_rows, "sw_direct_pct": t.sw_direct_pct, "sw_grid_scale": t.sw_grid_scale}
+
+    def set_tuning(self, sw16_max_rows: int = 16, sw_direct_pct: int = 50, sw_grid_scale: int = 1):
+        t = _Tuning()
+        t.sw16_max_rows, t.sw_direct_pct, t.sw_grid_scale = sw16_max_rows, sw_direct_pct, sw_grid_scale
+        self._check(lib().pastis_set_tuning(self._ctx, ctypes.byref(t)))
+
+    def autotune(self, residues, offsets, max_pairs: int = 1 << 21, stream=None) -> dict:
+        """Time schedule settings on a sample of these sequences' candidates and keep the fastest."""
+        t = _Tuning()
+        n = offsets.numel() - 1
+        self._check(lib().pastis_autotune(self._ctx, _dev_ptr(residues), _dev_ptr(offsets), n, int(residues.is_cuda),
+                                          int(max_pairs), _stream_ptr(stream), ctypes.byref(t)))
+        return {"sw16_max_rows": t.sw16_max_rows, "sw_direct_pct": t.sw_direct_pct, "sw_grid_scale": t.sw_grid_scale}
 
     # ---- learned pre-alignment filter ----
 

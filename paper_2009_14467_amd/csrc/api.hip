@@ -235,7 +235,7 @@ pastis_status align_core(pastis_ctx *ctx, const Staged &st, const uint8_t *codes
     PASTIS_TRY(read_flags(ctx, d_flags, h_flags, 2, s));
     if (h_flags[1] & 1ull) return set_error(ctx, PASTIS_E_INVAL, "pair index out of range or pi == pj");
     const pastis_params &P = ctx->params;
-    Scoring sc{P.gap_open, P.gap_extend, P.xdrop, P.min_identity_pct, P.min_coverage_pct, ctx->sw_direct_pct};
+    Scoring sc{P.gap_open, P.gap_extend, P.xdrop, P.min_identity_pct, P.min_coverage_pct, ctx->tune.sw_direct_pct};
     void *p1 = nullptr;
     PASTIS_TRY(ensure(ctx, kBufPass1, sizeof(SwPass1Out) * (size_t)npairs, &p1));
     SwWork wk;
@@ -243,7 +243,7 @@ pastis_status align_core(pastis_ctx *ctx, const Staged &st, const uint8_t *codes
     HIP_TRY(ctx, fill<unsigned long long>(wk.counters, kNumCounters, 0ull, s), "reset");
     ctx->stats.sw_bins = 0;
     ctx->stats.int32_pairs = 0;
-    ctx->last_use16 = false;
+    ctx->last_max16 = 0;
     // traceback statistics: every pair on request; none for the normalised
     // score weight; otherwise only where the coverage cut can still hold
     const int stats_mode = P.full_records ? 1 : (P.weight_mode == PASTIS_WEIGHT_NS ? 2 : 0);
@@ -252,11 +252,12 @@ pastis_status align_core(pastis_ctx *ctx, const Staged &st, const uint8_t *codes
         // inside the search (they omit end_b of pairs without statistics)
         const bool use16 = sw16_supported(sc) && stats_mode == 0 &&
                            (P.score_width == 16 || (P.score_width == 0 && ctx->records_internal));
-        if (use16) PASTIS_TRY(make_sort_work(ctx, npairs, wk));
-        ctx->last_use16 = use16;
+        const int max16 = !use16 ? 0 : P.score_width == 16 ? 16 : ctx->tune.sw16_max_rows;
+        if (max16 > 0) PASTIS_TRY(make_sort_work(ctx, npairs, wk));
+        ctx->last_max16 = max16;
         HIP_TRY(ctx,
                 launch_sw(ctx, codes, (const PairDesc *)pairs, npairs, ctx->d_blosum, sc, (SwPass1Out *)p1, out, wk,
-                          stats_mode, use16, s),
+                          stats_mode, max16, ctx->tune.sw_grid_scale, s),
                 "sw kernels");
     } else {
         void *redo = nullptr, *ring = nullptr;
@@ -283,7 +284,7 @@ pastis_status align_core(pastis_ctx *ctx, const Staged &st, const uint8_t *codes
         ctx->stats.sw_bins = nb;
         for (int b = 0; b < nb; ++b) {
             sw_bin_shape(b, &ctx->stats.sw_bin_rows[b], &ctx->stats.sw_bin_multi[b]);
-            const bool b16 = ctx->last_use16 && sw_bin_is16(b);
+            const bool b16 = sw_bin_is16(b, ctx->last_max16);
             ctx->stats.sw_bin_bits[b] = b16 ? 16 : 32;
             if (!b16) ctx->stats.int32_pairs += starts[b + 1] - starts[b];
             ctx->stats.sw_bin_pairs[b] = starts[b + 1] - starts[b];

@@ -103,8 +103,8 @@ struct pastis_ctx {
     int64_t n_seqs_last = 0;
     bool have_candidates = false;
     bool records_internal = false;  // the current alignment's records feed edges only
-    bool last_use16 = false;        // the last SW call ran 16-bit pass-1 bins
-    int sw_direct_pct = 50;         // see Scoring::direct_pct
+    int last_max16 = 0;             // the last SW call ran 16-bit pass-1 bins up to this R
+    pastis_tuning tune{16, 50, 1, {0, 0, 0, 0, 0}};
     // learned filter
     pastis::MlpState mlp{};
     bool mlp_alloc = false, mlp_set = false;
@@ -210,13 +210,14 @@ hipError_t launch_xd(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
                      uint32_t *n_redo, int *gring, unsigned long long *counters, hipStream_t s);
 int64_t sw_scratch_waves();
 
-// use16: pass 1 of one-strip pairs in 16-bit lanes, two pairs per wave; its
-// records leave end_b = -1 for pairs that skip the statistics pass.
+// max16 > 0: pass 1 of one-strip pairs with at most max16 rows per lane in
+// 16-bit lanes, two pairs per wave; its records leave end_b = -1 for pairs
+// that skip the statistics pass.  grid_scale multiplies the pass-1 grids.
 hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pairs, int64_t npairs,
                      const int8_t *blosum, const Scoring &sc, SwPass1Out *p1, pastis_pair_record *out,
-                     const SwWork &wk, int stats_mode, bool use16, hipStream_t s);
+                     const SwWork &wk, int stats_mode, int max16, int grid_scale, hipStream_t s);
 // 16-bit pass 1 needs o + e >= 4 (biased scores stay non-negative).
 bool sw16_supported(const Scoring &sc);
-bool sw_bin_is16(int bin);
+bool sw_bin_is16(int bin, int max16);
 
 }  // namespace pastis

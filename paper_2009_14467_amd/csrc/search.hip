@@ -66,6 +66,11 @@ enum DiscBuf {
     kDSubIds,
     kDSubD,
     kDSubN,
+    kDTuneLo,
+    kDTuneHi,
+    kDTuneS1,
+    kDTuneS2,
+    kDTuneRec,
     kDEnd
 };
 static_assert(kDEnd <= kNumBufs, "buffer ids");
@@ -367,6 +372,20 @@ pastis_status stage_and_encode(pastis_ctx *ctx, const uint8_t *residues, const i
 pastis_status mlp_filter_candidates(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, int64_t n,
                                    hipStream_t s);
 
+// An even stride of m of the nc candidates (lo, hi, seeds).
+__global__ void tune_sample_kernel(const uint32_t *__restrict__ lo, const uint32_t *__restrict__ hi,
+                                   const uint32_t *__restrict__ s1, const uint32_t *__restrict__ s2, int64_t nc,
+                                   int64_t m, uint32_t *__restrict__ olo, uint32_t *__restrict__ ohi,
+                                   uint32_t *__restrict__ os1, uint32_t *__restrict__ os2) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    const int64_t c = (int64_t)((__int128)q * nc / m);
+    olo[q] = lo[c];
+    ohi[q] = hi[c];
+    os1[q] = s1[c];
+    os2[q] = s2[c];
+}
+
 // Align the ctx's current candidates; records into kDRecords.
 pastis_status align_candidates(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, int64_t n, hipStream_t s,
                                pastis_pair_record **rec_out);
@@ -527,6 +546,101 @@ void pastis_result_free(pastis_result *r) {
         (void)hipFree(r->d_edges);
     }
     delete r;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+pastis_status pastis_get_tuning(const pastis_ctx *ctx, pastis_tuning *out) {
+    if (!ctx || !out) return PASTIS_E_INVAL;
+    *out = ctx->tune;
+    return PASTIS_OK;
+}
+
+pastis_status pastis_set_tuning(pastis_ctx *ctx, const pastis_tuning *t) {
+    if (!ctx || !t) return PASTIS_E_INVAL;
+    if (t->sw16_max_rows < 0 || t->sw16_max_rows > 16 || t->sw_direct_pct < 0 || t->sw_grid_scale < 1 ||
+        t->sw_grid_scale > 4)
+        return set_error(ctx, PASTIS_E_INVAL, "tuning value out of range");
+    for (int i = 0; i < 5; ++i)
+        if (t->reserved[i] != 0) return set_error(ctx, PASTIS_E_INVAL, "reserved fields must be zero");
+    ctx->tune = *t;
+    return PASTIS_OK;
+}
+
+pastis_status pastis_autotune(pastis_ctx *ctx, const uint8_t *residues, const int64_t *offsets, int64_t n,
+                              int input_on_device, int64_t max_pairs, void *stream, pastis_tuning *out) {
+    if (!ctx || max_pairs < 1) return PASTIS_E_INVAL;
+    hipStream_t s = (hipStream_t)stream;
+    PASTIS_TRY(begin_call(ctx));
+    Staged st;
+    uint8_t *codes = nullptr;
+    PASTIS_TRY(stage_and_encode(ctx, residues, offsets, n, input_on_device, s, st, &codes));
+    int64_t nc = 0;
+    PASTIS_TRY(discover(ctx, st, codes, n, s, &nc));
+    if (nc > 0 && ctx->params.align_mode == PASTIS_ALIGN_SW) {
+        const int64_t m = std::min<int64_t>(nc, max_pairs);
+        uint32_t *lo, *hi, *s1, *s2;
+        pastis_pair_record *rec;
+        PASTIS_TRY(get(ctx, kDTuneLo, m, &lo));
+        PASTIS_TRY(get(ctx, kDTuneHi, m, &hi));
+        PASTIS_TRY(get(ctx, kDTuneS1, m, &s1));
+        PASTIS_TRY(get(ctx, kDTuneS2, m, &s2));
+        PASTIS_TRY(get(ctx, kDTuneRec, m, &rec));
+        tune_sample_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(
+            (const uint32_t *)ctx->buf[kBufCandLo].ptr, (const uint32_t *)ctx->buf[kBufCandHi].ptr,
+            (const uint32_t *)ctx->buf[kBufCandS1].ptr, (const uint32_t *)ctx->buf[kBufCandS2].ptr, nc, m, lo, hi, s1,
+            s2);
+        HIP_TRY(ctx, hipGetLastError(), "sample kernel");
+        // time one alignment of the sample under the current ctx->tune
+        auto time_once = [&](double *ms) -> pastis_status {
+            ctx->stats = pastis_run_stats{};
+            ctx->records_internal = true;
+            const pastis_status r = align_core(ctx, st, codes, n, lo, hi, s1, s2, m, rec, s);
+            ctx->records_internal = false;
+            PASTIS_TRY(r);
+            HIP_TRY(ctx, stage_collect(ctx, s), "sync");
+            *ms = ctx->stats.ms_stage[kStSched] + ctx->stats.ms_stage[kStAlign1] + ctx->stats.ms_stage[kStAlign2];
+            return PASTIS_OK;
+        };
+        auto measure = [&](double *best) -> pastis_status {
+            double a = 0, b = 0;
+            PASTIS_TRY(time_once(&a));
+            PASTIS_TRY(time_once(&b));
+            *best = std::min(a, b);
+            return PASTIS_OK;
+        };
+        double cur = 0;
+        PASTIS_TRY(measure(&cur));  // also warms the buffers up
+        PASTIS_TRY(measure(&cur));
+        const int rows16[] = {16, 12, 8, 0};
+        const int direct[] = {0, 25, 50, 100, 200, 1 << 20};
+        const int grid[] = {1, 2};
+        auto sweep = [&](int32_t *knob, const int *vals, int nv) -> pastis_status {
+            const int32_t keep = *knob;
+            int32_t best_v = keep;
+            double best_ms = cur;
+            for (int i = 0; i < nv; ++i) {
+                if (vals[i] == keep) continue;
+                *knob = vals[i];
+                double ms = 0;
+                PASTIS_TRY(measure(&ms));
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best_v = vals[i];
+                }
+            }
+            *knob = best_v;
+            cur = best_ms;
+            return PASTIS_OK;
+        };
+        PASTIS_TRY(sweep(&ctx->tune.sw16_max_rows, rows16, 4));
+        PASTIS_TRY(sweep(&ctx->tune.sw_direct_pct, direct, 6));
+        PASTIS_TRY(sweep(&ctx->tune.sw_grid_scale, grid, 2));
+    }
+    if (out) *out = ctx->tune;
+    return PASTIS_OK;
 }
 
 }  // extern "C"

@@ -1035,11 +1035,12 @@ int64_t sw_scratch_waves() {
 
 bool sw16_supported(const Scoring &sc) { return sc.gap_open + sc.gap_extend >= 4; }
 
-bool sw_bin_is16(int bin) { return bin < kSingleBins; }
+bool sw_bin_is16(int bin, int max16) { return bin < kSingleBins && rows_of_bin(bin) <= max16; }
 
 hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pairs, int64_t npairs,
                      const int8_t *blosum, const Scoring &sc, SwPass1Out *p1, pastis_pair_record *out,
-                     const SwWork &wk, int stats_mode, bool use16, hipStream_t s) {
+                     const SwWork &wk, int stats_mode, int max16, int grid_scale, hipStream_t s) {
+    const bool use16 = max16 > 0;
     if (npairs <= 0) return hipSuccess;
     const int go_ge = sc.gap_open + sc.gap_extend, ge = sc.gap_extend;
     const int nb = (int)((npairs + 255) / 256);
@@ -1063,12 +1064,12 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
         return e;
     for (int bin = 0; bin < kNumBins; ++bin) {
         if ((e = hipEventRecord(ctx->bin_ev[2 * bin], s)) != hipSuccess) return e;
-        if (use16 && sw_bin_is16(bin))
-            e = kP16[bin](bin, blocks16(rows_of_bin(bin)), codes, pairs, idx1, wk.starts, blosum, go_ge, ge, p1, nullptr,
-                          0, s);
-        else
-            e = kP1[bin](bin, blocks_for_bin(bin), codes, pairs, idx1, wk.starts, blosum, go_ge, ge, p1, wk.scratch,
-                         wk.scratch_per_wave, s);
+        if (sw_bin_is16(bin, max16))
+            e = kP16[bin](bin, grid_scale * blocks16(rows_of_bin(bin)), codes, pairs, idx1, wk.starts, blosum, go_ge,
+                          ge, p1, nullptr, 0, s);
+        else  // multi-strip bins use per-wave boundary buffers: keep their grid
+            e = kP1[bin](bin, (bin >= kMultiBin ? 1 : grid_scale) * blocks_for_bin(bin), codes, pairs, idx1,
+                         wk.starts, blosum, go_ge, ge, p1, wk.scratch, wk.scratch_per_wave, s);
         if (e != hipSuccess) return e;
         if ((e = hipEventRecord(ctx->bin_ev[2 * bin + 1], s)) != hipSuccess) return e;
     }

@@ -66,3 +66,36 @@ def test_search_repeatable(gpu):
     a = ctx.search(_dev(s.residues, gpu), _dev(s.offsets, gpu))
     b = P.Context(P.Params(k=5, n_subs=10, ck_min=2)).search(_dev(s.residues, gpu), _dev(s.offsets, gpu))
     assert a.tobytes() == b.tobytes()
+
+
+@pytest.mark.parametrize("tuning", [dict(sw16_max_rows=0), dict(sw16_max_rows=8, sw_direct_pct=0),
+                                    dict(sw16_max_rows=12, sw_direct_pct=1 << 20, sw_grid_scale=2),
+                                    dict(sw16_max_rows=16, sw_direct_pct=25, sw_grid_scale=4)])
+def test_every_schedule_gives_the_same_edges(gpu, orc, tuning):
+    """Schedule knobs move time, never results: each setting against the oracle."""
+    import paper_2009_14467_amd as P
+    from synth import make_family_set
+
+    s = make_family_set(n_families=12, family_size=8, mean_len=500, min_len=30, max_len=1500, divergence=0.3,
+                        stream=55)
+    want = orc.search(s.residues, s.offsets, k=6, ck_min=1, mode="sw")
+    ctx = P.Context(P.Params(k=6, ck_min=1))
+    ctx.set_tuning(**tuning)
+    got = ctx.search(_dev(s.residues, gpu), _dev(s.offsets, gpu))
+    _compare_edges(got, want)
+
+
+def test_autotune_picks_a_valid_schedule(gpu):
+    import paper_2009_14467_amd as P
+    from synth import workload
+
+    s = workload("tiny")
+    res, off = _dev(s.residues, gpu), _dev(s.offsets, gpu)
+    ctx = P.Context(P.Params(k=6, ck_min=1))
+    before = ctx.search(res, off)
+    t = ctx.autotune(res, off, max_pairs=2000)
+    assert t == ctx.get_tuning()
+    assert t["sw16_max_rows"] in (0, 8, 12, 16) and t["sw_grid_scale"] in (1, 2)
+    assert before.tobytes() == ctx.search(res, off).tobytes()
+    with pytest.raises(P.PastisError):
+        ctx.set_tuning(sw16_max_rows=17)

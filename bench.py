@@ -61,6 +61,7 @@ def parse():
     ap.add_argument("--mlp-epochs", type=int, default=4)
     ap.add_argument("--no-xd", action="store_true", help="skip the x-drop leg")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default alignment schedule")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-mode leg")
     ap.add_argument("--tune-pairs", type=int, default=2_000_000, help="candidate sample size of the autotuner")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one 1 GiB device-to-device copy (a reference for HBM byte counters)")
@@ -98,6 +99,23 @@ def cpu_baseline(fs, lo, hi, target_s):
         "kind": "oracle",
         "sample": f"{n1} random candidate pairs of the step ({cells:.3e} cells), SW with full traceback, {dt:.1f} s",
     }
+
+
+def graph_leg(P, args, params, res, off, tuning):
+    """The same search with the alignment stage replayed as a captured HIP graph."""
+    import torch
+
+    ctx = P.Context(P.Params(graph_mode=True, **params))
+    if isinstance(tuning, dict):
+        ctx.set_tuning(**{k: tuning[k] for k in ("sw16_max_rows", "sw_direct_pct", "sw_grid_scale")})
+    for _ in range(max(args.warmup, 1)):
+        ctx.search(res, off)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.search(res, off)
+    torch.cuda.synchronize()
+    return {"ms_per_step": (time.perf_counter() - t0) * 1e3 / args.steps, "sw_graph": ctx.stats()["sw_graph"]}
 
 
 def xd_leg(P, args, params, res, off, n_cand):
@@ -300,6 +318,8 @@ def main():
         "sw_bins": [dict(b, gcups=b["cells"] / max(b["ms"], 1e-9) / 1e6) for b in st["sw_bins"] if b["pairs"]],
         "schedule": tuning if tuning is not None else "default",
     }
+    if not args.no_graph:
+        line["graph_mode"] = graph_leg(P, args, params, res, off, tuning)
     if not args.no_xd:
         line["xd"] = xd_leg(P, args, params, res, off, n_cand)
     if not args.no_mlp:

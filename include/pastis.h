@@ -86,7 +86,11 @@ typedef struct pastis_params {
                                  still hold (the others report beg = -1, passed = 0) */
     int32_t filter_mode;      /* 0: align every candidate; 1: align only candidates the
                                  learned filter keeps (pastis_mlp_set first) */
-    int32_t reserved[6];      /* must be zero */
+    int32_t graph_mode;       /* 1: run the Smith-Waterman stage as one captured HIP graph
+                                 on a stream of the context, replayed while the pair
+                                 count, buffers and schedule are unchanged (per-bin
+                                 times are then not recorded); 0: direct launches */
+    int32_t reserved[5];      /* must be zero */
 } pastis_params;
 
 /* One similarity edge, 48 bytes.  i < j; edges are sorted by (i, j).
@@ -148,6 +152,9 @@ typedef struct pastis_run_stats {
     int64_t bound_pass_pairs;
     int64_t bound_pass_cells;
     int64_t stats_pass_cells;
+    int32_t sw_graph;         /* Smith-Waterman stage: 0 direct launches, 1 graph captured
+                                 and launched, 2 graph replayed */
+    int32_t sw_graph_pad;
 } pastis_run_stats;
 
 typedef struct pastis_ctx pastis_ctx;

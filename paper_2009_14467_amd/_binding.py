@@ -81,7 +81,8 @@ class _Params(ctypes.Structure):
         ("score_width", ctypes.c_int32),
         ("full_records", ctypes.c_int32),
         ("filter_mode", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 6),
+        ("graph_mode", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 5),
     ]
 
 
@@ -117,6 +118,8 @@ class _Stats(ctypes.Structure):
         ("bound_pass_pairs", ctypes.c_int64),
         ("bound_pass_cells", ctypes.c_int64),
         ("stats_pass_cells", ctypes.c_int64),
+        ("sw_graph", ctypes.c_int32),
+        ("sw_graph_pad", ctypes.c_int32),
     ]
 
 
@@ -138,6 +141,7 @@ class Params:
     score_width: int = 0
     full_records: bool = False
     filter_mode: str = "none"  # "none" | "mlp" (the learned filter, set with Context.mlp_set)
+    graph_mode: bool = False  # replay the alignment stage as a captured HIP graph
 
     def to_c(self) -> _Params:
         p = _Params()
@@ -155,6 +159,7 @@ class Params:
         p.score_width = self.score_width
         p.full_records = int(self.full_records)
         p.filter_mode = {"none": 0, "mlp": 1}[self.filter_mode]
+        p.graph_mode = int(self.graph_mode)
         return p
 
 

@@ -97,7 +97,8 @@ pastis_status validate(const pastis_params *p, std::string &why) {
         return why = "score_width must be 0, 16 or 32", PASTIS_E_INVAL;
     if (p->full_records != 0 && p->full_records != 1) return why = "full_records must be 0 or 1", PASTIS_E_INVAL;
     if (p->filter_mode != 0 && p->filter_mode != 1) return why = "filter_mode must be 0 or 1", PASTIS_E_INVAL;
-    for (int t = 0; t < 6; ++t)
+    if (p->graph_mode != 0 && p->graph_mode != 1) return why = "graph_mode must be 0 or 1", PASTIS_E_INVAL;
+    for (int t = 0; t < 5; ++t)
         if (p->reserved[t] != 0) return why = "reserved fields must be zero", PASTIS_E_INVAL;
     return PASTIS_OK;
 }
@@ -219,6 +220,64 @@ static pastis_status make_sort_work(pastis_ctx *ctx, int64_t npairs, SwWork &wk)
 // record per pair.  Validates pair indices (PASTIS_E_INVAL).
 void mlp_free(pastis_ctx *ctx);
 
+// The SW stage as a HIP graph on the context's stream: captured when its
+// shape (pair count, buffers, scoring, schedule) differs from the cached one,
+// else replayed.  The caller's stream waits for it through events; the stage
+// time goes to the pass-1 slot.
+static uint64_t mix(uint64_t h, uint64_t v) {
+    h ^= v + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+    return h;
+}
+
+static pastis_status sw_graph(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pairs, int64_t npairs,
+                              const Scoring &sc, SwPass1Out *p1, pastis_pair_record *out, const SwWork &wk,
+                              int stats_mode, int max16, hipStream_t s) {
+    const int grid = ctx->tune.sw_grid_scale;
+    uint64_t key = 0;
+    const uint64_t parts[] = {(uint64_t)npairs, (uint64_t)codes, (uint64_t)pairs, (uint64_t)p1, (uint64_t)out,
+                              (uint64_t)wk.counters, (uint64_t)wk.bin_of, (uint64_t)wk.counts, (uint64_t)wk.idx,
+                              (uint64_t)wk.idx2, (uint64_t)wk.scratch, (uint64_t)wk.scratch_per_wave,
+                              (uint64_t)wk.sort_keys, (uint64_t)wk.sort_keys_alt, (uint64_t)wk.sort_vals_alt,
+                              (uint64_t)wk.sort_temp, (uint64_t)sc.gap_open, (uint64_t)sc.gap_extend,
+                              (uint64_t)sc.id_pct, (uint64_t)sc.cov_pct, (uint64_t)sc.direct_pct,
+                              (uint64_t)stats_mode, (uint64_t)max16, (uint64_t)grid, (uint64_t)ctx->d_blosum};
+    for (uint64_t v : parts) key = mix(key, v);
+    hipStream_t gs = ctx->graph_stream;
+    if (!ctx->sw_exec || key != ctx->sw_key) {
+        if (ctx->sw_exec) {
+            (void)hipGraphExecDestroy(ctx->sw_exec);
+            ctx->sw_exec = nullptr;
+        }
+        HIP_TRY(ctx, hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal), "graph capture");
+        const hipError_t le = launch_sw(ctx, codes, pairs, npairs, ctx->d_blosum, sc, p1, out, wk, stats_mode, max16,
+                                        grid, false, gs);
+        hipGraph_t g = nullptr;
+        const hipError_t ce = hipStreamEndCapture(gs, &g);
+        if (le != hipSuccess || ce != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return hip_error(ctx, le != hipSuccess ? le : ce, "graph capture");
+        }
+        const hipError_t ie = hipGraphInstantiate(&ctx->sw_exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) {
+            ctx->sw_exec = nullptr;
+            return hip_error(ctx, ie, "graph instantiate");
+        }
+        ctx->sw_key = key;
+        ctx->stats.sw_graph = 1;
+    } else {
+        ctx->stats.sw_graph = 2;
+    }
+    HIP_TRY(ctx, hipEventRecord(ctx->graph_join[0], s), "event");
+    HIP_TRY(ctx, hipStreamWaitEvent(gs, ctx->graph_join[0], 0), "event");
+    HIP_TRY(ctx, stage_begin(ctx, kStAlign1, gs), "event");
+    HIP_TRY(ctx, hipGraphLaunch(ctx->sw_exec, gs), "graph launch");
+    HIP_TRY(ctx, stage_end(ctx, kStAlign1, gs), "event");
+    HIP_TRY(ctx, hipEventRecord(ctx->graph_join[1], gs), "event");
+    HIP_TRY(ctx, hipStreamWaitEvent(s, ctx->graph_join[1], 0), "event");
+    return PASTIS_OK;
+}
+
 pastis_status align_core(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, int64_t n, const uint32_t *pi,
                          const uint32_t *pj, const uint32_t *seed1, const uint32_t *seed2, int64_t npairs,
                          pastis_pair_record *out, hipStream_t s) {
@@ -255,10 +314,15 @@ pastis_status align_core(pastis_ctx *ctx, const Staged &st, const uint8_t *codes
         const int max16 = !use16 ? 0 : P.score_width == 16 ? 16 : ctx->tune.sw16_max_rows;
         if (max16 > 0) PASTIS_TRY(make_sort_work(ctx, npairs, wk));
         ctx->last_max16 = max16;
-        HIP_TRY(ctx,
-                launch_sw(ctx, codes, (const PairDesc *)pairs, npairs, ctx->d_blosum, sc, (SwPass1Out *)p1, out, wk,
-                          stats_mode, max16, ctx->tune.sw_grid_scale, s),
-                "sw kernels");
+        if (P.graph_mode) {
+            PASTIS_TRY(sw_graph(ctx, codes, (const PairDesc *)pairs, npairs, sc, (SwPass1Out *)p1, out, wk, stats_mode,
+                                max16, s));
+        } else {
+            HIP_TRY(ctx,
+                    launch_sw(ctx, codes, (const PairDesc *)pairs, npairs, ctx->d_blosum, sc, (SwPass1Out *)p1, out,
+                              wk, stats_mode, max16, ctx->tune.sw_grid_scale, true, s),
+                    "sw kernels");
+        }
     } else {
         void *redo = nullptr, *ring = nullptr;
         PASTIS_TRY(ensure(ctx, kBufXdRedo, sizeof(uint32_t) * (size_t)(npairs + 4), &redo));
@@ -277,7 +341,7 @@ pastis_status align_core(pastis_ctx *ctx, const Staged &st, const uint8_t *codes
     ctx->stats.stats_pass_cells = (int64_t)c[2];
     ctx->stats.bound_pass_pairs = (int64_t)c[3];
     ctx->stats.bound_pass_cells = (int64_t)c[4];
-    if (P.align_mode == PASTIS_ALIGN_SW) {
+    if (P.align_mode == PASTIS_ALIGN_SW && !P.graph_mode) {
         int starts[33];  // pass-1 bin bounds (the pass-2 binning reuses the counts)
         PASTIS_TRY(read_device(ctx, wk.starts, starts, sizeof(starts), s));
         const int nb = sw_num_bins();
@@ -384,6 +448,15 @@ pastis_status pastis_create(const pastis_params *p, int device, pastis_ctx **out
             return PASTIS_E_DEVICE;
         }
     }
+    if (p->graph_mode) {
+        // default priority; non-blocking so it never waits on the null stream
+        if (hipStreamCreateWithFlags(&ctx->graph_stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&ctx->graph_join[0], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&ctx->graph_join[1], hipEventDisableTiming) != hipSuccess) {
+            pastis_destroy(ctx);
+            return PASTIS_E_DEVICE;
+        }
+    }
     *out = ctx;
     return PASTIS_OK;
 }
@@ -399,6 +472,13 @@ void pastis_destroy(pastis_ctx *ctx) {
     for (auto &ev : ctx->ev)
         if (ev) (void)hipEventDestroy(ev);
     for (auto &ev : ctx->bin_ev)
+        if (ev) (void)hipEventDestroy(ev);
+    if (ctx->sw_exec) (void)hipGraphExecDestroy(ctx->sw_exec);
+    if (ctx->graph_stream) {
+        (void)hipStreamSynchronize(ctx->graph_stream);
+        (void)hipStreamDestroy(ctx->graph_stream);
+    }
+    for (auto &ev : ctx->graph_join)
         if (ev) (void)hipEventDestroy(ev);
     delete ctx;
 }

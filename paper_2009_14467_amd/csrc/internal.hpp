@@ -114,6 +114,11 @@ struct pastis_ctx {
     size_t h_pinned_bytes = 0;
     hipEvent_t ev[2 * 9] = {};
     hipEvent_t bin_ev[2 * 32] = {};  // around each SW pass-1 bin launch
+    // graph mode: the SW stage captured on a stream of the context
+    hipStream_t graph_stream = nullptr;
+    hipEvent_t graph_join[2] = {};
+    hipGraphExec_t sw_exec = nullptr;
+    uint64_t sw_key = 0;
     bool ev_used[9] = {};
 };
 
@@ -215,7 +220,7 @@ int64_t sw_scratch_waves();
 // that skip the statistics pass.  grid_scale multiplies the pass-1 grids.
 hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pairs, int64_t npairs,
                      const int8_t *blosum, const Scoring &sc, SwPass1Out *p1, pastis_pair_record *out,
-                     const SwWork &wk, int stats_mode, int max16, int grid_scale, hipStream_t s);
+                     const SwWork &wk, int stats_mode, int max16, int grid_scale, bool timed, hipStream_t s);
 // 16-bit pass 1 needs o + e >= 4 (biased scores stay non-negative).
 bool sw16_supported(const Scoring &sc);
 bool sw_bin_is16(int bin, int max16);

@@ -1039,12 +1039,16 @@ bool sw_bin_is16(int bin, int max16) { return bin < kSingleBins && rows_of_bin(b
 
 hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pairs, int64_t npairs,
                      const int8_t *blosum, const Scoring &sc, SwPass1Out *p1, pastis_pair_record *out,
-                     const SwWork &wk, int stats_mode, int max16, int grid_scale, hipStream_t s) {
+                     const SwWork &wk, int stats_mode, int max16, int grid_scale, bool timed, hipStream_t s) {
+    // timed = false (graph capture): no stage or per-bin events
     const bool use16 = max16 > 0;
+    auto begin = [&](int st) { return timed ? stage_begin(ctx, st, s) : hipSuccess; };
+    auto end = [&](int st) { return timed ? stage_end(ctx, st, s) : hipSuccess; };
+    auto mark = [&](hipEvent_t ev) { return timed ? hipEventRecord(ev, s) : hipSuccess; };
     if (npairs <= 0) return hipSuccess;
     const int go_ge = sc.gap_open + sc.gap_extend, ge = sc.gap_extend;
     const int nb = (int)((npairs + 255) / 256);
-    hipError_t e = stage_begin(ctx, kStSched, s);
+    hipError_t e = begin(kStSched);
     if (e != hipSuccess) return e;
     sw_bin1_kernel<<<nb, 256, 0, s>>>(pairs, npairs, wk.bin_of, wk.counters);
     if ((e = launch_bins(wk.bin_of, npairs, kNumBins, wk.counts, wk.starts, wk.cursor, wk.idx, s)) != hipSuccess)
@@ -1060,10 +1064,10 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
             return e;
         if (alt) idx1 = (const int *)wk.sort_vals_alt;
     }
-    if ((e = stage_end(ctx, kStSched, s)) != hipSuccess || (e = stage_begin(ctx, kStAlign1, s)) != hipSuccess)
+    if ((e = end(kStSched)) != hipSuccess || (e = begin(kStAlign1)) != hipSuccess)
         return e;
     for (int bin = 0; bin < kNumBins; ++bin) {
-        if ((e = hipEventRecord(ctx->bin_ev[2 * bin], s)) != hipSuccess) return e;
+        if ((e = mark(ctx->bin_ev[2 * bin])) != hipSuccess) return e;
         if (sw_bin_is16(bin, max16))
             e = kP16[bin](bin, grid_scale * blocks16(rows_of_bin(bin)), codes, pairs, idx1, wk.starts, blosum, go_ge,
                           ge, p1, nullptr, 0, s);
@@ -1071,9 +1075,9 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
             e = kP1[bin](bin, (bin >= kMultiBin ? 1 : grid_scale) * blocks_for_bin(bin), codes, pairs, idx1,
                          wk.starts, blosum, go_ge, ge, p1, wk.scratch, wk.scratch_per_wave, s);
         if (e != hipSuccess) return e;
-        if ((e = hipEventRecord(ctx->bin_ev[2 * bin + 1], s)) != hipSuccess) return e;
+        if ((e = mark(ctx->bin_ev[2 * bin + 1])) != hipSuccess) return e;
     }
-    if ((e = stage_end(ctx, kStAlign1, s)) != hipSuccess || (e = stage_begin(ctx, kStAlign2, s)) != hipSuccess)
+    if ((e = end(kStAlign1)) != hipSuccess || (e = begin(kStAlign2)) != hipSuccess)
         return e;
     sw_bin2_kernel<<<nb, 256, 0, s>>>(pairs, p1, npairs, sc.cov_pct, stats_mode, sc.direct_pct, out, wk.bin_of,
                                       wk.counters);
@@ -1096,7 +1100,7 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
                      sc.id_pct, p1, out, wk.scratch, wk.scratch_per_wave, s);
         if (e != hipSuccess) return e;
     }
-    return stage_end(ctx, kStAlign2, s);
+    return end(kStAlign2);
 }
 
 }  // namespace pastis

@@ -99,3 +99,29 @@ def test_autotune_picks_a_valid_schedule(gpu):
     assert before.tobytes() == ctx.search(res, off).tobytes()
     with pytest.raises(P.PastisError):
         ctx.set_tuning(sw16_max_rows=17)
+
+
+def test_graph_mode_replays_match_direct_launches(gpu):
+    """The SW stage captured once and replayed: every replay, with direct
+    launches of another context in between, gives the direct result; a new
+    pair count forces a new capture."""
+    import paper_2009_14467_amd as P
+    from synth import workload
+
+    s = workload("tiny")
+    res, off = _dev(s.residues, gpu), _dev(s.offsets, gpu)
+    eager = P.Context(P.Params(k=6, ck_min=1))
+    graph = P.Context(P.Params(k=6, ck_min=1, graph_mode=True))
+    want = eager.search(res, off)
+    modes = []
+    for rep in range(4):
+        got = graph.search(res, off)
+        modes.append(graph.stats()["sw_graph"])
+        _compare_edges(got, want)
+        _compare_edges(eager.search(res, off), want)  # direct work between replays
+    assert modes == [1, 2, 2, 2]
+    s2 = workload("tiny", n_families=9)
+    r2, o2 = _dev(s2.residues, gpu), _dev(s2.offsets, gpu)
+    _compare_edges(graph.search(r2, o2), eager.search(r2, o2))
+    assert graph.stats()["sw_graph"] == 1
+    _compare_edges(graph.search(res, off), want)

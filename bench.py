@@ -28,8 +28,15 @@ METRIC = "alignment GCUPS + aligned pairs/s, 1 GPU; MLP-filtered vs plain at ≥
 # packed 16-bit ops (v_pk_*_i16) do two lane-ops each
 PEAK_INT32_TOPS = 256 * 64 * 2.4e9 / 1e12
 PEAK_INT16_TOPS = 2 * PEAK_INT32_TOPS
-# algorithmic integer ops per SW cell for score + end
+# algorithmic integer ops per SW cell: gap-open term, E and F updates,
+# diagonal + score, two maxima, end tracking
 OPS_PER_SW_CELL = 11
+# HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (KiB per
+# dispatch on the mid workload, profiles/sw_search_mid_kernel_stats.md), scaled
+# by what the counters read for a 1 GiB device copy (FETCH x 2.0, WRITE x 1.0);
+# only for kernels unchanged since those counters were taken
+MEASURED_TRAFFIC_KIB = {"sw16_pass1_kernel<9, 2>": (640832.625, 53097.625)}
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
 # method parameters of each workload (Section VI settings: BLOSUM62, gaps
 # 11/1, x-drop 49, identity >= 30%, coverage >= 70%)
@@ -60,7 +67,8 @@ def parse():
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-filter leg")
     ap.add_argument("--mlp-epochs", type=int, default=4)
     ap.add_argument("--no-xd", action="store_true", help="skip the x-drop leg")
-    ap.add_argument("--no-autotune", action="store_true", help="keep the default alignment schedule")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time schedule settings on a candidate sample first (default: the library's schedule)")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-mode leg")
     ap.add_argument("--tune-pairs", type=int, default=2_000_000, help="candidate sample size of the autotuner")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -235,7 +243,7 @@ def main():
     off = torch.from_numpy(fs.offsets).to(dev)
     ctx = P.Context(P.Params(**params))
     tuning = None
-    if not args.no_autotune:
+    if args.autotune:
         t0 = time.perf_counter()
         tuning = ctx.autotune(res, off, max_pairs=args.tune_pairs)
         torch.cuda.synchronize()
@@ -309,14 +317,16 @@ def main():
             "peak": peak,
             "unit": "Tops/s",
             "frac": achieved / peak,
-            "traffic": None,
+            "traffic": (None if dom_name not in MEASURED_TRAFFIC_KIB or args.workload != "mid" else
+                        1024 * (FETCH_SCALE * MEASURED_TRAFFIC_KIB[dom_name][0] +
+                                WRITE_SCALE * MEASURED_TRAFFIC_KIB[dom_name][1])),
             "kernel_ms": dom["ms"],
             "kernel_cells": dom["cells"],
             "ops_per_cell": OPS_PER_SW_CELL,
             "all_pass1_bins": {"achieved": pass1_tops, "frac_of_mix_peak": mix_peak_s / (pass1_ms * 1e-3)},
         },
         "sw_bins": [dict(b, gcups=b["cells"] / max(b["ms"], 1e-9) / 1e6) for b in st["sw_bins"] if b["pairs"]],
-        "schedule": tuning if tuning is not None else "default",
+        "schedule": tuning if tuning is not None else dict(ctx.get_tuning(), source="library default"),
     }
     if not args.no_graph:
         line["graph_mode"] = graph_leg(P, args, params, res, off, tuning)

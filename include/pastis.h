@@ -283,7 +283,7 @@ pastis_status pastis_mlp_calibrate(pastis_ctx *ctx, const float *X, const uint8_
 
 /* ---- schedule of the Smith-Waterman stage ----
  * Knobs of the length-binned launches (every setting gives the same results;
- * only the time changes).  pastis_autotune times candidate settings on a
+ * only the time changes).  A new context starts at {16, 50, 2}.  pastis_autotune times candidate settings on a
  * sample of the given sequences' own candidate pairs and keeps the fastest. */
 typedef struct pastis_tuning {
     int32_t sw16_max_rows; /* one-strip bins with at most this many rows per lane run two

@@ -373,7 +373,7 @@ class Context:
         self._check(lib().pastis_get_tuning(self._ctx, ctypes.byref(t)))
         return {"sw16_max_rows": t.sw16_max_rows, "sw_direct_pct": t.sw_direct_pct, "sw_grid_scale": t.sw_grid_scale}
 
-    def set_tuning(self, sw16_max_rows: int = 16, sw_direct_pct: int = 50, sw_grid_scale: int = 1):
+    def set_tuning(self, sw16_max_rows: int = 16, sw_direct_pct: int = 50, sw_grid_scale: int = 2):
         t = _Tuning()
         t.sw16_max_rows, t.sw_direct_pct, t.sw_grid_scale = sw16_max_rows, sw_direct_pct, sw_grid_scale
         self._check(lib().pastis_set_tuning(self._ctx, ctypes.byref(t)))

@@ -225,3 +225,49 @@ def test_search_same_edges_in_16_and_32_bits(gpu):
     e32 = P.Context(P.Params(k=6, ck_min=1, score_width=32)).search(res, off)
     assert e16.size == e32.size > 0
     assert e16.tobytes() == e32.tobytes()
+
+
+def test_longest_pairs_sw_and_xd(gpu, orc):
+    """Pairs of 20,000-30,000 residues (the heavy tail's range): many strips
+    of 1024 rows, scores far beyond 16 bits, the start bound skipped for
+    rectangles taller than its packing allows; SW and XD against the oracle."""
+    from synth.families import FamilySet
+
+    rng = np.random.default_rng(12)
+    anc = rng.integers(0, 20, 30000)
+    a = anc.copy()
+    sub = rng.random(a.size) < 0.2
+    a[sub] = rng.integers(0, 20, int(sub.sum()))
+    b = np.concatenate([anc[:12000], rng.integers(0, 20, 40), anc[12000:29000]])
+    c = rng.integers(0, 20, 20000)
+    seqs = [a, b, c]
+    letters = np.frombuffer(b"ARNDCQEGHILKMFPSTWYV", np.uint8)
+    res = np.concatenate([letters[x] for x in seqs]).astype(np.uint8)
+    off = np.zeros(len(seqs) + 1, np.int64)
+    np.cumsum([len(x) for x in seqs], out=off[1:])
+    s = FamilySet(res, off, np.zeros(len(seqs), np.int32), {})
+    codes = orc.encode(s.residues)
+    lo = np.array([0, 0, 1], np.uint32)
+    hi = np.array([1, 2, 2], np.uint32)
+    want = orc.align_pairs(codes, s.offsets, lo, hi, mode="sw")
+    assert want["score"][0] > 1 << 16 and want["passed"][0] == 1
+    _compare(_gpu_records(gpu, s, lo, hi, full_records=True), want)
+    _compare(_gpu_records(gpu, s, lo, hi), want, ("score", "end_a", "end_b", "passed", "swapped", "cells"))
+    p = orc.pair_counts(codes, s.offsets, lo, hi, 6)
+    wx = orc.align_pairs(codes, s.offsets, lo, hi, p["seed1"], p["seed2"], mode="xd", k=6)
+    gx = _gpu_records(gpu, s, lo, hi, p["seed1"], p["seed2"], align_mode="xd", full_records=True)
+    _compare(gx, wx)
+
+
+def test_rejects_sequences_beyond_u16_positions(gpu):
+    import paper_2009_14467_amd as P
+    from synth.families import FamilySet
+
+    res = np.full(65536 + 10, ord("A"), np.uint8)
+    off = np.array([0, 65536, 65546], np.int64)
+    s = FamilySet(res, off, np.zeros(2, np.int32), {})
+    with pytest.raises(P.PastisError):
+        _gpu_records(gpu, s, np.array([0], np.uint32), np.array([1], np.uint32))
+    ctx = P.Context(P.Params())
+    with pytest.raises(P.PastisError):
+        ctx.search(_to_dev(s.residues, gpu), _to_dev(s.offsets, gpu))

@@ -35,7 +35,7 @@ OPS_PER_SW_CELL = 11
 # dispatch on the mid workload, profiles/sw_search_mid_kernel_stats.md), scaled
 # by what the counters read for a 1 GiB device copy (FETCH x 2.0, WRITE x 1.0);
 # only for kernels unchanged since those counters were taken
-MEASURED_TRAFFIC_KIB = {"sw16_pass1_kernel<9, 2>": (640832.625, 53097.625)}
+MEASURED_TRAFFIC_KIB = {}
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
 # method parameters of each workload (Section VI settings: BLOSUM62, gaps
@@ -115,7 +115,8 @@ def graph_leg(P, args, params, res, off, tuning):
 
     ctx = P.Context(P.Params(graph_mode=True, **params))
     if isinstance(tuning, dict):
-        ctx.set_tuning(**{k: tuning[k] for k in ("sw16_max_rows", "sw_direct_pct", "sw_grid_scale")})
+        ctx.set_tuning(**{k: tuning[k] for k in ("sw16_max_rows", "sw_direct_pct", "sw_grid_scale",
+                                                  "sw_grid_scale_wide")})
     for _ in range(max(args.warmup, 1)):
         ctx.search(res, off)
     torch.cuda.synchronize()

@@ -283,7 +283,7 @@ pastis_status pastis_mlp_calibrate(pastis_ctx *ctx, const float *X, const uint8_
 
 /* ---- schedule of the Smith-Waterman stage ----
  * Knobs of the length-binned launches (every setting gives the same results;
- * only the time changes).  A new context starts at {16, 50, 2}.  pastis_autotune times candidate settings on a
+ * only the time changes).  A new context starts at {16, 50, 2, 1}.  pastis_autotune times candidate settings on a
  * sample of the given sequences' own candidate pairs and keeps the fastest. */
 typedef struct pastis_tuning {
     int32_t sw16_max_rows; /* one-strip bins with at most this many rows per lane run two
@@ -291,16 +291,18 @@ typedef struct pastis_tuning {
                               16-bit lanes are in use (see score_width) */
     int32_t sw_direct_pct; /* pairs with 100 * score >= this * (shorter length) skip the
                               start-bound pass and go straight to the statistics pass */
-    int32_t sw_grid_scale; /* pass-1 launches get this many times the blocks that fit on
-                              the device at once (1..4) */
-    int32_t reserved[5];
+    int32_t sw_grid_scale; /* one-strip pass-1 launches with at most 8 rows per lane get
+                              this many times the blocks that fit on the device at
+                              once (1..4) */
+    int32_t sw_grid_scale_wide; /* the same for 9..16 rows per lane (1..4) */
+    int32_t reserved[4];
 } pastis_tuning;
 
 pastis_status pastis_get_tuning(const pastis_ctx *ctx, pastis_tuning *out);
 /* PASTIS_E_INVAL for values out of range. */
 pastis_status pastis_set_tuning(pastis_ctx *ctx, const pastis_tuning *t);
 /* Discovery on the given sequences, then for each knob in turn (16-bit rows,
- * start-bound routing, grid scale) the alignment of up to max_pairs of the
+ * start-bound routing, the two grid scales) the alignment of up to max_pairs of the
  * candidates (an even stride through them) under each candidate value, twice,
  * timed with HIP events on the stream; the fastest setting is kept in ctx and
  * written to *out (may be NULL).  The discovery's candidates stay in ctx. */

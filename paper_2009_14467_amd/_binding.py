@@ -91,8 +91,14 @@ class _Tuning(ctypes.Structure):
         ("sw16_max_rows", ctypes.c_int32),
         ("sw_direct_pct", ctypes.c_int32),
         ("sw_grid_scale", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 5),
+        ("sw_grid_scale_wide", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
     ]
+
+
+def _tuning_dict(t) -> dict:
+    return {"sw16_max_rows": t.sw16_max_rows, "sw_direct_pct": t.sw_direct_pct, "sw_grid_scale": t.sw_grid_scale,
+            "sw_grid_scale_wide": t.sw_grid_scale_wide}
 
 
 class _Stats(ctypes.Structure):
@@ -371,11 +377,13 @@ class Context:
     def get_tuning(self) -> dict:
         t = _Tuning()
         self._check(lib().pastis_get_tuning(self._ctx, ctypes.byref(t)))
-        return {"sw16_max_rows": t.sw16_max_rows, "sw_direct_pct": t.sw_direct_pct, "sw_grid_scale": t.sw_grid_scale}
+        return _tuning_dict(t)
 
-    def set_tuning(self, sw16_max_rows: int = 16, sw_direct_pct: int = 50, sw_grid_scale: int = 2):
+    def set_tuning(self, sw16_max_rows: int = 16, sw_direct_pct: int = 50, sw_grid_scale: int = 2,
+                   sw_grid_scale_wide: int = 1):
         t = _Tuning()
-        t.sw16_max_rows, t.sw_direct_pct, t.sw_grid_scale = sw16_max_rows, sw_direct_pct, sw_grid_scale
+        t.sw16_max_rows, t.sw_direct_pct = sw16_max_rows, sw_direct_pct
+        t.sw_grid_scale, t.sw_grid_scale_wide = sw_grid_scale, sw_grid_scale_wide
         self._check(lib().pastis_set_tuning(self._ctx, ctypes.byref(t)))
 
     def autotune(self, residues, offsets, max_pairs: int = 1 << 21, stream=None) -> dict:
@@ -384,7 +392,7 @@ class Context:
         n = offsets.numel() - 1
         self._check(lib().pastis_autotune(self._ctx, _dev_ptr(residues), _dev_ptr(offsets), n, int(residues.is_cuda),
                                           int(max_pairs), _stream_ptr(stream), ctypes.byref(t)))
-        return {"sw16_max_rows": t.sw16_max_rows, "sw_direct_pct": t.sw_direct_pct, "sw_grid_scale": t.sw_grid_scale}
+        return _tuning_dict(t)
 
     # ---- learned pre-alignment filter ----
 

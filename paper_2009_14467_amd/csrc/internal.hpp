@@ -104,7 +104,7 @@ struct pastis_ctx {
     bool have_candidates = false;
     bool records_internal = false;  // the current alignment's records feed edges only
     int last_max16 = 0;             // the last SW call ran 16-bit pass-1 bins up to this R
-    pastis_tuning tune{16, 50, 2, {0, 0, 0, 0, 0}};
+    pastis_tuning tune{16, 50, 2, 1, {0, 0, 0, 0}};
     // learned filter
     pastis::MlpState mlp{};
     bool mlp_alloc = false, mlp_set = false;
@@ -220,7 +220,8 @@ int64_t sw_scratch_waves();
 // that skip the statistics pass.  grid_scale multiplies the pass-1 grids.
 hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pairs, int64_t npairs,
                      const int8_t *blosum, const Scoring &sc, SwPass1Out *p1, pastis_pair_record *out,
-                     const SwWork &wk, int stats_mode, int max16, int grid_scale, bool timed, hipStream_t s);
+                     const SwWork &wk, int stats_mode, int max16, int grid_scale, int grid_scale_wide, bool timed,
+                     hipStream_t s);
 // 16-bit pass 1 needs o + e >= 4 (biased scores stay non-negative).
 bool sw16_supported(const Scoring &sc);
 bool sw_bin_is16(int bin, int max16);

@@ -393,27 +393,41 @@ __global__ __launch_bounds__(64 * WPB) void sw16_pass1_kernel(const uint8_t *__r
                 const int y = c < lbQ ? (int)bQ[c] : kPadCode;
                 return x | (y << 8);
             };
-            int chunk = cres;
-            int nx = col(lane);
+            int chunk = col(lane);  // columns 0..63; nx holds the next 64
+            int nx = col(kWave + lane);
             const int steps = lb > 0 ? lb + kWave - 1 : 0;
+            // with few rows per lane the profile words of step t + 1 are loaded
+            // during step t (the column residues of step t + 1 follow from
+            // those of step t); with more rows the step itself hides the load
+            constexpr bool kAhead = R <= 8;
+            ProfWord<R> wP = prof[kPadCode][lane], wQ = wP;
             auto step = [&](const int t) {
-                if ((t & (kWave - 1)) == 0) {
+                const int tn = kAhead ? t + 1 : t;  // the step whose residues are fetched
+                if ((tn & (kWave - 1)) == 0 && (kAhead || t > 0)) {
                     chunk = nx;
-                    nx = col(t + kWave + lane);
+                    nx = col(tn + kWave + lane);
                 }
-                const int bt = __builtin_amdgcn_readlane(chunk, t & (kWave - 1));
+                const int bt = __builtin_amdgcn_readlane(chunk, tn & (kWave - 1));
                 const uint32_t rg = (uint32_t)shr1u(G0, glast);
                 const uint32_t rf = (uint32_t)shr1u(NEG2, flast);
+                ProfWord<R> cP, cQ;
                 cres = shr1(bt, cres);
-                const ProfWord<R> wP = prof[cres & 0xFF][lane];
-                const ProfWord<R> wQ = prof[(cres >> 8) & 0xFF][lane];
+                if constexpr (kAhead) {
+                    cP = wP;
+                    cQ = wQ;
+                    wP = prof[cres & 0xFF][lane];
+                    wQ = prof[(cres >> 8) & 0xFF][lane];
+                } else {
+                    cP = prof[cres & 0xFF][lane];
+                    cQ = prof[(cres >> 8) & 0xFF][lane];
+                }
                 short2_t gd = s2(gprev), gu = s2(rg), fu = s2(rf);
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     // byte r of P's and Q's words into the two halves
                     const uint32_t sel =
                         (uint32_t)(r & 3) | 0x0C00u | ((uint32_t)(4 + (r & 3)) << 16) | 0x0C000000u;
-                    const short2_t sig = s2(__builtin_amdgcn_perm(prof_word<R>(wQ, r), prof_word<R>(wP, r), sel));
+                    const short2_t sig = s2(__builtin_amdgcn_perm(prof_word<R>(cQ, r), prof_word<R>(cP, r), sel));
                     const short2_t e = pmax(s2(E[r]) - s2(GE2), s2(G[r]));
                     const short2_t f = pmax(fu - s2(GE2), gu);
                     const short2_t d = gd + sig;
@@ -430,6 +444,12 @@ __global__ __launch_bounds__(64 * WPB) void sw16_pass1_kernel(const uint8_t *__r
                 flast = u2(fu);
                 gprev = rg;
             };
+            if constexpr (kAhead) {  // step 0's residues (lane 0: column 0, the others padding)
+                const int bt0 = __builtin_amdgcn_readlane(chunk, 0);
+                cres = shr1(bt0, cres);
+                wP = prof[cres & 0xFF][lane];
+                wQ = prof[(cres >> 8) & 0xFF][lane];
+            }
             // two steps per iteration, so the old and new G registers can swap
             // roles instead of being copied back every step
             int t = 0;
@@ -1039,7 +1059,8 @@ bool sw_bin_is16(int bin, int max16) { return bin < kSingleBins && rows_of_bin(b
 
 hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pairs, int64_t npairs,
                      const int8_t *blosum, const Scoring &sc, SwPass1Out *p1, pastis_pair_record *out,
-                     const SwWork &wk, int stats_mode, int max16, int grid_scale, bool timed, hipStream_t s) {
+                     const SwWork &wk, int stats_mode, int max16, int grid_scale, int grid_scale_wide, bool timed,
+                     hipStream_t s) {
     // timed = false (graph capture): no stage or per-bin events
     const bool use16 = max16 > 0;
     auto begin = [&](int st) { return timed ? stage_begin(ctx, st, s) : hipSuccess; };
@@ -1068,12 +1089,14 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
         return e;
     for (int bin = 0; bin < kNumBins; ++bin) {
         if ((e = mark(ctx->bin_ev[2 * bin])) != hipSuccess) return e;
+        // multi-strip bins use per-wave boundary buffers: they keep their grid
+        const int scale = bin >= kMultiBin ? 1 : rows_of_bin(bin) <= 8 ? grid_scale : grid_scale_wide;
         if (sw_bin_is16(bin, max16))
-            e = kP16[bin](bin, grid_scale * blocks16(rows_of_bin(bin)), codes, pairs, idx1, wk.starts, blosum, go_ge,
-                          ge, p1, nullptr, 0, s);
-        else  // multi-strip bins use per-wave boundary buffers: keep their grid
-            e = kP1[bin](bin, (bin >= kMultiBin ? 1 : grid_scale) * blocks_for_bin(bin), codes, pairs, idx1,
-                         wk.starts, blosum, go_ge, ge, p1, wk.scratch, wk.scratch_per_wave, s);
+            e = kP16[bin](bin, scale * blocks16(rows_of_bin(bin)), codes, pairs, idx1, wk.starts, blosum, go_ge, ge, p1,
+                          nullptr, 0, s);
+        else
+            e = kP1[bin](bin, scale * blocks_for_bin(bin), codes, pairs, idx1, wk.starts, blosum, go_ge, ge, p1,
+                         wk.scratch, wk.scratch_per_wave, s);
         if (e != hipSuccess) return e;
         if ((e = mark(ctx->bin_ev[2 * bin + 1])) != hipSuccess) return e;
     }

@@ -275,7 +275,8 @@ pastis_status discover(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, 
     unsigned long long mxw = 0;
     PASTIS_TRY(read_device(ctx, M.max_big, &mxw, sizeof(mxw), s));
     const uint32_t gcap = next_pow2(2 * std::max<unsigned long long>(mxw, 12288ull));
-    sp.global_blocks = (int)std::max<int64_t>(8, std::min<int64_t>(256, (int64_t)(2ll << 30) / (16ll * gcap)));
+    // tables of the big rows: up to 8 GiB, at most 512 blocks
+    sp.global_blocks = (int)std::max<int64_t>(8, std::min<int64_t>(512, (int64_t)(8ll << 30) / (24ll * gcap)));
     PASTIS_TRY(get(ctx, kDGtab, (size_t)sp.global_blocks * gcap, &sp.gtables));
     PASTIS_TRY(get(ctx, kDGcand, (size_t)sp.global_blocks * 2 * gcap, &sp.gcand));
     uint32_t cap = (uint32_t)std::min<int64_t>(std::max<int64_t>(4 * n, 1 << 20), (int64_t)1 << 31);

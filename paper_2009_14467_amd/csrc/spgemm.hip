@@ -267,13 +267,15 @@ __global__ __launch_bounds__(kThreads) void spgemm_lds_kernel(RowView rv, Postin
 
 // Rows listed in rows[0..*nrows) with a per-block table of cap 64-bit slots
 // (j << 32 | count, later j << 32 | candidate + 1) and cap / 2 candidates.
+// Each row uses the first next_pow2(2 * work) slots of its block's table (at
+// least 4096, at most cap), so clearing and scanning cost follow the row.
 __global__ __launch_bounds__(kThreads) void spgemm_global_kernel(RowView rv, Postings P, const uint32_t *__restrict__ rows,
-                                                                 const uint32_t *__restrict__ nrows_p, int ck, Emit em,
+                                                                 const uint32_t *__restrict__ nrows_p,
+                                                                 const uint64_t *__restrict__ work, int ck, Emit em,
                                                                  unsigned long long *__restrict__ tables, uint32_t cap,
                                                                  uint32_t *__restrict__ cand) {
     __shared__ ChunkLds C;
     __shared__ uint32_t ncand;
-    const uint32_t mask = cap - 1;
     unsigned long long *slot = tables + (size_t)blockIdx.x * cap;
     uint32_t *cj = cand + (size_t)blockIdx.x * 2 * cap;  // cap/2 entries x 4 arrays
     uint32_t *cc = cj + cap / 2, *c1 = cc + cap / 2, *c2 = c1 + cap / 2;
@@ -286,6 +288,10 @@ __global__ __launch_bounds__(kThreads) void spgemm_global_kernel(RowView rv, Pos
     for (uint32_t w = blockIdx.x; w < nrows; w += gridDim.x) {
         const uint32_t i = rows[w];
         const bool exact = rv.exact;
+        uint64_t want = 2 * work[i];
+        uint32_t rcap = 4096;
+        while (rcap < want && rcap < cap) rcap <<= 1;
+        const uint32_t mask = rcap - 1;
         expand_row(rv, P, i, C, [&](uint32_t, uint32_t j, uint32_t) {
             if (j == i || (exact && j < i)) return;
             uint32_t h = hash32(j) & mask;
@@ -305,7 +311,7 @@ __global__ __launch_bounds__(kThreads) void spgemm_global_kernel(RowView rv, Pos
         });
         __threadfence_block();
         __syncthreads();
-        for (uint32_t t = threadIdx.x; t < cap; t += kThreads) {
+        for (uint32_t t = threadIdx.x; t < rcap; t += kThreads) {
             const unsigned long long v = slot[t];
             if (v == empty) continue;
             const uint32_t c = (uint32_t)v, j = (uint32_t)(v >> 32);
@@ -339,7 +345,7 @@ __global__ __launch_bounds__(kThreads) void spgemm_global_kernel(RowView rv, Pos
             for (uint32_t q = threadIdx.x; q < ncand; q += kThreads) emit(em, i, cj[q], cc[q], c1[q], c2[q]);
         }
         __syncthreads();
-        for (uint32_t t = threadIdx.x; t < cap; t += kThreads) slot[t] = empty;
+        for (uint32_t t = threadIdx.x; t < rcap; t += kThreads) slot[t] = empty;
         if (threadIdx.x == 0) ncand = 0;
         __threadfence_block();
         __syncthreads();
@@ -636,8 +642,8 @@ hipError_t spgemm_run(const SpgemmArgs &a, uint32_t gcap, hipStream_t s) {
                                                        a.n_big);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (gcap > 0) {
-        spgemm_global_kernel<<<a.global_blocks, kThreads, 0, s>>>(rv, P, a.big_rows, a.n_big, a.ck, em, a.gtables,
-                                                                   gcap, a.gcand);
+        spgemm_global_kernel<<<a.global_blocks, kThreads, 0, s>>>(rv, P, a.big_rows, a.n_big, a.work, a.ck, em,
+                                                                   a.gtables, gcap, a.gcand);
         e = hipGetLastError();
     }
     return e;

@@ -584,6 +584,7 @@ __global__ void sw_bin2_kernel(const PairDesc *__restrict__ pairs, SwPass1Out *_
 // Scores of the packed recomputation must fit 15 bits; a local alignment
 // gains at most 11 per row, so rectangles up to this many rows qualify.
 constexpr int kBoundMaxRows = 32000 / 11;
+constexpr int kBoundMaxRowsCoarse = (1 << 19) / 11;
 
 // For a pair that still needs the statistics pass, recompute its end
 // rectangle [0, end_a] x [0, end_b] with every DP value packed as
@@ -593,7 +594,11 @@ constexpr int kBoundMaxRows = 32000 / 11;
 // it (an empty alignment ending at row i starts the next path at row i + 1).
 // The canonical alignment is one of those ending at the end cell, so its
 // coverage of a is at most end_a - bound + 1.  The bound goes to p1[q].pad.
-// Taller rectangles keep bound 0 (no pruning).
+// Scores must fit the high bits: rectangles of up to kBoundMaxRows rows (a
+// local alignment gains at most 11 per row) use 16 low bits; up to
+// kBoundMaxRowsCoarse rows pack score * 4096 + (4095 - start row / 16), a
+// bound rounded down to a multiple of 16 rows (still a valid bound); taller
+// ones keep bound 0 (no pruning).
 template <int R, bool MULTI>
 __global__ __launch_bounds__(64 * wpb32(R)) void sw_bound_kernel(const uint8_t *__restrict__ codes,
                                                        const PairDesc *__restrict__ pairs,
@@ -614,8 +619,7 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_bound_kernel(const uint8_t *
     const int item_end = starts[bin + 1];
     constexpr int RS = kWave * R;
     constexpr int kNegP = -(1 << 30);
-    constexpr int kZero = 0xFFFF;  // score 0, start row 0
-    const int GO = go_ge * 65536, GE = ge * 65536;
+    const int GO16 = go_ge * 65536, GE16 = ge * 65536;
 
     for (int64_t w = starts[bin] + gwave; w < item_end; w += (int64_t)gridDim.x * WPB) {
         const int q = idx[w];
@@ -626,10 +630,15 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_bound_kernel(const uint8_t *
         // one where row end_a reaches the score
         const bool search = r1.end_b < 0;
         const int la = r1.end_a + 1, lb = search ? pd.lb : r1.end_b + 1;
-        if (la > kBoundMaxRows) {
+        if (la > kBoundMaxRowsCoarse) {
             if (lane == 0) p1[q].pad = 0;
             continue;
         }
+        // packing: sb low bits hold (mask - start row >> shift)
+        const int sb = la > kBoundMaxRows ? 12 : 16, shift = 16 - sb;
+        const int mask = (1 << sb) - 1, unit = 1 << sb;
+        const int kZero = mask;  // score 0, start row 0
+        const int GO = sb == 16 ? GO16 : go_ge * unit, GE = sb == 16 ? GE16 : ge * unit;
         const uint8_t *a = codes + pd.a_off;
         const uint8_t *b = codes + pd.b_off;
         const int nstrips = MULTI ? (la + RS - 1) / RS : 1;
@@ -644,7 +653,7 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_bound_kernel(const uint8_t *
             int H[R], G[R], E[R], Z[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                Z[r] = 0xFFFF - max(base + r + 1, 0);  // empty alignment ending in row base + r
+                Z[r] = mask - (max(base + r + 1, 0) >> shift);  // empty alignment ending in row base + r
                 H[r] = Z[r];                           // column -1
                 G[r] = Z[r] - GO;
                 E[r] = kNegP;
@@ -687,7 +696,7 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_bound_kernel(const uint8_t *
                 for (int r = 0; r < R; ++r) {
                     const int e = max(E[r] - GE, G[r]);
                     const int f = max(fu - GE, gu);
-                    const int d = hd + sigma_at<R>(pw, r) * 65536;
+                    const int d = hd + sigma_at<R>(pw, r) * unit;
                     const int h = max(max(d, Z[r]), max(e, f));
                     hd = H[r];
                     H[r] = h;
@@ -703,7 +712,7 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_bound_kernel(const uint8_t *
                 if (last && lane == kWave - 1 && j >= 0 && j < lb) {
                     if (!search) {
                         if (j == lb - 1) fin = hlast;
-                    } else if (fend < 0 && (hlast >> 16) == r1.score) {
+                    } else if (fend < 0 && (hlast >> sb) == r1.score) {
                         fin = hlast;
                         fend = j;
                     }
@@ -718,7 +727,7 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_bound_kernel(const uint8_t *
             if (MULTI) __threadfence_block();
         }
         if (lane == kWave - 1) {
-            p1[q].pad = 0xFFFF - (fin & 0xFFFF);
+            p1[q].pad = (mask - (fin & mask)) << shift;
             if (search) p1[q].end_b = fend;
         }
     }

@@ -207,3 +207,31 @@ def test_filter_needs_a_network(gpu):
     ctx = P.Context(P.Params(k=6, ck_min=1, filter_mode="mlp"))
     with pytest.raises(P.PastisError, match="network"):
         ctx.search(_dev(s.residues, gpu), _dev(s.offsets, gpu))
+
+
+def test_trained_filter_keeps_recall_and_skips_work(gpu):
+    """End to end: train on one sequence set (labels from exact alignment),
+    filter another one from the same recipe; the filtered search finds
+    nearly every exact edge while aligning a small share of the candidates,
+    and its edges are a subset of the exact ones, bit for bit."""
+    import paper_2009_14467_amd as P
+    from paper_2009_14467_amd import learned_filter as LF
+    from synth import workload
+
+    params = dict(k=6, n_subs=25, ck_min=2)
+    tr = workload("mid", n_families=120, seed=1)
+    te = workload("mid", n_families=120, seed=0)
+    tf = LF.train(P.Params(**params), _dev(tr.residues, gpu), _dev(tr.offsets, gpu), epochs=6, batch=1024)
+    assert tf.heldout_recall >= 0.97
+    res, off = _dev(te.residues, gpu), _dev(te.offsets, gpu)
+    exact = P.Context(P.Params(**params)).search(res, off)
+    ctx = P.Context(P.Params(filter_mode="mlp", **params))
+    tf.install(ctx)
+    got = ctx.search(res, off)
+    st = ctx.stats()
+    keys = lambda e: (e["i"].astype(np.uint64) << np.uint64(32)) | e["j"].astype(np.uint64)  # noqa: E731
+    sel = np.isin(keys(exact), keys(got))
+    assert sel.sum() == got.size  # a subset of the exact edges ...
+    assert got.tobytes() == exact[sel].tobytes()  # ... with identical fields
+    assert got.size >= 0.97 * exact.size
+    assert st["n_aligned"] < 0.5 * st["n_candidates"]  # a small training set: about a third kept

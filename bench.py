@@ -35,7 +35,8 @@ OPS_PER_SW_CELL = 11
 # dispatch on the mid workload, profiles/sw_search_mid_kernel_stats.md), scaled
 # by what the counters read for a 1 GiB device copy (FETCH x 2.0, WRITE x 1.0);
 # only for kernels unchanged since those counters were taken
-MEASURED_TRAFFIC_KIB = {}
+MEASURED_TRAFFIC_KIB = {"sw16_pass1_kernel<6, 4>": (1262951.0, 106064.375),
+                        "sw16_pass1_kernel<9, 2>": (641221.375, 53290.3125)}
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
 # method parameters of each workload (Section VI settings: BLOSUM62, gaps
@@ -297,6 +298,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload}: {fs.n} sequences ({fs.residues.size} residues), "
+            + ("" if args.families is None else f"scaled to {args.families} families; ")
             + WORKLOAD_TEXT[args.workload],
             "step": "pastis_search: sequences resident in HBM -> edges in HBM (discovery, SW, cut, edges)",
             **{k: v for k, v in params.items()},

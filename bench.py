@@ -28,15 +28,20 @@ METRIC = "alignment GCUPS + aligned pairs/s, 1 GPU; MLP-filtered vs plain at ≥
 # packed 16-bit ops (v_pk_*_i16) do two lane-ops each
 PEAK_INT32_TOPS = 256 * 64 * 2.4e9 / 1e12
 PEAK_INT16_TOPS = 2 * PEAK_INT32_TOPS
-# algorithmic integer ops per SW cell: gap-open term, E and F updates,
-# diagonal + score, two maxima, end tracking
-OPS_PER_SW_CELL = 11
+# algorithmic integer ops per pass-1 DP cell, as each lane width computes the
+# recurrence with the gap states floored at zero (E' = max(E, 0), F' = max(F, 0)):
+#   16-bit, per two cells (one packed op each): spread of the two scores (1),
+#     d = G + s (1), E' and F' (clamped subtract + max: 2 + 2), h = max(d, E', F')
+#     (2), G = h - (o + e) (1), row maximum (1)                       -> 10
+#   32-bit one strip: d (1), E' (2), F' (2), h (one 3-way max: 1), G (1),
+#     end key (h << 16 | ~column) and its maximum (2)                -> 9
+#   32-bit multi-strip: as one strip, but the row maximum and its column (3) -> 10
+OPS_PER_SW_CELL = {(16, False): 10, (32, False): 9, (32, True): 10}
 # HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (KiB per
 # dispatch on the mid workload, profiles/sw_search_mid_kernel_stats.md), scaled
 # by what the counters read for a 1 GiB device copy (FETCH x 2.0, WRITE x 1.0);
 # only for kernels unchanged since those counters were taken
-MEASURED_TRAFFIC_KIB = {"sw16_pass1_kernel<6, 4>": (1262951.0, 106064.375),
-                        "sw16_pass1_kernel<9, 2>": (641221.375, 53290.3125)}
+MEASURED_TRAFFIC_KIB = {}
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
 # method parameters of each workload (Section VI settings: BLOSUM62, gaps
@@ -277,10 +282,14 @@ def main():
     else:
         dom_name = "sw_pass1_kernel<%d, %s>" % (R, "true" if dom["multi_strip"] else "false")
         peak = PEAK_INT32_TOPS
-    achieved = dom["cells"] * OPS_PER_SW_CELL / (dom["ms"] * 1e-3) / 1e12
-    pass1_tops = cells * OPS_PER_SW_CELL / (pass1_ms * 1e-3) / 1e12
+    def ops(b):
+        return OPS_PER_SW_CELL[(b["bits"], bool(b["multi_strip"]))]
+
+    achieved = dom["cells"] * ops(dom) / (dom["ms"] * 1e-3) / 1e12
+    pass1_ops = sum(b["cells"] * ops(b) for b in st["sw_bins"])
+    pass1_tops = pass1_ops / (pass1_ms * 1e-3) / 1e12
     # peak of the pass-1 mix: each bin's cells at its own width's peak
-    mix_peak_s = sum(b["cells"] * OPS_PER_SW_CELL / ((PEAK_INT16_TOPS if b["bits"] == 16 else PEAK_INT32_TOPS) * 1e12)
+    mix_peak_s = sum(b["cells"] * ops(b) / ((PEAK_INT16_TOPS if b["bits"] == 16 else PEAK_INT32_TOPS) * 1e12)
                      for b in st["sw_bins"])
     names = ["encode", "kmers", "subs_AS", "spgemm", "schedule", "sw_pass1", "sw_pass2", "edges", "mlp_filter"]
     line = {
@@ -325,7 +334,7 @@ def main():
                                 WRITE_SCALE * MEASURED_TRAFFIC_KIB[dom_name][1])),
             "kernel_ms": dom["ms"],
             "kernel_cells": dom["cells"],
-            "ops_per_cell": OPS_PER_SW_CELL,
+            "ops_per_cell": ops(dom),
             "all_pass1_bins": {"achieved": pass1_tops, "frac_of_mix_peak": mix_peak_s / (pass1_ms * 1e-3)},
         },
         "sw_bins": [dict(b, gcups=b["cells"] / max(b["ms"], 1e-9) / 1e6) for b in st["sw_bins"] if b["pairs"]],

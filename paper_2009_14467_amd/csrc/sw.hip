@@ -64,6 +64,10 @@ __device__ __forceinline__ int shr1(int lane0, int v) {
     return __builtin_amdgcn_update_dpp(lane0, v, kDppWaveShr1, 0xF, 0xF, false);
 }
 
+// lane l receives lane l-1's value; lane 0 receives 0 (the move's bound
+// control zero-fills, so no separate write of lane 0's value is needed)
+__device__ __forceinline__ int shr1z(int v) { return __builtin_amdgcn_update_dpp(0, v, kDppWaveShr1, 0xF, 0xF, true); }
+
 // R int8 scores per lane and residue code, in ceil(R / 4) words
 template <int R>
 using ProfWord = typename std::conditional<
@@ -140,6 +144,15 @@ __device__ __forceinline__ T vload(const T *p) {
 
 // ---------------------------------------------------------------- pass 1
 
+// max(x - y, 0) for x >= 0, y >= 0 (one clamped subtract)
+__device__ __forceinline__ int subs(int x, int y) {
+    return (int)__builtin_elementwise_sub_sat((unsigned)x, (unsigned)y);
+}
+
+// Pass 1, 32-bit lanes.  The gap states are kept floored at zero, E' =
+// max(E, 0) and F' = max(F, 0) (max(E' - e, 0) = max(E - e, 0) for e >= 0,
+// one clamped subtract); max(d, E', F') then already holds the local
+// alignment's zero.  The strip boundary carries F'.
 template <int R, bool MULTI>
 __global__ __launch_bounds__(64 * wpb32(R)) void sw_pass1_kernel(const uint8_t *__restrict__ codes,
                                                        const PairDesc *__restrict__ pairs,
@@ -180,18 +193,18 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_pass1_kernel(const uint8_t *
             for (int r = 0; r < R; ++r) {
                 H[r] = 0;
                 G[r] = -go_ge;
-                E[r] = kNeg;
+                E[r] = 0;
                 key[r] = 0;
                 rmax[r] = 0;
                 rcol[r] = 0;
             }
-            int hlast = 0, flast = kNeg, hprev = 0, cres = kPadCode;
+            int hlast = 0, flast = 0, hprev = 0, cres = kPadCode;
             // column residues and the strip boundary row arrive in coalesced
             // chunks of 64 columns, fetched one chunk ahead; lane 0 reads its
             // value for step t with readlane
-            int chunk = kPadCode, ch_h = 0, ch_f = kNeg;
+            int chunk = kPadCode, ch_h = 0, ch_f = 0;
             int nx = (lane < lb) ? (int)b[lane] : kPadCode;
-            int nx_h = 0, nx_f = kNeg;
+            int nx_h = 0, nx_f = 0;
             if (MULTI && from_above && lane < lb) {
                 nx_h = vload(bnd_h + lane);
                 nx_f = vload(bnd_f + lane);
@@ -214,7 +227,7 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_pass1_kernel(const uint8_t *
                     }
                 }
                 const int bt = __builtin_amdgcn_readlane(chunk, t & (kWave - 1));
-                int in_h = 0, in_f = kNeg;
+                int in_h = 0, in_f = 0;
                 if (MULTI && !kTail && from_above) {
                     in_h = __builtin_amdgcn_readlane(ch_h, t & (kWave - 1));
                     in_f = __builtin_amdgcn_readlane(ch_f, t & (kWave - 1));
@@ -229,10 +242,10 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_pass1_kernel(const uint8_t *
                 int hd = hprev, gu = rh - go_ge, fu = rf;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const int e = max(E[r] - ge, G[r]);
-                    const int f = max(fu - ge, gu);
+                    const int e = max(subs(E[r], ge), G[r]);
+                    const int f = max(subs(fu, ge), gu);
                     const int d = hd + sigma_at<R>(pw, r);
-                    const int h = max(max(d, 0), max(e, f));
+                    const int h = max(d, max(e, f));
                     hd = H[r];
                     H[r] = h;
                     E[r] = e;
@@ -308,11 +321,21 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_pass1_kernel(const uint8_t *
 // below its best real cell, so the score and the first row holding it are
 // exact; the end column is found later, for the pairs that need it (end_b =
 // -1 here).  Scores stay below 11 * 1024, far from the 16-bit limit.
+// The gap states are kept floored at zero, E' = max(E, 0) and F' = max(F, 0):
+// their recurrences stay closed (max(E' - e, 0) = max(E - e, 0) for e >= 0,
+// one saturating subtract), and max(d, E', F') then already holds the local
+// alignment's zero, so a cell takes 10 packed ops instead of 11.
 constexpr int kMax16R = kMaxR;
 
 typedef short short2_t __attribute__((ext_vector_type(2)));
+typedef unsigned short ushort2_t __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ short2_t s2(uint32_t x) { return __builtin_bit_cast(short2_t, x); }
+// max(x - y, 0) per half, for 0 <= x < 2^15
+__device__ __forceinline__ short2_t psubs(short2_t x, uint32_t y) {
+    return __builtin_bit_cast(short2_t, __builtin_elementwise_sub_sat(__builtin_bit_cast(ushort2_t, x),
+                                                                      __builtin_bit_cast(ushort2_t, y)));
+}
 __device__ __forceinline__ uint32_t u2(short2_t x) { return __builtin_bit_cast(uint32_t, x); }
 __device__ __forceinline__ short2_t pmax(short2_t a, short2_t b) { return __builtin_elementwise_max(a, b); }
 __device__ __forceinline__ int shr1u(uint32_t lane0, uint32_t v) { return shr1((int)lane0, (int)v); }
@@ -345,6 +368,29 @@ __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
     return v;
 }
 
+// Profile of a shared by the waves of a block: the threads of wave k write
+// the codes c = k (mod WPB) for their lane's rows.
+template <int R, int WPB>
+__device__ __forceinline__ void build_profile16b(ProfWord<R> (*prof)[kWave], const int8_t *sblosum, const uint8_t *a,
+                                                 int la, int lane, int wave, int oe) {
+    int ar[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) ar[r] = (lane * R + r < la) ? a[lane * R + r] : kPadCode;
+    for (int c = wave; c < kProfCodes; c += WPB) {
+        uint32_t w[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int sc = max((int)sblosum[ar[r] * kProfCodes + c], -oe) + oe;
+            w[r >> 2] |= (uint32_t)sc << (8 * (r & 3));
+        }
+        prof[c][lane] = make_word<R>(w);
+    }
+}
+
+// Full-wave layout for the wider one-strip bins.  A block takes 2 * WPB
+// consecutive pairs (two per wave) and its waves share one profile, built
+// once per distinct sequence a among them (pairs are sorted by a), so the
+// LDS of a block does not grow with its wave count.
 template <int R, int WPB>
 __global__ __launch_bounds__(64 * WPB) void sw16_pass1_kernel(const uint8_t *__restrict__ codes,
                                                               const PairDesc *__restrict__ pairs,
@@ -353,40 +399,53 @@ __global__ __launch_bounds__(64 * WPB) void sw16_pass1_kernel(const uint8_t *__r
                                                               const int8_t *__restrict__ blosum, int go_ge, int ge,
                                                               SwPass1Out *__restrict__ out) {
     static_assert(R <= kMax16R, "one strip");
-    __shared__ ProfWord<R> prof_all[WPB][kProfCodes][kWave];
+    constexpr int NI = 2 * WPB;  // pairs per block
+    __shared__ ProfWord<R> prof[kProfCodes][kWave];
     __shared__ int8_t sblosum[kProfCodes * kProfCodes];
+    // first unfinished pair of each wave, double-buffered by round parity so
+    // that a round's writes never meet the previous round's reads
+    __shared__ int s_next[2][WPB];
     load_blosum(sblosum, blosum);
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
-    ProfWord<R>(*prof)[kWave] = prof_all[wave];
-    const int64_t gwave = (int64_t)blockIdx.x * WPB + wave;
     const int item_end = starts[bin + 1];
     const uint32_t OE2 = (uint32_t)go_ge * 0x10001u, GE2 = (uint32_t)ge * 0x10001u;
-    const uint32_t NEG2 = 0xC000C000u;  // -16384 in both halves
     const uint32_t G0 = ((uint32_t)(-go_ge) & 0xFFFFu) * 0x10001u;  // G of an H = 0 cell
+    int par = 0;
 
-    for (int64_t w = starts[bin] + 2 * gwave; w < item_end; w += 2 * (int64_t)gridDim.x * WPB) {
-        const bool two = w + 1 < item_end;
-        const int q0 = idx[w], q1 = two ? idx[w + 1] : q0;
-        const PairDesc d0 = pairs[q0], d1 = pairs[q1];
-        const bool same = two && d0.a_seq == d1.a_seq;
-        const int rounds = (two && !same) ? 2 : 1;
-        for (int round = 0; round < rounds; ++round) {
-            const PairDesc pP = round == 0 ? d0 : d1;
-            const int qP = round == 0 ? q0 : q1;
-            const bool hasQ = same;
-            const int laP = pP.la, lbP = pP.lb, lbQ = hasQ ? d1.lb : 0;
-            const uint8_t *bP = codes + pP.b_off, *bQ = codes + d1.b_off;
-            build_profile16<R>(prof, sblosum, codes + pP.a_off, laP, lane, go_ge);
+    for (int64_t w = starts[bin] + (int64_t)NI * blockIdx.x; w < item_end; w += (int64_t)NI * gridDim.x) {
+        const int nit = (int)min((int64_t)NI, item_end - w);
+        const int iP = 2 * wave, iQ = iP + 1;
+        const int qP = iP < nit ? idx[w + iP] : -1;
+        const int qQ = iQ < nit ? idx[w + iQ] : -1;
+        const int q0 = idx[w];
+        const PairDesc dP = pairs[qP < 0 ? q0 : qP], dQ = pairs[qQ < 0 ? q0 : qQ];
+        bool doneP = qP < 0, doneQ = qQ < 0;
+        for (;;) {
+            // this round's sequence a: that of the block's first unfinished pair
+            if (lane == 0) s_next[par][wave] = !doneP ? iP : !doneQ ? iQ : NI;
+            __syncthreads();
+            int first = NI;
+#pragma unroll
+            for (int k = 0; k < WPB; ++k) first = min(first, s_next[par][k]);
+            par ^= 1;
+            if (first >= NI) break;
+            const PairDesc dA = pairs[idx[w + first]];
+            const bool actP = !doneP && dP.a_seq == dA.a_seq;
+            const bool actQ = !doneQ && dQ.a_seq == dA.a_seq;
+            const int laP = dA.la, lbP = actP ? dP.lb : 0, lbQ = actQ ? dQ.lb : 0;
+            const uint8_t *bP = codes + dP.b_off, *bQ = codes + dQ.b_off;
+            build_profile16b<R, WPB>(prof, sblosum, codes + dA.a_off, laP, lane, wave, go_ge);
+            __syncthreads();
             const int lb = max(lbP, lbQ);
             uint32_t G[R], E[R], M[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 G[r] = G0;
-                E[r] = NEG2;
+                E[r] = 0u;
                 M[r] = 0u;
             }
-            uint32_t glast = G0, flast = NEG2, gprev = G0;
+            uint32_t glast = G0, flast = 0u, gprev = G0;
             int cres = kPadCode | (kPadCode << 8);
             auto col = [&](int c) {
                 const int x = c < lbP ? (int)bP[c] : kPadCode;
@@ -409,7 +468,7 @@ __global__ __launch_bounds__(64 * WPB) void sw16_pass1_kernel(const uint8_t *__r
                 }
                 const int bt = __builtin_amdgcn_readlane(chunk, tn & (kWave - 1));
                 const uint32_t rg = (uint32_t)shr1u(G0, glast);
-                const uint32_t rf = (uint32_t)shr1u(NEG2, flast);
+                const uint32_t rf = (uint32_t)shr1z((int)flast);
                 ProfWord<R> cP, cQ;
                 cres = shr1(bt, cres);
                 if constexpr (kAhead) {
@@ -428,10 +487,10 @@ __global__ __launch_bounds__(64 * WPB) void sw16_pass1_kernel(const uint8_t *__r
                     const uint32_t sel =
                         (uint32_t)(r & 3) | 0x0C00u | ((uint32_t)(4 + (r & 3)) << 16) | 0x0C000000u;
                     const short2_t sig = s2(__builtin_amdgcn_perm(prof_word<R>(cQ, r), prof_word<R>(cP, r), sel));
-                    const short2_t e = pmax(s2(E[r]) - s2(GE2), s2(G[r]));
-                    const short2_t f = pmax(fu - s2(GE2), gu);
+                    const short2_t e = pmax(psubs(s2(E[r]), GE2), s2(G[r]));
+                    const short2_t f = pmax(psubs(fu, GE2), gu);
                     const short2_t d = gd + sig;
-                    const short2_t h = pmax(pmax(d, s2(0u)), pmax(e, f));
+                    const short2_t h = pmax(d, pmax(e, f));
                     gd = s2(G[r]);
                     const short2_t g = h - s2(OE2);
                     G[r] = u2(g);
@@ -473,17 +532,260 @@ __global__ __launch_bounds__(64 * WPB) void sw16_pass1_kernel(const uint8_t *__r
             kq = wave_max_u32(kq);
             if (lane == 0) {
                 SwPass1Out o;
-                o.score = (int32_t)(kp >> 16);
-                o.end_a = o.score > 0 ? (int32_t)(0xFFFFu - (kp & 0xFFFFu)) : -1;
                 o.end_b = -1;
                 o.pad = 0;
-                out[qP] = o;
-                if (hasQ) {
+                if (actP) {
+                    o.score = (int32_t)(kp >> 16);
+                    o.end_a = o.score > 0 ? (int32_t)(0xFFFFu - (kp & 0xFFFFu)) : -1;
+                    out[qP] = o;
+                }
+                if (actQ) {
                     o.score = (int32_t)(kq >> 16);
                     o.end_a = o.score > 0 ? (int32_t)(0xFFFFu - (kq & 0xFFFFu)) : -1;
-                    out[q1] = o;
+                    out[qQ] = o;
                 }
             }
+            doneP = doneP || actP;
+            doneQ = doneQ || actQ;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- pass 1, 16-bit lanes, strips of S lanes
+
+// For short sequences a the wave splits into 64 / S independent strips of S
+// lanes (S = 16 or 32).  Each strip runs two pairs of the wave's sequence a in
+// the halves of its words, with the same recurrence as above; lane p of a
+// strip owns rows [p * RP, p * RP + RP), so a bin of 64 R rows takes RP =
+// 64 R / S rows per lane.  A pair then pays S - 1 steps of wavefront fill and
+// drain instead of 63, and the fixed work of a step (lane shifts, residue and
+// profile fetches) serves 64 / S times more cells.  All strips read one
+// profile of 25 codes x S lanes.  Column residues enter at a strip's first
+// lane from a chunk of 16 columns held across the strip's first 16 lanes,
+// rotated by one lane per step.
+constexpr int kDppRowShr1 = 0x111;
+constexpr int kDppRowRor15 = 0x12F;
+
+// lane p of a strip receives lane p - 1's value; the strip's first lane
+// receives `first`
+template <int S>
+__device__ __forceinline__ uint32_t strip_shr(uint32_t first, uint32_t v, int lane) {
+    if constexpr (S == 16) {
+        return (uint32_t)__builtin_amdgcn_update_dpp((int)first, (int)v, kDppRowShr1, 0xF, 0xF, false);
+    } else {
+        const uint32_t t = (uint32_t)__builtin_amdgcn_update_dpp((int)first, (int)v, kDppWaveShr1, 0xF, 0xF, false);
+        return lane == kWave / 2 ? first : t;
+    }
+}
+
+// as strip_shr with first = 0 (zero-filled by the move's bound control)
+template <int S>
+__device__ __forceinline__ uint32_t strip_shrz(uint32_t v, int lane) {
+    if constexpr (S == 16) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowShr1, 0xF, 0xF, true);
+    } else {
+        const uint32_t t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppWaveShr1, 0xF, 0xF, true);
+        return lane == kWave / 2 ? 0u : t;
+    }
+}
+
+template <int S>
+__device__ __forceinline__ unsigned strip_max_u32(unsigned v) {
+#pragma unroll
+    for (int off = S / 2; off > 0; off >>= 1) v = max(v, (unsigned)__shfl_xor((int)v, off, kWave));
+    return v;
+}
+
+__device__ __forceinline__ int wave_min_i32(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max_i32(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+// Profile of a for strips of S lanes: entry [c][p] holds the biased scores of
+// rows p * RP .. p * RP + RP - 1 against code c.  The lanes of strip k write
+// the codes c = k (mod 64 / S); every lane then reads entries written by
+// other lanes of its wave (LDS operations of one wave complete in order).
+template <int RP, int S>
+__device__ __forceinline__ void build_profile16s(ProfWord<RP> (*prof)[S], const int8_t *sblosum, const uint8_t *a,
+                                                 int la, int pos, int strip, int oe) {
+    int ar[RP];
+#pragma unroll
+    for (int r = 0; r < RP; ++r) ar[r] = (pos * RP + r < la) ? a[pos * RP + r] : kPadCode;
+    for (int c = strip; c < kProfCodes; c += kWave / S) {
+        uint32_t w[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int r = 0; r < RP; ++r) {
+            const int sc = max((int)sblosum[ar[r] * kProfCodes + c], -oe) + oe;
+            w[r >> 2] |= (uint32_t)sc << (8 * (r & 3));
+        }
+        prof[c][pos] = make_word<RP>(w);
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <int S, int RP, int WPB>
+__global__ __launch_bounds__(64 * WPB) void sw16s_pass1_kernel(const uint8_t *__restrict__ codes,
+                                                               const PairDesc *__restrict__ pairs,
+                                                               const int *__restrict__ idx,
+                                                               const int *__restrict__ starts, int bin,
+                                                               const int8_t *__restrict__ blosum, int go_ge, int ge,
+                                                               SwPass1Out *__restrict__ out) {
+    static_assert((S == 16 || S == 32) && RP <= kMax16R, "strip shape");
+    constexpr int NI = 2 * kWave / S;  // pairs per wave: two per strip
+    __shared__ ProfWord<RP> prof_all[WPB][kProfCodes][S];
+    __shared__ int8_t sblosum[kProfCodes * kProfCodes];
+    load_blosum(sblosum, blosum);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int pos = lane % S, strip = lane / S, cl = lane & 15;
+    ProfWord<RP>(*prof)[S] = prof_all[wave];
+    const int64_t gwave = (int64_t)blockIdx.x * WPB + wave;
+    const int item_end = starts[bin + 1];
+    const uint32_t OE2 = (uint32_t)go_ge * 0x10001u, GE2 = (uint32_t)ge * 0x10001u;
+    const uint32_t G0 = ((uint32_t)(-go_ge) & 0xFFFFu) * 0x10001u;  // G of an H = 0 cell
+
+    for (int64_t w = starts[bin] + NI * gwave; w < item_end; w += NI * (int64_t)gridDim.x * WPB) {
+        const int nit = (int)min((int64_t)NI, item_end - w);
+        const int iP = 2 * strip, iQ = iP + 1;
+        const int qP = iP < nit ? idx[w + iP] : -1;
+        const int qQ = iQ < nit ? idx[w + iQ] : -1;
+        const int q0 = idx[w];
+        const PairDesc dP = pairs[qP < 0 ? q0 : qP], dQ = pairs[qQ < 0 ? q0 : qQ];
+        bool doneP = qP < 0, doneQ = qQ < 0;
+        // one round per distinct sequence a among the wave's pairs (pairs are
+        // sorted by a, so nearly always one)
+        for (;;) {
+            const int mine = !doneP ? iP : !doneQ ? iQ : NI;
+            const int first = __builtin_amdgcn_readfirstlane(wave_min_i32(mine));
+            if (first >= NI) break;
+            const int src = (first >> 1) * S;
+            const bool fq = (first & 1) != 0;
+            const int a_seq = __builtin_amdgcn_readlane(fq ? dQ.a_seq : dP.a_seq, src);
+            const int la = __builtin_amdgcn_readlane(fq ? dQ.la : dP.la, src);
+            const int64_t a_off_v = fq ? dQ.a_off : dP.a_off;
+            const uint32_t off_lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)a_off_v, src);
+            const uint32_t off_hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(a_off_v >> 32), src);
+            const int64_t a_off = (int64_t)(((uint64_t)off_hi << 32) | off_lo);
+            const bool actP = !doneP && dP.a_seq == a_seq;
+            const bool actQ = !doneQ && dQ.a_seq == a_seq;
+            const int lbP = actP ? dP.lb : 0, lbQ = actQ ? dQ.lb : 0;
+            const uint8_t *bP = codes + dP.b_off, *bQ = codes + dQ.b_off;
+            build_profile16s<RP, S>(prof, sblosum, codes + a_off, la, pos, strip, go_ge);
+            const int lbmax = wave_max_i32(max(lbP, lbQ));
+            const int steps = __builtin_amdgcn_readfirstlane(lbmax > 0 ? lbmax + S - 1 : 0);
+            uint32_t G[RP], E[RP], M[RP];
+#pragma unroll
+            for (int r = 0; r < RP; ++r) {
+                G[r] = G0;
+                E[r] = 0u;
+                M[r] = 0u;
+            }
+            uint32_t glast = G0, flast = 0u, gprev = G0;
+            uint32_t cres = kPadCode | (kPadCode << 8);
+            auto col = [&](int c) -> uint32_t {
+                const int x = c < lbP ? (int)bP[c] : kPadCode;
+                const int y = c < lbQ ? (int)bQ[c] : kPadCode;
+                return (uint32_t)(x | (y << 8));
+            };
+            uint32_t chunk = col(cl);  // columns 0..15; nx holds the next 16
+            uint32_t nx = col(16 + cl);
+            // the residues of step tn enter at each strip's first lane
+            auto feed = [&](const int tn) {
+                if ((tn & 15) == 0 && tn > 0) {
+                    chunk = nx;
+                    nx = col(tn + 16 + cl);
+                }
+                cres = strip_shr<S>(chunk, cres, lane);
+                chunk = (uint32_t)__builtin_amdgcn_mov_dpp((int)chunk, kDppRowRor15, 0xF, 0xF, false);
+            };
+            // as in the full-wave kernel: with few rows per lane the profile
+            // words of step t + 1 are loaded during step t
+            constexpr bool kAhead = RP <= 8;
+            ProfWord<RP> wP = prof[kPadCode][pos], wQ = wP;
+            auto step = [&](const int t) {
+                const uint32_t rg = strip_shr<S>(G0, glast, lane);
+                const uint32_t rf = strip_shrz<S>(flast, lane);
+                ProfWord<RP> cP, cQ;
+                if constexpr (kAhead) {
+                    feed(t + 1);
+                    cP = wP;
+                    cQ = wQ;
+                    wP = prof[cres & 0xFF][pos];
+                    wQ = prof[(cres >> 8) & 0xFF][pos];
+                } else {
+                    feed(t);
+                    cP = prof[cres & 0xFF][pos];
+                    cQ = prof[(cres >> 8) & 0xFF][pos];
+                }
+                short2_t gd = s2(gprev), gu = s2(rg), fu = s2(rf);
+#pragma unroll
+                for (int r = 0; r < RP; ++r) {
+                    const uint32_t sel =
+                        (uint32_t)(r & 3) | 0x0C00u | ((uint32_t)(4 + (r & 3)) << 16) | 0x0C000000u;
+                    const short2_t sig = s2(__builtin_amdgcn_perm(prof_word<RP>(cQ, r), prof_word<RP>(cP, r), sel));
+                    const short2_t e = pmax(psubs(s2(E[r]), GE2), s2(G[r]));
+                    const short2_t f = pmax(psubs(fu, GE2), gu);
+                    const short2_t d = gd + sig;
+                    const short2_t h = pmax(d, pmax(e, f));
+                    gd = s2(G[r]);
+                    const short2_t g = h - s2(OE2);
+                    G[r] = u2(g);
+                    E[r] = u2(e);
+                    M[r] = u2(pmax(s2(M[r]), h));
+                    gu = g;
+                    fu = f;
+                }
+                glast = G[RP - 1];
+                flast = u2(fu);
+                gprev = rg;
+            };
+            if constexpr (kAhead) {
+                feed(0);
+                wP = prof[cres & 0xFF][pos];
+                wQ = prof[(cres >> 8) & 0xFF][pos];
+            }
+            int t = 0;
+            for (; t + 1 < steps; t += 2) {
+                step(t);
+                step(t + 1);
+            }
+            if (t < steps) step(t);
+            unsigned kp = 0u, kq = 0u;
+#pragma unroll
+            for (int r = 0; r < RP; ++r) {
+                const int row = pos * RP + r;
+                const unsigned rk = 0xFFFFu - (unsigned)row;
+                if (row < la) {
+                    kp = max(kp, ((M[r] & 0xFFFFu) << 16) | rk);
+                    kq = max(kq, (M[r] & 0xFFFF0000u) | rk);
+                }
+            }
+            kp = strip_max_u32<S>(kp);
+            kq = strip_max_u32<S>(kq);
+            if (pos == 0) {
+                SwPass1Out o;
+                o.end_b = -1;
+                o.pad = 0;
+                if (actP) {
+                    o.score = (int32_t)(kp >> 16);
+                    o.end_a = o.score > 0 ? (int32_t)(0xFFFFu - (kp & 0xFFFFu)) : -1;
+                    out[qP] = o;
+                }
+                if (actQ) {
+                    o.score = (int32_t)(kq >> 16);
+                    o.end_a = o.score > 0 ? (int32_t)(0xFFFFu - (kq & 0xFFFFu)) : -1;
+                    out[qQ] = o;
+                }
+            }
+            doneP = doneP || actP;
+            doneQ = doneQ || actQ;
         }
     }
 }
@@ -1001,17 +1303,26 @@ hipError_t launch_pb(int bin, int blocks, const uint8_t *codes, const PairDesc *
     return hipGetLastError();
 }
 
-// waves per block of the 16-bit pass: one int8 profile of 25 x 64 x R bytes
-// per wave, blocks of at most ~51 KB of LDS
-constexpr int wpb16(int R) { return R <= 8 ? 4 : 2; }
+// waves per block of the 16-bit pass (strips: one profile per wave; full
+// waves: one profile per block) and blocks per launch
+constexpr int wpb16(int R) { return 4; }
 static int blocks16(int R) { return R <= 4 ? 256 * 6 : (R > 8 && R <= 12) ? 256 * 4 : 256 * 3; }
 
+// R <= 4: strips of 16 lanes with 4 R rows per lane; R = 5..8: strips of 32
+// lanes with 2 R rows; wider bins: the full-wave kernel
 template <int R>
 hipError_t launch_p16(int bin, int blocks, const uint8_t *codes, const PairDesc *pairs, const int *idx,
                       const int *starts, const int8_t *blosum, int go_ge, int ge, SwPass1Out *p1, int *, int64_t,
                       hipStream_t s) {
     constexpr int WPB = wpb16(R);
-    sw16_pass1_kernel<R, WPB><<<blocks, 64 * WPB, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, p1);
+    if constexpr (R <= 4)
+        sw16s_pass1_kernel<16, 4 * R, WPB><<<blocks, 64 * WPB, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge,
+                                                                      ge, p1);
+    else if constexpr (R <= 8)
+        sw16s_pass1_kernel<32, 2 * R, WPB><<<blocks, 64 * WPB, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge,
+                                                                      ge, p1);
+    else
+        sw16_pass1_kernel<R, WPB><<<blocks, 64 * WPB, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, p1);
     return hipGetLastError();
 }
 

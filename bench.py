@@ -36,7 +36,8 @@ PEAK_INT16_TOPS = 2 * PEAK_INT32_TOPS
 #   32-bit one strip: d (1), E' (2), F' (2), h (one 3-way max: 1), G (1),
 #     end key (h << 16 | ~column) and its maximum (2)                -> 9
 #   32-bit multi-strip: as one strip, but the row maximum and its column (3) -> 10
-OPS_PER_SW_CELL = {(16, False): 10, (32, False): 9, (32, True): 10}
+#   16-bit multi-strip: as 16-bit (the strip boundary is a lane move)        -> 10
+OPS_PER_SW_CELL = {(16, False): 10, (16, True): 10, (32, False): 9, (32, True): 10}
 # HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (KiB per
 # dispatch on the mid workload, profiles/sw_search_mid_kernel_stats.md), scaled
 # by what the counters read for a 1 GiB device copy (FETCH x 2.0, WRITE x 1.0);
@@ -277,7 +278,14 @@ def main():
     dom = max(st["sw_bins"], key=lambda b: b["ms"])
     R = dom["rows_per_lane"]
     if dom["bits"] == 16:
-        dom_name = "sw16_pass1_kernel<%d, %d>" % (R, 4 if R <= 8 else 2)
+        if dom["multi_strip"]:
+            dom_name = "sw16_pass1_kernel<%d, 4, true>" % R
+        elif R <= 4:
+            dom_name = "sw16s_pass1_kernel<16, %d, 4>" % (4 * R)
+        elif R <= 8:
+            dom_name = "sw16s_pass1_kernel<32, %d, 4>" % (2 * R)
+        else:
+            dom_name = "sw16_pass1_kernel<%d, 4, false>" % R
         peak = PEAK_INT16_TOPS
     else:
         dom_name = "sw_pass1_kernel<%d, %s>" % (R, "true" if dom["multi_strip"] else "false")

@@ -75,8 +75,8 @@ typedef struct pastis_params {
     int32_t min_coverage_pct; /* ANI cut: 100 * aligned span >= pct * shorter length */
     int32_t weight_mode;      /* pastis_weight_mode */
     int32_t score_width;      /* DP word width of Smith-Waterman pass 1: 16 runs pairs
-                                 whose shorter side fits one strip of 1024 rows two
-                                 per wave in 16-bit lanes (records of pairs without
+                                 whose shorter side has at most 2978 rows (scores below
+                                 2^15) two per wave in 16-bit lanes (records of pairs without
                                  the statistics pass then carry end_b = -1); 32 runs
                                  every pair in 32-bit lanes; 0 (automatic) takes 16
                                  inside pastis_search with identity weights and 32

@@ -189,9 +189,10 @@ pastis_status make_sw_work(pastis_ctx *ctx, int64_t npairs, int max_len, SwWork 
     PASTIS_TRY(ensure(ctx, kBufBinMeta, sizeof(int) * 160 + sizeof(unsigned long long) * kNumCounters, &p));
     wk.counts = (int *)p;
     wk.counters = (unsigned long long *)((int *)p + 160);
+    // counts: 32 bins; starts, starts2: 33 bounds each; cursor: 32
     wk.starts = wk.counts + 32;
-    wk.starts2 = wk.counts + 64;
-    wk.cursor = wk.counts + 96;
+    wk.starts2 = wk.counts + 72;
+    wk.cursor = wk.counts + 112;
     PASTIS_TRY(ensure(ctx, kBufIdx, sizeof(int) * (size_t)std::max<int64_t>(npairs, 1), &p));
     wk.idx = (int *)p;
     PASTIS_TRY(ensure(ctx, kBufIdx2, sizeof(int) * (size_t)std::max<int64_t>(npairs, 1), &p));

@@ -51,11 +51,16 @@ constexpr int kMaxR = 16;               // rows per lane
 constexpr int kSingleBins = kMaxR;      // bins 0..15: one strip of 64 * (bin + 1) rows
 constexpr int kMultiBin = kSingleBins;  // bins 16..23: several strips of 64 * R rows, R = bin - 7
 constexpr int kMultiMinR = kMaxR / 2 + 1;
-constexpr int kNumBins = kMultiBin + kMaxR - kMultiMinR + 1;
+// bins 24..31: as 16..23 for sequences a of at most kMax16Rows rows, whose
+// scores (at most 11 per row with BLOSUM62) stay below 2^15
+constexpr int kMulti16Bin = kMultiBin + kMaxR - kMultiMinR + 1;
+constexpr int kNumBins = kMulti16Bin + kMaxR - kMultiMinR + 1;
+constexpr int kMax16Rows = 32767 / 11;
 static_assert(kNumBins <= 32, "bin tables hold 32 entries");
 
 __host__ __device__ constexpr int rows_of_bin(int bin) {
-    return bin >= kMultiBin ? bin - kMultiBin + kMultiMinR : bin + 1;
+    return bin >= kMulti16Bin ? bin - kMulti16Bin + kMultiMinR : bin >= kMultiBin ? bin - kMultiBin + kMultiMinR
+                                                                                   : bin + 1;
 }
 constexpr int kDppWaveShr1 = 0x138;
 
@@ -340,20 +345,24 @@ __device__ __forceinline__ uint32_t u2(short2_t x) { return __builtin_bit_cast(u
 __device__ __forceinline__ short2_t pmax(short2_t a, short2_t b) { return __builtin_elementwise_max(a, b); }
 __device__ __forceinline__ int shr1u(uint32_t lane0, uint32_t v) { return shr1((int)lane0, (int)v); }
 
-template <int R>
-__device__ __forceinline__ void build_profile16(ProfWord<R> (*prof)[kWave], const int8_t *sblosum, const uint8_t *a,
-                                                int la, int lane, int oe) {
-    int ar[R];
+// 16-bit profile: entry [c][p] holds the biased scores s + o + e >= 0 (pad
+// rows: 0) of rows p * RP .. p * RP + RP - 1 of a against code c, one byte
+// each.  The calling thread writes the codes c = group (mod NG) for position
+// pos; NG groups of threads together cover all codes.
+template <int RP, int W, int NG>
+__device__ __forceinline__ void build_profile16(ProfWord<RP> (*prof)[W], const int8_t *sblosum, const uint8_t *a,
+                                                int la, int pos, int group, int oe) {
+    int ar[RP];
 #pragma unroll
-    for (int r = 0; r < R; ++r) ar[r] = (lane * R + r < la) ? a[lane * R + r] : kPadCode;
-    for (int c = 0; c < kProfCodes; ++c) {
+    for (int r = 0; r < RP; ++r) ar[r] = (pos * RP + r < la) ? a[pos * RP + r] : kPadCode;
+    for (int c = group; c < kProfCodes; c += NG) {
         uint32_t w[4] = {0, 0, 0, 0};
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
+        for (int r = 0; r < RP; ++r) {
             const int sc = max((int)sblosum[ar[r] * kProfCodes + c], -oe) + oe;
             w[r >> 2] |= (uint32_t)sc << (8 * (r & 3));
         }
-        prof[c][lane] = make_word<R>(w);
+        prof[c][pos] = make_word<RP>(w);
     }
 }
 
@@ -368,38 +377,26 @@ __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
     return v;
 }
 
-// Profile of a shared by the waves of a block: the threads of wave k write
-// the codes c = k (mod WPB) for their lane's rows.
-template <int R, int WPB>
-__device__ __forceinline__ void build_profile16b(ProfWord<R> (*prof)[kWave], const int8_t *sblosum, const uint8_t *a,
-                                                 int la, int lane, int wave, int oe) {
-    int ar[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) ar[r] = (lane * R + r < la) ? a[lane * R + r] : kPadCode;
-    for (int c = wave; c < kProfCodes; c += WPB) {
-        uint32_t w[4] = {0, 0, 0, 0};
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int sc = max((int)sblosum[ar[r] * kProfCodes + c], -oe) + oe;
-            w[r >> 2] |= (uint32_t)sc << (8 * (r & 3));
-        }
-        prof[c][lane] = make_word<R>(w);
-    }
-}
 
-// Full-wave layout for the wider one-strip bins.  A block takes 2 * WPB
-// consecutive pairs (two per wave) and its waves share one profile, built
-// once per distinct sequence a among them (pairs are sorted by a), so the
-// LDS of a block does not grow with its wave count.
-template <int R, int WPB>
+// Full-wave layout for the wider bins.  A block takes 2 * WPB consecutive
+// pairs (two per wave) and its waves share one profile, built once per
+// distinct sequence a among them (pairs are sorted by a), so the LDS of a
+// block does not grow with its wave count.  MULTI: sequences a of more than
+// 1024 rows (and at most kMax16Rows, so that scores stay below 2^15) run in
+// strips of 64 R rows, one after the other; lane 63 leaves the G and F' words
+// of the strip's bottom row for every column in a per-wave buffer, and lane 0
+// reads them back as the top boundary of the next strip.
+template <int R, int WPB, bool MULTI>
 __global__ __launch_bounds__(64 * WPB) void sw16_pass1_kernel(const uint8_t *__restrict__ codes,
                                                               const PairDesc *__restrict__ pairs,
                                                               const int *__restrict__ idx,
                                                               const int *__restrict__ starts, int bin,
                                                               const int8_t *__restrict__ blosum, int go_ge, int ge,
-                                                              SwPass1Out *__restrict__ out) {
-    static_assert(R <= kMax16R, "one strip");
+                                                              SwPass1Out *__restrict__ out, uint32_t *scratch,
+                                                              int64_t scratch_per_wave) {
+    static_assert(R > 8 && R <= kMax16R, "more than 512 rows per strip");
     constexpr int NI = 2 * WPB;  // pairs per block
+    constexpr int RS = kWave * R;  // rows per strip
     __shared__ ProfWord<R> prof[kProfCodes][kWave];
     __shared__ int8_t sblosum[kProfCodes * kProfCodes];
     // first unfinished pair of each wave, double-buffered by round parity so
@@ -411,6 +408,11 @@ __global__ __launch_bounds__(64 * WPB) void sw16_pass1_kernel(const uint8_t *__r
     const int item_end = starts[bin + 1];
     const uint32_t OE2 = (uint32_t)go_ge * 0x10001u, GE2 = (uint32_t)ge * 0x10001u;
     const uint32_t G0 = ((uint32_t)(-go_ge) & 0xFFFFu) * 0x10001u;  // G of an H = 0 cell
+    uint32_t *bnd_g = nullptr, *bnd_f = nullptr;
+    if constexpr (MULTI) {
+        bnd_g = scratch + ((int64_t)blockIdx.x * WPB + wave) * scratch_per_wave;
+        bnd_f = bnd_g + scratch_per_wave / 2;
+    }
     int par = 0;
 
     for (int64_t w = starts[bin] + (int64_t)NI * blockIdx.x; w < item_end; w += (int64_t)NI * gridDim.x) {
@@ -433,100 +435,132 @@ __global__ __launch_bounds__(64 * WPB) void sw16_pass1_kernel(const uint8_t *__r
             const PairDesc dA = pairs[idx[w + first]];
             const bool actP = !doneP && dP.a_seq == dA.a_seq;
             const bool actQ = !doneQ && dQ.a_seq == dA.a_seq;
-            const int laP = dA.la, lbP = actP ? dP.lb : 0, lbQ = actQ ? dQ.lb : 0;
+            const int laA = dA.la, lbP = actP ? dP.lb : 0, lbQ = actQ ? dQ.lb : 0;
             const uint8_t *bP = codes + dP.b_off, *bQ = codes + dQ.b_off;
-            build_profile16b<R, WPB>(prof, sblosum, codes + dA.a_off, laP, lane, wave, go_ge);
-            __syncthreads();
             const int lb = max(lbP, lbQ);
-            uint32_t G[R], E[R], M[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                G[r] = G0;
-                E[r] = 0u;
-                M[r] = 0u;
-            }
-            uint32_t glast = G0, flast = 0u, gprev = G0;
-            int cres = kPadCode | (kPadCode << 8);
-            auto col = [&](int c) {
-                const int x = c < lbP ? (int)bP[c] : kPadCode;
-                const int y = c < lbQ ? (int)bQ[c] : kPadCode;
-                return x | (y << 8);
-            };
-            int chunk = col(lane);  // columns 0..63; nx holds the next 64
-            int nx = col(kWave + lane);
             const int steps = lb > 0 ? lb + kWave - 1 : 0;
-            // with few rows per lane the profile words of step t + 1 are loaded
-            // during step t (the column residues of step t + 1 follow from
-            // those of step t); with more rows the step itself hides the load
-            constexpr bool kAhead = R <= 8;
-            ProfWord<R> wP = prof[kPadCode][lane], wQ = wP;
-            auto step = [&](const int t) {
-                const int tn = kAhead ? t + 1 : t;  // the step whose residues are fetched
-                if ((tn & (kWave - 1)) == 0 && (kAhead || t > 0)) {
-                    chunk = nx;
-                    nx = col(tn + kWave + lane);
-                }
-                const int bt = __builtin_amdgcn_readlane(chunk, tn & (kWave - 1));
-                const uint32_t rg = (uint32_t)shr1u(G0, glast);
-                const uint32_t rf = (uint32_t)shr1z((int)flast);
-                ProfWord<R> cP, cQ;
-                cres = shr1(bt, cres);
-                if constexpr (kAhead) {
-                    cP = wP;
-                    cQ = wQ;
-                    wP = prof[cres & 0xFF][lane];
-                    wQ = prof[(cres >> 8) & 0xFF][lane];
-                } else {
-                    cP = prof[cres & 0xFF][lane];
-                    cQ = prof[(cres >> 8) & 0xFF][lane];
-                }
-                short2_t gd = s2(gprev), gu = s2(rg), fu = s2(rf);
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    // byte r of P's and Q's words into the two halves
-                    const uint32_t sel =
-                        (uint32_t)(r & 3) | 0x0C00u | ((uint32_t)(4 + (r & 3)) << 16) | 0x0C000000u;
-                    const short2_t sig = s2(__builtin_amdgcn_perm(prof_word<R>(cQ, r), prof_word<R>(cP, r), sel));
-                    const short2_t e = pmax(psubs(s2(E[r]), GE2), s2(G[r]));
-                    const short2_t f = pmax(psubs(fu, GE2), gu);
-                    const short2_t d = gd + sig;
-                    const short2_t h = pmax(d, pmax(e, f));
-                    gd = s2(G[r]);
-                    const short2_t g = h - s2(OE2);
-                    G[r] = u2(g);
-                    E[r] = u2(e);
-                    M[r] = u2(pmax(s2(M[r]), h));
-                    gu = g;
-                    fu = f;
-                }
-                glast = G[R - 1];
-                flast = u2(fu);
-                gprev = rg;
-            };
-            if constexpr (kAhead) {  // step 0's residues (lane 0: column 0, the others padding)
-                const int bt0 = __builtin_amdgcn_readlane(chunk, 0);
-                cres = shr1(bt0, cres);
-                wP = prof[cres & 0xFF][lane];
-                wQ = prof[(cres >> 8) & 0xFF][lane];
-            }
-            // two steps per iteration, so the old and new G registers can swap
-            // roles instead of being copied back every step
-            int t = 0;
-            for (; t + 1 < steps; t += 2) {
-                step(t);
-                step(t + 1);
-            }
-            if (t < steps) step(t);
+            const int nstrips = MULTI ? (laA + RS - 1) / RS : 1;
             // best row of each pair: (score << 16) | (0xFFFF - row), maximised
             unsigned kp = 0u, kq = 0u;
+            for (int sidx = 0; sidx < nstrips; ++sidx) {
+                const int base = sidx * RS;
+                if (sidx > 0) __syncthreads();  // every wave is done with the last strip's profile
+                build_profile16<R, kWave, WPB>(prof, sblosum, codes + dA.a_off + base, laA - base, lane, wave,
+                                               go_ge);
+                __syncthreads();
+                const bool from_above = MULTI && sidx > 0;
+                const bool to_below = MULTI && sidx + 1 < nstrips;
+                uint32_t G[R], E[R], M[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int row = lane * R + r;
-                const unsigned rk = 0xFFFFu - (unsigned)row;
-                if (row < laP) {
-                    kp = max(kp, ((M[r] & 0xFFFFu) << 16) | rk);
-                    kq = max(kq, (M[r] & 0xFFFF0000u) | rk);
+                for (int r = 0; r < R; ++r) {
+                    G[r] = G0;
+                    E[r] = 0u;
+                    M[r] = 0u;
                 }
+                uint32_t glast = G0, flast = 0u, gprev = G0;
+                int cres = kPadCode | (kPadCode << 8);
+                auto col = [&](int c) {
+                    const int x = c < lbP ? (int)bP[c] : kPadCode;
+                    const int y = c < lbQ ? (int)bQ[c] : kPadCode;
+                    return x | (y << 8);
+                };
+                int chunk = col(lane);  // columns 0..63; nx holds the next 64
+                int nx = col(kWave + lane);
+                // top boundary words of columns 0..63 and 64..127 (columns past
+                // lb: an H = 0 row above)
+                uint32_t ch_g = G0, ch_f = 0u, nx_g = G0, nx_f = 0u;
+                if (from_above) {
+                    if (lane < lb) {
+                        ch_g = vload(bnd_g + lane);
+                        ch_f = vload(bnd_f + lane);
+                    }
+                    if (kWave + lane < lb) {
+                        nx_g = vload(bnd_g + kWave + lane);
+                        nx_f = vload(bnd_f + kWave + lane);
+                    }
+                }
+                // kTop: lane 0 takes its top boundary from the buffer (t < lb)
+                auto step = [&](const int t, auto top_tag) {
+                    constexpr bool kTop = decltype(top_tag)::value;
+                    if ((t & (kWave - 1)) == 0 && t > 0) {
+                        chunk = nx;
+                        nx = col(t + kWave + lane);
+                        if constexpr (kTop) {
+                            ch_g = nx_g;
+                            ch_f = nx_f;
+                            const int c = t + kWave + lane;
+                            nx_g = c < lb ? vload(bnd_g + c) : G0;
+                            nx_f = c < lb ? vload(bnd_f + c) : 0u;
+                        }
+                    }
+                    const int bt = __builtin_amdgcn_readlane(chunk, t & (kWave - 1));
+                    uint32_t rg, rf;
+                    if constexpr (kTop) {
+                        rg = (uint32_t)shr1u((uint32_t)__builtin_amdgcn_readlane((int)ch_g, t & (kWave - 1)), glast);
+                        rf = (uint32_t)shr1u((uint32_t)__builtin_amdgcn_readlane((int)ch_f, t & (kWave - 1)), flast);
+                    } else {
+                        rg = (uint32_t)shr1u(G0, glast);
+                        rf = (uint32_t)shr1z((int)flast);
+                    }
+                    cres = shr1(bt, cres);
+                    const ProfWord<R> cP = prof[cres & 0xFF][lane];
+                    const ProfWord<R> cQ = prof[(cres >> 8) & 0xFF][lane];
+                    short2_t gd = s2(gprev), gu = s2(rg), fu = s2(rf);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        // byte r of P's and Q's words into the two halves
+                        const uint32_t sel =
+                            (uint32_t)(r & 3) | 0x0C00u | ((uint32_t)(4 + (r & 3)) << 16) | 0x0C000000u;
+                        const short2_t sig =
+                            s2(__builtin_amdgcn_perm(prof_word<R>(cQ, r), prof_word<R>(cP, r), sel));
+                        const short2_t e = pmax(psubs(s2(E[r]), GE2), s2(G[r]));
+                        const short2_t f = pmax(psubs(fu, GE2), gu);
+                        const short2_t d = gd + sig;
+                        const short2_t h = pmax(d, pmax(e, f));
+                        gd = s2(G[r]);
+                        const short2_t g = h - s2(OE2);
+                        G[r] = u2(g);
+                        E[r] = u2(e);
+                        M[r] = u2(pmax(s2(M[r]), h));
+                        gu = g;
+                        fu = f;
+                    }
+                    glast = G[R - 1];
+                    flast = u2(fu);
+                    gprev = rg;
+                    if (to_below) {
+                        const int j = t - (kWave - 1);
+                        if (lane == kWave - 1 && j >= 0 && j < lb) {
+                            bnd_g[j] = glast;
+                            bnd_f[j] = flast;
+                        }
+                    }
+                };
+                // two steps per iteration, so the old and new G registers can
+                // swap roles instead of being copied back every step
+                int t = 0;
+                if (from_above) {
+                    for (; t + 1 < lb; t += 2) {
+                        step(t, std::true_type{});
+                        step(t + 1, std::true_type{});
+                    }
+                    if (t < lb) step(t++, std::true_type{});
+                }
+                for (; t + 1 < steps; t += 2) {
+                    step(t, std::false_type{});
+                    step(t + 1, std::false_type{});
+                }
+                if (t < steps) step(t, std::false_type{});
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int row = base + lane * R + r;
+                    const unsigned rk = 0xFFFFu - (unsigned)row;
+                    if (row < laA) {
+                        kp = max(kp, ((M[r] & 0xFFFFu) << 16) | rk);
+                        kq = max(kq, (M[r] & 0xFFFF0000u) | rk);
+                    }
+                }
+                if (to_below) __threadfence_block();  // lane 0 of the next strip reads lane 63's row
             }
             kp = wave_max_u32(kp);
             kq = wave_max_u32(kq);
@@ -608,27 +642,6 @@ __device__ __forceinline__ int wave_max_i32(int v) {
     return v;
 }
 
-// Profile of a for strips of S lanes: entry [c][p] holds the biased scores of
-// rows p * RP .. p * RP + RP - 1 against code c.  The lanes of strip k write
-// the codes c = k (mod 64 / S); every lane then reads entries written by
-// other lanes of its wave (LDS operations of one wave complete in order).
-template <int RP, int S>
-__device__ __forceinline__ void build_profile16s(ProfWord<RP> (*prof)[S], const int8_t *sblosum, const uint8_t *a,
-                                                 int la, int pos, int strip, int oe) {
-    int ar[RP];
-#pragma unroll
-    for (int r = 0; r < RP; ++r) ar[r] = (pos * RP + r < la) ? a[pos * RP + r] : kPadCode;
-    for (int c = strip; c < kProfCodes; c += kWave / S) {
-        uint32_t w[4] = {0, 0, 0, 0};
-#pragma unroll
-        for (int r = 0; r < RP; ++r) {
-            const int sc = max((int)sblosum[ar[r] * kProfCodes + c], -oe) + oe;
-            w[r >> 2] |= (uint32_t)sc << (8 * (r & 3));
-        }
-        prof[c][pos] = make_word<RP>(w);
-    }
-    __builtin_amdgcn_wave_barrier();
-}
 
 template <int S, int RP, int WPB>
 __global__ __launch_bounds__(64 * WPB) void sw16s_pass1_kernel(const uint8_t *__restrict__ codes,
@@ -677,7 +690,10 @@ __global__ __launch_bounds__(64 * WPB) void sw16s_pass1_kernel(const uint8_t *__
             const bool actQ = !doneQ && dQ.a_seq == a_seq;
             const int lbP = actP ? dP.lb : 0, lbQ = actQ ? dQ.lb : 0;
             const uint8_t *bP = codes + dP.b_off, *bQ = codes + dQ.b_off;
-            build_profile16s<RP, S>(prof, sblosum, codes + a_off, la, pos, strip, go_ge);
+            build_profile16<RP, S, kWave / S>(prof, sblosum, codes + a_off, la, pos, strip, go_ge);
+            // lanes read entries written by other lanes of the wave (LDS
+            // operations of one wave complete in order)
+            __builtin_amdgcn_wave_barrier();
             const int lbmax = wave_max_i32(max(lbP, lbQ));
             const int steps = __builtin_amdgcn_readfirstlane(lbmax > 0 ? lbmax + S - 1 : 0);
             uint32_t G[RP], E[RP], M[RP];
@@ -814,7 +830,7 @@ __device__ __forceinline__ int rows_bin(int rows) {
     if (r <= kSingleBins) return r - 1;
     const int strips = (rows + kWave * kSingleBins - 1) / (kWave * kSingleBins);
     const int rm = (rows + kWave * strips - 1) / (kWave * strips);  // in [kMultiMinR, kMaxR]
-    return kMultiBin + rm - kMultiMinR;
+    return (rows <= kMax16Rows ? kMulti16Bin : kMultiBin) + rm - kMultiMinR;
 }
 
 // Bins by rows per lane; counters[0] += DP cells of the pairs, and
@@ -1322,7 +1338,21 @@ hipError_t launch_p16(int bin, int blocks, const uint8_t *codes, const PairDesc 
         sw16s_pass1_kernel<32, 2 * R, WPB><<<blocks, 64 * WPB, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge,
                                                                       ge, p1);
     else
-        sw16_pass1_kernel<R, WPB><<<blocks, 64 * WPB, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, p1);
+        sw16_pass1_kernel<R, WPB, false><<<blocks, 64 * WPB, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge,
+                                                                    ge, p1, nullptr, 0);
+    return hipGetLastError();
+}
+
+// 16-bit multi-strip bins: one boundary buffer per wave of the grid
+static int blocks16m() { return 256 * 3; }
+
+template <int R>
+hipError_t launch_p16m(int bin, int blocks, const uint8_t *codes, const PairDesc *pairs, const int *idx,
+                       const int *starts, const int8_t *blosum, int go_ge, int ge, SwPass1Out *p1, int *scratch,
+                       int64_t spw, hipStream_t s) {
+    constexpr int WPB = wpb16(R);
+    sw16_pass1_kernel<R, WPB, true><<<blocks, 64 * WPB, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, p1,
+                                                               (uint32_t *)scratch, spw);
     return hipGetLastError();
 }
 
@@ -1334,19 +1364,27 @@ typedef hipError_t (*P2Fn)(int, int, const uint8_t *, const PairDesc *, const in
 const P1Fn kP1[kNumBins] = {launch_p1<1>,  launch_p1<2>,  launch_p1<3>,  launch_p1<4>,  launch_p1<5>,  launch_p1<6>,
                             launch_p1<7>,  launch_p1<8>,  launch_p1<9>,  launch_p1<10>, launch_p1<11>, launch_p1<12>,
                             launch_p1<13>, launch_p1<14>, launch_p1<15>, launch_p1<16>, launch_p1<9>,  launch_p1<10>,
-                            launch_p1<11>, launch_p1<12>, launch_p1<13>, launch_p1<14>, launch_p1<15>, launch_p1<16>};
+                            launch_p1<11>, launch_p1<12>, launch_p1<13>, launch_p1<14>, launch_p1<15>, launch_p1<16>,
+                            launch_p1<9>,  launch_p1<10>, launch_p1<11>, launch_p1<12>, launch_p1<13>, launch_p1<14>,
+                            launch_p1<15>, launch_p1<16>};
 const P1Fn kP16[kMax16R] = {launch_p16<1>,  launch_p16<2>,  launch_p16<3>,  launch_p16<4>,
                             launch_p16<5>,  launch_p16<6>,  launch_p16<7>,  launch_p16<8>,
                             launch_p16<9>,  launch_p16<10>, launch_p16<11>, launch_p16<12>,
                             launch_p16<13>, launch_p16<14>, launch_p16<15>, launch_p16<16>};
+const P1Fn kP16M[kMaxR - kMultiMinR + 1] = {launch_p16m<9>,  launch_p16m<10>, launch_p16m<11>, launch_p16m<12>,
+                                           launch_p16m<13>, launch_p16m<14>, launch_p16m<15>, launch_p16m<16>};
 const P1Fn kPB[kNumBins] = {launch_pb<1>,  launch_pb<2>,  launch_pb<3>,  launch_pb<4>,  launch_pb<5>,  launch_pb<6>,
                             launch_pb<7>,  launch_pb<8>,  launch_pb<9>,  launch_pb<10>, launch_pb<11>, launch_pb<12>,
                             launch_pb<13>, launch_pb<14>, launch_pb<15>, launch_pb<16>, launch_pb<9>,  launch_pb<10>,
-                            launch_pb<11>, launch_pb<12>, launch_pb<13>, launch_pb<14>, launch_pb<15>, launch_pb<16>};
+                            launch_pb<11>, launch_pb<12>, launch_pb<13>, launch_pb<14>, launch_pb<15>, launch_pb<16>,
+                            launch_pb<9>,  launch_pb<10>, launch_pb<11>, launch_pb<12>, launch_pb<13>, launch_pb<14>,
+                            launch_pb<15>, launch_pb<16>};
 const P2Fn kP2[kNumBins] = {launch_p2<1>,  launch_p2<2>,  launch_p2<3>,  launch_p2<4>,  launch_p2<5>,  launch_p2<6>,
                             launch_p2<7>,  launch_p2<8>,  launch_p2<9>,  launch_p2<10>, launch_p2<11>, launch_p2<12>,
                             launch_p2<13>, launch_p2<14>, launch_p2<15>, launch_p2<16>, launch_p2<9>,  launch_p2<10>,
-                            launch_p2<11>, launch_p2<12>, launch_p2<13>, launch_p2<14>, launch_p2<15>, launch_p2<16>};
+                            launch_p2<11>, launch_p2<12>, launch_p2<13>, launch_p2<14>, launch_p2<15>, launch_p2<16>,
+                            launch_p2<9>,  launch_p2<10>, launch_p2<11>, launch_p2<12>, launch_p2<13>, launch_p2<14>,
+                            launch_p2<15>, launch_p2<16>};
 
 }  // namespace
 
@@ -1365,17 +1403,22 @@ static int blocks_for_bin(int bin) {
     return r <= 4 ? 256 * 6 : (r > 8 && r <= 12) ? 256 * 4 : 256 * 3;
 }
 
-// Only the multi-strip bins use the boundary buffers.
+// Only the multi-strip bins use the boundary buffers (one per wave of the
+// grid, 32-bit or 16-bit kernel).
 int64_t sw_scratch_waves() {
     int64_t w = 0;
-    for (int b = kMultiBin; b < kNumBins; ++b)
+    for (int b = kMultiBin; b < kNumBins; ++b) {
         w = std::max<int64_t>(w, (int64_t)blocks_for_bin(b) * wpb32(rows_of_bin(b)));
+        w = std::max<int64_t>(w, (int64_t)blocks16m() * wpb16(rows_of_bin(b)));
+    }
     return w;
 }
 
 bool sw16_supported(const Scoring &sc) { return sc.gap_open + sc.gap_extend >= 4; }
 
-bool sw_bin_is16(int bin, int max16) { return bin < kSingleBins && rows_of_bin(bin) <= max16; }
+bool sw_bin_is16(int bin, int max16) {
+    return (bin < kSingleBins || bin >= kMulti16Bin) && rows_of_bin(bin) <= max16;
+}
 
 hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pairs, int64_t npairs,
                      const int8_t *blosum, const Scoring &sc, SwPass1Out *p1, pastis_pair_record *out,
@@ -1411,7 +1454,10 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
         if ((e = mark(ctx->bin_ev[2 * bin])) != hipSuccess) return e;
         // multi-strip bins use per-wave boundary buffers: they keep their grid
         const int scale = bin >= kMultiBin ? 1 : rows_of_bin(bin) <= 8 ? grid_scale : grid_scale_wide;
-        if (sw_bin_is16(bin, max16))
+        if (sw_bin_is16(bin, max16) && bin >= kMulti16Bin)
+            e = kP16M[bin - kMulti16Bin](bin, blocks16m(), codes, pairs, idx1, wk.starts, blosum, go_ge, ge, p1,
+                                         wk.scratch, wk.scratch_per_wave, s);
+        else if (sw_bin_is16(bin, max16))
             e = kP16[bin](bin, scale * blocks16(rows_of_bin(bin)), codes, pairs, idx1, wk.starts, blosum, go_ge, ge, p1,
                           nullptr, 0, s);
         else

@@ -215,6 +215,44 @@ def test_sw16_every_one_strip_bin_and_odd_counts(gpu, orc):
     _check16(got, want)
 
 
+def test_sw16_multi_strip_bins(gpu, orc):
+    """Rows 1025..2978 run in 16-bit lanes over strips of 64 R rows (R = 9..16)
+    with the boundary row passed through a per-wave buffer; 2979 rows and more
+    stay in 32 bits.  Identical runs of W (11 per row) put the score at the
+    16-bit limit: 11 * 2978 = 32758 in 16 bits, 32769 in 32."""
+    from synth.families import FamilySet
+
+    rng = np.random.default_rng(9)
+    lens = [1025, 1100, 1152, 1153, 1344, 1345, 1536, 1537, 1792, 2048, 2049, 2500, 2977, 2978, 2979, 3100]
+    seqs = []
+    for L in lens:
+        a = rng.integers(0, 20, L)
+        b = a.copy()
+        sub = rng.random(L) < 0.3
+        b[sub] = rng.integers(0, 20, int(sub.sum()))
+        b = np.concatenate([rng.integers(0, 20, int(rng.integers(0, 40))), b, rng.integers(0, 20, 5)])
+        seqs += [a, b]
+    w = np.full(2978, 17)  # W
+    seqs += [w, w.copy(), np.full(2979, 17), np.full(2979, 17)]
+    letters = np.frombuffer(b"ARNDCQEGHILKMFPSTWYV", np.uint8)
+    res = np.concatenate([letters[x] for x in seqs]).astype(np.uint8)
+    off = np.zeros(len(seqs) + 1, np.int64)
+    np.cumsum([len(x) for x in seqs], out=off[1:])
+    s = FamilySet(res, off, np.zeros(len(seqs), np.int32), {})
+    codes = orc.encode(s.residues)
+    lo = np.arange(0, len(seqs), 2, dtype=np.uint32)
+    hi = lo + 1
+    # several pairs sharing their shorter sequence (1025 rows), one wave apart
+    a = np.zeros(9, np.uint32)
+    lo = np.concatenate([lo, a])
+    hi = np.concatenate([hi, np.arange(3, 30, 3, dtype=np.uint32)])
+    want = orc.align_pairs(codes, s.offsets, lo, hi, mode="sw")
+    assert want["score"][len(lens)] == 11 * 2978 and want["score"][len(lens) + 1] == 11 * 2979
+    got = _gpu_records(gpu, s, lo, hi, score_width=16)
+    _check16(got, want)
+    _compare(_gpu_records(gpu, s, lo, hi, full_records=True, score_width=16), want)
+
+
 def test_search_same_edges_in_16_and_32_bits(gpu):
     import paper_2009_14467_amd as P
     from synth import workload

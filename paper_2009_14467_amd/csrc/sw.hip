@@ -961,7 +961,10 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_bound_kernel(const uint8_t *
         const uint8_t *b = codes + pd.b_off;
         const int nstrips = MULTI ? (la + RS - 1) / RS : 1;
         const int top = nstrips * RS - la;  // padding rows above row 0
-        int fin = 0, fend = -1;
+        int fin = 0, fend = -1;  // lane 63: the end cell's value and (search) its column
+        // profile entries are addressed by byte offset: lane base + code * stride
+        const char *prof_lane = (const char *)&prof[0][lane];
+        constexpr int kStride = (int)(sizeof(ProfWord<R>) * kWave);
         for (int s = 0; s < nstrips; ++s) {
             const int base = s * RS - top + lane * R;
             build_profile<R>(prof, sblosum, a, la, base, lane);
@@ -976,19 +979,19 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_bound_kernel(const uint8_t *
                 G[r] = Z[r] - GO;
                 E[r] = kNegP;
             }
-            int hlast = kZero, flast = kNegP, hprev = kZero, cres = kPadCode, chunk = kPadCode;
-            int nx = (lane < lb) ? (int)b[lane] : kPadCode;
+            int hlast = kZero, flast = kNegP, hprev = kZero, cres = kPadCode * kStride, chunk = kPadCode * kStride;
+            int nx = ((lane < lb) ? (int)b[lane] : kPadCode) * kStride;
             int ch_h = kZero, ch_f = kNegP, nx_h = kZero, nx_f = kNegP;
             if (MULTI && from_above && lane < lb) {
                 nx_h = vload(bnd_h + lane);
                 nx_f = vload(bnd_f + lane);
             }
-            const int steps = lb + kWave - 1;
-            for (int t = 0; t < steps; ++t) {
+            const int steps = __builtin_amdgcn_readfirstlane(lb + kWave - 1);
+            auto step = [&](const int t) {
                 if ((t & (kWave - 1)) == 0) {
                     chunk = nx;
                     const int c = t + kWave + lane;
-                    nx = (c < lb) ? (int)b[c] : kPadCode;
+                    nx = ((c < lb) ? (int)b[c] : kPadCode) * kStride;
                     if (MULTI && from_above) {
                         ch_h = nx_h;
                         ch_f = nx_f;
@@ -1007,15 +1010,17 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_bound_kernel(const uint8_t *
                 const int rh = shr1(in_h, hlast);
                 const int rf = shr1(in_f, flast);
                 cres = shr1(bt, cres);
-                const int j = t - lane;
-                const ProfWord<R> pw = prof[cres][lane];
+                const ProfWord<R> pw = *(const ProfWord<R> *)(prof_lane + cres);
                 int hd = hprev, gu = rh - GO, fu = rf;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const int e = max(E[r] - GE, G[r]);
+                    // E' = max(E, Z): the row's empty-alignment floor rides
+                    // along the row (max(E' - e, Z) = max(E - e, Z), since Z
+                    // - e < Z), so h is one three-way max
+                    const int e = max(max(E[r] - GE, G[r]), Z[r]);
                     const int f = max(fu - GE, gu);
                     const int d = hd + sigma_at<R>(pw, r) * unit;
-                    const int h = max(max(d, Z[r]), max(e, f));
+                    const int h = max(max(d, e), f);
                     hd = H[r];
                     H[r] = h;
                     E[r] = e;
@@ -1027,20 +1032,50 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_bound_kernel(const uint8_t *
                 hlast = H[R - 1];
                 flast = fu;
                 hprev = rh;
-                if (last && lane == kWave - 1 && j >= 0 && j < lb) {
-                    if (!search) {
-                        if (j == lb - 1) fin = hlast;
-                    } else if (fend < 0 && (hlast >> sb) == r1.score) {
-                        fin = hlast;
-                        fend = j;
+                if (MULTI && to_below) {
+                    const int j = t - (kWave - 1);
+                    if (lane == kWave - 1 && j >= 0 && j < lb) {
+                        bnd_h[j] = hlast;
+                        bnd_f[j] = flast;
                     }
                 }
-                if (MULTI && to_below && lane == kWave - 1 && j >= 0 && j < lb) {
-                    bnd_h[j] = hlast;
-                    bnd_f[j] = flast;
+            };
+            int t = 0;
+            if (!(search && last)) {
+                // two steps per iteration; lane 63's last value is the end cell's
+                for (; t + 1 < steps; t += 2) {
+                    step(t);
+                    step(t + 1);
                 }
-                // the end cell is the last one this pass needs
-                if (search && last && __builtin_amdgcn_readlane(fend, kWave - 1) >= 0) break;
+                if (t < steps) step(t);
+                if (last) fin = hlast;
+            } else {
+                // the end column is the first where lane 63 (row end_a) reaches
+                // the score; no cell exceeds it, so reaching is h >= score * unit
+                const int thr = r1.score * unit;
+                for (; t < kWave - 1; ++t) step(t);  // lane 63 is still left of column 0
+                for (; t + 1 < steps; t += 2) {
+                    step(t);
+                    const int h1 = hlast;
+                    step(t + 1);
+                    if (__builtin_amdgcn_readlane(h1, kWave - 1) >= thr) {
+                        fin = h1;
+                        fend = t - (kWave - 1);
+                        break;
+                    }
+                    if (__builtin_amdgcn_readlane(hlast, kWave - 1) >= thr) {
+                        fin = hlast;
+                        fend = t + 1 - (kWave - 1);
+                        break;
+                    }
+                }
+                if (fend < 0 && t < steps) {
+                    step(t);
+                    if (__builtin_amdgcn_readlane(hlast, kWave - 1) >= thr) {
+                        fin = hlast;
+                        fend = t - (kWave - 1);
+                    }
+                }
             }
             if (MULTI) __threadfence_block();
         }

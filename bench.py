@@ -78,6 +78,9 @@ def parse():
                     help="time schedule settings on a candidate sample first (default: the library's schedule)")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-mode leg")
     ap.add_argument("--tune-pairs", type=int, default=2_000_000, help="candidate sample size of the autotuner")
+    ap.add_argument("--schedule", default=None,
+                    help="explicit SW schedule, e.g. sw16_max_rows=16,sw_direct_pct=50,sw_grid_scale=2,"
+                    "sw_grid_scale_wide=1 (unnamed knobs keep the library default)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one 1 GiB device-to-device copy (a reference for HBM byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
@@ -251,7 +254,11 @@ def main():
     off = torch.from_numpy(fs.offsets).to(dev)
     ctx = P.Context(P.Params(**params))
     tuning = None
-    if args.autotune:
+    if args.schedule:
+        knobs = dict(kv.split("=") for kv in args.schedule.split(","))
+        ctx.set_tuning(**{k: int(v) for k, v in knobs.items()})
+        tuning = dict(ctx.get_tuning(), source="--schedule")
+    elif args.autotune:
         t0 = time.perf_counter()
         tuning = ctx.autotune(res, off, max_pairs=args.tune_pairs)
         torch.cuda.synchronize()

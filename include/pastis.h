@@ -283,12 +283,13 @@ pastis_status pastis_mlp_calibrate(pastis_ctx *ctx, const float *X, const uint8_
 
 /* ---- schedule of the Smith-Waterman stage ----
  * Knobs of the length-binned launches (every setting gives the same results;
- * only the time changes).  A new context starts at {16, 50, 2, 1}.  pastis_autotune times candidate settings on a
+ * only the time changes).  A new context starts at {16, 50, 3, 3}.  pastis_autotune times candidate settings on a
  * sample of the given sequences' own candidate pairs and keeps the fastest. */
 typedef struct pastis_tuning {
-    int32_t sw16_max_rows; /* one-strip bins with at most this many rows per lane run two
-                              pairs per wave in 16-bit lanes (0: none; at most 16), where
-                              16-bit lanes are in use (see score_width) */
+    int32_t sw16_max_rows; /* bins with at most this many rows per lane run two pairs per
+                              wave in 16-bit lanes (0: none; at most 16): one-strip bins,
+                              and multi-strip bins of sequences of at most 2978 rows;
+                              where 16-bit lanes are in use (see score_width) */
     int32_t sw_direct_pct; /* pairs with 100 * score >= this * (shorter length) skip the
                               start-bound pass and go straight to the statistics pass */
     int32_t sw_grid_scale; /* one-strip pass-1 launches with at most 8 rows per lane get

@@ -42,7 +42,9 @@ OPS_PER_SW_CELL = {(16, False): 10, (16, True): 10, (32, False): 9, (32, True): 
 # dispatch on the mid workload, profiles/sw_search_mid_kernel_stats.md), scaled
 # by what the counters read for a 1 GiB device copy (FETCH x 2.0, WRITE x 1.0);
 # only for kernels unchanged since those counters were taken
-MEASURED_TRAFFIC_KIB = {}
+MEASURED_TRAFFIC_KIB = {"sw16s_pass1_kernel<32, 12, 4>": (1249786.75, 105933.594),
+                        "sw16s_pass1_kernel<16, 16, 4>": (1336287.75, 118015.188),
+                        "sw16_pass1_kernel<9, 4, false>": (605403.938, 53349.906)}
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
 # method parameters of each workload (Section VI settings: BLOSUM62, gaps

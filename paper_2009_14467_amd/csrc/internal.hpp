@@ -104,7 +104,7 @@ struct pastis_ctx {
     bool have_candidates = false;
     bool records_internal = false;  // the current alignment's records feed edges only
     int last_max16 = 0;             // the last SW call ran 16-bit pass-1 bins up to this R
-    pastis_tuning tune{16, 50, 3, 3, {0, 0, 0, 0}};
+    pastis_tuning tune{16, 50, 24, 24, {0, 0, 0, 0}};
     // learned filter
     pastis::MlpState mlp{};
     bool mlp_alloc = false, mlp_set = false;

@@ -562,7 +562,7 @@ pastis_status pastis_get_tuning(const pastis_ctx *ctx, pastis_tuning *out) {
 pastis_status pastis_set_tuning(pastis_ctx *ctx, const pastis_tuning *t) {
     if (!ctx || !t) return PASTIS_E_INVAL;
     if (t->sw16_max_rows < 0 || t->sw16_max_rows > 16 || t->sw_direct_pct < 0 || t->sw_grid_scale < 1 ||
-        t->sw_grid_scale > 4 || t->sw_grid_scale_wide < 1 || t->sw_grid_scale_wide > 4)
+        t->sw_grid_scale > 64 || t->sw_grid_scale_wide < 1 || t->sw_grid_scale_wide > 64)
         return set_error(ctx, PASTIS_E_INVAL, "tuning value out of range");
     for (int i = 0; i < 4; ++i)
         if (t->reserved[i] != 0) return set_error(ctx, PASTIS_E_INVAL, "reserved fields must be zero");
@@ -617,7 +617,7 @@ pastis_status pastis_autotune(pastis_ctx *ctx, const uint8_t *residues, const in
         PASTIS_TRY(measure(&cur));
         const int rows16[] = {16, 12, 8, 0};
         const int direct[] = {0, 25, 50, 100, 200, 1 << 20};
-        const int grid[] = {1, 2, 3, 4};
+        const int grid[] = {4, 8, 16, 24, 32};
         auto sweep = [&](int32_t *knob, const int *vals, int nv) -> pastis_status {
             const int32_t keep = *knob;
             int32_t best_v = keep;
@@ -638,8 +638,8 @@ pastis_status pastis_autotune(pastis_ctx *ctx, const uint8_t *residues, const in
         };
         PASTIS_TRY(sweep(&ctx->tune.sw16_max_rows, rows16, 4));
         PASTIS_TRY(sweep(&ctx->tune.sw_direct_pct, direct, 6));
-        PASTIS_TRY(sweep(&ctx->tune.sw_grid_scale, grid, 4));
-        PASTIS_TRY(sweep(&ctx->tune.sw_grid_scale_wide, grid, 4));
+        PASTIS_TRY(sweep(&ctx->tune.sw_grid_scale, grid, 5));
+        PASTIS_TRY(sweep(&ctx->tune.sw_grid_scale_wide, grid, 5));
     }
     if (out) *out = ctx->tune;
     return PASTIS_OK;

@@ -1357,6 +1357,8 @@ hipError_t launch_pb(int bin, int blocks, const uint8_t *codes, const PairDesc *
 // waves per block of the 16-bit pass (strips: one profile per wave; full
 // waves: one profile per block) and blocks per launch
 constexpr int wpb16(int R) { return 4; }
+// pairs one block of the 16-bit one-strip launch takes per window
+static int pairs_per_block16(int R) { return R <= 4 ? 4 * 8 : R <= 8 ? 4 * 4 : 2 * 4; }
 static int blocks16(int R) { return R <= 4 ? 256 * 6 : (R > 8 && R <= 12) ? 256 * 4 : 256 * 3; }
 
 // R <= 4: strips of 16 lanes with 4 R rows per lane; R = 5..8: strips of 32
@@ -1466,6 +1468,14 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
     auto mark = [&](hipEvent_t ev) { return timed ? hipEventRecord(ev, s) : hipSuccess; };
     if (npairs <= 0) return hipSuccess;
     const int go_ge = sc.gap_open + sc.gap_extend, ge = sc.gap_extend;
+    // Grids larger than what fits at once let the dispatcher balance blocks of
+    // uneven work (grid scale); no launch needs more blocks than the call's
+    // pairs could fill (per_block pairs each), or fewer than one full wave of
+    // resident blocks (base).
+    auto capped = [&](int blocks, int base, int per_block) {
+        const int64_t fill = (npairs + per_block - 1) / per_block;
+        return (int)std::max<int64_t>(std::min<int64_t>(blocks, fill), std::min<int64_t>(base, blocks));
+    };
     const int nb = (int)((npairs + 255) / 256);
     hipError_t e = begin(kStSched);
     if (e != hipSuccess) return e;
@@ -1488,21 +1498,27 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
     for (int bin = 0; bin < kNumBins; ++bin) {
         if ((e = mark(ctx->bin_ev[2 * bin])) != hipSuccess) return e;
         // multi-strip bins use per-wave boundary buffers: they keep their grid
-        const int scale = bin >= kMultiBin ? 1 : rows_of_bin(bin) <= 8 ? grid_scale : grid_scale_wide;
+        const int R = rows_of_bin(bin);
+        const int scale = bin >= kMultiBin ? 1 : R <= 8 ? grid_scale : grid_scale_wide;
         if (sw_bin_is16(bin, max16) && bin >= kMulti16Bin)
             e = kP16M[bin - kMulti16Bin](bin, blocks16m(), codes, pairs, idx1, wk.starts, blosum, go_ge, ge, p1,
                                          wk.scratch, wk.scratch_per_wave, s);
         else if (sw_bin_is16(bin, max16))
-            e = kP16[bin](bin, scale * blocks16(rows_of_bin(bin)), codes, pairs, idx1, wk.starts, blosum, go_ge, ge, p1,
-                          nullptr, 0, s);
+            e = kP16[bin](bin, capped(scale * blocks16(R), blocks16(R), pairs_per_block16(R)), codes, pairs, idx1,
+                          wk.starts, blosum, go_ge, ge, p1, nullptr, 0, s);
         else
-            e = kP1[bin](bin, scale * blocks_for_bin(bin), codes, pairs, idx1, wk.starts, blosum, go_ge, ge, p1,
-                         wk.scratch, wk.scratch_per_wave, s);
+            e = kP1[bin](bin, capped(scale * blocks_for_bin(bin), blocks_for_bin(bin), wpb32(R)), codes, pairs, idx1,
+                         wk.starts, blosum, go_ge, ge, p1, wk.scratch, wk.scratch_per_wave, s);
         if (e != hipSuccess) return e;
         if ((e = mark(ctx->bin_ev[2 * bin + 1])) != hipSuccess) return e;
     }
     if ((e = end(kStAlign1)) != hipSuccess || (e = begin(kStAlign2)) != hipSuccess)
         return e;
+    // the start-bound and statistics launches take the same grid scales
+    // (multi-strip bins keep their grid: one boundary buffer per wave)
+    auto scale2 = [&](int bin) {
+        return bin >= kMultiBin ? 1 : rows_of_bin(bin) <= 8 ? grid_scale : grid_scale_wide;
+    };
     sw_bin2_kernel<<<nb, 256, 0, s>>>(pairs, p1, npairs, sc.cov_pct, stats_mode, sc.direct_pct, out, wk.bin_of,
                                       wk.counters);
     if ((e = launch_bins(wk.bin_of, npairs, kNumBins, wk.counts, wk.starts2, wk.cursor, wk.idx2, s)) != hipSuccess)
@@ -1510,8 +1526,9 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
     if (stats_mode == 0) {
         // start bound, then only the pairs whose coverage can still hold
         for (int bin = 0; bin < kNumBins; ++bin) {
-            e = kPB[bin](bin, blocks_for_bin(bin), codes, pairs, wk.idx2, wk.starts2, blosum, go_ge, ge, p1,
-                         wk.scratch, wk.scratch_per_wave, s);
+            const int R = rows_of_bin(bin);
+            e = kPB[bin](bin, capped(scale2(bin) * blocks_for_bin(bin), blocks_for_bin(bin), wpb32(R)), codes, pairs,
+                         wk.idx2, wk.starts2, blosum, go_ge, ge, p1, wk.scratch, wk.scratch_per_wave, s);
             if (e != hipSuccess) return e;
         }
         sw_bin3_kernel<<<nb, 256, 0, s>>>(pairs, p1, npairs, sc.cov_pct, out, wk.bin_of, wk.counters);
@@ -1520,8 +1537,10 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
             return e;
     }
     for (int bin = 0; bin < kNumBins; ++bin) {
-        e = kP2[bin](bin, blocks_for_bin(bin), codes, pairs, wk.idx2, wk.starts2, blosum, go_ge, ge, sc.cov_pct,
-                     sc.id_pct, p1, out, wk.scratch, wk.scratch_per_wave, s);
+        const int R = rows_of_bin(bin);
+        e = kP2[bin](bin, capped(scale2(bin) * blocks_for_bin(bin), blocks_for_bin(bin), wpb32(R)), codes, pairs,
+                     wk.idx2, wk.starts2, blosum, go_ge, ge, sc.cov_pct, sc.id_pct, p1, out, wk.scratch,
+                     wk.scratch_per_wave, s);
         if (e != hipSuccess) return e;
     }
     return end(kStAlign2);

@@ -81,8 +81,8 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-mode leg")
     ap.add_argument("--tune-pairs", type=int, default=2_000_000, help="candidate sample size of the autotuner")
     ap.add_argument("--schedule", default=None,
-                    help="explicit SW schedule, e.g. sw16_max_rows=16,sw_direct_pct=50,sw_grid_scale=24,"
-                    "sw_grid_scale_wide=24 (unnamed knobs keep the library default)")
+                    help="explicit SW schedule, e.g. sw16_max_rows=16,sw_direct_pct=50,sw_grid_scale=1,"
+                    "sw_grid_scale_wide=1 (unnamed knobs keep the library default)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one 1 GiB device-to-device copy (a reference for HBM byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")

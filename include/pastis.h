@@ -283,7 +283,7 @@ pastis_status pastis_mlp_calibrate(pastis_ctx *ctx, const float *X, const uint8_
 
 /* ---- schedule of the Smith-Waterman stage ----
  * Knobs of the length-binned launches (every setting gives the same results;
- * only the time changes).  A new context starts at {16, 50, 24, 24}.  pastis_autotune times candidate settings on a
+ * only the time changes).  A new context starts at {16, 50, 1, 1}.  pastis_autotune times candidate settings on a
  * sample of the given sequences' own candidate pairs and keeps the fastest. */
 typedef struct pastis_tuning {
     int32_t sw16_max_rows; /* bins with at most this many rows per lane run two pairs per
@@ -295,8 +295,8 @@ typedef struct pastis_tuning {
     int32_t sw_grid_scale; /* one-strip launches (pass 1, start bound, statistics) of bins
                               with at most 8 rows per lane get this many times the
                               blocks that fit on the device at once (1..64; never more
-                              than the call's pairs can fill), so that the dispatcher
-                              evens out blocks of uneven work */
+                              than the call's pairs can fill).  Every launch drains a
+                              work queue, so 1 (a resident grid) suffices */
     int32_t sw_grid_scale_wide; /* the same for 9..16 rows per lane (1..64) */
     int32_t reserved[4];
 } pastis_tuning;

@@ -379,8 +379,8 @@ class Context:
         self._check(lib().pastis_get_tuning(self._ctx, ctypes.byref(t)))
         return _tuning_dict(t)
 
-    def set_tuning(self, sw16_max_rows: int = 16, sw_direct_pct: int = 50, sw_grid_scale: int = 24,
-                   sw_grid_scale_wide: int = 24):
+    def set_tuning(self, sw16_max_rows: int = 16, sw_direct_pct: int = 50, sw_grid_scale: int = 1,
+                   sw_grid_scale_wide: int = 1):
         t = _Tuning()
         t.sw16_max_rows, t.sw_direct_pct = sw16_max_rows, sw_direct_pct
         t.sw_grid_scale, t.sw_grid_scale_wide = sw_grid_scale, sw_grid_scale_wide

@@ -104,7 +104,7 @@ struct pastis_ctx {
     bool have_candidates = false;
     bool records_internal = false;  // the current alignment's records feed edges only
     int last_max16 = 0;             // the last SW call ran 16-bit pass-1 bins up to this R
-    pastis_tuning tune{16, 50, 24, 24, {0, 0, 0, 0}};
+    pastis_tuning tune{16, 50, 1, 1, {0, 0, 0, 0}};
     // learned filter
     pastis::MlpState mlp{};
     bool mlp_alloc = false, mlp_set = false;
@@ -186,8 +186,10 @@ struct SwPass1Out {
 // bin starts for the two passes, a cursor, the two binned index lists, and
 // boundary-row scratch for pairs taller than one strip (6 planes of max_len
 // ints per wave, for sw_scratch_waves() waves).
-// counters: [0] cells, [1] statistics-pass pairs, [2] their cells,
-// [kCounterBinCells + b] pass-1 cells of SW bin b
+// counters: [0] cells, [1] statistics-pass pairs, [2] their cells, [3]
+// start-bound pairs, [4] their cells, [kCounterXdQueue] the x-drop kernel's
+// work queue, [kCounterBinCells + b] pass-1 cells of SW bin b
+constexpr int kCounterXdQueue = 5;
 constexpr int kCounterBinCells = 8;
 constexpr int kNumCounters = kCounterBinCells + 32;
 
@@ -198,6 +200,7 @@ struct SwWork {
     int *idx, *idx2;
     int *scratch;
     int64_t scratch_per_wave;
+    int *queue;  // work-queue counters: pass 1, start bound, statistics (32 bins each)
     // pairing of the 16-bit pass (pairs sorted by bin, then longer b first)
     uint64_t *sort_keys = nullptr, *sort_keys_alt = nullptr;
     uint32_t *sort_vals_alt = nullptr;

@@ -617,7 +617,7 @@ pastis_status pastis_autotune(pastis_ctx *ctx, const uint8_t *residues, const in
         PASTIS_TRY(measure(&cur));
         const int rows16[] = {16, 12, 8, 0};
         const int direct[] = {0, 25, 50, 100, 200, 1 << 20};
-        const int grid[] = {4, 8, 16, 24, 32};
+        const int grid[] = {1, 2, 4};
         auto sweep = [&](int32_t *knob, const int *vals, int nv) -> pastis_status {
             const int32_t keep = *knob;
             int32_t best_v = keep;
@@ -638,8 +638,8 @@ pastis_status pastis_autotune(pastis_ctx *ctx, const uint8_t *residues, const in
         };
         PASTIS_TRY(sweep(&ctx->tune.sw16_max_rows, rows16, 4));
         PASTIS_TRY(sweep(&ctx->tune.sw_direct_pct, direct, 6));
-        PASTIS_TRY(sweep(&ctx->tune.sw_grid_scale, grid, 5));
-        PASTIS_TRY(sweep(&ctx->tune.sw_grid_scale_wide, grid, 5));
+        PASTIS_TRY(sweep(&ctx->tune.sw_grid_scale, grid, 3));
+        PASTIS_TRY(sweep(&ctx->tune.sw_grid_scale_wide, grid, 3));
     }
     if (out) *out = ctx->tune;
     return PASTIS_OK;

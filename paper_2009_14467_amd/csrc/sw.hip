@@ -147,6 +147,16 @@ __device__ __forceinline__ T vload(const T *p) {
     return __builtin_nontemporal_load(p);
 }
 
+// A wave's next window of `count` consecutive items of its bin: lane 0 claims
+// it from the bin's queue counter (zeroed before the launch), so that a
+// resident grid stays busy until the bin is empty, waves that finish early
+// taking more work.  The counter is claimed by a vector atomic.
+__device__ __forceinline__ int64_t take(int *queue, const int *starts, int bin, int count) {
+    int v = 0;
+    if ((threadIdx.x & (kWave - 1)) == 0) v = atomicAdd(queue + bin, count);
+    return starts[bin] + (int64_t)__builtin_amdgcn_readfirstlane(v);
+}
+
 // ---------------------------------------------------------------- pass 1
 
 // max(x - y, 0) for x >= 0, y >= 0 (one clamped subtract)
@@ -164,7 +174,7 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_pass1_kernel(const uint8_t *
                                                        const int *__restrict__ idx, const int *__restrict__ starts,
                                                        int bin, const int8_t *__restrict__ blosum, int go_ge, int ge,
                                                        SwPass1Out *__restrict__ out, int *__restrict__ scratch,
-                                                       int64_t scratch_per_wave) {
+                                                       int64_t scratch_per_wave, int *queue) {
     constexpr int WPB = wpb32(R);
     __shared__ ProfWord<R> prof_all[WPB][kProfCodes][kWave];
     __shared__ int8_t sblosum[kProfCodes * kProfCodes];
@@ -178,7 +188,7 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_pass1_kernel(const uint8_t *
     const int item_end = starts[bin + 1];
     constexpr int RS = kWave * R;
 
-    for (int64_t w = starts[bin] + gwave; w < item_end; w += (int64_t)gridDim.x * WPB) {
+    for (int64_t w = take(queue, starts, bin, 1); w < item_end; w = take(queue, starts, bin, 1)) {
         const int q = idx[w];
         const PairDesc pd = pairs[q];
         const uint8_t *a = codes + pd.a_off;
@@ -393,7 +403,7 @@ __global__ __launch_bounds__(64 * WPB) void sw16_pass1_kernel(const uint8_t *__r
                                                               const int *__restrict__ starts, int bin,
                                                               const int8_t *__restrict__ blosum, int go_ge, int ge,
                                                               SwPass1Out *__restrict__ out, uint32_t *scratch,
-                                                              int64_t scratch_per_wave) {
+                                                              int64_t scratch_per_wave, int *queue) {
     static_assert(R > 8 && R <= kMax16R, "more than 512 rows per strip");
     constexpr int NI = 2 * WPB;  // pairs per block
     constexpr int RS = kWave * R;  // rows per strip
@@ -402,6 +412,7 @@ __global__ __launch_bounds__(64 * WPB) void sw16_pass1_kernel(const uint8_t *__r
     // first unfinished pair of each wave, double-buffered by round parity so
     // that a round's writes never meet the previous round's reads
     __shared__ int s_next[2][WPB];
+    __shared__ int s_take;  // the block's window, claimed from the bin's queue
     load_blosum(sblosum, blosum);
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
@@ -415,7 +426,13 @@ __global__ __launch_bounds__(64 * WPB) void sw16_pass1_kernel(const uint8_t *__r
     }
     int par = 0;
 
-    for (int64_t w = starts[bin] + (int64_t)NI * blockIdx.x; w < item_end; w += (int64_t)NI * gridDim.x) {
+    for (;;) {
+        // every thread has read the last window before the round loop's
+        // first barrier, so thread 0 may claim the next one
+        if (threadIdx.x == 0) s_take = atomicAdd(queue + bin, NI);
+        __syncthreads();
+        const int64_t w = starts[bin] + s_take;
+        if (w >= item_end) break;
         const int nit = (int)min((int64_t)NI, item_end - w);
         const int iP = 2 * wave, iQ = iP + 1;
         const int qP = iP < nit ? idx[w + iP] : -1;
@@ -649,7 +666,7 @@ __global__ __launch_bounds__(64 * WPB) void sw16s_pass1_kernel(const uint8_t *__
                                                                const int *__restrict__ idx,
                                                                const int *__restrict__ starts, int bin,
                                                                const int8_t *__restrict__ blosum, int go_ge, int ge,
-                                                               SwPass1Out *__restrict__ out) {
+                                                               SwPass1Out *__restrict__ out, int *queue) {
     static_assert((S == 16 || S == 32) && RP <= kMax16R, "strip shape");
     constexpr int NI = 2 * kWave / S;  // pairs per wave: two per strip
     __shared__ ProfWord<RP> prof_all[WPB][kProfCodes][S];
@@ -659,12 +676,11 @@ __global__ __launch_bounds__(64 * WPB) void sw16s_pass1_kernel(const uint8_t *__
     const int wave = threadIdx.x / kWave;
     const int pos = lane % S, strip = lane / S, cl = lane & 15;
     ProfWord<RP>(*prof)[S] = prof_all[wave];
-    const int64_t gwave = (int64_t)blockIdx.x * WPB + wave;
     const int item_end = starts[bin + 1];
     const uint32_t OE2 = (uint32_t)go_ge * 0x10001u, GE2 = (uint32_t)ge * 0x10001u;
     const uint32_t G0 = ((uint32_t)(-go_ge) & 0xFFFFu) * 0x10001u;  // G of an H = 0 cell
 
-    for (int64_t w = starts[bin] + NI * gwave; w < item_end; w += NI * (int64_t)gridDim.x * WPB) {
+    for (int64_t w = take(queue, starts, bin, NI); w < item_end; w = take(queue, starts, bin, NI)) {
         const int nit = (int)min((int64_t)NI, item_end - w);
         const int iP = 2 * strip, iQ = iP + 1;
         const int qP = iP < nit ? idx[w + iP] : -1;
@@ -836,7 +852,9 @@ __device__ __forceinline__ int rows_bin(int rows) {
 // Bins by rows per lane; counters[0] += DP cells of the pairs, and
 // counters[kCounterBinCells + bin] += those of each bin.
 __global__ void sw_bin1_kernel(const PairDesc *__restrict__ pairs, int64_t npairs, int8_t *__restrict__ bin_of,
-                               unsigned long long *__restrict__ counters) {
+                               unsigned long long *__restrict__ counters, int *__restrict__ queue) {
+    // the work queues of this call's launches (pass 1, start bound, statistics)
+    if (blockIdx.x == 0 && threadIdx.x < 3 * kNumBins) queue[threadIdx.x] = 0;
     __shared__ unsigned long long cells[kNumBins];
     if (threadIdx.x < kNumBins) cells[threadIdx.x] = 0;
     __syncthreads();
@@ -923,7 +941,7 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_bound_kernel(const uint8_t *
                                                        const int *__restrict__ idx, const int *__restrict__ starts,
                                                        int bin, const int8_t *__restrict__ blosum, int go_ge, int ge,
                                                        SwPass1Out *__restrict__ p1, int *__restrict__ scratch,
-                                                       int64_t scratch_per_wave) {
+                                                       int64_t scratch_per_wave, int *queue) {
     constexpr int WPB = wpb32(R);
     __shared__ ProfWord<R> prof_all[WPB][kProfCodes][kWave];
     __shared__ int8_t sblosum[kProfCodes * kProfCodes];
@@ -939,7 +957,9 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_bound_kernel(const uint8_t *
     constexpr int kNegP = -(1 << 30);
     const int GO16 = go_ge * 65536, GE16 = ge * 65536;
 
-    for (int64_t w = starts[bin] + gwave; w < item_end; w += (int64_t)gridDim.x * WPB) {
+    // windows of two pairs per claim
+    for (int64_t w0 = take(queue, starts, bin, 2); w0 < item_end; w0 = take(queue, starts, bin, 2))
+    for (int64_t w = w0; w < min(w0 + 2, (int64_t)item_end); ++w) {
         const int q = idx[w];
         const PairDesc pd = pairs[q];
         const SwPass1Out r1 = p1[q];
@@ -1127,7 +1147,7 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_pass2_kernel(const uint8_t *
                                                        int bin, const int8_t *__restrict__ blosum, int go_ge, int ge,
                                                        int cov_pct, int id_pct, const SwPass1Out *__restrict__ p1,
                                                        pastis_pair_record *__restrict__ out,
-                                                       int *__restrict__ scratch, int64_t scratch_per_wave) {
+                                                       int *__restrict__ scratch, int64_t scratch_per_wave, int *queue) {
     constexpr int WPB = wpb32(R);
     __shared__ ProfWord<R> prof_all[WPB][kProfCodes][kWave];
     __shared__ int8_t sblosum[kProfCodes * kProfCodes];
@@ -1142,7 +1162,7 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_pass2_kernel(const uint8_t *
     const int item_end = starts[bin + 1];
     constexpr int RS = kWave * R;
 
-    for (int64_t w = starts[bin] + gwave; w < item_end; w += (int64_t)gridDim.x * WPB) {
+    for (int64_t w = take(queue, starts, bin, 1); w < item_end; w = take(queue, starts, bin, 1)) {
         const int q = idx[w];
         const PairDesc pd = pairs[q];
         const SwPass1Out r1 = p1[q];
@@ -1318,44 +1338,45 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_pass2_kernel(const uint8_t *
 template <int R>
 hipError_t launch_p1(int bin, int blocks, const uint8_t *codes, const PairDesc *pairs, const int *idx,
                      const int *starts, const int8_t *blosum, int go_ge, int ge, SwPass1Out *p1, int *scratch,
-                     int64_t spw, hipStream_t s) {
+                     int64_t spw, int *queue, hipStream_t s) {
     if (bin >= kMultiBin)
-        sw_pass1_kernel<R, true><<<blocks, 64 * wpb32(R), 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, p1, scratch,
-                                                        spw);
+        sw_pass1_kernel<R, true><<<blocks, 64 * wpb32(R), 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, p1,
+                                                                 scratch, spw, queue);
     else
-        sw_pass1_kernel<R, false><<<blocks, 64 * wpb32(R), 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, p1,
-                                                         scratch, spw);
+        sw_pass1_kernel<R, false><<<blocks, 64 * wpb32(R), 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge,
+                                                                  p1, scratch, spw, queue);
     return hipGetLastError();
 }
 
 template <int R>
 hipError_t launch_p2(int bin, int blocks, const uint8_t *codes, const PairDesc *pairs, const int *idx,
                      const int *starts, const int8_t *blosum, int go_ge, int ge, int cov, int id,
-                     const SwPass1Out *p1, pastis_pair_record *out, int *scratch, int64_t spw, hipStream_t s) {
+                     const SwPass1Out *p1, pastis_pair_record *out, int *scratch, int64_t spw, int *queue,
+                     hipStream_t s) {
     if (bin >= kMultiBin)
-        sw_pass2_kernel<R, true><<<blocks, 64 * wpb32(R), 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, cov, id, p1,
-                                                        out, scratch, spw);
+        sw_pass2_kernel<R, true><<<blocks, 64 * wpb32(R), 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, cov,
+                                                                 id, p1, out, scratch, spw, queue);
     else
-        sw_pass2_kernel<R, false><<<blocks, 64 * wpb32(R), 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, cov, id,
-                                                         p1, out, scratch, spw);
+        sw_pass2_kernel<R, false><<<blocks, 64 * wpb32(R), 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge,
+                                                                  cov, id, p1, out, scratch, spw, queue);
     return hipGetLastError();
 }
 
 template <int R>
 hipError_t launch_pb(int bin, int blocks, const uint8_t *codes, const PairDesc *pairs, const int *idx,
                      const int *starts, const int8_t *blosum, int go_ge, int ge, SwPass1Out *p1, int *scratch,
-                     int64_t spw, hipStream_t s) {
+                     int64_t spw, int *queue, hipStream_t s) {
     if (bin >= kMultiBin)
-        sw_bound_kernel<R, true><<<blocks, 64 * wpb32(R), 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, p1, scratch,
-                                                        spw);
+        sw_bound_kernel<R, true><<<blocks, 64 * wpb32(R), 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, p1,
+                                                                 scratch, spw, queue);
     else
-        sw_bound_kernel<R, false><<<blocks, 64 * wpb32(R), 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, p1,
-                                                         scratch, spw);
+        sw_bound_kernel<R, false><<<blocks, 64 * wpb32(R), 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge,
+                                                                  p1, scratch, spw, queue);
     return hipGetLastError();
 }
 
 // waves per block of the 16-bit pass (strips: one profile per wave; full
-// waves: one profile per block) and blocks per launch
+// waves: one profile per block) and the blocks that fit on the device at once
 constexpr int wpb16(int R) { return 4; }
 // pairs one block of the 16-bit one-strip launch takes per window
 static int pairs_per_block16(int R) { return R <= 4 ? 4 * 8 : R <= 8 ? 4 * 4 : 2 * 4; }
@@ -1366,17 +1387,17 @@ static int blocks16(int R) { return R <= 4 ? 256 * 6 : (R > 8 && R <= 12) ? 256 
 template <int R>
 hipError_t launch_p16(int bin, int blocks, const uint8_t *codes, const PairDesc *pairs, const int *idx,
                       const int *starts, const int8_t *blosum, int go_ge, int ge, SwPass1Out *p1, int *, int64_t,
-                      hipStream_t s) {
+                      int *queue, hipStream_t s) {
     constexpr int WPB = wpb16(R);
     if constexpr (R <= 4)
         sw16s_pass1_kernel<16, 4 * R, WPB><<<blocks, 64 * WPB, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge,
-                                                                      ge, p1);
+                                                                      ge, p1, queue);
     else if constexpr (R <= 8)
         sw16s_pass1_kernel<32, 2 * R, WPB><<<blocks, 64 * WPB, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge,
-                                                                      ge, p1);
+                                                                      ge, p1, queue);
     else
         sw16_pass1_kernel<R, WPB, false><<<blocks, 64 * WPB, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge,
-                                                                    ge, p1, nullptr, 0);
+                                                                    ge, p1, nullptr, 0, queue);
     return hipGetLastError();
 }
 
@@ -1386,17 +1407,18 @@ static int blocks16m() { return 256 * 3; }
 template <int R>
 hipError_t launch_p16m(int bin, int blocks, const uint8_t *codes, const PairDesc *pairs, const int *idx,
                        const int *starts, const int8_t *blosum, int go_ge, int ge, SwPass1Out *p1, int *scratch,
-                       int64_t spw, hipStream_t s) {
+                       int64_t spw, int *queue, hipStream_t s) {
     constexpr int WPB = wpb16(R);
     sw16_pass1_kernel<R, WPB, true><<<blocks, 64 * WPB, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge, ge, p1,
-                                                               (uint32_t *)scratch, spw);
+                                                               (uint32_t *)scratch, spw, queue);
     return hipGetLastError();
 }
 
 typedef hipError_t (*P1Fn)(int, int, const uint8_t *, const PairDesc *, const int *, const int *, const int8_t *, int,
-                           int, SwPass1Out *, int *, int64_t, hipStream_t);
+                           int, SwPass1Out *, int *, int64_t, int *, hipStream_t);
 typedef hipError_t (*P2Fn)(int, int, const uint8_t *, const PairDesc *, const int *, const int *, const int8_t *, int,
-                           int, int, int, const SwPass1Out *, pastis_pair_record *, int *, int64_t, hipStream_t);
+                           int, int, int, const SwPass1Out *, pastis_pair_record *, int *, int64_t, int *,
+                           hipStream_t);
 
 const P1Fn kP1[kNumBins] = {launch_p1<1>,  launch_p1<2>,  launch_p1<3>,  launch_p1<4>,  launch_p1<5>,  launch_p1<6>,
                             launch_p1<7>,  launch_p1<8>,  launch_p1<9>,  launch_p1<10>, launch_p1<11>, launch_p1<12>,
@@ -1468,18 +1490,17 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
     auto mark = [&](hipEvent_t ev) { return timed ? hipEventRecord(ev, s) : hipSuccess; };
     if (npairs <= 0) return hipSuccess;
     const int go_ge = sc.gap_open + sc.gap_extend, ge = sc.gap_extend;
-    // Grids larger than what fits at once let the dispatcher balance blocks of
-    // uneven work (grid scale); no launch needs more blocks than the call's
-    // pairs could fill (per_block pairs each), or fewer than one full wave of
-    // resident blocks (base).
-    auto capped = [&](int blocks, int base, int per_block) {
+    // Every launch drains its bin's work queue with a resident grid (times
+    // the grid scale); no launch needs more blocks than the call's pairs
+    // could fill (per_block pairs each).
+    auto capped = [&](int blocks, int per_block) {
         const int64_t fill = (npairs + per_block - 1) / per_block;
-        return (int)std::max<int64_t>(std::min<int64_t>(blocks, fill), std::min<int64_t>(base, blocks));
+        return (int)std::max<int64_t>(1, std::min<int64_t>(blocks, fill));
     };
     const int nb = (int)((npairs + 255) / 256);
     hipError_t e = begin(kStSched);
     if (e != hipSuccess) return e;
-    sw_bin1_kernel<<<nb, 256, 0, s>>>(pairs, npairs, wk.bin_of, wk.counters);
+    sw_bin1_kernel<<<nb, 256, 0, s>>>(pairs, npairs, wk.bin_of, wk.counters, wk.queue);
     if ((e = launch_bins(wk.bin_of, npairs, kNumBins, wk.counts, wk.starts, wk.cursor, wk.idx, s)) != hipSuccess)
         return e;
     const int *idx1 = wk.idx;
@@ -1502,20 +1523,20 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
         const int scale = bin >= kMultiBin ? 1 : R <= 8 ? grid_scale : grid_scale_wide;
         if (sw_bin_is16(bin, max16) && bin >= kMulti16Bin)
             e = kP16M[bin - kMulti16Bin](bin, blocks16m(), codes, pairs, idx1, wk.starts, blosum, go_ge, ge, p1,
-                                         wk.scratch, wk.scratch_per_wave, s);
+                                         wk.scratch, wk.scratch_per_wave, wk.queue, s);
         else if (sw_bin_is16(bin, max16))
-            e = kP16[bin](bin, capped(scale * blocks16(R), blocks16(R), pairs_per_block16(R)), codes, pairs, idx1,
-                          wk.starts, blosum, go_ge, ge, p1, nullptr, 0, s);
+            e = kP16[bin](bin, capped(scale * blocks16(R), pairs_per_block16(R)), codes, pairs, idx1,
+                          wk.starts, blosum, go_ge, ge, p1, nullptr, 0, wk.queue, s);
         else
-            e = kP1[bin](bin, capped(scale * blocks_for_bin(bin), blocks_for_bin(bin), wpb32(R)), codes, pairs, idx1,
-                         wk.starts, blosum, go_ge, ge, p1, wk.scratch, wk.scratch_per_wave, s);
+            e = kP1[bin](bin, capped(scale * blocks_for_bin(bin), wpb32(R)), codes, pairs, idx1,
+                         wk.starts, blosum, go_ge, ge, p1, wk.scratch, wk.scratch_per_wave, wk.queue, s);
         if (e != hipSuccess) return e;
         if ((e = mark(ctx->bin_ev[2 * bin + 1])) != hipSuccess) return e;
     }
     if ((e = end(kStAlign1)) != hipSuccess || (e = begin(kStAlign2)) != hipSuccess)
         return e;
     // the start-bound and statistics launches take the same grid scales
-    // (multi-strip bins keep their grid: one boundary buffer per wave)
+    // (multi-strip bins keep a resident grid: one boundary buffer per wave)
     auto scale2 = [&](int bin) {
         return bin >= kMultiBin ? 1 : rows_of_bin(bin) <= 8 ? grid_scale : grid_scale_wide;
     };
@@ -1527,8 +1548,9 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
         // start bound, then only the pairs whose coverage can still hold
         for (int bin = 0; bin < kNumBins; ++bin) {
             const int R = rows_of_bin(bin);
-            e = kPB[bin](bin, capped(scale2(bin) * blocks_for_bin(bin), blocks_for_bin(bin), wpb32(R)), codes, pairs,
-                         wk.idx2, wk.starts2, blosum, go_ge, ge, p1, wk.scratch, wk.scratch_per_wave, s);
+            e = kPB[bin](bin, capped(scale2(bin) * blocks_for_bin(bin), wpb32(R)), codes, pairs,
+                         wk.idx2, wk.starts2, blosum, go_ge, ge, p1, wk.scratch, wk.scratch_per_wave,
+                         wk.queue + kNumBins, s);
             if (e != hipSuccess) return e;
         }
         sw_bin3_kernel<<<nb, 256, 0, s>>>(pairs, p1, npairs, sc.cov_pct, out, wk.bin_of, wk.counters);
@@ -1538,9 +1560,9 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
     }
     for (int bin = 0; bin < kNumBins; ++bin) {
         const int R = rows_of_bin(bin);
-        e = kP2[bin](bin, capped(scale2(bin) * blocks_for_bin(bin), blocks_for_bin(bin), wpb32(R)), codes, pairs,
+        e = kP2[bin](bin, capped(scale2(bin) * blocks_for_bin(bin), wpb32(R)), codes, pairs,
                      wk.idx2, wk.starts2, blosum, go_ge, ge, sc.cov_pct, sc.id_pct, p1, out, wk.scratch,
-                     wk.scratch_per_wave, s);
+                     wk.scratch_per_wave, wk.queue + 2 * kNumBins, s);
         if (e != hipSuccess) return e;
     }
     return end(kStAlign2);

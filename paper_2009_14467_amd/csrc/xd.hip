@@ -482,7 +482,20 @@ __global__ __launch_bounds__(256) void xd_kernel(const uint8_t *__restrict__ cod
     }
     const int64_t count = GLOBAL ? (int64_t)*n_redo : npairs;
     unsigned long long my_cells = 0;
-    for (int64_t w = gwave; w < count; w += (int64_t)gridDim.x * kWavesPerBlock) {
+    // register band: pairs claimed one at a time from the call's queue
+    // counter (extension lengths vary widely); global ring: grid stride
+    auto next = [&](int64_t w) -> int64_t {
+        if constexpr (GLOBAL) {
+            return w + (int64_t)gridDim.x * kWavesPerBlock;
+        } else {
+            unsigned long long v = 0;
+            if (lane == 0) v = atomicAdd(&counters[kCounterXdQueue], 1ull);
+            const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+            const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+            return (int64_t)(((uint64_t)hi << 32) | lo);
+        }
+    };
+    for (int64_t w = GLOBAL ? gwave : next(0); w < count; w = next(w)) {
         const int64_t q = GLOBAL ? (int64_t)redo[w] : w;
         const PairDesc pd = pairs[q];
         const uint8_t *a = codes + pd.a_off;
@@ -540,8 +553,9 @@ hipError_t launch_xd(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
     if (npairs <= 0) return hipSuccess;
     hipError_t e = stage_begin(ctx, kStAlign1, s);
     if (e != hipSuccess) return e;
+    // a resident grid (six blocks of four waves per CU) draining the queue
     int64_t blocks = (npairs + kWavesPerBlock - 1) / kWavesPerBlock;
-    if (blocks > 4096) blocks = 4096;
+    if (blocks > 256 * 6 * 2) blocks = 256 * 6 * 2;
     xd_kernel<false><<<(unsigned)blocks, 256, 0, s>>>(codes, pairs, npairs, blosum, k, sc.gap_open, sc.gap_extend,
                                                        sc.xdrop, sc.id_pct, sc.cov_pct, out, redo, n_redo, gring,
                                                        counters);

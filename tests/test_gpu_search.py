@@ -95,8 +95,8 @@ def test_autotune_picks_a_valid_schedule(gpu):
     before = ctx.search(res, off)
     t = ctx.autotune(res, off, max_pairs=2000)
     assert t == ctx.get_tuning()
-    assert t["sw16_max_rows"] in (0, 8, 12, 16) and t["sw_grid_scale"] in (4, 8, 16, 24, 32)
-    assert t["sw_grid_scale_wide"] in (4, 8, 16, 24, 32)
+    assert t["sw16_max_rows"] in (0, 8, 12, 16) and t["sw_grid_scale"] in (1, 2, 4)
+    assert t["sw_grid_scale_wide"] in (1, 2, 4)
     assert before.tobytes() == ctx.search(res, off).tobytes()
     with pytest.raises(P.PastisError):
         ctx.set_tuning(sw16_max_rows=17)

@@ -239,7 +239,9 @@ __device__ Ext extend(const uint8_t *a0, int la, int adir, const uint8_t *b0, in
 
 constexpr int kDppWaveRor1 = 0x13C;  // lane l receives lane l-1 (lane 0 from 63)
 
-__device__ __forceinline__ int ror1(int v) { return __builtin_amdgcn_update_dpp(0, v, kDppWaveRor1, 0xF, 0xF, false); }
+// a full rotation has no out-of-range lanes, so no prior value of the result
+// register is needed
+__device__ __forceinline__ int ror1(int v) { return __builtin_amdgcn_mov_dpp(v, kDppWaveRor1, 0xF, 0xF, false); }
 
 struct Stream {
     const uint8_t *p;
@@ -363,7 +365,12 @@ __device__ Ext extend_reg(const uint8_t *a0, int la, int adir, const uint8_t *b0
         const int H_ = max(D_, max(E_, F_));
         const unsigned sE_ = ee ? SE1 : SH1;
         const unsigned sF_ = fe ? rSF : rSH;
-        const unsigned sH_ = H_ == D_ ? sD : (H_ == E_ ? sE_ : sF_);
+        // the diagonal wins ties; H_ - D_ >= 0, so min(H_ - D_, 1) - 1 is an
+        // all-ones mask exactly when it wins (arithmetic rather than a select,
+        // which would be turned into a branch around the diagonal's counts)
+        const unsigned sEF = H_ == E_ ? sE_ : sF_;
+        const unsigned dmask = (unsigned)min(H_ - D_, 1) - 1u;
+        const unsigned sH_ = sEF + ((sD - sEF) & dmask);
         const bool any = u <= hi && max(Hd, max(Hu, Hl)) > kNeg / 2;
         const bool live = any && H_ >= best - X;
         cells += any ? 1 : 0;

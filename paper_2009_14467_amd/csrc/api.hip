@@ -452,6 +452,18 @@ pastis_status pastis_create(const pastis_params *p, int device, pastis_ctx **out
             return PASTIS_E_DEVICE;
         }
     }
+    // default priority; non-blocking so it never waits on the null stream
+    if (hipStreamCreateWithFlags(&ctx->long_stream, hipStreamNonBlocking) != hipSuccess) {
+        pastis_destroy(ctx);
+        return PASTIS_E_DEVICE;
+    }
+    for (int i = 0; i < 3; ++i) {
+        if (hipEventCreateWithFlags(&ctx->long_fork[i], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&ctx->long_join[i], hipEventDisableTiming) != hipSuccess) {
+            pastis_destroy(ctx);
+            return PASTIS_E_DEVICE;
+        }
+    }
     if (p->graph_mode) {
         // default priority; non-blocking so it never waits on the null stream
         if (hipStreamCreateWithFlags(&ctx->graph_stream, hipStreamNonBlocking) != hipSuccess ||
@@ -478,6 +490,14 @@ void pastis_destroy(pastis_ctx *ctx) {
     for (auto &ev : ctx->bin_ev)
         if (ev) (void)hipEventDestroy(ev);
     if (ctx->sw_exec) (void)hipGraphExecDestroy(ctx->sw_exec);
+    if (ctx->long_stream) {
+        (void)hipStreamSynchronize(ctx->long_stream);
+        (void)hipStreamDestroy(ctx->long_stream);
+    }
+    for (int i = 0; i < 3; ++i) {
+        if (ctx->long_fork[i]) (void)hipEventDestroy(ctx->long_fork[i]);
+        if (ctx->long_join[i]) (void)hipEventDestroy(ctx->long_join[i]);
+    }
     if (ctx->graph_stream) {
         (void)hipStreamSynchronize(ctx->graph_stream);
         (void)hipStreamDestroy(ctx->graph_stream);

@@ -114,6 +114,10 @@ struct pastis_ctx {
     size_t h_pinned_bytes = 0;
     hipEvent_t ev[2 * 9] = {};
     hipEvent_t bin_ev[2 * 32] = {};  // around each SW pass-1 bin launch
+    // the multi-strip (long) SW bins run on a second stream, concurrently with
+    // the one-strip bins: fork / join events of pass 1, start bound, statistics
+    hipStream_t long_stream = nullptr;
+    hipEvent_t long_fork[3] = {}, long_join[3] = {};
     // graph mode: the SW stage captured on a stream of the context
     hipStream_t graph_stream = nullptr;
     hipEvent_t graph_join[2] = {};

@@ -1487,7 +1487,19 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
     const bool use16 = max16 > 0;
     auto begin = [&](int st) { return timed ? stage_begin(ctx, st, s) : hipSuccess; };
     auto end = [&](int st) { return timed ? stage_end(ctx, st, s) : hipSuccess; };
-    auto mark = [&](hipEvent_t ev) { return timed ? hipEventRecord(ev, s) : hipSuccess; };
+    auto mark = [&](hipEvent_t ev, hipStream_t st) { return timed ? hipEventRecord(ev, st) : hipSuccess; };
+    // multi-strip bins (long sequences a, few pairs, long tails) run on the
+    // context's second stream beside the one-strip bins; they share the
+    // boundary buffers, so they stay in order among themselves there
+    const hipStream_t ls = ctx->long_stream;
+    auto fork = [&](int i) {
+        hipError_t r = hipEventRecord(ctx->long_fork[i], s);
+        return r != hipSuccess ? r : hipStreamWaitEvent(ls, ctx->long_fork[i], 0);
+    };
+    auto join = [&](int i) {
+        hipError_t r = hipEventRecord(ctx->long_join[i], ls);
+        return r != hipSuccess ? r : hipStreamWaitEvent(s, ctx->long_join[i], 0);
+    };
     if (npairs <= 0) return hipSuccess;
     const int go_ge = sc.gap_open + sc.gap_extend, ge = sc.gap_extend;
     // Every launch drains its bin's work queue with a resident grid (times
@@ -1514,26 +1526,29 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
             return e;
         if (alt) idx1 = (const int *)wk.sort_vals_alt;
     }
-    if ((e = end(kStSched)) != hipSuccess || (e = begin(kStAlign1)) != hipSuccess)
+    if ((e = end(kStSched)) != hipSuccess || (e = begin(kStAlign1)) != hipSuccess || (e = fork(0)) != hipSuccess)
         return e;
-    for (int bin = 0; bin < kNumBins; ++bin) {
-        if ((e = mark(ctx->bin_ev[2 * bin])) != hipSuccess) return e;
+    // long bins first, so that their tails overlap the one-strip bins
+    for (int k = 0; k < kNumBins; ++k) {
+        const int bin = (k + kMultiBin) % kNumBins;
+        const hipStream_t st = bin >= kMultiBin ? ls : s;
+        if ((e = mark(ctx->bin_ev[2 * bin], st)) != hipSuccess) return e;
         // multi-strip bins use per-wave boundary buffers: they keep their grid
         const int R = rows_of_bin(bin);
         const int scale = bin >= kMultiBin ? 1 : R <= 8 ? grid_scale : grid_scale_wide;
         if (sw_bin_is16(bin, max16) && bin >= kMulti16Bin)
             e = kP16M[bin - kMulti16Bin](bin, blocks16m(), codes, pairs, idx1, wk.starts, blosum, go_ge, ge, p1,
-                                         wk.scratch, wk.scratch_per_wave, wk.queue, s);
+                                         wk.scratch, wk.scratch_per_wave, wk.queue, st);
         else if (sw_bin_is16(bin, max16))
             e = kP16[bin](bin, capped(scale * blocks16(R), pairs_per_block16(R)), codes, pairs, idx1,
-                          wk.starts, blosum, go_ge, ge, p1, nullptr, 0, wk.queue, s);
+                          wk.starts, blosum, go_ge, ge, p1, nullptr, 0, wk.queue, st);
         else
             e = kP1[bin](bin, capped(scale * blocks_for_bin(bin), wpb32(R)), codes, pairs, idx1,
-                         wk.starts, blosum, go_ge, ge, p1, wk.scratch, wk.scratch_per_wave, wk.queue, s);
+                         wk.starts, blosum, go_ge, ge, p1, wk.scratch, wk.scratch_per_wave, wk.queue, st);
         if (e != hipSuccess) return e;
-        if ((e = mark(ctx->bin_ev[2 * bin + 1])) != hipSuccess) return e;
+        if ((e = mark(ctx->bin_ev[2 * bin + 1], st)) != hipSuccess) return e;
     }
-    if ((e = end(kStAlign1)) != hipSuccess || (e = begin(kStAlign2)) != hipSuccess)
+    if ((e = join(0)) != hipSuccess || (e = end(kStAlign1)) != hipSuccess || (e = begin(kStAlign2)) != hipSuccess)
         return e;
     // the start-bound and statistics launches take the same grid scales
     // (multi-strip bins keep a resident grid: one boundary buffer per wave)
@@ -1546,25 +1561,33 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
         return e;
     if (stats_mode == 0) {
         // start bound, then only the pairs whose coverage can still hold
-        for (int bin = 0; bin < kNumBins; ++bin) {
+        if ((e = fork(1)) != hipSuccess) return e;
+        for (int k = 0; k < kNumBins; ++k) {
+            const int bin = (k + kMultiBin) % kNumBins;
+            const hipStream_t st = bin >= kMultiBin ? ls : s;
             const int R = rows_of_bin(bin);
             e = kPB[bin](bin, capped(scale2(bin) * blocks_for_bin(bin), wpb32(R)), codes, pairs,
                          wk.idx2, wk.starts2, blosum, go_ge, ge, p1, wk.scratch, wk.scratch_per_wave,
-                         wk.queue + kNumBins, s);
+                         wk.queue + kNumBins, st);
             if (e != hipSuccess) return e;
         }
+        if ((e = join(1)) != hipSuccess) return e;
         sw_bin3_kernel<<<nb, 256, 0, s>>>(pairs, p1, npairs, sc.cov_pct, out, wk.bin_of, wk.counters);
         if ((e = launch_bins(wk.bin_of, npairs, kNumBins, wk.counts, wk.starts2, wk.cursor, wk.idx2, s)) !=
             hipSuccess)
             return e;
     }
-    for (int bin = 0; bin < kNumBins; ++bin) {
+    if ((e = fork(2)) != hipSuccess) return e;
+    for (int k = 0; k < kNumBins; ++k) {
+        const int bin = (k + kMultiBin) % kNumBins;
+        const hipStream_t st = bin >= kMultiBin ? ls : s;
         const int R = rows_of_bin(bin);
         e = kP2[bin](bin, capped(scale2(bin) * blocks_for_bin(bin), wpb32(R)), codes, pairs,
                      wk.idx2, wk.starts2, blosum, go_ge, ge, sc.cov_pct, sc.id_pct, p1, out, wk.scratch,
-                     wk.scratch_per_wave, wk.queue + 2 * kNumBins, s);
+                     wk.scratch_per_wave, wk.queue + 2 * kNumBins, st);
         if (e != hipSuccess) return e;
     }
+    if ((e = join(2)) != hipSuccess) return e;
     return end(kStAlign2);
 }
 

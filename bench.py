@@ -128,7 +128,7 @@ def graph_leg(P, args, params, res, off, tuning):
     ctx = P.Context(P.Params(graph_mode=True, **params))
     if isinstance(tuning, dict):
         ctx.set_tuning(**{k: tuning[k] for k in ("sw16_max_rows", "sw_direct_pct", "sw_grid_scale",
-                                                  "sw_grid_scale_wide")})
+                                                  "sw_grid_scale_wide", "sw_intra_pair")})
     for _ in range(max(args.warmup, 1)):
         ctx.search(res, off)
     torch.cuda.synchronize()

@@ -283,7 +283,7 @@ pastis_status pastis_mlp_calibrate(pastis_ctx *ctx, const float *X, const uint8_
 
 /* ---- schedule of the Smith-Waterman stage ----
  * Knobs of the length-binned launches (every setting gives the same results;
- * only the time changes).  A new context starts at {16, 50, 1, 1}.  pastis_autotune times candidate settings on a
+ * only the time changes).  A new context starts at {16, 50, 1, 1, 0}.  pastis_autotune times candidate settings on a
  * sample of the given sequences' own candidate pairs and keeps the fastest. */
 typedef struct pastis_tuning {
     int32_t sw16_max_rows; /* bins with at most this many rows per lane run two pairs per
@@ -298,7 +298,11 @@ typedef struct pastis_tuning {
                               than the call's pairs can fill).  Every launch drains a
                               work queue, so 1 (a resident grid) suffices */
     int32_t sw_grid_scale_wide; /* the same for 9..16 rows per lane (1..64) */
-    int32_t reserved[4];
+    int32_t sw_intra_pair; /* 1: pass 1 of sequences a longer than 2978 rows (32-bit lanes)
+                              runs one workgroup of four waves per pair, strips
+                              pipelined across the waves (intra-pair mode); 0: one
+                              wave per pair (inter-pair mode) */
+    int32_t reserved[3];
 } pastis_tuning;
 
 pastis_status pastis_get_tuning(const pastis_ctx *ctx, pastis_tuning *out);

@@ -92,13 +92,14 @@ class _Tuning(ctypes.Structure):
         ("sw_direct_pct", ctypes.c_int32),
         ("sw_grid_scale", ctypes.c_int32),
         ("sw_grid_scale_wide", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("sw_intra_pair", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 
 def _tuning_dict(t) -> dict:
     return {"sw16_max_rows": t.sw16_max_rows, "sw_direct_pct": t.sw_direct_pct, "sw_grid_scale": t.sw_grid_scale,
-            "sw_grid_scale_wide": t.sw_grid_scale_wide}
+            "sw_grid_scale_wide": t.sw_grid_scale_wide, "sw_intra_pair": t.sw_intra_pair}
 
 
 class _Stats(ctypes.Structure):
@@ -380,10 +381,11 @@ class Context:
         return _tuning_dict(t)
 
     def set_tuning(self, sw16_max_rows: int = 16, sw_direct_pct: int = 50, sw_grid_scale: int = 1,
-                   sw_grid_scale_wide: int = 1):
+                   sw_grid_scale_wide: int = 1, sw_intra_pair: int = 0):
         t = _Tuning()
         t.sw16_max_rows, t.sw_direct_pct = sw16_max_rows, sw_direct_pct
         t.sw_grid_scale, t.sw_grid_scale_wide = sw_grid_scale, sw_grid_scale_wide
+        t.sw_intra_pair = sw_intra_pair
         self._check(lib().pastis_set_tuning(self._ctx, ctypes.byref(t)))
 
     def autotune(self, residues, offsets, max_pairs: int = 1 << 21, stream=None) -> dict:

@@ -104,7 +104,7 @@ struct pastis_ctx {
     bool have_candidates = false;
     bool records_internal = false;  // the current alignment's records feed edges only
     int last_max16 = 0;             // the last SW call ran 16-bit pass-1 bins up to this R
-    pastis_tuning tune{16, 50, 1, 1, {0, 0, 0, 0}};
+    pastis_tuning tune{16, 50, 1, 1, 0, {0, 0, 0}};
     // learned filter
     pastis::MlpState mlp{};
     bool mlp_alloc = false, mlp_set = false;
@@ -194,6 +194,7 @@ struct SwPass1Out {
 // start-bound pairs, [4] their cells, [kCounterXdQueue] the x-drop kernel's
 // work queue, [kCounterBinCells + b] pass-1 cells of SW bin b
 constexpr int kCounterXdQueue = 5;
+constexpr int kCounterIntraFlag = 6;  // an intra-pair wait ran out of its bound
 constexpr int kCounterBinCells = 8;
 constexpr int kNumCounters = kCounterBinCells + 32;
 
@@ -224,11 +225,12 @@ int64_t sw_scratch_waves();
 
 // max16 > 0: pass 1 of one-strip pairs with at most max16 rows per lane in
 // 16-bit lanes, two pairs per wave; its records leave end_b = -1 for pairs
-// that skip the statistics pass.  grid_scale multiplies the pass-1 grids.
+// that skip the statistics pass.  grid_scale multiplies the pass-1 grids;
+// intra = 1 runs pass 1 of the 32-bit multi-strip bins one workgroup per pair.
 hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pairs, int64_t npairs,
                      const int8_t *blosum, const Scoring &sc, SwPass1Out *p1, pastis_pair_record *out,
-                     const SwWork &wk, int stats_mode, int max16, int grid_scale, int grid_scale_wide, bool timed,
-                     hipStream_t s);
+                     const SwWork &wk, int stats_mode, int max16, int grid_scale, int grid_scale_wide, int intra,
+                     bool timed, hipStream_t s);
 // 16-bit pass 1 needs o + e >= 4 (biased scores stay non-negative).
 bool sw16_supported(const Scoring &sc);
 bool sw_bin_is16(int bin, int max16);

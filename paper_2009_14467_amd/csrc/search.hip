@@ -562,9 +562,10 @@ pastis_status pastis_get_tuning(const pastis_ctx *ctx, pastis_tuning *out) {
 pastis_status pastis_set_tuning(pastis_ctx *ctx, const pastis_tuning *t) {
     if (!ctx || !t) return PASTIS_E_INVAL;
     if (t->sw16_max_rows < 0 || t->sw16_max_rows > 16 || t->sw_direct_pct < 0 || t->sw_grid_scale < 1 ||
-        t->sw_grid_scale > 64 || t->sw_grid_scale_wide < 1 || t->sw_grid_scale_wide > 64)
+        t->sw_grid_scale > 64 || t->sw_grid_scale_wide < 1 || t->sw_grid_scale_wide > 64 || t->sw_intra_pair < 0 ||
+        t->sw_intra_pair > 1)
         return set_error(ctx, PASTIS_E_INVAL, "tuning value out of range");
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 3; ++i)
         if (t->reserved[i] != 0) return set_error(ctx, PASTIS_E_INVAL, "reserved fields must be zero");
     ctx->tune = *t;
     return PASTIS_OK;
@@ -640,6 +641,8 @@ pastis_status pastis_autotune(pastis_ctx *ctx, const uint8_t *residues, const in
         PASTIS_TRY(sweep(&ctx->tune.sw_direct_pct, direct, 6));
         PASTIS_TRY(sweep(&ctx->tune.sw_grid_scale, grid, 3));
         PASTIS_TRY(sweep(&ctx->tune.sw_grid_scale_wide, grid, 3));
+        const int intra[] = {0, 1};
+        PASTIS_TRY(sweep(&ctx->tune.sw_intra_pair, intra, 2));
     }
     if (out) *out = ctx->tune;
     return PASTIS_OK;

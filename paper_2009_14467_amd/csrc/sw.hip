@@ -321,6 +321,204 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_pass1_kernel(const uint8_t *
     }
 }
 
+// ---------------------------------------------------------------- pass 1, one workgroup per long pair
+
+// Intra-pair mode for long sequences a: the W waves of a block work on one
+// pair.  Wave w takes strips w, w + W, ... (strips of 64 R rows in 32-bit
+// lanes, as in the multi-strip kernel above), so W strips run at once, each
+// a little behind the one above.  The bottom row of strip s (H and F' of
+// every column) reaches strip s + 1 through a full-length row buffer of slot
+// s mod W in global memory.  Two monotone LDS counters per slot order the
+// hand-off, in columns over all strips that used the slot for this pair:
+// prod (written) and cons (loaded by the reader).  The reader of strip s + 1
+// waits for prod (strip s); the writer of strip s + W waits until strip
+// s + 1 has loaded the columns it overwrites.  Every wait is for an earlier
+// strip, so the earliest unfinished strip never waits and the pipeline
+// drains; each wait is also bounded, and a wait that runs out sets *flag and
+// gives up (the call then fails) instead of spinning on.  The counters are
+// released and acquired at workgroup scope, which orders the row buffer's
+// global stores and loads between the waves of the block.
+constexpr int kIntraWaves = 4;
+constexpr int kIntraSpinLimit = 1 << 24;
+
+__device__ __forceinline__ int lds_acquire(int *p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_release(int *p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+// wait until *p >= need; false when the bound runs out
+__device__ __forceinline__ bool lds_wait(int *p, int need) {
+    for (int spin = 0; spin < kIntraSpinLimit; ++spin) {
+        if (__builtin_amdgcn_readfirstlane(lds_acquire(p)) >= need) return true;
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return false;
+}
+
+template <int R>
+__global__ __launch_bounds__(64 * kIntraWaves) void sw_intra_pass1_kernel(
+    const uint8_t *__restrict__ codes, const PairDesc *__restrict__ pairs, const int *__restrict__ idx,
+    const int *__restrict__ starts, int bin, const int8_t *__restrict__ blosum, int go_ge, int ge,
+    SwPass1Out *__restrict__ out, int *scratch, int64_t scratch_per_wave, int *queue, unsigned long long *flag) {
+    constexpr int W = kIntraWaves;
+    __shared__ ProfWord<R> prof_all[W][kProfCodes][kWave];
+    __shared__ int8_t sblosum[kProfCodes * kProfCodes];
+    __shared__ int prod[W], cons[W];
+    __shared__ unsigned long long s_best[W];
+    __shared__ int s_take;
+    load_blosum(sblosum, blosum);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    ProfWord<R>(*prof)[kWave] = prof_all[wave];
+    const int item_end = starts[bin + 1];
+    constexpr int RS = kWave * R;
+    const int in_slot = (wave + W - 1) % W;  // the slot this wave's strips read
+    // slot k's row buffer: H at row[k], F' at row[k] + scratch_per_wave / 2
+    int *const out_h = scratch + ((int64_t)blockIdx.x * W + wave) * scratch_per_wave;
+    int *const out_f = out_h + scratch_per_wave / 2;
+    const int *const in_h = scratch + ((int64_t)blockIdx.x * W + in_slot) * scratch_per_wave;
+    const int *const in_f = in_h + scratch_per_wave / 2;
+
+    for (;;) {
+        // every wave is past the last pair (the barrier at its end), so the
+        // block's counters and window may be reset
+        if (threadIdx.x == 0) s_take = atomicAdd(queue + bin, 1);
+        if (threadIdx.x < W) {
+            prod[threadIdx.x] = 0;
+            cons[threadIdx.x] = 0;
+        }
+        __syncthreads();
+        const int64_t w = starts[bin] + s_take;
+        if (w >= item_end) break;
+        const int q = idx[w];
+        const PairDesc pd = pairs[q];
+        const uint8_t *a = codes + pd.a_off;
+        const uint8_t *b = codes + pd.b_off;
+        const int la = pd.la, lb = pd.lb;
+        unsigned long long best = 0;  // (score << 32) | ~(row << 16 | col)
+        bool ok = true;
+        const int nstrips = (la > 0 && lb > 0) ? (la + RS - 1) / RS : 0;
+        for (int s = wave; ok && s < nstrips; s += W) {
+            const int base = s * RS + lane * R;
+            build_profile<R>(prof, sblosum, a, la, base, lane);
+            const bool from_above = s > 0;
+            const bool to_below = s + 1 < nstrips;
+            // first absolute column of the slot uses this strip reads / writes
+            const int in0 = (s > 0 ? (s - 1) / W : 0) * lb, out0 = (s / W) * lb;
+            int H[R], G[R], E[R], rmax[R], rcol[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                H[r] = 0;
+                G[r] = -go_ge;
+                E[r] = 0;
+                rmax[r] = 0;
+                rcol[r] = 0;
+            }
+            int hlast = 0, flast = 0, hprev = 0, cres = kPadCode;
+            int chunk = kPadCode, nx = (lane < lb) ? (int)b[lane] : kPadCode;
+            // the row above arrives in chunks of 64 columns, one chunk ahead
+            int ch_h = 0, ch_f = 0, nx_h = 0, nx_f = 0;
+            auto fetch_above = [&](int c0) {  // columns c0 .. c0 + 63 into nx
+                const int hi = min(c0 + kWave, lb);
+                if (ok && !lds_wait(&prod[in_slot], in0 + hi)) ok = false;
+                nx_h = c0 + lane < lb ? in_h[c0 + lane] : 0;
+                nx_f = c0 + lane < lb ? in_f[c0 + lane] : 0;
+                if (lane == 0) lds_release(&cons[in_slot], in0 + hi);
+            };
+            if (from_above) fetch_above(0);
+            auto step = [&](const int t, auto tail_tag) {
+                constexpr bool kTail = decltype(tail_tag)::value;
+                if ((t & (kWave - 1)) == 0) {
+                    chunk = nx;
+                    const int c = t + kWave + lane;
+                    nx = (c < lb) ? (int)b[c] : kPadCode;
+                    if (!kTail && from_above) {
+                        ch_h = nx_h;
+                        ch_f = nx_f;
+                        if (t + kWave < lb) fetch_above(t + kWave);
+                    }
+                }
+                const int bt = __builtin_amdgcn_readlane(chunk, t & (kWave - 1));
+                int in_hv = 0, in_fv = 0;
+                if (!kTail && from_above) {
+                    in_hv = __builtin_amdgcn_readlane(ch_h, t & (kWave - 1));
+                    in_fv = __builtin_amdgcn_readlane(ch_f, t & (kWave - 1));
+                }
+                const int rh = shr1(in_hv, hlast);
+                const int rf = shr1(in_fv, flast);
+                cres = shr1(bt, cres);
+                const int j = t - lane;
+                const bool valid = j < lb;
+                const ProfWord<R> pw = prof[cres][lane];
+                int hd = hprev, gu = rh - go_ge, fu = rf;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int e = max(subs(E[r], ge), G[r]);
+                    const int f = max(subs(fu, ge), gu);
+                    const int d = hd + sigma_at<R>(pw, r);
+                    const int h = max(d, max(e, f));
+                    hd = H[r];
+                    H[r] = h;
+                    E[r] = e;
+                    const int g = h - go_ge;
+                    G[r] = g;
+                    gu = g;
+                    fu = f;
+                    if ((!kTail || valid) && h > rmax[r]) {
+                        rmax[r] = h;
+                        rcol[r] = j;
+                    }
+                }
+                hlast = H[R - 1];
+                flast = fu;
+                hprev = rh;
+                // lane 63 leaves column jw = t - 63 for the strip below
+                const int jw = t - (kWave - 1);
+                if (to_below && jw >= 0 && jw < lb) {
+                    // the reader of the slot's previous use (strip s + 1 - W)
+                    // must have loaded columns jw .. jw + 63 first
+                    if ((jw & (kWave - 1)) == 0 && out0 > 0 && ok &&
+                        !lds_wait(&cons[wave], out0 - lb + min(jw + kWave, lb)))
+                        ok = false;
+                    if (lane == kWave - 1) {
+                        out_h[jw] = hlast;
+                        out_f[jw] = flast;
+                        if ((jw & (kWave - 1)) == kWave - 1 || jw == lb - 1) lds_release(&prod[wave], out0 + jw + 1);
+                    }
+                }
+            };
+            for (int t = 0; t < lb; ++t) step(t, std::false_type{});
+            for (int t = lb; t < lb + kWave - 1; ++t) step(t, std::true_type{});
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int row = base + r;
+                if (row < la && rmax[r] > 0) {
+                    const unsigned pos = ((unsigned)row << 16) | (unsigned)rcol[r];
+                    const unsigned long long k = ((unsigned long long)(unsigned)rmax[r] << 32) | (unsigned)(~pos);
+                    best = k > best ? k : best;
+                }
+            }
+        }
+        if (!ok && lane == 0) atomicOr(flag, 1ull);
+        best = wave_max_u64(best);
+        if (lane == 0) s_best[wave] = best;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long m = 0;
+            for (int k = 0; k < W; ++k) m = s_best[k] > m ? s_best[k] : m;
+            SwPass1Out o;
+            o.score = (int32_t)(m >> 32);
+            const unsigned pos = ~(unsigned)m;
+            o.end_a = o.score > 0 ? (int32_t)(pos >> 16) : -1;
+            o.end_b = o.score > 0 ? (int32_t)(pos & 0xFFFF) : -1;
+            o.pad = 0;
+            out[q] = o;
+        }
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------- pass 1, 16-bit lanes
 
 // Two pairs per wave in the 16-bit halves of every DP word (pair P low, Q
@@ -1414,6 +1612,23 @@ hipError_t launch_p16m(int bin, int blocks, const uint8_t *codes, const PairDesc
     return hipGetLastError();
 }
 
+// intra-pair pass 1: one block of four waves per pair, one block per CU (the
+// four strip profiles take up to 100 KB of LDS); the row buffers of the
+// block's slots are four of the per-wave boundary buffers
+constexpr int kIntraBlocks = 256;
+
+typedef hipError_t (*PIFn)(int, const uint8_t *, const PairDesc *, const int *, const int *, const int8_t *, int, int,
+                           SwPass1Out *, int *, int64_t, int *, unsigned long long *, hipStream_t);
+
+template <int R>
+hipError_t launch_pi(int bin, const uint8_t *codes, const PairDesc *pairs, const int *idx, const int *starts,
+                     const int8_t *blosum, int go_ge, int ge, SwPass1Out *p1, int *scratch, int64_t spw, int *queue,
+                     unsigned long long *flag, hipStream_t s) {
+    sw_intra_pass1_kernel<R><<<kIntraBlocks, 64 * kIntraWaves, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge,
+                                                                      ge, p1, scratch, spw, queue, flag);
+    return hipGetLastError();
+}
+
 typedef hipError_t (*P1Fn)(int, int, const uint8_t *, const PairDesc *, const int *, const int *, const int8_t *, int,
                            int, SwPass1Out *, int *, int64_t, int *, hipStream_t);
 typedef hipError_t (*P2Fn)(int, int, const uint8_t *, const PairDesc *, const int *, const int *, const int8_t *, int,
@@ -1430,6 +1645,8 @@ const P1Fn kP16[kMax16R] = {launch_p16<1>,  launch_p16<2>,  launch_p16<3>,  laun
                             launch_p16<5>,  launch_p16<6>,  launch_p16<7>,  launch_p16<8>,
                             launch_p16<9>,  launch_p16<10>, launch_p16<11>, launch_p16<12>,
                             launch_p16<13>, launch_p16<14>, launch_p16<15>, launch_p16<16>};
+const PIFn kPI[kMaxR - kMultiMinR + 1] = {launch_pi<9>,  launch_pi<10>, launch_pi<11>, launch_pi<12>,
+                                          launch_pi<13>, launch_pi<14>, launch_pi<15>, launch_pi<16>};
 const P1Fn kP16M[kMaxR - kMultiMinR + 1] = {launch_p16m<9>,  launch_p16m<10>, launch_p16m<11>, launch_p16m<12>,
                                            launch_p16m<13>, launch_p16m<14>, launch_p16m<15>, launch_p16m<16>};
 const P1Fn kPB[kNumBins] = {launch_pb<1>,  launch_pb<2>,  launch_pb<3>,  launch_pb<4>,  launch_pb<5>,  launch_pb<6>,
@@ -1469,6 +1686,7 @@ int64_t sw_scratch_waves() {
     for (int b = kMultiBin; b < kNumBins; ++b) {
         w = std::max<int64_t>(w, (int64_t)blocks_for_bin(b) * wpb32(rows_of_bin(b)));
         w = std::max<int64_t>(w, (int64_t)blocks16m() * wpb16(rows_of_bin(b)));
+        w = std::max<int64_t>(w, (int64_t)kIntraBlocks * kIntraWaves);
     }
     return w;
 }
@@ -1481,8 +1699,8 @@ bool sw_bin_is16(int bin, int max16) {
 
 hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pairs, int64_t npairs,
                      const int8_t *blosum, const Scoring &sc, SwPass1Out *p1, pastis_pair_record *out,
-                     const SwWork &wk, int stats_mode, int max16, int grid_scale, int grid_scale_wide, bool timed,
-                     hipStream_t s) {
+                     const SwWork &wk, int stats_mode, int max16, int grid_scale, int grid_scale_wide, int intra,
+                     bool timed, hipStream_t s) {
     // timed = false (graph capture): no stage or per-bin events
     const bool use16 = max16 > 0;
     auto begin = [&](int st) { return timed ? stage_begin(ctx, st, s) : hipSuccess; };
@@ -1539,6 +1757,9 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
         if (sw_bin_is16(bin, max16) && bin >= kMulti16Bin)
             e = kP16M[bin - kMulti16Bin](bin, blocks16m(), codes, pairs, idx1, wk.starts, blosum, go_ge, ge, p1,
                                          wk.scratch, wk.scratch_per_wave, wk.queue, st);
+        else if (intra && bin >= kMultiBin)
+            e = kPI[R - kMultiMinR](bin, codes, pairs, idx1, wk.starts, blosum, go_ge, ge, p1, wk.scratch,
+                                    wk.scratch_per_wave, wk.queue, wk.counters + kCounterIntraFlag, st);
         else if (sw_bin_is16(bin, max16))
             e = kP16[bin](bin, capped(scale * blocks16(R), pairs_per_block16(R)), codes, pairs, idx1,
                           wk.starts, blosum, go_ge, ge, p1, nullptr, 0, wk.queue, st);

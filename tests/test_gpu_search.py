@@ -70,7 +70,8 @@ def test_search_repeatable(gpu):
 
 @pytest.mark.parametrize("tuning", [dict(sw16_max_rows=0), dict(sw16_max_rows=8, sw_direct_pct=0),
                                     dict(sw16_max_rows=12, sw_direct_pct=1 << 20, sw_grid_scale=1),
-                                    dict(sw16_max_rows=16, sw_direct_pct=25, sw_grid_scale=64, sw_grid_scale_wide=3)])
+                                    dict(sw16_max_rows=16, sw_direct_pct=25, sw_grid_scale=64, sw_grid_scale_wide=3),
+                                    dict(sw16_max_rows=0, sw_intra_pair=1)])
 def test_every_schedule_gives_the_same_edges(gpu, orc, tuning):
     """Schedule knobs move time, never results: each setting against the oracle."""
     import paper_2009_14467_amd as P

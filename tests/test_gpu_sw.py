@@ -21,10 +21,12 @@ def _to_dev(x, dev, dtype=None):
     return torch.from_numpy(a).to(dev)
 
 
-def _gpu_records(dev, s, lo, hi, s1=None, s2=None, **params):
+def _gpu_records(dev, s, lo, hi, s1=None, s2=None, tuning=None, **params):
     import paper_2009_14467_amd as P
 
     ctx = P.Context(P.Params(**params))
+    if tuning:
+        ctx.set_tuning(**tuning)
     out = ctx.align_pairs(
         _to_dev(s.residues, dev), _to_dev(s.offsets, dev), _to_dev(lo, dev), _to_dev(hi, dev),
         None if s1 is None else _to_dev(s1, dev), None if s2 is None else _to_dev(s2, dev),
@@ -251,6 +253,40 @@ def test_sw16_multi_strip_bins(gpu, orc):
     got = _gpu_records(gpu, s, lo, hi, score_width=16)
     _check16(got, want)
     _compare(_gpu_records(gpu, s, lo, hi, full_records=True, score_width=16), want)
+
+
+def test_intra_pair_mode(gpu, orc):
+    """One workgroup per pair (strips pipelined across four waves) for
+    sequences a over 2,978 rows, and for every multi-strip pair once 16-bit
+    lanes are off: 1 to 20 strips, pairs sharing sequences, against the oracle."""
+    from synth.families import FamilySet
+
+    rng = np.random.default_rng(13)
+    lens = [1100, 2500, 2979, 3100, 4100, 5000, 9000, 20000]
+    seqs = []
+    for L in lens:
+        a = rng.integers(0, 20, L)
+        b = a.copy()
+        sub = rng.random(L) < 0.25
+        b[sub] = rng.integers(0, 20, int(sub.sum()))
+        b = np.concatenate([rng.integers(0, 20, int(rng.integers(0, 60))), b, rng.integers(0, 20, 9)])
+        seqs += [a, b]
+    letters = np.frombuffer(b"ARNDCQEGHILKMFPSTWYV", np.uint8)
+    res = np.concatenate([letters[x] for x in seqs]).astype(np.uint8)
+    off = np.zeros(len(seqs) + 1, np.int64)
+    np.cumsum([len(x) for x in seqs], out=off[1:])
+    s = FamilySet(res, off, np.zeros(len(seqs), np.int32), {})
+    codes = orc.encode(s.residues)
+    lo = np.arange(0, len(seqs), 2, dtype=np.uint32)
+    hi = lo + 1
+    # unrelated pairs and pairs sharing their shorter sequence
+    lo = np.concatenate([lo, np.array([4, 4, 6, 8, 10], np.uint32)])
+    hi = np.concatenate([hi, np.array([9, 13, 11, 15, 13], np.uint32)])
+    want = orc.align_pairs(codes, s.offsets, lo, hi, mode="sw")
+    intra = dict(sw_intra_pair=1)
+    _compare(_gpu_records(gpu, s, lo, hi, tuning=intra, full_records=True), want)
+    _compare(_gpu_records(gpu, s, lo, hi, tuning=intra), want, ("score", "end_a", "end_b", "passed", "swapped", "cells"))
+    _check16(_gpu_records(gpu, s, lo, hi, tuning=intra, score_width=16), want)
 
 
 def test_search_same_edges_in_16_and_32_bits(gpu):

@@ -28,6 +28,7 @@ METRIC = "alignment GCUPS + aligned pairs/s, 1 GPU; MLP-filtered vs plain at ≥
 # packed 16-bit ops (v_pk_*_i16) do two lane-ops each
 PEAK_INT32_TOPS = 256 * 64 * 2.4e9 / 1e12
 PEAK_INT16_TOPS = 2 * PEAK_INT32_TOPS
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 # algorithmic integer ops per pass-1 DP cell, as each lane width computes the
 # recurrence with the gap states floored at zero (E' = max(E, 0), F' = max(F, 0)):
 #   16-bit, per two cells (one packed op each): spread of the two scores (1),
@@ -339,6 +340,17 @@ def main():
         "bound_pass_cells": int(st["bound_pass_cells"]),
         "stage_ms": {k: v / args.steps for k, v in zip(names, stage)},
         "align_gcups": cells / ((stage[5] + stage[6]) / args.steps * 1e-3) / 1e9,
+        # candidate discovery's product against HBM bandwidth: one 6-byte
+        # posting (sequence u32, position u16) per product is the least the
+        # product must read; the stage time includes symmetrisation and sorting
+        "spgemm": {
+            "products": int(st["spgemm_products"]),
+            "ms": stage[3] / args.steps,
+            "products_per_s": st["spgemm_products"] / (stage[3] / args.steps * 1e-3),
+            "achieved_gb_s": 6 * st["spgemm_products"] / (stage[3] / args.steps * 1e-3) / 1e9,
+            "peak_gb_s": PEAK_HBM_GBS,
+            "frac": 6 * st["spgemm_products"] / (stage[3] / args.steps * 1e-3) / 1e9 / PEAK_HBM_GBS,
+        },
         "roofline": {
             "kernel": dom_name,
             "bound": "alu",

@@ -155,6 +155,10 @@ typedef struct pastis_run_stats {
     int32_t sw_graph;         /* Smith-Waterman stage: 0 direct launches, 1 graph captured
                                  and launched, 2 graph replayed */
     int32_t sw_graph_pad;
+    /* candidate discovery: postings visited by the sparse product (one pass
+     * over every row's entries; the counting and the seed phase each make
+     * one such pass) */
+    int64_t spgemm_products;
 } pastis_run_stats;
 
 typedef struct pastis_ctx pastis_ctx;

@@ -127,6 +127,7 @@ class _Stats(ctypes.Structure):
         ("stats_pass_cells", ctypes.c_int64),
         ("sw_graph", ctypes.c_int32),
         ("sw_graph_pad", ctypes.c_int32),
+        ("spgemm_products", ctypes.c_int64),
     ]
 
 

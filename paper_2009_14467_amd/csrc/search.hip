@@ -98,6 +98,7 @@ struct Misc {
     uint32_t *d_overflow;         // 1
     uint32_t *n_cand;             // 1
     uint32_t *n_edges;            // 1
+    unsigned long long *products; // 1
     int *bin_meta;                // 160
 };
 
@@ -112,6 +113,7 @@ pastis_status misc(pastis_ctx *ctx, Misc &m) {
     m.d_overflow = w + 3;
     m.n_cand = w + 4;
     m.n_edges = w + 5;
+    m.products = base + 6;
     m.bin_meta = (int *)(base + 8);
     return PASTIS_OK;
 }
@@ -266,14 +268,17 @@ pastis_status discover(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, 
     sp.bins = BinBufs{M.bin_meta, M.bin_meta + 32, M.bin_meta + 64, nullptr};
     PASTIS_TRY(get(ctx, kBufIdx, n, &sp.bins.idx));
     sp.max_big = M.max_big;
+    sp.products = M.products;
     PASTIS_TRY(get(ctx, kDBigRows, n, &sp.big_rows));
     sp.n_big = M.n_big;
     sp.d_count = M.d_count;
     sp.d_overflow = M.d_overflow;
     sp.nbits = key_bits(n);
     HIP_TRY(ctx, spgemm_plan(sp, s), "product plan");
-    unsigned long long mxw = 0;
+    unsigned long long mxw = 0, prods = 0;
     PASTIS_TRY(read_device(ctx, M.max_big, &mxw, sizeof(mxw), s));
+    PASTIS_TRY(read_device(ctx, M.products, &prods, sizeof(prods), s));
+    ctx->stats.spgemm_products = (int64_t)prods;
     const uint32_t gcap = next_pow2(2 * std::max<unsigned long long>(mxw, 12288ull));
     // tables of the big rows: up to 8 GiB, at most 512 blocks
     sp.global_blocks = (int)std::max<int64_t>(8, std::min<int64_t>(512, (int64_t)(8ll << 30) / (24ll * gcap)));

@@ -507,7 +507,8 @@ __global__ void as_ub_kernel(AsIn in, int64_t n, uint32_t *__restrict__ ub, uint
 // products of row i (postings visited), and the row's bin
 __global__ void work_kernel(RowView rv, Postings P, int64_t n, int n_big_ok, uint64_t *__restrict__ work,
                             int8_t *__restrict__ bin_of, unsigned long long *__restrict__ max_big,
-                            uint32_t *__restrict__ big_rows, uint32_t *__restrict__ n_big) {
+                            uint32_t *__restrict__ big_rows, uint32_t *__restrict__ n_big,
+                            unsigned long long *__restrict__ products) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         uint64_t b, e;
         rv.bounds((uint32_t)i, b, e);
@@ -517,6 +518,7 @@ __global__ void work_kernel(RowView rv, Postings P, int64_t n, int n_big_ok, uin
             w += P.uk_start[s + 1] - P.uk_start[s];
         }
         work[i] = w;
+        if (w) atomicAdd(products, (unsigned long long)w);
         int8_t bin;
         if (w == 0)
             bin = -1;
@@ -621,8 +623,9 @@ hipError_t spgemm_plan(const SpgemmArgs &a, hipStream_t s) {
     hipError_t e;
     if ((e = fill<unsigned long long>(a.max_big, 1, 0ull, s)) != hipSuccess) return e;
     if ((e = fill<uint32_t>(a.n_big, 2, 0u, s)) != hipSuccess) return e;
+    if ((e = fill<unsigned long long>(a.products, 1, 0ull, s)) != hipSuccess) return e;
     work_kernel<<<grid_for(a.n), 256, 0, s>>>(rv, P, a.n, a.n < (1ll << 18) ? 1 : 0, a.work, a.bin_of, a.max_big,
-                                               a.big_rows, a.n_big);
+                                               a.big_rows, a.n_big, a.products);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return launch_bins(a.bin_of, a.n, 2, a.bins.counts, a.bins.starts, a.bins.cursor, a.bins.idx, s);
 }

@@ -58,6 +58,7 @@ struct SpgemmArgs {
     int8_t *bin_of;
     BinBufs bins;
     unsigned long long *max_big;
+    unsigned long long *products;  // postings visited by one pass over the rows
     uint32_t *big_rows, *n_big;  // n_big: 2 counters
     // directional entries
     uint32_t *d_count, *d_overflow;

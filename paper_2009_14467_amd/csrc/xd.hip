@@ -339,13 +339,24 @@ __device__ Ext extend_reg(const uint8_t *a0, int la, int adir, const uint8_t *b0
         // means u <= d-1, and rows of d-2 are <= d-2
         const int rH = ror1(H1), rF = ror1(F1);
         const unsigned rSH = (unsigned)ror1((int)SH1), rSF = (unsigned)ror1((int)SF1);
-        const int nh = uni(max(min(c1 + n1, d) - c1, 0));  // rows of d-1 in [c1, d-1]
-        const bool okv = in_range(u, c1 + 1, n1);
-        const bool okh = in_range(u, c1, nh);
-        const bool okd = in_range(u, c2 + 1, n2);
-        const int Hu = okv ? rH : kNeg, Fu = okv ? rF : kNeg;
-        const int Hl = okh ? H1 : kNeg, El = okh ? E1 : kNeg;
-        const int Hd = okd ? VH : kNeg;
+        // After every anti-diagonal a lane holds its row's live values or
+        // kNeg, and the band's first row never decreases; so while the two
+        // previous bands are narrower than 64 rows, every lane (and its
+        // rotation) holds exactly the predecessor row it needs, or kNeg when
+        // that row was not computed.  Only a band of 64 rows reuses a lane
+        // for another row, and then the ranges are checked.
+        int Hu = rH, Fu = rF, Hl = H1, El = E1, Hd = VH;
+        if (n1 == kWave || n2 == kWave) {
+            const int nh = uni(max(min(c1 + n1, d) - c1, 0));  // rows of d-1 in [c1, d-1]
+            const bool okv = in_range(u, c1 + 1, n1);
+            const bool okh = in_range(u, c1, nh);
+            const bool okd = in_range(u, c2 + 1, n2);
+            Hu = okv ? rH : kNeg;
+            Fu = okv ? rF : kNeg;
+            Hl = okh ? H1 : kNeg;
+            El = okh ? E1 : kNeg;
+            Hd = okd ? VH : kNeg;
+        }
         const unsigned sHd = VSH;
         VH = rH;
         VSH = rSH;

@@ -104,6 +104,7 @@ struct pastis_ctx {
     bool have_candidates = false;
     bool records_internal = false;  // the current alignment's records feed edges only
     int last_max16 = 0;             // the last SW call ran 16-bit pass-1 bins up to this R
+    uint64_t last_n_dir = 0;        // directional entries of the last candidate discovery
     pastis_tuning tune{16, 50, 1, 1, 0, {0, 0, 0}};
     // learned filter
     pastis::MlpState mlp{};

@@ -284,7 +284,15 @@ pastis_status discover(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, 
     sp.global_blocks = (int)std::max<int64_t>(8, std::min<int64_t>(512, (int64_t)(8ll << 30) / (24ll * gcap)));
     PASTIS_TRY(get(ctx, kDGtab, (size_t)sp.global_blocks * gcap, &sp.gtables));
     PASTIS_TRY(get(ctx, kDGcand, (size_t)sp.global_blocks * 2 * gcap, &sp.gcand));
-    uint32_t cap = (uint32_t)std::min<int64_t>(std::max<int64_t>(4 * n, 1 << 20), (int64_t)1 << 31);
+    // Room for the directional entries: every entry takes at least ck_min
+    // products, so products / ck_min bounds them; that bound is used when its
+    // buffers stay within 6 GiB (24 bytes an entry), else the last call's
+    // count plus a quarter.  A run that still overflows is redone with room
+    // for all of its entries.
+    const uint64_t dir_ub = prods / (uint64_t)std::max(1, sp.ck) + 1024;
+    uint64_t want = std::max<uint64_t>({(uint64_t)4 * n, 1ull << 20, ctx->last_n_dir + ctx->last_n_dir / 4});
+    if (dir_ub <= (1ull << 28)) want = std::max(want, dir_ub);
+    uint32_t cap = (uint32_t)std::min<uint64_t>({want, dir_ub, 0xFFFFFFF0ull});
     for (;;) {
         sp.cap = cap;
         PASTIS_TRY(get(ctx, kDDirKey, cap, &sp.d_key));
@@ -306,6 +314,7 @@ pastis_status discover(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, 
     }
     uint32_t n_dir = 0;
     PASTIS_TRY(read_device(ctx, M.d_count, &n_dir, sizeof(n_dir), s));
+    ctx->last_n_dir = n_dir;
 
     // ---- symmetrise, sort, threshold already applied
     SymArgs sy{};

@@ -32,7 +32,6 @@ namespace {
 
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr int kChunk = 512;
-constexpr int kCandCap = 512;
 constexpr int kThreads = 256;
 
 __device__ __forceinline__ uint32_t hash32(uint32_t x) { return x * 0x9E3779B1u; }
@@ -169,21 +168,28 @@ __device__ __forceinline__ void expand_row(const RowView &rv, const Postings &P,
 
 // ------------------------------------------------------------ LDS kernel
 
-template <int CAP>
+// CAP slots for rows of at most 3/4 CAP products (so at most that many keys
+// and counts below 2^14), and up to CC candidates, each staged as one word
+// (j << 14 | count).  A row's candidates take consecutive output entries,
+// reserved by one atomic; their two smallest seed keys are kept in place in
+// the output arrays.
+template <int CAP, int CC>
 struct RowLds {
     uint32_t slot[CAP];  // (j << 14) | count, then (j << 14) | (candidate + 1)
-    uint32_t cj[kCandCap], cc[kCandCap], c1[kCandCap], c2[kCandCap];
+    uint32_t cand[CC];   // (j << 14) | count
     ChunkLds chunk;
     uint32_t ncand;
     uint32_t spill;
+    uint32_t base;
 };
 
-template <int CAP>
+template <int CAP, int CC>
 __global__ __launch_bounds__(kThreads) void spgemm_lds_kernel(RowView rv, Postings P, const int *__restrict__ idx,
                                                               const int *__restrict__ starts, int bin, int ck,
                                                               Emit em, uint32_t *__restrict__ spill_rows,
                                                               uint32_t *__restrict__ spill_count) {
-    __shared__ RowLds<CAP> L;
+    static_assert(CC < (1 << 14), "candidate tags fit 14 bits");
+    __shared__ RowLds<CAP, CC> L;
     constexpr uint32_t mask = CAP - 1;
     for (int t = threadIdx.x; t < CAP; t += kThreads) L.slot[t] = kEmpty;
     if (threadIdx.x == 0) {
@@ -221,11 +227,8 @@ __global__ __launch_bounds__(kThreads) void spgemm_lds_kernel(RowView rv, Postin
             uint32_t tag = 0;
             if (c >= (uint32_t)ck) {
                 const uint32_t q = atomicAdd(&L.ncand, 1u);
-                if (q < kCandCap) {
-                    L.cj[q] = j;
-                    L.cc[q] = c;
-                    L.c1[q] = kEmpty;
-                    L.c2[q] = kEmpty;
+                if (q < (uint32_t)CC) {
+                    L.cand[q] = v;
                     tag = q + 1;
                 } else {
                     L.spill = 1;
@@ -238,20 +241,42 @@ __global__ __launch_bounds__(kThreads) void spgemm_lds_kernel(RowView rv, Postin
             // too many candidates for this table: the global path redoes the row
             if (threadIdx.x == 0) spill_rows[atomicAdd(spill_count, 1u)] = i;
         } else if (L.ncand > 0) {
-            // phase 2: seeds of candidate entries
-            expand_row(rv, P, i, L.chunk, [&](uint32_t pi, uint32_t j, uint32_t pj) {
-                if (j == i || (exact && j < i)) return;
-                uint32_t h = hash32(j) & mask;
-                uint32_t v = L.slot[h];
-                while ((v >> 14) != j) {
-                    h = (h + 1) & mask;
-                    v = L.slot[h];
+            const uint32_t nc = L.ncand;
+            if (threadIdx.x == 0) {
+                uint32_t b = atomicAdd(em.count, nc);
+                if (b + (uint64_t)nc > em.cap) {
+                    atomicOr(em.overflow, 1u);  // the call is redone with more room
+                    b = kEmpty;
                 }
-                const uint32_t tag = v & 0x3FFFu;
-                if (tag) seed_min2(&L.c1[tag - 1], &L.c2[tag - 1], seed_key(i, j, pi, pj));
-            });
+                L.base = b;
+            }
             __syncthreads();
-            for (uint32_t q = threadIdx.x; q < L.ncand; q += kThreads) emit(em, i, L.cj[q], L.cc[q], L.c1[q], L.c2[q]);
+            const uint32_t base = L.base;
+            if (base != kEmpty) {
+                for (uint32_t q = threadIdx.x; q < nc; q += kThreads) {
+                    const uint32_t v = L.cand[q], j = v >> 14;
+                    const uint32_t lo = i < j ? i : j, hi = i < j ? j : i;
+                    em.key[base + q] = ((uint64_t)lo << em.nbits) | hi;
+                    em.cnt[base + q] = v & 0x3FFFu;
+                    em.s1[base + q] = kEmpty;
+                    em.s2[base + q] = kEmpty;
+                    em.dir[base + q] = i < j ? 0u : 1u;
+                }
+                __threadfence_block();
+                __syncthreads();
+                // phase 2: seeds of candidate entries
+                expand_row(rv, P, i, L.chunk, [&](uint32_t pi, uint32_t j, uint32_t pj) {
+                    if (j == i || (exact && j < i)) return;
+                    uint32_t h = hash32(j) & mask;
+                    uint32_t v = L.slot[h];
+                    while ((v >> 14) != j) {
+                        h = (h + 1) & mask;
+                        v = L.slot[h];
+                    }
+                    const uint32_t tag = v & 0x3FFFu;
+                    if (tag) seed_min2(&em.s1[base + tag - 1], &em.s2[base + tag - 1], seed_key(i, j, pi, pj));
+                });
+            }
         }
         __syncthreads();
         for (int t = threadIdx.x; t < CAP; t += kThreads) L.slot[t] = kEmpty;
@@ -405,15 +430,17 @@ struct LdsSlots {
     __device__ void vmin(uint32_t h, uint32_t dp) { atomicMin(&v[h], dp); }
 };
 
+// CAP slots (8 bytes each) for rows of at most 3/4 CAP entries
+template <int CAP>
 __global__ __launch_bounds__(kThreads) void as_lds_kernel(AsIn in, const int *__restrict__ idx,
                                                           const int *__restrict__ starts, int bin,
                                                           const uint64_t *__restrict__ as_start,
                                                           uint32_t *__restrict__ as_len, uint32_t *__restrict__ as_s,
                                                           uint32_t *__restrict__ as_dp) {
-    __shared__ uint32_t K[kAsCap], V[kAsCap];
+    __shared__ uint32_t K[CAP], V[CAP];
     __shared__ uint32_t n_out;
     LdsSlots tab{K, V};
-    for (int t = threadIdx.x; t < kAsCap; t += kThreads) {
+    for (int t = threadIdx.x; t < CAP; t += kThreads) {
         K[t] = kEmpty;
         V[t] = kEmpty;
     }
@@ -422,10 +449,10 @@ __global__ __launch_bounds__(kThreads) void as_lds_kernel(AsIn in, const int *__
     const int end = starts[bin + 1];
     for (int w = starts[bin] + blockIdx.x; w < end; w += gridDim.x) {
         const uint32_t i = (uint32_t)idx[w];
-        as_reduce(in, i, tab, kAsCap - 1);
+        as_reduce(in, i, tab, CAP - 1);
         __syncthreads();
         const uint64_t base = as_start[i];
-        for (int t = threadIdx.x; t < kAsCap; t += kThreads) {
+        for (int t = threadIdx.x; t < CAP; t += kThreads) {
             if (K[t] == kEmpty) continue;
             const uint32_t q = atomicAdd(&n_out, 1u);
             as_s[base + q] = K[t];
@@ -499,8 +526,10 @@ __global__ void as_ub_kernel(AsIn in, int64_t n, uint32_t *__restrict__ ub, uint
         for (uint32_t x = in.row_start[i]; x < in.row_start[i + 1]; ++x) s += in.s_cnt[in.row_u[x]];
         ub[i] = s;
         as_len[i] = 0;
-        bin_of[i] = s == 0 ? (int8_t)-1 : (s * 4u <= (uint32_t)kAsCap * 3u ? (int8_t)0 : (int8_t)1);
-        if (s * 4u > (uint32_t)kAsCap * 3u) atomicMax(max_ub, (unsigned long long)s);
+        // bins: 0 = 8192 LDS slots, 1 = 16384 LDS slots, 2 = a table in global memory
+        const int8_t bin = s * 4u <= (uint32_t)kAsCap * 3u ? 0 : s * 4u <= (uint32_t)kAsCap * 6u ? 1 : 2;
+        bin_of[i] = s == 0 ? (int8_t)-1 : bin;
+        if (bin == 2) atomicMax(max_ub, (unsigned long long)s);
     }
 }
 
@@ -526,10 +555,12 @@ __global__ void work_kernel(RowView rv, Postings P, int64_t n, int n_big_ok, uin
             bin = 0;  // 8192 slots
         else if (n_big_ok && w <= 12288)
             bin = 1;  // 16384 slots
+        else if (n_big_ok && w <= 24576)
+            bin = 2;  // 32768 slots
         else
             bin = -1;
         bin_of[i] = bin;
-        if (w > 0 && (!n_big_ok || w > 12288)) {
+        if (w > 0 && (!n_big_ok || w > 24576)) {
             big_rows[atomicAdd(n_big, 1u)] = (uint32_t)i;
             atomicMax(max_big, (unsigned long long)w);
         }
@@ -601,16 +632,21 @@ hipError_t as_stage(const AsArgs &a, hipStream_t s) {
     if ((e = hipGetLastError()) != hipSuccess) return e;
     e = exclusive_scan<uint32_t, uint64_t>(a.ub, a.n, a.as_start, a.as_start + a.n, a.scan_temp, s);
     if (e != hipSuccess) return e;
-    return launch_bins(a.bin_of, a.n, 2, a.bins.counts, a.bins.starts, a.bins.cursor, a.bins.idx, s);
+    return launch_bins(a.bin_of, a.n, 3, a.bins.counts, a.bins.starts, a.bins.cursor, a.bins.idx, s);
 }
 
 hipError_t as_run(const AsArgs &a, uint32_t gcap, hipStream_t s) {
     AsIn in{a.kt->row_start, a.kt->row_u, a.kt->row_pos, a.s_u, a.s_d, a.s_cnt, a.W};
-    as_lds_kernel<<<512, kThreads, 0, s>>>(in, a.bins.idx, a.bins.starts, 0, a.as_start, a.as_len, a.as_s, a.as_dp);
+    // LDS per block: 64 KB (two blocks per CU), 128 KB (one)
+    as_lds_kernel<kAsCap><<<512, kThreads, 0, s>>>(in, a.bins.idx, a.bins.starts, 0, a.as_start, a.as_len, a.as_s,
+                                                   a.as_dp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    as_lds_kernel<2 * kAsCap><<<256, kThreads, 0, s>>>(in, a.bins.idx, a.bins.starts, 1, a.as_start, a.as_len,
+                                                       a.as_s, a.as_dp);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     if (gcap > 0) {
-        as_global_kernel<<<a.global_blocks, kThreads, 0, s>>>(in, a.bins.idx, a.bins.starts, 1, a.as_start, a.as_len,
+        as_global_kernel<<<a.global_blocks, kThreads, 0, s>>>(in, a.bins.idx, a.bins.starts, 2, a.as_start, a.as_len,
                                                                a.as_s, a.as_dp, a.gtables, gcap);
         e = hipGetLastError();
     }
@@ -627,7 +663,7 @@ hipError_t spgemm_plan(const SpgemmArgs &a, hipStream_t s) {
     work_kernel<<<grid_for(a.n), 256, 0, s>>>(rv, P, a.n, a.n < (1ll << 18) ? 1 : 0, a.work, a.bin_of, a.max_big,
                                                a.big_rows, a.n_big, a.products);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    return launch_bins(a.bin_of, a.n, 2, a.bins.counts, a.bins.starts, a.bins.cursor, a.bins.idx, s);
+    return launch_bins(a.bin_of, a.n, 3, a.bins.counts, a.bins.starts, a.bins.cursor, a.bins.idx, s);
 }
 
 hipError_t spgemm_run(const SpgemmArgs &a, uint32_t gcap, hipStream_t s) {
@@ -638,11 +674,15 @@ hipError_t spgemm_run(const SpgemmArgs &a, uint32_t gcap, hipStream_t s) {
     if ((e = fill<uint32_t>(a.d_count, 1, 0u, s)) != hipSuccess) return e;
     if ((e = fill<uint32_t>(a.d_overflow, 1, 0u, s)) != hipSuccess) return e;
     // spilled rows (too many candidates for LDS) join the big-row list
-    spgemm_lds_kernel<8192><<<768, kThreads, 0, s>>>(rv, P, a.bins.idx, a.bins.starts, 0, a.ck, em, a.big_rows,
-                                                      a.n_big);
+    // LDS per block: 51 KB (three blocks per CU), 78 KB (two), 150 KB (one)
+    spgemm_lds_kernel<8192, 3072><<<768, kThreads, 0, s>>>(rv, P, a.bins.idx, a.bins.starts, 0, a.ck, em,
+                                                            a.big_rows, a.n_big);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    spgemm_lds_kernel<16384><<<512, kThreads, 0, s>>>(rv, P, a.bins.idx, a.bins.starts, 1, a.ck, em, a.big_rows,
-                                                       a.n_big);
+    spgemm_lds_kernel<16384, 2048><<<512, kThreads, 0, s>>>(rv, P, a.bins.idx, a.bins.starts, 1, a.ck, em,
+                                                             a.big_rows, a.n_big);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    spgemm_lds_kernel<32768, 4096><<<256, kThreads, 0, s>>>(rv, P, a.bins.idx, a.bins.starts, 2, a.ck, em,
+                                                             a.big_rows, a.n_big);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (gcap > 0) {
         spgemm_global_kernel<<<a.global_blocks, kThreads, 0, s>>>(rv, P, a.big_rows, a.n_big, a.work, a.ck, em,

@@ -73,6 +73,17 @@ def test_exact_large_rows_use_global_tables(gpu, orc):
     _compare(_gpu_candidates(gpu, s.residues, s.offsets, k=3, ck_min=1), want)
 
 
+@pytest.mark.parametrize("ck", [1, 2])
+def test_exact_rows_of_every_table_size(gpu, orc, ck):
+    """Posting lists of ~1,600 entries: rows of 3 to 38 k-mers span every
+    table size (8K, 16K and 32K LDS slots, global memory), and most rows have
+    more candidates than their LDS table stages, so the global redo of
+    those rows is exercised too."""
+    s = _random_set(91 + ck, 5000, 3, 40, "ACDE")
+    want = orc.candidates(orc.encode(s.residues), s.offsets, 3, ck_min=ck)
+    _compare(_gpu_candidates(gpu, s.residues, s.offsets, k=3, ck_min=ck), want)
+
+
 @pytest.mark.parametrize("k,m,ck,alpha", [(3, 5, 2, 20), (4, 10, 2, 20), (6, 25, 2, 20), (3, 8, 1, 24)])
 def test_substitutes(gpu, orc, k, m, ck, alpha):
     from synth import workload

@@ -519,11 +519,18 @@ __global__ __launch_bounds__(kThreads) void as_global_kernel(AsIn in, const int 
 
 // upper bound of (A S)_i entries = sum of present S-row sizes of i's k-mers;
 // every row's length starts at 0 (rows without k-mers are never filled)
-__global__ void as_ub_kernel(AsIn in, int64_t n, uint32_t *__restrict__ ub, uint32_t *__restrict__ as_len,
-                             int8_t *__restrict__ bin_of, unsigned long long *__restrict__ max_ub) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+// (one wave per row: lanes stride the row's k-mers, then a wave sum)
+__global__ __launch_bounds__(256) void as_ub_kernel(AsIn in, int64_t n, uint32_t *__restrict__ ub,
+                                                    uint32_t *__restrict__ as_len, int8_t *__restrict__ bin_of,
+                                                    unsigned long long *__restrict__ max_ub) {
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / 64);
+    for (int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; i < n; i += waves) {
         uint32_t s = 0;
-        for (uint32_t x = in.row_start[i]; x < in.row_start[i + 1]; ++x) s += in.s_cnt[in.row_u[x]];
+        for (uint32_t x = in.row_start[i] + lane; x < in.row_start[i + 1]; x += 64) s += in.s_cnt[in.row_u[x]];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += (uint32_t)__shfl_xor((int)s, off, 64);
+        if (lane != 0) continue;
         ub[i] = s;
         as_len[i] = 0;
         // bins: 0 = 8192 LDS slots, 1 = 16384 LDS slots, 2 = a table in global memory
@@ -533,19 +540,30 @@ __global__ void as_ub_kernel(AsIn in, int64_t n, uint32_t *__restrict__ ub, uint
     }
 }
 
-// products of row i (postings visited), and the row's bin
-__global__ void work_kernel(RowView rv, Postings P, int64_t n, int n_big_ok, uint64_t *__restrict__ work,
-                            int8_t *__restrict__ bin_of, unsigned long long *__restrict__ max_big,
-                            uint32_t *__restrict__ big_rows, uint32_t *__restrict__ n_big,
-                            unsigned long long *__restrict__ products) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+// products of row i (postings visited), and the row's bin; one wave per row
+// (lanes stride the row's entries, then a wave sum)
+__global__ __launch_bounds__(256) void work_kernel(RowView rv, Postings P, int64_t n, int n_big_ok,
+                                                   uint64_t *__restrict__ work, int8_t *__restrict__ bin_of,
+                                                   unsigned long long *__restrict__ max_big,
+                                                   uint32_t *__restrict__ big_rows, uint32_t *__restrict__ n_big,
+                                                   unsigned long long *__restrict__ products) {
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / 64);
+    for (int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; i < n; i += waves) {
         uint64_t b, e;
         rv.bounds((uint32_t)i, b, e);
         uint64_t w = 0;
-        for (uint64_t x = b; x < e; ++x) {
+        for (uint64_t x = b + lane; x < e; x += 64) {
             const uint32_t s = rv.ent_s[x];
             w += P.uk_start[s + 1] - P.uk_start[s];
         }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)w, off, 64);
+            const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(w >> 32), off, 64);
+            w += ((uint64_t)hi << 32) | lo;
+        }
+        if (lane != 0) continue;
         work[i] = w;
         if (w) atomicAdd(products, (unsigned long long)w);
         int8_t bin;
@@ -628,7 +646,7 @@ hipError_t as_stage(const AsArgs &a, hipStream_t s) {
     AsIn in{a.kt->row_start, a.kt->row_u, a.kt->row_pos, a.s_u, a.s_d, a.s_cnt, a.W};
     hipError_t e;
     if ((e = fill<unsigned long long>(a.max_ub, 1, 0ull, s)) != hipSuccess) return e;
-    as_ub_kernel<<<grid_for(a.n), 256, 0, s>>>(in, a.n, a.ub, a.as_len, a.bin_of, a.max_ub);
+    as_ub_kernel<<<grid_for(64 * a.n), 256, 0, s>>>(in, a.n, a.ub, a.as_len, a.bin_of, a.max_ub);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     e = exclusive_scan<uint32_t, uint64_t>(a.ub, a.n, a.as_start, a.as_start + a.n, a.scan_temp, s);
     if (e != hipSuccess) return e;
@@ -660,8 +678,8 @@ hipError_t spgemm_plan(const SpgemmArgs &a, hipStream_t s) {
     if ((e = fill<unsigned long long>(a.max_big, 1, 0ull, s)) != hipSuccess) return e;
     if ((e = fill<uint32_t>(a.n_big, 2, 0u, s)) != hipSuccess) return e;
     if ((e = fill<unsigned long long>(a.products, 1, 0ull, s)) != hipSuccess) return e;
-    work_kernel<<<grid_for(a.n), 256, 0, s>>>(rv, P, a.n, a.n < (1ll << 18) ? 1 : 0, a.work, a.bin_of, a.max_big,
-                                               a.big_rows, a.n_big, a.products);
+    work_kernel<<<grid_for(64 * a.n), 256, 0, s>>>(rv, P, a.n, a.n < (1ll << 18) ? 1 : 0, a.work, a.bin_of,
+                                                   a.max_big, a.big_rows, a.n_big, a.products);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return launch_bins(a.bin_of, a.n, 3, a.bins.counts, a.bins.starts, a.bins.cursor, a.bins.idx, s);
 }

@@ -1070,35 +1070,16 @@ __global__ void sw_bin1_kernel(const PairDesc *__restrict__ pairs, int64_t npair
     }
 }
 
-// Records of pairs that need no statistics pass are final here; the others
-// are binned by the height of their end rectangle (counters[3], [4]: pairs
-// and cells of the start-bound pass; counters[1], [2] in full-records mode).
-// stats_mode: 0 = only pairs whose coverage cut can hold, 1 = every aligned
-// pair, 2 = none (the normalised-score weight needs no traceback).
-__global__ void sw_bin2_kernel(const PairDesc *__restrict__ pairs, SwPass1Out *__restrict__ p1, int64_t npairs,
-                               int cov_pct, int stats_mode, int direct_pct, pastis_pair_record *__restrict__ out,
-                               int8_t *__restrict__ bin_of, unsigned long long *__restrict__ counters) {
-    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= npairs) return;
-    const PairDesc pd = pairs[q];
-    const SwPass1Out r1 = p1[q];
-    // coverage needs span_a >= cov% of la, and span_a <= end_a + 1
-    const bool need = r1.score > 0 && stats_mode != 2 &&
-                      (stats_mode == 1 || 100LL * (r1.end_a + 1) >= (long long)cov_pct * pd.la);
-    if (need) {
-        bin_of[q] = (int8_t)rows_bin(r1.end_a + 1);
-        if (stats_mode == 1) {  // no start bound: every such pair takes pass 2
-            atomicAdd(&counters[1], 1ull);
-            atomicAdd(&counters[2], (unsigned long long)(r1.end_a + 1) * (unsigned long long)(r1.end_b + 1));
-        } else if (100LL * r1.score >= (long long)direct_pct * pd.la) {
-            p1[q].pad = -1;  // likely to pass: no start bound
-        } else {
-            const int cols = r1.end_b >= 0 ? r1.end_b + 1 : pd.lb;
-            atomicAdd(&counters[3], 1ull);
-            atomicAdd(&counters[4], (unsigned long long)(r1.end_a + 1) * (unsigned long long)cols);
-        }
-        return;
-    }
+// Pair and cell counts are summed per block in LDS and added to counters[]
+// once per block (one atomic per pair would serialise on a few addresses).
+__device__ __forceinline__ void flush_counts(unsigned long long (&acc)[4], unsigned long long *counters) {
+    __syncthreads();
+    if (threadIdx.x < 4 && acc[threadIdx.x]) atomicAdd(&counters[1 + threadIdx.x], acc[threadIdx.x]);
+}
+
+// the final record of a pair that takes no statistics pass
+__device__ __forceinline__ void sw_final_record(const PairDesc &pd, const SwPass1Out &r1, int64_t q,
+                                                pastis_pair_record *__restrict__ out, int8_t *__restrict__ bin_of) {
     bin_of[q] = -1;
     pastis_pair_record rec;
     rec.score = r1.score;
@@ -1111,6 +1092,46 @@ __global__ void sw_bin2_kernel(const PairDesc *__restrict__ pairs, SwPass1Out *_
     rec.swapped = pd.swapped;
     rec.cells = (int64_t)pd.la * pd.lb;
     out[q] = rec;
+}
+
+// Records of pairs that need no statistics pass are final here; the others
+// are binned by the height of their end rectangle (counters[3], [4]: pairs
+// and cells of the start-bound pass; counters[1], [2] in full-records mode).
+// stats_mode: 0 = only pairs whose coverage cut can hold, 1 = every aligned
+// pair, 2 = none (the normalised-score weight needs no traceback).
+__global__ __launch_bounds__(256) void sw_bin2_kernel(const PairDesc *__restrict__ pairs,
+                                                      SwPass1Out *__restrict__ p1, int64_t npairs, int cov_pct,
+                                                      int stats_mode, int direct_pct,
+                                                      pastis_pair_record *__restrict__ out,
+                                                      int8_t *__restrict__ bin_of,
+                                                      unsigned long long *__restrict__ counters) {
+    __shared__ unsigned long long acc[4];  // counters[1..4]
+    if (threadIdx.x < 4) acc[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < npairs) {
+        const PairDesc pd = pairs[q];
+        const SwPass1Out r1 = p1[q];
+        // coverage needs span_a >= cov% of la, and span_a <= end_a + 1
+        const bool need = r1.score > 0 && stats_mode != 2 &&
+                          (stats_mode == 1 || 100LL * (r1.end_a + 1) >= (long long)cov_pct * pd.la);
+        if (need) {
+            bin_of[q] = (int8_t)rows_bin(r1.end_a + 1);
+            if (stats_mode == 1) {  // no start bound: every such pair takes pass 2
+                atomicAdd(&acc[0], 1ull);
+                atomicAdd(&acc[1], (unsigned long long)(r1.end_a + 1) * (unsigned long long)(r1.end_b + 1));
+            } else if (100LL * r1.score >= (long long)direct_pct * pd.la) {
+                p1[q].pad = -1;  // likely to pass: no start bound
+            } else {
+                const int cols = r1.end_b >= 0 ? r1.end_b + 1 : pd.lb;
+                atomicAdd(&acc[2], 1ull);
+                atomicAdd(&acc[3], (unsigned long long)(r1.end_a + 1) * (unsigned long long)cols);
+            }
+        } else {
+            sw_final_record(pd, r1, q, out, bin_of);
+        }
+    }
+    flush_counts(acc, counters);
 }
 
 // ---------------------------------------------------------------- start bound
@@ -1307,33 +1328,29 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_bound_kernel(const uint8_t *
 // Pairs binned for the statistics pass whose coverage bound already fails
 // get their final record here; the rest keep their bin.  counters[1] and [2]
 // count the pairs and cells left for pass 2.
-__global__ void sw_bin3_kernel(const PairDesc *__restrict__ pairs, const SwPass1Out *__restrict__ p1,
-                               int64_t npairs, int cov_pct, pastis_pair_record *__restrict__ out,
-                               int8_t *__restrict__ bin_of, unsigned long long *__restrict__ counters) {
-    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= npairs || bin_of[q] < 0) return;
-    const PairDesc pd = pairs[q];
-    const SwPass1Out r1 = p1[q];
-    // pad < 0: sent straight here (bound 0 in effect: the coverage test of
-    // the first binning already holds)
-    if (r1.pad < 0 || 100LL * (r1.end_a - r1.pad + 1) >= (long long)cov_pct * pd.la) {
-        const int cols = r1.end_b >= 0 ? r1.end_b + 1 : pd.lb;
-        atomicAdd(&counters[1], 1ull);
-        atomicAdd(&counters[2], (unsigned long long)(r1.end_a + 1) * (unsigned long long)cols);
-        return;
+__global__ __launch_bounds__(256) void sw_bin3_kernel(const PairDesc *__restrict__ pairs,
+                                                      const SwPass1Out *__restrict__ p1, int64_t npairs,
+                                                      int cov_pct, pastis_pair_record *__restrict__ out,
+                                                      int8_t *__restrict__ bin_of,
+                                                      unsigned long long *__restrict__ counters) {
+    __shared__ unsigned long long acc[4];  // counters[1..4]; [1] and [2] here
+    if (threadIdx.x < 4) acc[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < npairs && bin_of[q] >= 0) {
+        const PairDesc pd = pairs[q];
+        const SwPass1Out r1 = p1[q];
+        // pad < 0: sent straight here (bound 0 in effect: the coverage test of
+        // the first binning already holds)
+        if (r1.pad < 0 || 100LL * (r1.end_a - r1.pad + 1) >= (long long)cov_pct * pd.la) {
+            const int cols = r1.end_b >= 0 ? r1.end_b + 1 : pd.lb;
+            atomicAdd(&acc[0], 1ull);
+            atomicAdd(&acc[1], (unsigned long long)(r1.end_a + 1) * (unsigned long long)cols);
+        } else {
+            sw_final_record(pd, r1, q, out, bin_of);
+        }
     }
-    bin_of[q] = -1;
-    pastis_pair_record rec;
-    rec.score = r1.score;
-    rec.beg_a = rec.beg_b = -1;
-    rec.end_a = r1.end_a;
-    rec.end_b = r1.end_b;
-    rec.matches = rec.columns = 0;
-    rec.seed_used = -1;
-    rec.passed = 0;
-    rec.swapped = pd.swapped;
-    rec.cells = (int64_t)pd.la * pd.lb;
-    out[q] = rec;
+    flush_counts(acc, counters);
 }
 
 // ---------------------------------------------------------------- pass 2

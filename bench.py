@@ -43,9 +43,17 @@ OPS_PER_SW_CELL = {(16, False): 10, (16, True): 10, (32, False): 9, (32, True): 
 # dispatch on the mid workload, profiles/sw_search_mid_kernel_stats.md), scaled
 # by what the counters read for a 1 GiB device copy (FETCH x 2.0, WRITE x 1.0);
 # only for kernels unchanged since those counters were taken
-MEASURED_TRAFFIC_KIB = {"sw16s_pass1_kernel<32, 12, 4>": (1249786.75, 105933.594),
-                        "sw16s_pass1_kernel<16, 16, 4>": (1336287.75, 118015.188),
-                        "sw16_pass1_kernel<9, 4, false>": (605403.938, 53349.906)}
+MEASURED_TRAFFIC_KIB = {"sw16s_pass1_kernel<32, 12, 4>": (1246447.938, 129420.594),
+                        "sw16s_pass1_kernel<16, 16, 4>": (1311777.312, 130501.812),
+                        "sw16_pass1_kernel<9, 4, false>": (592888.875, 58662.781)}
+# the same counters for the product kernels of candidate discovery (one launch
+# of each per step on the mid workload): their posting reads are scattered
+# (a few bytes per product from lines of 64-128 bytes), so the traffic
+# exceeds the algorithmic bytes many times over
+SPGEMM_TRAFFIC_KIB = {"spgemm_lds_kernel<8192, 3072>": (22683088.438, 1786380.531),
+                      "spgemm_lds_kernel<16384, 2048>": (20538483.188, 2089386.625),
+                      "spgemm_lds_kernel<32768, 4096>": (8515256.438, 1052616.625),
+                      "spgemm_global_kernel": (2528738.0, 1480944.656)}
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
 # method parameters of each workload (Section VI settings: BLOSUM62, gaps
@@ -283,9 +291,15 @@ def main():
     n_cand = int(st["n_candidates"])
     pass1_ms = stage[5] / args.steps
 
-    # the dominant kernel: the pass-1 length bin with the most device time
-    # (one launch per step), its own cells over its own HIP-event time
-    dom = max(st["sw_bins"], key=lambda b: b["ms"])
+    def ops(b):
+        return OPS_PER_SW_CELL[(b["bits"], bool(b["multi_strip"]))]
+
+    # the dominant kernel: the pass-1 length bin with the most DP work (cells x
+    # ops per cell; one launch per step), its own cells over its own HIP-event
+    # time.  Chosen by work, not by event time: the multi-strip bins run on a
+    # second stream beside the one-strip bins, so their event spans include
+    # time shared with other kernels.
+    dom = max(st["sw_bins"], key=lambda b: b["cells"] * ops(b))
     R = dom["rows_per_lane"]
     if dom["bits"] == 16:
         if dom["multi_strip"]:
@@ -300,8 +314,6 @@ def main():
     else:
         dom_name = "sw_pass1_kernel<%d, %s>" % (R, "true" if dom["multi_strip"] else "false")
         peak = PEAK_INT32_TOPS
-    def ops(b):
-        return OPS_PER_SW_CELL[(b["bits"], bool(b["multi_strip"]))]
 
     achieved = dom["cells"] * ops(dom) / (dom["ms"] * 1e-3) / 1e12
     pass1_ops = sum(b["cells"] * ops(b) for b in st["sw_bins"])
@@ -350,6 +362,10 @@ def main():
             "achieved_gb_s": 6 * st["spgemm_products"] / (stage[3] / args.steps * 1e-3) / 1e9,
             "peak_gb_s": PEAK_HBM_GBS,
             "frac": 6 * st["spgemm_products"] / (stage[3] / args.steps * 1e-3) / 1e9 / PEAK_HBM_GBS,
+            # counted HBM traffic of the product kernels (FETCH_SIZE / WRITE_SIZE,
+            # scaled as above; mid workload only) over the stage time
+            "traffic": (None if args.workload != "mid" or args.families is not None else
+                        1024 * sum(FETCH_SCALE * f + WRITE_SCALE * w for f, w in SPGEMM_TRAFFIC_KIB.values())),
         },
         "roofline": {
             "kernel": dom_name,
@@ -358,7 +374,8 @@ def main():
             "peak": peak,
             "unit": "Tops/s",
             "frac": achieved / peak,
-            "traffic": (None if dom_name not in MEASURED_TRAFFIC_KIB or args.workload != "mid" else
+            "traffic": (None if dom_name not in MEASURED_TRAFFIC_KIB or args.workload != "mid"
+                        or args.families is not None else
                         1024 * (FETCH_SCALE * MEASURED_TRAFFIC_KIB[dom_name][0] +
                                 WRITE_SCALE * MEASURED_TRAFFIC_KIB[dom_name][1])),
             "kernel_ms": dom["ms"],

@@ -673,11 +673,15 @@ __global__ __launch_bounds__(64 * WPB) void sw16_pass1_kernel(const uint8_t *__r
                     M[r] = 0u;
                 }
                 uint32_t glast = G0, flast = 0u, gprev = G0;
-                int cres = kPadCode | (kPadCode << 8);
+                // column residues travel as byte offsets into the profile, P's
+                // in the low half and Q's in the high half (at most 24 * 1024)
+                constexpr uint32_t kStride = (uint32_t)(sizeof(ProfWord<R>) * kWave);
+                const char *plane = (const char *)&prof[0][lane];
+                int cres = (int)((kPadCode * kStride) * 0x10001u);
                 auto col = [&](int c) {
-                    const int x = c < lbP ? (int)bP[c] : kPadCode;
-                    const int y = c < lbQ ? (int)bQ[c] : kPadCode;
-                    return x | (y << 8);
+                    const uint32_t x = c < lbP ? (uint32_t)bP[c] : (uint32_t)kPadCode;
+                    const uint32_t y = c < lbQ ? (uint32_t)bQ[c] : (uint32_t)kPadCode;
+                    return (int)((x * kStride) | ((y * kStride) << 16));
                 };
                 int chunk = col(lane);  // columns 0..63; nx holds the next 64
                 int nx = col(kWave + lane);
@@ -718,8 +722,8 @@ __global__ __launch_bounds__(64 * WPB) void sw16_pass1_kernel(const uint8_t *__r
                         rf = (uint32_t)shr1z((int)flast);
                     }
                     cres = shr1(bt, cres);
-                    const ProfWord<R> cP = prof[cres & 0xFF][lane];
-                    const ProfWord<R> cQ = prof[(cres >> 8) & 0xFF][lane];
+                    const ProfWord<R> cP = *(const ProfWord<R> *)(plane + ((uint32_t)cres & 0xFFFFu));
+                    const ProfWord<R> cQ = *(const ProfWord<R> *)(plane + ((uint32_t)cres >> 16));
                     short2_t gd = s2(gprev), gu = s2(rg), fu = s2(rf);
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
@@ -822,8 +826,10 @@ __device__ __forceinline__ uint32_t strip_shr(uint32_t first, uint32_t v, int la
     if constexpr (S == 16) {
         return (uint32_t)__builtin_amdgcn_update_dpp((int)first, (int)v, kDppRowShr1, 0xF, 0xF, false);
     } else {
-        const uint32_t t = (uint32_t)__builtin_amdgcn_update_dpp((int)first, (int)v, kDppWaveShr1, 0xF, 0xF, false);
-        return lane == kWave / 2 ? first : t;
+        // a zero-filled shift writes every lane (no prior value of the result
+        // is needed); the strips' first lanes, 0 and 32, then take `first`
+        const uint32_t t = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppWaveShr1, 0xF, 0xF, true);
+        return (lane & (S - 1)) == 0 ? first : t;
     }
 }
 
@@ -918,12 +924,17 @@ __global__ __launch_bounds__(64 * WPB) void sw16s_pass1_kernel(const uint8_t *__
                 M[r] = 0u;
             }
             uint32_t glast = G0, flast = 0u, gprev = G0;
-            uint32_t cres = kPadCode | (kPadCode << 8);
+            // column residues travel as byte offsets into the profile, P's in
+            // the low half and Q's in the high half (at most 24 * 512 bytes)
+            constexpr uint32_t kStride = (uint32_t)(sizeof(ProfWord<RP>) * S);
+            const char *plane = (const char *)&prof[0][pos];
+            uint32_t cres = (kPadCode * kStride) * 0x10001u;
             auto col = [&](int c) -> uint32_t {
-                const int x = c < lbP ? (int)bP[c] : kPadCode;
-                const int y = c < lbQ ? (int)bQ[c] : kPadCode;
-                return (uint32_t)(x | (y << 8));
+                const uint32_t x = c < lbP ? (uint32_t)bP[c] : (uint32_t)kPadCode;
+                const uint32_t y = c < lbQ ? (uint32_t)bQ[c] : (uint32_t)kPadCode;
+                return (x * kStride) | ((y * kStride) << 16);
             };
+            auto at = [&](uint32_t off) { return *(const ProfWord<RP> *)(plane + off); };
             uint32_t chunk = col(cl);  // columns 0..15; nx holds the next 16
             uint32_t nx = col(16 + cl);
             // the residues of step tn enter at each strip's first lane
@@ -947,12 +958,12 @@ __global__ __launch_bounds__(64 * WPB) void sw16s_pass1_kernel(const uint8_t *__
                     feed(t + 1);
                     cP = wP;
                     cQ = wQ;
-                    wP = prof[cres & 0xFF][pos];
-                    wQ = prof[(cres >> 8) & 0xFF][pos];
+                    wP = at(cres & 0xFFFFu);
+                    wQ = at(cres >> 16);
                 } else {
                     feed(t);
-                    cP = prof[cres & 0xFF][pos];
-                    cQ = prof[(cres >> 8) & 0xFF][pos];
+                    cP = at(cres & 0xFFFFu);
+                    cQ = at(cres >> 16);
                 }
                 short2_t gd = s2(gprev), gu = s2(rg), fu = s2(rf);
 #pragma unroll
@@ -978,8 +989,8 @@ __global__ __launch_bounds__(64 * WPB) void sw16s_pass1_kernel(const uint8_t *__
             };
             if constexpr (kAhead) {
                 feed(0);
-                wP = prof[cres & 0xFF][pos];
-                wQ = prof[(cres >> 8) & 0xFF][pos];
+                wP = at(cres & 0xFFFFu);
+                wQ = at(cres >> 16);
             }
             int t = 0;
             for (; t + 1 < steps; t += 2) {

@@ -43,17 +43,17 @@ OPS_PER_SW_CELL = {(16, False): 10, (16, True): 10, (32, False): 9, (32, True): 
 # dispatch on the mid workload, profiles/sw_search_mid_kernel_stats.md), scaled
 # by what the counters read for a 1 GiB device copy (FETCH x 2.0, WRITE x 1.0);
 # only for kernels unchanged since those counters were taken
-MEASURED_TRAFFIC_KIB = {"sw16s_pass1_kernel<32, 12, 4>": (1246447.938, 129420.594),
-                        "sw16s_pass1_kernel<16, 16, 4>": (1311777.312, 130501.812),
-                        "sw16_pass1_kernel<9, 4, false>": (592888.875, 58662.781)}
+MEASURED_TRAFFIC_KIB = {"sw16s_pass1_kernel<32, 12, 4>": (1246851.25, 129269.531),
+                        "sw16s_pass1_kernel<16, 16, 4>": (1311538.562, 130976.219),
+                        "sw16_pass1_kernel<9, 4, false>": (592586.188, 58720.5)}
 # the same counters for the product kernels of candidate discovery (one launch
 # of each per step on the mid workload): their posting reads are scattered
 # (a few bytes per product from lines of 64-128 bytes), so the traffic
 # exceeds the algorithmic bytes many times over
-SPGEMM_TRAFFIC_KIB = {"spgemm_lds_kernel<8192, 3072>": (22683088.438, 1786380.531),
-                      "spgemm_lds_kernel<16384, 2048>": (20538483.188, 2089386.625),
-                      "spgemm_lds_kernel<32768, 4096>": (8515256.438, 1052616.625),
-                      "spgemm_global_kernel": (2528738.0, 1480944.656)}
+SPGEMM_TRAFFIC_KIB = {"spgemm_lds_kernel<8192, 3072>": (22681976.375, 1786420.969),
+                      "spgemm_lds_kernel<16384, 2048>": (20535281.375, 2089283.875),
+                      "spgemm_lds_kernel<32768, 4096>": (8518133.125, 1052639.531),
+                      "spgemm_global_kernel": (2528286.188, 1480974.312)}
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
 # method parameters of each workload (Section VI settings: BLOSUM62, gaps

@@ -168,11 +168,12 @@ __device__ __forceinline__ void expand_row(const RowView &rv, const Postings &P,
 
 // ------------------------------------------------------------ LDS kernel
 
-// CAP slots for rows of at most 3/4 CAP products (so at most that many keys
-// and counts below 2^14), and up to CC candidates, each staged as one word
-// (j << 14 | count).  A row's candidates take consecutive output entries,
-// reserved by one atomic; their two smallest seed keys are kept in place in
-// the output arrays.
+// CAP slots for rows of at most 3/4 CAP products (so at most that many keys),
+// and up to CC candidates, each staged as one word (j << 14 | count).  A
+// count that would pass 2^14 - 1 (possible only where a row has more products
+// than that) or more than CC candidates send the row to the global path.  A
+// row's candidates take consecutive output entries, reserved by one atomic;
+// their two smallest seed keys are kept in place in the output arrays.
 template <int CAP, int CC>
 struct RowLds {
     uint32_t slot[CAP];  // (j << 14) | count, then (j << 14) | (candidate + 1)
@@ -213,7 +214,10 @@ __global__ __launch_bounds__(kThreads) void spgemm_lds_kernel(RowView rv, Postin
                     v = old;
                 }
                 if ((v >> 14) == j) {
-                    atomicAdd(&L.slot[h], 1u);
+                    // a count of 2^14 - 1 carries into j: the row is redone
+                    // with 64-bit slots (the table keeps fewer than CAP keys,
+                    // so later probes still end)
+                    if ((atomicAdd(&L.slot[h], 1u) & 0x3FFFu) == 0x3FFFu) L.spill = 1;
                     return;
                 }
                 h = (h + 1) & mask;

@@ -90,7 +90,13 @@ typedef struct pastis_params {
                                  on a stream of the context, replayed while the pair
                                  count, buffers and schedule are unchanged (per-bin
                                  times are then not recorded); 0: direct launches */
-    int32_t reserved[5];      /* must be zero */
+    int32_t candidate_room;   /* room, in entries, for the directional candidates of a
+                                 discovery (before the two directions merge): 0 sizes it
+                                 automatically (products / ck_min when that fits 2^28
+                                 entries, else the last call's count plus a quarter); a
+                                 discovery that needs more is redone once with room for
+                                 all of its entries.  >= 0 */
+    int32_t reserved[4];      /* must be zero */
 } pastis_params;
 
 /* One similarity edge, 48 bytes.  i < j; edges are sorted by (i, j).

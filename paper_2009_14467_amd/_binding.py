@@ -82,7 +82,8 @@ class _Params(ctypes.Structure):
         ("full_records", ctypes.c_int32),
         ("filter_mode", ctypes.c_int32),
         ("graph_mode", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 5),
+        ("candidate_room", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 
@@ -150,6 +151,7 @@ class Params:
     full_records: bool = False
     filter_mode: str = "none"  # "none" | "mlp" (the learned filter, set with Context.mlp_set)
     graph_mode: bool = False  # replay the alignment stage as a captured HIP graph
+    candidate_room: int = 0  # initial room for directional candidates (0: automatic)
 
     def to_c(self) -> _Params:
         p = _Params()
@@ -168,6 +170,7 @@ class Params:
         p.full_records = int(self.full_records)
         p.filter_mode = {"none": 0, "mlp": 1}[self.filter_mode]
         p.graph_mode = int(self.graph_mode)
+        p.candidate_room = self.candidate_room
         return p
 
 

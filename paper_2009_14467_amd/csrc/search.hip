@@ -292,6 +292,7 @@ pastis_status discover(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, 
     const uint64_t dir_ub = prods / (uint64_t)std::max(1, sp.ck) + 1024;
     uint64_t want = std::max<uint64_t>({(uint64_t)4 * n, 1ull << 20, ctx->last_n_dir + ctx->last_n_dir / 4});
     if (dir_ub <= (1ull << 28)) want = std::max(want, dir_ub);
+    if (P.candidate_room > 0) want = (uint64_t)P.candidate_room;  // the caller's setting
     uint32_t cap = (uint32_t)std::min<uint64_t>({want, dir_ub, 0xFFFFFFF0ull});
     for (;;) {
         sp.cap = cap;

@@ -84,6 +84,32 @@ def test_exact_rows_of_every_table_size(gpu, orc, ck):
     _compare(_gpu_candidates(gpu, s.residues, s.offsets, k=3, ck_min=ck), want)
 
 
+@pytest.mark.parametrize("case", ["exact", "substitutes", "global_rows"])
+def test_redone_with_room_for_every_candidate(gpu, orc, case):
+    """A candidate room far below the directional entries overflows in the
+    LDS and global-table kernels; the discovery is redone with enough room
+    and gives the same candidates."""
+    from synth import workload
+
+    if case == "exact":
+        s, kw = workload("tiny"), dict(k=6, ck_min=1)
+    elif case == "substitutes":
+        s, kw = workload("tiny", n_families=6), dict(k=6, ck_min=2, n_subs=25)
+    else:
+        s, kw = _random_set(77, 300, 100, 400, "AC"), dict(k=3, ck_min=1)
+    want = orc.candidates(orc.encode(s.residues), s.offsets, kw["k"], ck_min=kw["ck_min"],
+                          n_subs=kw.get("n_subs", 0))
+    assert len(want["lo"]) > 1000
+    _compare(_gpu_candidates(gpu, s.residues, s.offsets, candidate_room=64, **kw), want)
+
+
+def test_negative_candidate_room_is_rejected(gpu):
+    import paper_2009_14467_amd as P
+
+    with pytest.raises(P.PastisError):
+        P.Context(P.Params(candidate_room=-1))
+
+
 @pytest.mark.parametrize("k,m,ck,alpha", [(3, 5, 2, 20), (4, 10, 2, 20), (6, 25, 2, 20), (3, 8, 1, 24)])
 def test_substitutes(gpu, orc, k, m, ck, alpha):
     from synth import workload

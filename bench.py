@@ -88,6 +88,8 @@ def parse():
     ap.add_argument("--autotune", action="store_true",
                     help="time schedule settings on a candidate sample first (default: the library's schedule)")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-mode leg")
+    ap.add_argument("--pairs", type=int, default=0,
+                    help="also time the alignment stage alone on this many seeded pairs (0: off)")
     ap.add_argument("--tune-pairs", type=int, default=2_000_000, help="candidate sample size of the autotuner")
     ap.add_argument("--schedule", default=None,
                     help="explicit SW schedule, e.g. sw16_max_rows=16,sw_direct_pct=50,sw_grid_scale=1,"
@@ -173,6 +175,55 @@ def xd_leg(P, args, params, res, off, n_cand):
         "wide_band_redo_ms": xstage[6] / args.steps,
         "align_pairs_per_s": n_cand / ((xstage[5] + xstage[6]) / args.steps * 1e-3),
         "edges": int(xedges.size),
+    }
+
+
+def pairs_leg(P, args, params, fs, res, off, tuning):
+    """The alignment stage alone on a seeded list of --pairs pairs of the
+    workload's sequences (every within-family pair, then uniformly random
+    unrelated pairs, shuffled), through the pair-list entry point: the
+    candidate volume the large configuration expects, which i.i.d. synthetic
+    sequences do not reach through k-mer sharing."""
+    import numpy as np
+    import torch
+
+    from synth.families import pair_list
+
+    lab = fs.labels[fs.labels >= 0]
+    fam = int(sum(c * (c - 1) // 2 for c in np.unique(lab, return_counts=True)[1]))
+    per_seq = max(0.0, (args.pairs - fam) / fs.n) * 1.05 + 1.0  # a little over: duplicates are dropped
+    lo, hi = pair_list(fs, random_per_seq=per_seq, seed=0)
+    rng = np.random.default_rng(np.random.SeedSequence(0, spawn_key=(200,)))
+    sel = rng.permutation(lo.size)[: args.pairs]
+    lo, hi = lo[sel], hi[sel]
+    print(f"bench.py: pair list of {lo.size} pairs ({fam} within families)", file=sys.stderr, flush=True)
+    lens = np.diff(fs.offsets)
+    cells = float((lens[lo].astype(np.float64) * lens[hi].astype(np.float64)).sum())
+    dev = res.device
+    pi = torch.from_numpy(lo.view(np.int32)).to(dev)
+    pj = torch.from_numpy(hi.view(np.int32)).to(dev)
+    # 16-bit pass 1 where the scores fit, as in the search
+    ctx = P.Context(P.Params(score_width=16, **params))
+    if isinstance(tuning, dict):
+        ctx.set_tuning(**{k: tuning[k] for k in ("sw16_max_rows", "sw_direct_pct", "sw_grid_scale",
+                                                  "sw_grid_scale_wide", "sw_intra_pair")})
+    for _ in range(max(args.warmup, 1)):
+        recs = ctx.align_pairs(res, off, pi, pj)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        recs = ctx.align_pairs(res, off, pi, pj)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    passed = int(recs.view(torch.int32).view(-1, 12)[:, 8].sum().item())  # pastis_pair_record.passed
+    return {
+        "pairs": int(lo.size),
+        "family_pairs": fam,
+        "ms_per_step": ms,
+        "pairs_per_s": lo.size / (ms * 1e-3),
+        "gcups": cells / (ms * 1e-3) / 1e9,
+        "cells": cells,
+        "passed": passed,
     }
 
 
@@ -392,6 +443,8 @@ def main():
         line["xd"] = xd_leg(P, args, params, res, off, n_cand)
     if not args.no_mlp:
         line["mlp_filter"] = mlp_leg(P, args, params, over, res, off, edges, ms_step)
+    if args.pairs > 0:
+        line["pair_list"] = pairs_leg(P, args, params, fs, res, off, tuning)
     if not args.no_cpu_baseline:
         c = ctx.candidates(n_cand)
         lo = c["lo"].cpu().numpy().view(np.uint32)

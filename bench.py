@@ -50,10 +50,10 @@ MEASURED_TRAFFIC_KIB = {"sw16s_pass1_kernel<32, 12, 4>": (1246851.25, 129269.531
 # of each per step on the mid workload): their posting reads are scattered
 # (a few bytes per product from lines of 64-128 bytes), so the traffic
 # exceeds the algorithmic bytes many times over
-SPGEMM_TRAFFIC_KIB = {"spgemm_lds_kernel<8192, 3072>": (22682913.375, 1786381.594),
-                      "spgemm_lds_kernel<16384, 2048>": (20538620.875, 2089379.781),
-                      "spgemm_lds_kernel<32768, 4096>": (8517224.750, 1052649.969),
-                      "spgemm_global_kernel": (2530332.062, 1481049.781)}
+SPGEMM_TRAFFIC_KIB = {"spgemm_lds_kernel<8192, 3072>": (18749019.875, 1786354.969),
+                      "spgemm_lds_kernel<16384, 2048>": (16981704.562, 2089405.750),
+                      "spgemm_lds_kernel<32768, 4096>": (7057943.812, 1052681.688),
+                      "spgemm_global_kernel": (2245486.812, 1480966.438)}
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
 # method parameters of each workload (Section VI settings: BLOSUM62, gaps

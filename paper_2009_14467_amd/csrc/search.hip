@@ -71,6 +71,7 @@ enum DiscBuf {
     kDTuneS1,
     kDTuneS2,
     kDTuneRec,
+    kDPostRec,
     kDEnd
 };
 static_assert(kDEnd <= kNumBufs, "buffer ids");
@@ -270,6 +271,8 @@ pastis_status discover(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, 
     sp.max_big = M.max_big;
     sp.products = M.products;
     PASTIS_TRY(get(ctx, kDBigRows, n, &sp.big_rows));
+    PASTIS_TRY(get(ctx, kDPostRec, nnz, &sp.post_rec));
+    sp.nnz = nnz;
     sp.n_big = M.n_big;
     sp.d_count = M.d_count;
     sp.d_overflow = M.d_overflow;

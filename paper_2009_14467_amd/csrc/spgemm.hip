@@ -61,10 +61,12 @@ struct RowView {
     }
 };
 
+// Postings of A^T: uk_start[s] .. uk_start[s + 1] index the (sequence,
+// position) records of k-mer s, one 8-byte record each, so a product reads
+// one line for both.
 struct Postings {
     const uint32_t *uk_start;
-    const uint32_t *seq;
-    const uint16_t *pos;
+    const uint2 *rec;
 };
 
 struct Emit {
@@ -159,8 +161,8 @@ __device__ __forceinline__ void expand_row(const RowView &rv, const Postings &P,
                 else
                     hi = mid;
             }
-            const uint32_t z = C.pbeg[lo] + (p - C.pref[lo]);
-            f(C.epos[lo], P.seq[z], (uint32_t)P.pos[z]);
+            const uint2 r = P.rec[C.pbeg[lo] + (p - C.pref[lo])];
+            f(C.epos[lo], r.x, r.y);
         }
         __syncthreads();
     }
@@ -544,6 +546,12 @@ __global__ __launch_bounds__(256) void as_ub_kernel(AsIn in, int64_t n, uint32_t
     }
 }
 
+__global__ void posting_records_kernel(const uint32_t *__restrict__ seq, const uint16_t *__restrict__ pos, int64_t n,
+                                       uint2 *__restrict__ rec) {
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
+        rec[x] = make_uint2(seq[x], (uint32_t)pos[x]);
+}
+
 // products of row i (postings visited), and the row's bin; one wave per row
 // (lanes stride the row's entries, then a wave sum)
 __global__ __launch_bounds__(256) void work_kernel(RowView rv, Postings P, int64_t n, int n_big_ok,
@@ -677,11 +685,13 @@ hipError_t as_run(const AsArgs &a, uint32_t gcap, hipStream_t s) {
 
 hipError_t spgemm_plan(const SpgemmArgs &a, hipStream_t s) {
     RowView rv{a.row_start32, a.row_start64, a.row_len, a.ent_s, a.ent_pos16, a.ent_dp, a.exact};
-    Postings P{a.kt->uk_start, a.kt->post_seq, a.kt->post_pos};
+    Postings P{a.kt->uk_start, a.post_rec};
     hipError_t e;
     if ((e = fill<unsigned long long>(a.max_big, 1, 0ull, s)) != hipSuccess) return e;
     if ((e = fill<uint32_t>(a.n_big, 2, 0u, s)) != hipSuccess) return e;
     if ((e = fill<unsigned long long>(a.products, 1, 0ull, s)) != hipSuccess) return e;
+    posting_records_kernel<<<grid_for(a.nnz), 256, 0, s>>>(a.kt->post_seq, a.kt->post_pos, a.nnz, a.post_rec);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     work_kernel<<<grid_for(64 * a.n), 256, 0, s>>>(rv, P, a.n, a.n < (1ll << 18) ? 1 : 0, a.work, a.bin_of,
                                                    a.max_big, a.big_rows, a.n_big, a.products);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -690,7 +700,7 @@ hipError_t spgemm_plan(const SpgemmArgs &a, hipStream_t s) {
 
 hipError_t spgemm_run(const SpgemmArgs &a, uint32_t gcap, hipStream_t s) {
     RowView rv{a.row_start32, a.row_start64, a.row_len, a.ent_s, a.ent_pos16, a.ent_dp, a.exact};
-    Postings P{a.kt->uk_start, a.kt->post_seq, a.kt->post_pos};
+    Postings P{a.kt->uk_start, a.post_rec};
     Emit em{a.d_count, a.d_overflow, a.d_key, a.d_cnt, a.d_s1, a.d_s2, a.d_dir, a.cap, a.nbits};
     hipError_t e;
     if ((e = fill<uint32_t>(a.d_count, 1, 0u, s)) != hipSuccess) return e;

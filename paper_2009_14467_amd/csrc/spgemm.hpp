@@ -60,6 +60,9 @@ struct SpgemmArgs {
     unsigned long long *max_big;
     unsigned long long *products;  // postings visited by one pass over the rows
     uint32_t *big_rows, *n_big;  // n_big: 2 counters
+    // the postings of A^T as one (sequence, position) record each (nnz of them)
+    uint2 *post_rec;
+    int64_t nnz;
     // directional entries
     uint32_t *d_count, *d_overflow;
     uint64_t *d_key;

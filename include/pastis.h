@@ -322,7 +322,8 @@ pastis_status pastis_set_tuning(pastis_ctx *ctx, const pastis_tuning *t);
  * start-bound routing, the two grid scales) the alignment of up to max_pairs of the
  * candidates (an even stride through them) under each candidate value, twice,
  * timed with HIP events on the stream; the fastest setting is kept in ctx and
- * written to *out (may be NULL).  The discovery's candidates stay in ctx. */
+ * written to *out (may be NULL).  A value replaces the one in force only when
+ * it is at least 1% faster on the sample.  The discovery's candidates stay in ctx. */
 pastis_status pastis_autotune(pastis_ctx *ctx, const uint8_t *residues, const int64_t *offsets, int64_t n,
                               int input_on_device, int64_t max_pairs, void *stream, pastis_tuning *out);
 

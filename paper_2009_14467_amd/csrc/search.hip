@@ -637,6 +637,9 @@ pastis_status pastis_autotune(pastis_ctx *ctx, const uint8_t *residues, const in
         const int rows16[] = {16, 12, 8, 0};
         const int direct[] = {0, 25, 50, 100, 200, 1 << 20};
         const int grid[] = {1, 2, 4};
+        // a value replaces the one in force only when it is at least 1%
+        // faster on the sample: smaller differences are within timing noise
+        // and need not carry over to the whole candidate set
         auto sweep = [&](int32_t *knob, const int *vals, int nv) -> pastis_status {
             const int32_t keep = *knob;
             int32_t best_v = keep;
@@ -646,7 +649,7 @@ pastis_status pastis_autotune(pastis_ctx *ctx, const uint8_t *residues, const in
                 *knob = vals[i];
                 double ms = 0;
                 PASTIS_TRY(measure(&ms));
-                if (ms < best_ms) {
+                if (ms < 0.99 * best_ms) {
                     best_ms = ms;
                     best_v = vals[i];
                 }

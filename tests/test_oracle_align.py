@@ -3,7 +3,9 @@
 Independent of the oracle's DP: exhaustive enumeration of every alignment of
 tiny sequences (maximum score, canonical end, and the canonical path chosen by
 comparing whole alignments), hand-worked cases, self-alignment, swap symmetry,
-and the XD <= SW bound (every x-drop alignment is a local alignment).
+the XD <= SW bound (every x-drop alignment is a local alignment), and x-drop
+at finite X against a dictionary enumeration of the grid (scores, ends, paths
+and the live-predecessor cell count) plus hand-worked pruning cases.
 """
 
 import functools
@@ -205,6 +207,124 @@ def test_xdrop_stops_on_drop(orc):
     r49 = orc.xdrop_extend(a, b, O, E, 49)
     assert (r49["score"], r49["u"], r49["v"], r49["matches"], r49["columns"]) == (130, 26, 26, 14, 26)
     assert r20["cells"] < r49["cells"]
+
+
+def _xdrop_dense(B, a, b, x):
+    """x-drop extension (Section IV-E) enumerated over a dictionary of every
+    grid cell: anti-diagonal d = u + v visits all of its cells, computes those
+    with a live predecessor, then marks live the computed cells that are not
+    below the best score of the earlier anti-diagonals minus x, and only then
+    raises the best.  Stops at the first anti-diagonal without a live cell.
+    Returns the same fields as the oracle, with the live-predecessor cell count."""
+    neg = -(10**9)
+    la, lb = len(a), len(b)
+    H, Eg, Fg = {(0, 0): 0}, {(0, 0): neg}, {(0, 0): neg}
+    live = {(0, 0)}
+    best, end, cells = 0, (0, 0), 0
+    for d in range(1, la + lb + 1):
+        computed = []
+        for u in range(la + 1):
+            v = d - u
+            if not 0 <= v <= lb:
+                continue
+            up, left, dia = (u - 1, v), (u, v - 1), (u - 1, v - 1)
+            has_up, has_left, has_dia = up in live, left in live, dia in live
+            if not (has_up or has_left or has_dia):
+                continue
+            cells += 1
+            Eg[(u, v)] = max(Eg[left] - E, H[left] - O - E) if has_left else neg
+            Fg[(u, v)] = max(Fg[up] - E, H[up] - O - E) if has_up else neg
+            dval = H[dia] + int(B[a[u - 1], b[v - 1]]) if has_dia else neg
+            H[(u, v)] = max(dval, Eg[(u, v)], Fg[(u, v)])
+            computed.append((u, v))
+        survivors = [c for c in computed if H[c] >= best - x]
+        if not survivors:
+            break
+        live.update(survivors)
+        top = max(H[c] for c in survivors)
+        if top > best:
+            best, end = top, min(c for c in survivors if H[c] == top)
+    # canonical path back to the anchor: diagonal, then E, then F; extend first
+    (u, v), state, matches, columns = end, "H", 0, 0
+    while (u, v, state) != (0, 0, "H"):
+        if state == "H":
+            dia = (u - 1, v - 1)
+            if dia in live and H[(u, v)] == H[dia] + int(B[a[u - 1], b[v - 1]]):
+                columns += 1
+                matches += int(a[u - 1] == b[v - 1])
+                u, v = u - 1, v - 1
+            else:
+                state = "E" if H[(u, v)] == Eg[(u, v)] else "F"
+        elif state == "E":
+            columns += 1
+            left = (u, v - 1)
+            state = "E" if Eg[left] - E >= H[left] - O - E else "H"
+            v -= 1
+        else:
+            columns += 1
+            up = (u - 1, v)
+            state = "F" if Fg[up] - E >= H[up] - O - E else "H"
+            u -= 1
+    return dict(score=best, u=end[0], v=end[1], matches=matches, columns=columns, cells=cells)
+
+
+def test_xdrop_cell_exactly_x_below_stays_live(orc):
+    # A against A: anti-diagonal 1 holds the two gap cells at -12 = 0 - 12.
+    # With X = 12 they stay live (only scores below best - X die), and the
+    # diagonal cell (1,1) = 4 follows: 3 cells, score 4.  With X = 11 both gap
+    # cells die, anti-diagonal 1 has no live cell and the extension stops.
+    a, b = enc("A"), enc("A")
+    assert orc.xdrop_extend(a, b, O, E, 12) == dict(score=4, u=1, v=1, matches=1, columns=1, cells=3)
+    assert orc.xdrop_extend(a, b, O, E, 11) == dict(score=0, u=0, v=0, matches=0, columns=0, cells=2)
+    # WWWW against AWWWW: the best path opens with the gap cell (0,1) at
+    # exactly best - X = -12 and then matches four W: -12 + 4 * 11 = 32 at
+    # (4,5), one gap column and four matches.  The gap-free path scores only
+    # -3 + 3 * 11 = 30 at (4,4); no path with four matches avoids a gap.
+    r = orc.xdrop_extend(enc("WWWW"), enc("AWWWW"), O, E, 12)
+    assert (r["score"], r["u"], r["v"], r["matches"], r["columns"]) == (32, 4, 5, 4, 5)
+    assert orc.xdrop_extend(enc("WWWW"), enc("AWWWW"), O, E, 11)["score"] == 0
+
+
+def test_xdrop_prunes_against_earlier_antidiagonals_only(orc):
+    # WKA (rows) against W (one column), X = 16, worked by hand:
+    #   d=1: (1,0) = (0,1) = -12, both live (>= 0 - 16); best stays 0.  2 cells
+    #   d=2: (1,1) = 0 + W/W 11 = 11; (2,0) = -13.  Both are judged against the
+    #        best of anti-diagonals < 2, which is 0: both live (-13 >= -16).
+    #        A best raised within the anti-diagonal (11 - 16 = -5) would have
+    #        killed (2,0).  best = 11.  4 cells
+    #   d=3: (2,1) = max(-12 + K/W -3, 11 - 12, (2,0) - 12) = -1 (live);
+    #        (3,0) = -14 from the live (2,0) (dead, < -5).  6 cells
+    #   d=4: (3,1) = max((2,0) + A/W -3 = -16, -1 - 12 = -13) = -13, dead: stop.
+    #        7 cells; without (2,0) there would be no (3,0) and 6 cells.
+    assert orc.xdrop_extend(enc("WKA"), enc("W"), O, E, 16) == dict(score=11, u=1, v=1, matches=1, columns=1,
+                                                                      cells=7)
+    # a case where the rule changes the score: a best raised within an
+    # anti-diagonal would prune the start of the optimal path and end at 3
+    B = orc.blosum62()
+    a, b = enc("CPKPKW"), enc("EPPW")
+    r = orc.xdrop_extend(a, b, O, E, 14)
+    assert r == _xdrop_dense(B, a, b, 14)
+    assert (r["score"], r["u"], r["v"], r["matches"], r["columns"], r["cells"]) == (5, 6, 4, 2, 6, 30)
+
+
+def test_xdrop_matches_dense_enumeration(orc):
+    # every field, the live-predecessor cell count included, at drops small
+    # enough that pruning and ties at exactly best - X happen often
+    B = orc.blosum62()
+    rng = np.random.default_rng(8)
+    letters = np.array([ALPHA.index(c) for c in "WAGCSPKE"], np.uint8)
+    for _ in range(1500):
+        a = rng.choice(letters, int(rng.integers(0, 9)))
+        b = rng.choice(letters, int(rng.integers(0, 9)))
+        x = int(rng.integers(0, 30))
+        assert orc.xdrop_extend(a, b, O, E, x) == _xdrop_dense(B, a, b, x), (a, b, x)
+    for _ in range(40):
+        a = rng.integers(0, 20, int(rng.integers(20, 60))).astype(np.uint8)
+        b = a.copy()
+        for t in rng.choice(b.size, b.size // 3, replace=False):
+            b[t] = rng.integers(0, 20)
+        x = int(rng.integers(5, 50))
+        assert orc.xdrop_extend(a, b, O, E, x) == _xdrop_dense(B, a, b, x)
 
 
 def test_xd_self_pair_and_bound_by_sw(orc):

@@ -14,6 +14,8 @@ What each function follows:
     the common-k-mer threshold of Section VI.
   * ``align_pairs``/``sw``/``xdrop_extend``: Section IV-E (SW and XD).
   * ``search``: the pipeline of Section IV with the filter of Section IV-F.
+  * ``components``/``weighted_scores`` (``oracle.clusters``): connected
+    components of the similarity graph as families, scored as in Section VI-B.
 Points where the paper is silent are resolved in the C sources' headers.
 """
 
@@ -122,12 +124,19 @@ def lib():
         L.orc_passes.restype = ctypes.c_int
         L.orc_passes.argtypes = [aln_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_threads.restype = None
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops (n <= 0: all cores); results do not depend on it."""
+    lib().orc_set_threads(int(n))
 
 
 # ---------------------------------------------------------------- alphabet
@@ -363,3 +372,8 @@ def search(residues, offsets, *, k: int = 6, n_subs: int = 0, alpha: int = 20, c
     if return_all:
         return edges, cand, rec
     return edges
+
+
+# ---------------------------------------------------------------- graph
+
+from .clusters import components, weighted_scores  # noqa: E402,F401

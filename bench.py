@@ -3,15 +3,19 @@
 
 Prints ONE JSON line.  `value` is whole-step alignment throughput in GCUPS
 (DP cells per second over the whole timed step, inputs already resident in
-HBM); `pairs_per_s`, the per-kernel roofline of the dominant kernel and a CPU
-oracle baseline are reported beside it.
+HBM); `pairs_per_s`, the roofline of the dominant kernel, the learned filter
+against the plain search, and a CPU oracle baseline are reported beside it.
 
-Default workload: 50,000 synthetic protein sequences (2,000 families x 25,
-lengths lognormal mean 350 clamped to [30, 2000], 30% divergence, indels
-0.02 / mean 3, seed 0), k = 6 with 25 substitute k-mers per k-mer, pairs
-sharing >= 2 (substitute) k-mers aligned by Smith-Waterman (BLOSUM62,
-gaps 11/1) and cut at 30% identity / 70% coverage.  One step is one
-pastis_search call from HBM-resident sequences to HBM-resident edges.
+Default workload ("large"): 250,000 synthetic protein sequences (10,000
+families x 20 plus 50,000 unrelated singletons, lengths lognormal mean 350
+clamped to [30, 5000], 30% divergence, indels 0.02 / mean 3, seed 0), exact
+6-mers, pairs sharing >= 2 k-mers aligned by Smith-Waterman (BLOSUM62, gaps
+11/1) and cut at 30% identity / 70% coverage.  One step is one pastis_search
+call from HBM-resident sequences to HBM-resident edges, with the SW schedule
+chosen by the library's autotuner on a candidate sample and the SW stage
+replayed as a captured HIP graph.  The learned filter is trained on the mid
+recipe (50,000 sequences, another seed; candidates of 25 substitute 6-mers
+and of exact 6-mers, both >= 2 shared) and applied to this workload.
 """
 
 import argparse
@@ -39,6 +43,12 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 #   32-bit multi-strip: as one strip, but the row maximum and its column (3) -> 10
 #   16-bit multi-strip: as 16-bit (the strip boundary is a lane move)        -> 10
 OPS_PER_SW_CELL = {(16, False): 10, (16, True): 10, (32, False): 9, (32, True): 10}
+# the method's own count per SW cell, independent of the formulation: the gap
+# open term (1), E and F (2 + 2), the diagonal with its score (1), the 3-way
+# maximum with zero (2), and the running best with its position (3)
+ALGO_OPS_PER_SW_CELL = 11
+# x-drop: the same recurrence plus the drop test per live cell
+ALGO_OPS_PER_XD_CELL = 12
 # HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (KiB per
 # dispatch on the mid workload, profiles/sw_search_mid_kernel_stats.md), scaled
 # by what the counters read for a 1 GiB device copy (FETCH x 2.0, WRITE x 1.0);
@@ -79,15 +89,18 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="mid", choices=["tiny", "mid", "large", "heavy"])
+    ap.add_argument("--workload", default="large", choices=["tiny", "mid", "large", "heavy"])
     ap.add_argument("--families", type=int, default=None, help="scale the workload down (tests)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-filter leg")
     ap.add_argument("--mlp-epochs", type=int, default=4)
     ap.add_argument("--no-xd", action="store_true", help="skip the x-drop leg")
-    ap.add_argument("--autotune", action="store_true",
-                    help="time schedule settings on a candidate sample first (default: the library's schedule)")
-    ap.add_argument("--no-graph", action="store_true", help="skip the graph-mode leg")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="run the library's default schedule instead of tuning it on a candidate sample first")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="time the step with direct launches only (default: the SW stage replayed as a HIP graph)")
+    ap.add_argument("--no-mid", action="store_true", help="skip the mid-workload sub-object")
+    ap.add_argument("--ns", action="store_true", help="also time the normalised-score weight mode (no traceback)")
     ap.add_argument("--pairs", type=int, default=0,
                     help="also time the alignment stage alone on this many seeded pairs (0: off)")
     ap.add_argument("--tune-pairs", type=int, default=2_000_000, help="candidate sample size of the autotuner")
@@ -100,9 +113,20 @@ def parse():
     return ap.parse_args()
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(fs, lo, hi, target_s):
     """The CPU oracle (textbook SW with traceback, OpenMP over pairs) on a
-    bounded random sample of the step's candidate pairs."""
+    bounded random sample of the step's candidate pairs: once on every host
+    core the process may use, once on one core (a smaller sample)."""
     import numpy as np
 
     import oracle
@@ -111,69 +135,139 @@ def cpu_baseline(fs, lo, hi, target_s):
     L = np.diff(fs.offsets)
     rng = np.random.default_rng(7)
     take = rng.permutation(lo.size)
+
+    def timed(sel):
+        t0 = time.perf_counter()
+        rec = oracle.align_pairs(codes, fs.offsets, lo[sel], hi[sel], mode="sw")
+        dt = time.perf_counter() - t0
+        cells = float((L[lo[sel]].astype(np.int64) * L[hi[sel]]).sum())
+        assert int(rec["cells"].sum()) == int(cells)
+        return dt, cells
+
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    oracle.set_threads(cores)
     n0 = min(256, lo.size)
-    t0 = time.perf_counter()
-    oracle.align_pairs(codes, fs.offsets, lo[take[:n0]], hi[take[:n0]], mode="sw")
-    dt0 = time.perf_counter() - t0
+    dt0, _ = timed(take[:n0])
     n1 = int(min(lo.size, max(n0, n0 * target_s / max(dt0, 1e-3))))
-    sel = take[:n1]
-    t0 = time.perf_counter()
-    rec = oracle.align_pairs(codes, fs.offsets, lo[sel], hi[sel], mode="sw")
-    dt = time.perf_counter() - t0
-    cells = float((L[lo[sel]].astype(np.int64) * L[hi[sel]]).sum())
-    assert int(rec["cells"].sum()) == int(cells)
+    dt, cells = timed(take[:n1])
+    used = oracle.num_threads()
+    # one core: a sample sized for about a third of the target time
+    oracle.set_threads(1)
+    n2 = int(min(lo.size, max(64, n1 / max(used, 1) / 3)))
+    dt1, cells1 = timed(take[:n2])
+    oracle.set_threads(cores)
     return {
         "value": cells / dt / 1e9,
         "unit": "GCUPS",
         "pairs_per_s": n1 / dt,
-        "cores": oracle.num_threads(),
+        "cores": used,
         "kind": "oracle",
-        "sample": f"{n1} random candidate pairs of the step ({cells:.3e} cells), SW with full traceback, {dt:.1f} s",
+        "cpu_model": cpu_model(),
+        "sample": f"{n1} random candidate pairs of the step ({cells:.3e} cells), SW with full traceback, "
+        f"{dt:.1f} s on {used} threads",
+        "single_core": {"value": cells1 / dt1 / 1e9, "unit": "GCUPS", "pairs_per_s": n2 / dt1,
+                        "sample": f"the first {n2} pairs of the same sample ({cells1:.3e} cells), {dt1:.1f} s"},
     }
 
 
-def graph_leg(P, args, params, res, off, tuning):
-    """The same search with the alignment stage replayed as a captured HIP graph."""
-    import torch
-
-    ctx = P.Context(P.Params(graph_mode=True, **params))
+def set_tuning(ctx, tuning):
     if isinstance(tuning, dict):
         ctx.set_tuning(**{k: tuning[k] for k in ("sw16_max_rows", "sw_direct_pct", "sw_grid_scale",
                                                   "sw_grid_scale_wide", "sw_intra_pair")})
-    for _ in range(max(args.warmup, 1)):
-        ctx.search(res, off)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ctx.search(res, off)
-    torch.cuda.synchronize()
-    return {"ms_per_step": (time.perf_counter() - t0) * 1e3 / args.steps, "sw_graph": ctx.stats()["sw_graph"]}
 
 
-def xd_leg(P, args, params, res, off, n_cand):
-    """The same workload with x-drop seed extension from the stored seeds (X = 49)."""
+def timed_steps(ctx, args, res, off):
+    """W untimed steps, then K timed ones; (ms per step, last edges, summed stage ms, last stats)."""
     import torch
 
-    ctx_xd = P.Context(P.Params(align_mode="xd", **params))
     for _ in range(args.warmup):
-        ctx_xd.search(res, off)
+        ctx.search(res, off)
     torch.cuda.synchronize()
+    stage = [0.0] * 9
     t0 = time.perf_counter()
-    xstage = [0.0] * 9
     for _ in range(args.steps):
-        xedges = ctx_xd.search(res, off)
-        xst = ctx_xd.stats()
-        xstage = [a + b for a, b in zip(xstage, xst["ms_stage"])]
+        edges = ctx.search(res, off)
+        st = ctx.stats()
+        stage = [a + b for a, b in zip(stage, st["ms_stage"])]
     torch.cuda.synchronize()
-    xms = (time.perf_counter() - t0) * 1e3 / args.steps
+    return (time.perf_counter() - t0) * 1e3 / args.steps, edges, [x / args.steps for x in stage], st
+
+
+STAGE_NAMES = ["encode", "kmers", "subs_AS", "spgemm", "schedule", "sw_pass1", "sw_pass2", "edges", "mlp_filter"]
+
+
+def kernel_name(b):
+    R = b["rows_per_lane"]
+    if b["bits"] == 16:
+        if b["multi_strip"]:
+            return "sw16_pass1_kernel<%d, 4, true>" % R
+        if R <= 4:
+            return "sw16s_pass1_kernel<16, %d, 4>" % (4 * R)
+        if R <= 8:
+            return "sw16s_pass1_kernel<32, %d, 4>" % (2 * R)
+        return "sw16_pass1_kernel<%d, 4, false>" % R
+    return "sw_pass1_kernel<%d, %s>" % (R, "true" if b["multi_strip"] else "false")
+
+
+def roofline(st, pass1_ms, traffic_ok):
+    """The dominant pass-1 kernel (the length bin with the most DP work; one
+    launch per step) against the integer VALU peak of its lane width: its
+    cells x the method's 11 ops per cell over its HIP-event time on the
+    stream it was launched on.  The kernel's own formulation count (10 or 9
+    ops per cell) is reported beside it."""
+
+    def ops(b):
+        return OPS_PER_SW_CELL[(b["bits"], bool(b["multi_strip"]))]
+
+    def peak_of(b):
+        return PEAK_INT16_TOPS if b["bits"] == 16 else PEAK_INT32_TOPS
+
+    # chosen by work, not by event time: the multi-strip bins run on a second
+    # stream beside the one-strip bins, so their event spans include time
+    # shared with other kernels
+    dom = max(st["sw_bins"], key=lambda b: b["cells"] / peak_of(b))
+    name = kernel_name(dom)
+    peak = peak_of(dom)
+    achieved = dom["cells"] * ALGO_OPS_PER_SW_CELL / (dom["ms"] * 1e-3) / 1e12
+    kernel_ops = dom["cells"] * ops(dom) / (dom["ms"] * 1e-3) / 1e12
+    mix_peak_s = sum(b["cells"] * ALGO_OPS_PER_SW_CELL / (peak_of(b) * 1e12) for b in st["sw_bins"])
+    traffic = None
+    if traffic_ok and name in MEASURED_TRAFFIC_KIB:
+        f, w = MEASURED_TRAFFIC_KIB[name]
+        traffic = 1024 * (FETCH_SCALE * f + WRITE_SCALE * w)
     return {
-        "ms_per_step": xms,
-        "pairs_per_s": n_cand / (xms * 1e-3),
-        "live_cells": float(xst["cells"]),
-        "align_ms": (xstage[5] + xstage[6]) / args.steps,
-        "register_band_ms": xstage[5] / args.steps,
-        "wide_band_redo_ms": xstage[6] / args.steps,
-        "align_pairs_per_s": n_cand / ((xstage[5] + xstage[6]) / args.steps * 1e-3),
+        "kernel": name,
+        "bound": "alu",
+        "achieved": achieved,
+        "peak": peak,
+        "unit": "Tops/s",
+        "frac": achieved / peak,
+        "traffic": traffic,
+        "kernel_ms": dom["ms"],
+        "kernel_cells": dom["cells"],
+        "ops_per_cell": ALGO_OPS_PER_SW_CELL,
+        "kernel_ops_per_cell": ops(dom),
+        "frac_kernel_ops": kernel_ops / peak,
+        "all_pass1_bins": {"frac_of_mix_peak": mix_peak_s / (pass1_ms * 1e-3)},
+    }
+
+
+def xd_leg(P, args, params, res, off, n_cand, tuning=None):
+    """The same workload with x-drop seed extension from the stored seeds (X = 49)."""
+    ctx = P.Context(P.Params(align_mode="xd", **params))
+    ms, xedges, stage, st = timed_steps(ctx, args, res, off)
+    align_ms = stage[5] + stage[6]
+    live = float(st["cells"])
+    return {
+        "ms_per_step": ms,
+        "pairs_per_s": n_cand / (ms * 1e-3),
+        "live_cells": live,
+        "gcups_live": live / (ms * 1e-3) / 1e9,
+        "align_ms": align_ms,
+        "register_band_ms": stage[5],
+        "wide_band_redo_ms": stage[6],
+        "align_pairs_per_s": n_cand / (align_ms * 1e-3),
+        "align_frac_int32_peak": live * ALGO_OPS_PER_XD_CELL / (align_ms * 1e-3) / 1e12 / PEAK_INT32_TOPS,
         "edges": int(xedges.size),
     }
 
@@ -181,9 +275,7 @@ def xd_leg(P, args, params, res, off, n_cand):
 def pairs_leg(P, args, params, fs, res, off, tuning):
     """The alignment stage alone on a seeded list of --pairs pairs of the
     workload's sequences (every within-family pair, then uniformly random
-    unrelated pairs, shuffled), through the pair-list entry point: the
-    candidate volume the large configuration expects, which i.i.d. synthetic
-    sequences do not reach through k-mer sharing."""
+    unrelated pairs, shuffled), through the pair-list entry point."""
     import numpy as np
     import torch
 
@@ -202,11 +294,8 @@ def pairs_leg(P, args, params, fs, res, off, tuning):
     dev = res.device
     pi = torch.from_numpy(lo.view(np.int32)).to(dev)
     pj = torch.from_numpy(hi.view(np.int32)).to(dev)
-    # 16-bit pass 1 where the scores fit, as in the search
     ctx = P.Context(P.Params(score_width=16, **params))
-    if isinstance(tuning, dict):
-        ctx.set_tuning(**{k: tuning[k] for k in ("sw16_max_rows", "sw_direct_pct", "sw_grid_scale",
-                                                  "sw_grid_scale_wide", "sw_intra_pair")})
+    set_tuning(ctx, tuning)
     for _ in range(max(args.warmup, 1)):
         recs = ctx.align_pairs(res, off, pi, pj)
     torch.cuda.synchronize()
@@ -216,51 +305,38 @@ def pairs_leg(P, args, params, fs, res, off, tuning):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
     passed = int(recs.view(torch.int32).view(-1, 12)[:, 8].sum().item())  # pastis_pair_record.passed
-    return {
-        "pairs": int(lo.size),
-        "family_pairs": fam,
-        "ms_per_step": ms,
-        "pairs_per_s": lo.size / (ms * 1e-3),
-        "gcups": cells / (ms * 1e-3) / 1e9,
-        "cells": cells,
-        "passed": passed,
-    }
+    return {"pairs": int(lo.size), "family_pairs": fam, "ms_per_step": ms, "pairs_per_s": lo.size / (ms * 1e-3),
+            "gcups": cells / (ms * 1e-3) / 1e9, "cells": cells, "passed": passed}
 
 
-# training sequences of the learned filter for each bench workload: the mid
-# recipe (another seed) with the bench workload's discovery parameters
-TRAIN_SET = {"tiny": "tiny", "mid": "mid", "large": "mid", "heavy": "mid"}
+# training sets of the learned filter: the mid recipe with another seed, its
+# candidates collected with 25 substitute 6-mers and with exact 6-mers (both
+# >= 2 shared), so both feature regimes are covered
+TRAIN_COLLECTIONS = [dict(k=6, n_subs=25, ck_min=2), dict(k=6, n_subs=0, ck_min=2)]
 
 
-def mlp_leg(P, args, params, over, res, off, edges, plain_ms):
-    """Train the learned pre-alignment filter on other sequences (labels from
-    exact alignment), then time the filtered search on the bench workload and
-    measure its recall of the exact edges."""
+def mlp_leg(P, args, params, res, off, edges, plain_ms, tuning, graph):
+    """Train the learned pre-alignment filter inside the library on other
+    sequences (labels from exact alignment), then time the filtered search on
+    the bench workload and measure its recall of the exact edges."""
     import numpy as np
     import torch
 
     from paper_2009_14467_amd import learned_filter as LF
     from synth import workload
 
-    train_name = TRAIN_SET[args.workload]
-    fs_tr = workload(train_name, seed=1, **(over if train_name == args.workload else {}))
+    train_over = {} if args.families is None else {"n_families": max(4, args.families // 2)}
+    fs_tr = workload("mid", seed=1, **train_over)
     dev = res.device
-    tf = LF.train(P.Params(**params), torch.from_numpy(fs_tr.residues).to(dev),
-                  torch.from_numpy(fs_tr.offsets).to(dev), epochs=args.mlp_epochs)
+    rt, ot = torch.from_numpy(fs_tr.residues).to(dev), torch.from_numpy(fs_tr.offsets).to(dev)
+    tf = LF.train(P.Params(**params), sets=[(rt, ot, P.Params(**c)) for c in TRAIN_COLLECTIONS],
+                  epochs=args.mlp_epochs)
+    del rt, ot
     torch.cuda.empty_cache()
-    ctx = P.Context(P.Params(filter_mode="mlp", **params))
+    ctx = P.Context(P.Params(filter_mode="mlp", graph_mode=graph, **params))
+    set_tuning(ctx, tuning)
     tf.install(ctx)
-    for _ in range(args.warmup):
-        ctx.search(res, off)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    fstage = [0.0] * 9
-    for _ in range(args.steps):
-        fedges = ctx.search(res, off)
-        st = ctx.stats()
-        fstage = [a + b for a, b in zip(fstage, st["ms_stage"])]
-    torch.cuda.synchronize()
-    fms = (time.perf_counter() - t0) * 1e3 / args.steps
+    fms, fedges, fstage, st = timed_steps(ctx, args, res, off)
 
     def keys(e):
         return (e["i"].astype(np.uint64) << np.uint64(32)) | e["j"].astype(np.uint64)
@@ -273,11 +349,13 @@ def mlp_leg(P, args, params, over, res, off, edges, plain_ms):
         "pairs_skipped": int(st["n_candidates"] - st["n_aligned"]),
         "precision": int(fedges.size) / max(int(st["n_aligned"]), 1),
         "ms_per_step": fms,
+        "plain_ms_per_step": plain_ms,
         "speedup": plain_ms / fms,
-        "filter_ms": fstage[8] / args.steps,
-        "align_ms": (fstage[5] + fstage[6]) / args.steps,
+        "filter_ms": fstage[8],
+        "align_ms": fstage[5] + fstage[6],
         "train": {
-            "workload": f"{train_name} recipe, seed 1: {fs_tr.n} sequences, the bench's discovery parameters",
+            "workload": f"mid recipe, seed 1: {fs_tr.n} sequences; collections "
+            + "; ".join(f"k={c['k']} n_subs={c['n_subs']} ck>={c['ck_min']}" for c in TRAIN_COLLECTIONS),
             "examples": tf.n_examples,
             "positive_frac": tf.positive_frac,
             "epochs": args.mlp_epochs,
@@ -288,6 +366,39 @@ def mlp_leg(P, args, params, over, res, off, edges, plain_ms):
             "tau": tf.tau,
         },
     }
+
+
+def mid_leg(P, args, dev):
+    """The mid workload (50,000 sequences, 25 substitute 6-mers): the plain
+    SW step with the library's schedule, and the x-drop step."""
+    from synth import workload
+
+    import torch
+
+    over = {} if args.families is None else {"n_families": args.families}
+    fs = workload("mid", **over)
+    params = WORKLOAD_PARAMS["mid"]
+    res = torch.from_numpy(fs.residues).to(dev)
+    off = torch.from_numpy(fs.offsets).to(dev)
+    ctx = P.Context(P.Params(**params))
+    ms, edges, stage, st = timed_steps(ctx, args, res, off)
+    cells = float(st["cells"])
+    out = {
+        "workload": f"mid: {fs.n} sequences ({fs.residues.size} residues), " + WORKLOAD_TEXT["mid"],
+        "ms_per_step": ms,
+        "gcups": cells / (ms * 1e-3) / 1e9,
+        "pairs_per_s": st["n_candidates"] / (ms * 1e-3),
+        "candidates": int(st["n_candidates"]),
+        "cells": cells,
+        "edges": int(edges.size),
+        "stage_ms": dict(zip(STAGE_NAMES, stage)),
+        "roofline": roofline(st, stage[5], args.families is None),
+    }
+    if not args.no_xd:
+        out["xd"] = xd_leg(P, args, params, res, off, int(st["n_candidates"]))
+    del res, off
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -301,10 +412,12 @@ def main():
     import paper_2009_14467_amd as P
     from synth import workload
 
+    def note(msg):
+        print(f"bench.py: {msg}", file=sys.stderr, flush=True)
+
     over = {} if args.families is None else {"n_families": args.families}
     fs = workload(args.workload, **over)
     params = dict(WORKLOAD_PARAMS[args.workload])
-
     dev = torch.device("cuda:0")
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
@@ -320,59 +433,29 @@ def main():
         knobs = dict(kv.split("=") for kv in args.schedule.split(","))
         ctx.set_tuning(**{k: int(v) for k, v in knobs.items()})
         tuning = dict(ctx.get_tuning(), source="--schedule")
-    elif args.autotune:
+    elif not args.no_autotune:
         t0 = time.perf_counter()
         tuning = ctx.autotune(res, off, max_pairs=args.tune_pairs)
         torch.cuda.synchronize()
-        tuning = dict(tuning, seconds=time.perf_counter() - t0, sample_pairs=args.tune_pairs)
+        tuning = dict(tuning, source="pastis_autotune", seconds=time.perf_counter() - t0,
+                      sample_pairs=args.tune_pairs)
+    note(f"schedule {tuning}")
 
-    for _ in range(args.warmup):
-        ctx.search(res, off)
-    torch.cuda.synchronize()
-    stage = [0.0] * 9
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        edges = ctx.search(res, off)
-        st = ctx.stats()
-        stage = [a + b for a, b in zip(stage, st["ms_stage"])]
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_step = dt * 1e3 / args.steps
+    # direct launches: per-stage and per-bin HIP-event times (the roofline's source)
+    d_ms, edges, stage, st = timed_steps(ctx, args, res, off)
+    note(f"direct launches: {d_ms:.1f} ms per step")
     cells = float(st["cells"])
     n_cand = int(st["n_candidates"])
-    pass1_ms = stage[5] / args.steps
-
-    def ops(b):
-        return OPS_PER_SW_CELL[(b["bits"], bool(b["multi_strip"]))]
-
-    # the dominant kernel: the pass-1 length bin with the most DP work (cells x
-    # ops per cell; one launch per step), its own cells over its own HIP-event
-    # time.  Chosen by work, not by event time: the multi-strip bins run on a
-    # second stream beside the one-strip bins, so their event spans include
-    # time shared with other kernels.
-    dom = max(st["sw_bins"], key=lambda b: b["cells"] * ops(b))
-    R = dom["rows_per_lane"]
-    if dom["bits"] == 16:
-        if dom["multi_strip"]:
-            dom_name = "sw16_pass1_kernel<%d, 4, true>" % R
-        elif R <= 4:
-            dom_name = "sw16s_pass1_kernel<16, %d, 4>" % (4 * R)
-        elif R <= 8:
-            dom_name = "sw16s_pass1_kernel<32, %d, 4>" % (2 * R)
-        else:
-            dom_name = "sw16_pass1_kernel<%d, 4, false>" % R
-        peak = PEAK_INT16_TOPS
-    else:
-        dom_name = "sw_pass1_kernel<%d, %s>" % (R, "true" if dom["multi_strip"] else "false")
-        peak = PEAK_INT32_TOPS
-
-    achieved = dom["cells"] * ops(dom) / (dom["ms"] * 1e-3) / 1e12
-    pass1_ops = sum(b["cells"] * ops(b) for b in st["sw_bins"])
-    pass1_tops = pass1_ops / (pass1_ms * 1e-3) / 1e12
-    # peak of the pass-1 mix: each bin's cells at its own width's peak
-    mix_peak_s = sum(b["cells"] * ops(b) / ((PEAK_INT16_TOPS if b["bits"] == 16 else PEAK_INT32_TOPS) * 1e12)
-                     for b in st["sw_bins"])
-    names = ["encode", "kmers", "subs_AS", "spgemm", "schedule", "sw_pass1", "sw_pass2", "edges", "mlp_filter"]
+    graph = not args.no_graph
+    ms_step = d_ms
+    if graph:
+        gctx = P.Context(P.Params(graph_mode=True, **params))
+        set_tuning(gctx, tuning)
+        ms_step, gedges, _, gst = timed_steps(gctx, args, res, off)
+        assert gedges.tobytes() == edges.tobytes(), "graph replay changed the edges"
+        graph_info = {"ms_per_step": ms_step, "sw_graph": gst["sw_graph"]}
+        del gctx
+        note(f"graph mode: {ms_step:.1f} ms per step")
     line = {
         "metric": METRIC,
         "value": cells / (ms_step * 1e-3) / 1e9,
@@ -390,65 +473,65 @@ def main():
             "workload": f"{args.workload}: {fs.n} sequences ({fs.residues.size} residues), "
             + ("" if args.families is None else f"scaled to {args.families} families; ")
             + WORKLOAD_TEXT[args.workload],
-            "step": "pastis_search: sequences resident in HBM -> edges in HBM (discovery, SW, cut, edges)",
+            "step": "pastis_search: sequences resident in HBM -> edges in HBM (discovery, SW, cut, edges)"
+            + ("; SW stage replayed as a captured HIP graph" if graph else "; direct launches"),
+            "schedule": "autotuned" if tuning is not None and not args.schedule else
+            ("--schedule" if args.schedule else "library default"),
             **{k: v for k, v in params.items()},
         },
         "pairs_per_s": n_cand / (ms_step * 1e-3),
         "candidates": n_cand,
         "cells": cells,
         "edges": int(edges.size),
+        "direct_launch": {"ms_per_step": d_ms, "gcups": cells / (d_ms * 1e-3) / 1e9},
         "stats_pass_pairs": int(st["stats_pass_pairs"]),
         "stats_pass_cells": int(st["stats_pass_cells"]),
         "bound_pass_pairs": int(st["bound_pass_pairs"]),
         "bound_pass_cells": int(st["bound_pass_cells"]),
-        "stage_ms": {k: v / args.steps for k, v in zip(names, stage)},
-        "align_gcups": cells / ((stage[5] + stage[6]) / args.steps * 1e-3) / 1e9,
+        "stage_ms": dict(zip(STAGE_NAMES, stage)),
+        "align_gcups": cells / ((stage[5] + stage[6]) * 1e-3) / 1e9,
         # candidate discovery's product against HBM bandwidth: one 6-byte
         # posting (sequence u32, position u16) per product is the least the
         # product must read; the stage time includes symmetrisation and sorting
         "spgemm": {
             "products": int(st["spgemm_products"]),
-            "ms": stage[3] / args.steps,
-            "products_per_s": st["spgemm_products"] / (stage[3] / args.steps * 1e-3),
-            "achieved_gb_s": 6 * st["spgemm_products"] / (stage[3] / args.steps * 1e-3) / 1e9,
+            "ms": stage[3],
+            "products_per_s": st["spgemm_products"] / (stage[3] * 1e-3),
+            "achieved_gb_s": 6 * st["spgemm_products"] / (stage[3] * 1e-3) / 1e9,
             "peak_gb_s": PEAK_HBM_GBS,
-            "frac": 6 * st["spgemm_products"] / (stage[3] / args.steps * 1e-3) / 1e9 / PEAK_HBM_GBS,
-            # counted HBM traffic of the product kernels (FETCH_SIZE / WRITE_SIZE,
-            # scaled as above; mid workload only) over the stage time
-            "traffic": (None if args.workload != "mid" or args.families is not None else
-                        1024 * sum(FETCH_SCALE * f + WRITE_SCALE * w for f, w in SPGEMM_TRAFFIC_KIB.values())),
+            "frac": 6 * st["spgemm_products"] / (stage[3] * 1e-3) / 1e9 / PEAK_HBM_GBS,
         },
-        "roofline": {
-            "kernel": dom_name,
-            "bound": "alu",
-            "achieved": achieved,
-            "peak": peak,
-            "unit": "Tops/s",
-            "frac": achieved / peak,
-            "traffic": (None if dom_name not in MEASURED_TRAFFIC_KIB or args.workload != "mid"
-                        or args.families is not None else
-                        1024 * (FETCH_SCALE * MEASURED_TRAFFIC_KIB[dom_name][0] +
-                                WRITE_SCALE * MEASURED_TRAFFIC_KIB[dom_name][1])),
-            "kernel_ms": dom["ms"],
-            "kernel_cells": dom["cells"],
-            "ops_per_cell": ops(dom),
-            "all_pass1_bins": {"achieved": pass1_tops, "frac_of_mix_peak": mix_peak_s / (pass1_ms * 1e-3)},
-        },
+        "roofline": roofline(st, stage[5], args.families is None),
         "sw_bins": [dict(b, gcups=b["cells"] / max(b["ms"], 1e-9) / 1e6) for b in st["sw_bins"] if b["pairs"]],
         "schedule": tuning if tuning is not None else dict(ctx.get_tuning(), source="library default"),
     }
-    if not args.no_graph:
-        line["graph_mode"] = graph_leg(P, args, params, res, off, tuning)
+    if graph:
+        line["graph_mode"] = graph_info
     if not args.no_xd:
         line["xd"] = xd_leg(P, args, params, res, off, n_cand)
+        note(f"xd: {line['xd']['ms_per_step']:.1f} ms per step")
+    if args.ns:
+        nctx = P.Context(P.Params(weight_mode="ns", **params))
+        set_tuning(nctx, tuning)
+        nms, _, nstage, _ = timed_steps(nctx, args, res, off)
+        line["ns_weight"] = {"ms_per_step": nms, "gcups": cells / (nms * 1e-3) / 1e9,
+                             "align_ms": nstage[5] + nstage[6]}
     if not args.no_mlp:
-        line["mlp_filter"] = mlp_leg(P, args, params, over, res, off, edges, ms_step)
+        line["mlp_filter"] = mlp_leg(P, args, params, res, off, edges, ms_step, tuning, graph)
+        note(f"learned filter: {line['mlp_filter']['speedup']:.2f}x at recall {line['mlp_filter']['recall']:.4f}")
     if args.pairs > 0:
         line["pair_list"] = pairs_leg(P, args, params, fs, res, off, tuning)
+    c = None
     if not args.no_cpu_baseline:
         c = ctx.candidates(n_cand)
         lo = c["lo"].cpu().numpy().view(np.uint32)
         hi = c["hi"].cpu().numpy().view(np.uint32)
+    del ctx, res, off
+    torch.cuda.empty_cache()
+    if not args.no_mid and args.workload != "mid":
+        line["mid"] = mid_leg(P, args, dev)
+        note(f"mid: {line['mid']['ms_per_step']:.1f} ms per step")
+    if c is not None:
         line["cpu_baseline"] = cpu_baseline(fs, lo, hi, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 

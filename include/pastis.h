@@ -291,6 +291,79 @@ pastis_status pastis_mlp_train_epoch(pastis_ctx *ctx, const float *X, const uint
 pastis_status pastis_mlp_calibrate(pastis_ctx *ctx, const float *X, const uint8_t *labels, int64_t n,
                                    double target_recall, float *tau, void *stream);
 
+/* ---- filter lifecycle inside the library ----
+ * Labelled examples come from the exact pipeline: pastis_mlp_collect runs
+ * discovery on a sequence set, computes the 16 features of every candidate
+ * and labels it with the pass/fail of its exact alignment (the context's
+ * align_mode, the Section IV-F identity/coverage cut), appending both to an
+ * example pool the context owns in device memory.  pastis_mlp_train then
+ * trains a fresh network on the pool and calibrates its threshold. */
+
+/* Append the labelled candidates of one sequence set to the context's pool.
+ * discovery (may be NULL) overrides k, n_subs, sub_alphabet and ck_min for
+ * this collection only (so one pool can mix exact and substitute k-mer
+ * candidates); the other fields of *discovery are ignored.  *n_added (host,
+ * may be NULL) gets the number of examples added.  The discovery's
+ * candidates replace the context's current ones.  Errors as for
+ * pastis_discover; PASTIS_E_INVAL for discovery fields out of range. */
+pastis_status pastis_mlp_collect(pastis_ctx *ctx, const uint8_t *residues, const int64_t *offsets, int64_t n,
+                                 int input_on_device, const pastis_params *discovery, void *stream,
+                                 int64_t *n_added);
+/* Empty the example pool (its memory is kept for the next collection). */
+pastis_status pastis_mlp_clear(pastis_ctx *ctx);
+/* Examples in the pool. */
+pastis_status pastis_mlp_pool_size(const pastis_ctx *ctx, int64_t *n);
+
+typedef struct pastis_mlp_train_opts {
+    int32_t epochs;       /* passes over the training share, 1..1000 */
+    int32_t batch;        /* minibatch: a multiple of 16 in 16..65536 */
+    float lr;             /* Adam step size, > 0 */
+    float pos_weight;     /* positive-class weight; <= 0: negatives / positives of the training share */
+    double target_recall; /* in (0, 1]: share of the calibration positives kept at tau */
+    double heldout;       /* in (0, 0.9]: share of the pool held out; one half calibrates
+                             tau, the other measures recall and the kept share */
+    uint64_t seed;        /* initial weights, the split and every epoch's shuffle */
+    int32_t reserved[4];  /* zero */
+} pastis_mlp_train_opts;
+
+typedef struct pastis_mlp_train_report {
+    int64_t n_examples;    /* pool size */
+    int64_t n_train;       /* examples trained on */
+    int64_t n_positive;    /* positives among them */
+    float pos_weight;      /* positive-class weight used */
+    float tau;             /* calibrated logit threshold, also installed in the context */
+    double heldout_recall; /* positives of the measuring half with logit >= tau */
+    double heldout_kept;   /* share of the measuring half with logit >= tau */
+    double seconds;        /* wall time of the call */
+    int32_t epochs;        /* epochs run */
+    float epoch_loss[32];  /* mean minibatch loss of the first 32 epochs */
+} pastis_mlp_train_report;
+
+/* {4, 8192, 2e-3, 0 (auto), 0.995, 0.2, seed 0}. */
+void pastis_mlp_default_train_opts(pastis_mlp_train_opts *opts);
+/* Train a new network on the pool (opts NULL: the defaults), all on the GPU:
+ * a seeded permutation splits the pool into held-out and training shares;
+ * the positive-class weight, the z-score normalisation and He-normal initial
+ * weights come from the training share; each epoch reshuffles it and runs
+ * minibatch gradients and Adam steps (as pastis_mlp_train_epoch); tau is
+ * calibrated on half of the held-out share (as pastis_mlp_calibrate) and
+ * measured on the other half.  The network replaces the context's.
+ * PASTIS_E_STATE if the pool holds fewer than 64 examples or the training
+ * share has no positive; PASTIS_E_INVAL for options out of range.  *report
+ * (host, may be NULL). */
+pastis_status pastis_mlp_train(pastis_ctx *ctx, const pastis_mlp_train_opts *opts, void *stream,
+                               pastis_mlp_train_report *report);
+/* Write the network (parameters, normalisation, tau) to a file: an 8-byte
+ * magic "PASTMLP1", int32 features (16), hidden width (128), parameter count
+ * (18817) and 0, then float32 params, mean[16], std[16], tau, little-endian.
+ * PASTIS_E_STATE without a network; PASTIS_E_INVAL if the file cannot be
+ * written. */
+pastis_status pastis_mlp_save(pastis_ctx *ctx, const char *path);
+/* Read a network written by pastis_mlp_save and install it (as
+ * pastis_mlp_set).  PASTIS_E_INVAL for a missing, short or foreign file or a
+ * non-positive std; the context's network is unchanged then. */
+pastis_status pastis_mlp_load(pastis_ctx *ctx, const char *path);
+
 /* ---- schedule of the Smith-Waterman stage ----
  * Knobs of the length-binned launches (every setting gives the same results;
  * only the time changes).  A new context starts at {16, 50, 1, 1, 0}.  pastis_autotune times candidate settings on a

@@ -376,6 +376,16 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* Threads of the parallel loops from now on (n <= 0: every available core);
+ * a harness setting for timing runs, no effect on any result. */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+#else
+    (void)n;
+#endif
+}
+
 /* Row i of A S as a list sorted by substitute id: for every k-mer s reached
  * from a k-mer of i, the closest such k-mer's position (smaller position on
  * equal distance).  Exact mode (n_subs = 0) gives K(i) itself. */

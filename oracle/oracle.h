@@ -112,6 +112,7 @@ void orc_align_pairs(const uint8_t *codes, const int64_t *offsets, const uint32_
                      int x, int id_pct, int cov_pct, orc_aln *out);
 
 int orc_num_threads(void);
+void orc_set_threads(int n);
 
 #ifdef __cplusplus
 }

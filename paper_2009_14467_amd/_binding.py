@@ -98,6 +98,34 @@ class _Tuning(ctypes.Structure):
     ]
 
 
+class _TrainOpts(ctypes.Structure):
+    _fields_ = [
+        ("epochs", ctypes.c_int32),
+        ("batch", ctypes.c_int32),
+        ("lr", ctypes.c_float),
+        ("pos_weight", ctypes.c_float),
+        ("target_recall", ctypes.c_double),
+        ("heldout", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("reserved", ctypes.c_int32 * 4),
+    ]
+
+
+class _TrainReport(ctypes.Structure):
+    _fields_ = [
+        ("n_examples", ctypes.c_int64),
+        ("n_train", ctypes.c_int64),
+        ("n_positive", ctypes.c_int64),
+        ("pos_weight", ctypes.c_float),
+        ("tau", ctypes.c_float),
+        ("heldout_recall", ctypes.c_double),
+        ("heldout_kept", ctypes.c_double),
+        ("seconds", ctypes.c_double),
+        ("epochs", ctypes.c_int32),
+        ("epoch_loss", ctypes.c_float * 32),
+    ]
+
+
 def _tuning_dict(t) -> dict:
     return {"sw16_max_rows": t.sw16_max_rows, "sw_direct_pct": t.sw_direct_pct, "sw_grid_scale": t.sw_grid_scale,
             "sw_grid_scale_wide": t.sw_grid_scale_wide, "sw_intra_pair": t.sw_intra_pair}
@@ -206,6 +234,14 @@ _SIGNATURES = [
     ("pastis_mlp_train_epoch", ctypes.c_int,
      [_VP, _VP, _VP, ctypes.c_int64, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_float, ctypes.c_float, _VP, _VP]),
     ("pastis_mlp_calibrate", ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_double, _VP, _VP]),
+    ("pastis_mlp_collect", ctypes.c_int,
+     [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(_Params), _VP, ctypes.POINTER(ctypes.c_int64)]),
+    ("pastis_mlp_clear", ctypes.c_int, [_VP]),
+    ("pastis_mlp_pool_size", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int64)]),
+    ("pastis_mlp_default_train_opts", None, [ctypes.POINTER(_TrainOpts)]),
+    ("pastis_mlp_train", ctypes.c_int, [_VP, ctypes.POINTER(_TrainOpts), _VP, ctypes.POINTER(_TrainReport)]),
+    ("pastis_mlp_save", ctypes.c_int, [_VP, ctypes.c_char_p]),
+    ("pastis_mlp_load", ctypes.c_int, [_VP, ctypes.c_char_p]),
     ("pastis_get_tuning", ctypes.c_int, [_VP, ctypes.POINTER(_Tuning)]),
     ("pastis_set_tuning", ctypes.c_int, [_VP, ctypes.POINTER(_Tuning)]),
     ("pastis_autotune", ctypes.c_int,
@@ -464,6 +500,47 @@ class Context:
         self._check(lib().pastis_mlp_calibrate(self._ctx, _dev_ptr(X), _dev_ptr(labels), X.shape[0],
                                                float(target_recall), tau.ctypes.data, _stream_ptr(stream)))
         return float(tau[0])
+
+
+    def mlp_collect(self, residues, offsets, discovery: Params | None = None, stream=None) -> int:
+        """Append the labelled candidates of one sequence set to the training
+        pool (discovery overrides k, n_subs, sub_alphabet and ck_min); returns
+        the number of examples added."""
+        n = offsets.numel() - 1
+        added = ctypes.c_int64(0)
+        dp = None if discovery is None else ctypes.byref(discovery.to_c())
+        self._check(lib().pastis_mlp_collect(self._ctx, _dev_ptr(residues), _dev_ptr(offsets), n,
+                                             int(residues.is_cuda), dp, _stream_ptr(stream), ctypes.byref(added)))
+        return int(added.value)
+
+    def mlp_clear(self):
+        self._check(lib().pastis_mlp_clear(self._ctx))
+
+    def mlp_pool_size(self) -> int:
+        n = ctypes.c_int64(0)
+        self._check(lib().pastis_mlp_pool_size(self._ctx, ctypes.byref(n)))
+        return int(n.value)
+
+    def mlp_train(self, stream=None, **opts) -> dict:
+        """Train a new network on the pool inside the library (options as in
+        pastis_mlp_train_opts; unnamed ones keep the library defaults)."""
+        o = _TrainOpts()
+        lib().pastis_mlp_default_train_opts(ctypes.byref(o))
+        for k, v in opts.items():
+            if k not in dict(_TrainOpts._fields_) or k == "reserved":
+                raise ValueError(f"unknown training option {k}")
+            setattr(o, k, v)
+        r = _TrainReport()
+        self._check(lib().pastis_mlp_train(self._ctx, ctypes.byref(o), _stream_ptr(stream), ctypes.byref(r)))
+        out = {f: getattr(r, f) for f, _ in _TrainReport._fields_ if f != "epoch_loss"}
+        out["epoch_loss"] = list(r.epoch_loss)[: min(r.epochs, 32)]
+        return out
+
+    def mlp_save(self, path: str):
+        self._check(lib().pastis_mlp_save(self._ctx, os.fsencode(path)))
+
+    def mlp_load(self, path: str):
+        self._check(lib().pastis_mlp_load(self._ctx, os.fsencode(path)))
 
 
 def records_to_numpy(t) -> np.ndarray:

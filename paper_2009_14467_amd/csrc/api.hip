@@ -19,8 +19,8 @@ pastis_status hip_error(pastis_ctx *ctx, hipError_t e, const char *what) {
 }
 
 pastis_status ensure(pastis_ctx *ctx, int id, size_t bytes, void **out) {
-    DeviceBuffer &b = ctx->buf[id];
     if (bytes == 0) bytes = 256;
+    DeviceBuffer &b = ctx->buf[id];
     if (b.bytes < bytes) {
         if (b.ptr) {
             hipError_t e = hipFree(b.ptr);
@@ -201,7 +201,12 @@ pastis_status make_sw_work(pastis_ctx *ctx, int64_t npairs, int max_len, SwWork 
     PASTIS_TRY(ensure(ctx, kBufIdx2, sizeof(int) * (size_t)std::max<int64_t>(npairs, 1), &p));
     wk.idx2 = (int *)p;
     wk.scratch_per_wave = 6 * (int64_t)std::max(max_len, 1);
-    PASTIS_TRY(ensure(ctx, kBufScratch, sizeof(int) * (size_t)wk.scratch_per_wave * (size_t)sw_scratch_waves(), &p));
+    // only multi-strip pairs (a sequence a longer than one strip) touch the
+    // boundary rows; without such a sequence the buffer is never read
+    const size_t scratch_bytes = max_len > sw_one_strip_max_rows()
+                                     ? sizeof(int) * (size_t)wk.scratch_per_wave * (size_t)sw_scratch_waves()
+                                     : 256;
+    PASTIS_TRY(ensure(ctx, kBufScratch, scratch_bytes, &p));
     wk.scratch = (int *)p;
     return PASTIS_OK;
 }
@@ -546,10 +551,13 @@ pastis_status pastis_encode(pastis_ctx *ctx, const uint8_t *residues, int64_t n_
     return PASTIS_OK;
 }
 
-pastis_status pastis_align_pairs(pastis_ctx *ctx, const uint8_t *residues, const int64_t *offsets, int64_t n,
-                                 int input_on_device, const uint32_t *pi, const uint32_t *pj, const uint32_t *seed1,
-                                 const uint32_t *seed2, int64_t npairs, pastis_pair_record *out, void *stream) {
-    if (!ctx) return PASTIS_E_INVAL;
+}  // extern "C"
+
+namespace {
+
+pastis_status align_pairs_impl(pastis_ctx *ctx, const uint8_t *residues, const int64_t *offsets, int64_t n,
+                               int input_on_device, const uint32_t *pi, const uint32_t *pj, const uint32_t *seed1,
+                               const uint32_t *seed2, int64_t npairs, pastis_pair_record *out, void *stream) {
     if (npairs < 0 || (npairs > 0 && (!pi || !pj || !out)))
         return set_error(ctx, PASTIS_E_INVAL, "bad pair arguments");
     hipStream_t s = (hipStream_t)stream;
@@ -577,6 +585,17 @@ pastis_status pastis_align_pairs(pastis_ctx *ctx, const uint8_t *residues, const
     ctx->stats.n_residues = st.n_res;
     ctx->stats.ms_total = std::chrono::duration<double, std::milli>(t1 - t0).count();
     return PASTIS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pastis_status pastis_align_pairs(pastis_ctx *ctx, const uint8_t *residues, const int64_t *offsets, int64_t n,
+                                 int input_on_device, const uint32_t *pi, const uint32_t *pj, const uint32_t *seed1,
+                                 const uint32_t *seed2, int64_t npairs, pastis_pair_record *out, void *stream) {
+    if (!ctx) return PASTIS_E_INVAL;
+    return align_pairs_impl(ctx, residues, offsets, n, input_on_device, pi, pj, seed1, seed2, npairs, out, stream);
 }
 
 }  // extern "C"

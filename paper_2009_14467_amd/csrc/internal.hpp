@@ -84,6 +84,10 @@ pastis_status make_sw_work(pastis_ctx *ctx, int64_t npairs, int max_len, SwWork 
 pastis_status align_core(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, int64_t n, const uint32_t *pi,
                          const uint32_t *pj, const uint32_t *seed1, const uint32_t *seed2, int64_t npairs,
                          pastis_pair_record *out, hipStream_t s);
+// Append the features and pass/fail labels (records rec of the exact
+// alignment) of the ctx's current candidates to the training pool.
+pastis_status mlp_pool_append(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, int64_t n,
+                              const pastis_pair_record *rec, hipStream_t s, int64_t *added);
 // Read `count` device words into host memory (synchronises the stream).
 pastis_status read_device(pastis_ctx *ctx, const void *d, void *h, size_t bytes, hipStream_t s);
 
@@ -97,7 +101,7 @@ struct pastis_ctx {
     pastis_run_stats stats{};
     int8_t *d_blosum = nullptr;  // 24 x 24 int8 + pad row (25 x 25 when padded)
     // grow-only device buffers, reused across calls
-    pastis::DeviceBuffer buf[96];
+    pastis::DeviceBuffer buf[128];
     // discovery results kept for the align stage / candidate copies
     int64_t n_candidates = 0;
     int64_t n_seqs_last = 0;
@@ -162,7 +166,7 @@ enum BufId {
     kBufSortTemp,
     kBufCount  // first id used by the discovery stage
 };
-constexpr int kNumBufs = 96;
+constexpr int kNumBufs = 128;
 
 pastis_status set_error(pastis_ctx *ctx, pastis_status s, const std::string &msg);
 pastis_status hip_error(pastis_ctx *ctx, hipError_t e, const char *what);
@@ -223,6 +227,8 @@ hipError_t launch_xd(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
                      const int8_t *blosum, const Scoring &sc, int k, pastis_pair_record *out, uint32_t *redo,
                      uint32_t *n_redo, int *gring, unsigned long long *counters, hipStream_t s);
 int64_t sw_scratch_waves();
+// Sequences a of at most this many rows run in one strip (no boundary rows).
+int sw_one_strip_max_rows();
 
 // max16 > 0: pass 1 of one-strip pairs with at most max16 rows per lane in
 // 16-bit lanes, two pairs per wave; its records leave end_b = -1 for pairs

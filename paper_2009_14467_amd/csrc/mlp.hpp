@@ -25,6 +25,10 @@ struct MlpState {
     double *moments;                       // 2 * kMlpIn
     uint16_t *ZT, *H1, *DH2, *DH1;         // per-batch activations, feature-major
     int batch_cap;                         // pairs the activation buffers hold
+    // labelled examples collected for training: features [pool_cap][16], labels
+    float *pool_X = nullptr;
+    uint8_t *pool_y = nullptr;
+    int64_t pool_n = 0, pool_cap = 0;
 };
 
 hipError_t mlp_refresh(const MlpState &S, hipStream_t s);

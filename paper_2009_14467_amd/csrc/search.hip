@@ -95,7 +95,7 @@ struct Misc {
     unsigned long long *max_ub;   // 1
     unsigned long long *max_big;  // 1
     uint32_t *n_big;              // 2
-    uint32_t *d_count;            // 1
+    unsigned long long *d_count;  // 1 (its own 64-bit word)
     uint32_t *d_overflow;         // 1
     uint32_t *n_cand;             // 1
     uint32_t *n_edges;            // 1
@@ -110,7 +110,7 @@ pastis_status misc(pastis_ctx *ctx, Misc &m) {
     m.max_big = base + 1;
     uint32_t *w = (uint32_t *)(base + 2);
     m.n_big = w;
-    m.d_count = w + 2;
+    m.d_count = base + 7;
     m.d_overflow = w + 3;
     m.n_cand = w + 4;
     m.n_edges = w + 5;
@@ -296,8 +296,9 @@ pastis_status discover(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, 
     uint64_t want = std::max<uint64_t>({(uint64_t)4 * n, 1ull << 20, ctx->last_n_dir + ctx->last_n_dir / 4});
     if (dir_ub <= (1ull << 28)) want = std::max(want, dir_ub);
     if (P.candidate_room > 0) want = (uint64_t)P.candidate_room;  // the caller's setting
-    uint32_t cap = (uint32_t)std::min<uint64_t>({want, dir_ub, 0xFFFFFFF0ull});
-    for (;;) {
+    constexpr uint64_t kMaxDir = 0xFFFFFFF0ull;  // entries are indexed with 32 bits downstream
+    uint32_t cap = (uint32_t)std::min<uint64_t>({want, dir_ub, kMaxDir});
+    for (int attempt = 0;; ++attempt) {
         sp.cap = cap;
         PASTIS_TRY(get(ctx, kDDirKey, cap, &sp.d_key));
         PASTIS_TRY(get(ctx, kDDirCnt, cap, &sp.d_cnt));
@@ -309,21 +310,31 @@ pastis_status discover(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, 
         uint32_t nb0 = 0;
         PASTIS_TRY(read_device(ctx, sp.n_big, &nb0, sizeof(nb0), s));
         HIP_TRY(ctx, spgemm_run(sp, gcap, s), "product kernels");
-        uint32_t got[2];
-        PASTIS_TRY(read_device(ctx, M.d_count, got, sizeof(got), s));
-        if (!got[1]) break;
-        cap = (uint32_t)std::min<uint64_t>((uint64_t)got[0] + got[0] / 4 + 1024, 0xFFFFFFF0ull);
+        uint32_t ovf = 0;
+        PASTIS_TRY(read_device(ctx, M.d_overflow, &ovf, sizeof(ovf), s));
+        if (!ovf) break;
+        // the 64-bit counter holds every entry the run asked for, so one redo
+        // with that much room succeeds; a count beyond 32-bit indexing cannot
+        unsigned long long need = 0;
+        PASTIS_TRY(read_device(ctx, M.d_count, &need, sizeof(need), s));
+        if (need > kMaxDir || attempt >= 2)
+            return set_error(ctx, PASTIS_E_CAPACITY,
+                             "candidate discovery produced " + std::to_string(need) +
+                                 " directional entries; at most " + std::to_string(kMaxDir) +
+                                 " fit one call (split the sequences or raise ck_min)");
+        cap = (uint32_t)std::min<uint64_t>(need + need / 4 + 1024, kMaxDir);
         // redo from the planned state: restore the big-row count of the plan
         HIP_TRY(ctx, fill<uint32_t>(sp.n_big, 1, nb0, s), "reset");
     }
-    uint32_t n_dir = 0;
-    PASTIS_TRY(read_device(ctx, M.d_count, &n_dir, sizeof(n_dir), s));
+    unsigned long long n_dir64 = 0;
+    PASTIS_TRY(read_device(ctx, M.d_count, &n_dir64, sizeof(n_dir64), s));
+    const uint32_t n_dir = (uint32_t)n_dir64;  // <= cap <= kMaxDir after a run without overflow
     ctx->last_n_dir = n_dir;
 
     // ---- symmetrise, sort, threshold already applied
     SymArgs sy{};
     sy.n_dir = n_dir;
-    sy.d_ndir = M.d_count;
+    sy.d_ndir = (const uint32_t *)M.d_count;  // low word (little-endian), below 2^32 here
     sy.key = sp.d_key;
     PASTIS_TRY(get(ctx, kDDirKeyAlt, n_dir, &sy.key_alt));
     PASTIS_TRY(get(ctx, kDPerm, n_dir, &sy.perm));
@@ -533,6 +544,54 @@ pastis_status pastis_search(pastis_ctx *ctx, const uint8_t *residues, const int6
     ctx->stats.n_edges = ne;
     ctx->stats.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     *out = res;
+    return PASTIS_OK;
+}
+
+pastis_status pastis_mlp_collect(pastis_ctx *ctx, const uint8_t *residues, const int64_t *offsets, int64_t n,
+                                 int input_on_device, const pastis_params *discovery, void *stream,
+                                 int64_t *n_added) {
+    if (!ctx) return PASTIS_E_INVAL;
+    if (n_added) *n_added = 0;
+    hipStream_t s = (hipStream_t)stream;
+    // this collection's discovery parameters, and an alignment that only
+    // decides the cut (no filter, no graph, records kept inside)
+    struct Restore {
+        pastis_ctx *c;
+        pastis_params p;
+        ~Restore() { c->params = p; }
+    } restore{ctx, ctx->params};
+    pastis_params &P = ctx->params;
+    if (discovery) {
+        if (discovery->k < 1 || discovery->k > kMaxK) return set_error(ctx, PASTIS_E_INVAL, "discovery k out of range");
+        if (discovery->n_subs < 0 || discovery->n_subs > 64)
+            return set_error(ctx, PASTIS_E_INVAL, "discovery n_subs must be in 0..64");
+        if (discovery->sub_alphabet != 20 && discovery->sub_alphabet != 24)
+            return set_error(ctx, PASTIS_E_INVAL, "discovery sub_alphabet must be 20 or 24");
+        if (discovery->ck_min < 1) return set_error(ctx, PASTIS_E_INVAL, "discovery ck_min must be >= 1");
+        P.k = discovery->k;
+        P.n_subs = discovery->n_subs;
+        P.sub_alphabet = discovery->sub_alphabet;
+        P.ck_min = discovery->ck_min;
+    }
+    P.weight_mode = PASTIS_WEIGHT_ANI;
+    P.filter_mode = 0;
+    P.full_records = 0;
+    P.graph_mode = 0;
+    auto t0 = std::chrono::steady_clock::now();
+    PASTIS_TRY(begin_call(ctx));
+    ctx->have_candidates = false;
+    Staged st;
+    uint8_t *codes = nullptr;
+    PASTIS_TRY(stage_and_encode(ctx, residues, offsets, n, input_on_device, s, st, &codes));
+    int64_t nc = 0;
+    PASTIS_TRY(discover(ctx, st, codes, n, s, &nc));
+    pastis_pair_record *rec = nullptr;
+    PASTIS_TRY(align_candidates(ctx, st, codes, n, s, &rec));
+    int64_t added = 0;
+    PASTIS_TRY(mlp_pool_append(ctx, st, codes, n, rec, s, &added));
+    HIP_TRY(ctx, stage_collect(ctx, s), "sync");
+    ctx->stats.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (n_added) *n_added = added;
     return PASTIS_OK;
 }
 

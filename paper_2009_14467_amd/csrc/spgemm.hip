@@ -70,7 +70,7 @@ struct Postings {
 };
 
 struct Emit {
-    uint32_t *count;  // device counter
+    unsigned long long *count;  // device counter (64-bit: it keeps counting past cap without wrapping)
     uint32_t *overflow;
     uint64_t *key;
     uint32_t *cnt, *s1, *s2, *dir;
@@ -89,7 +89,7 @@ __device__ __forceinline__ uint32_t seed_key(uint32_t i, uint32_t j, uint32_t pi
 }
 
 __device__ __forceinline__ void emit(const Emit &em, uint32_t i, uint32_t j, uint32_t c, uint32_t a, uint32_t b) {
-    const uint32_t slot = atomicAdd(em.count, 1u);
+    const unsigned long long slot = atomicAdd(em.count, 1ull);
     if (slot >= em.cap) {
         atomicOr(em.overflow, 1u);
         return;
@@ -249,12 +249,13 @@ __global__ __launch_bounds__(kThreads) void spgemm_lds_kernel(RowView rv, Postin
         } else if (L.ncand > 0) {
             const uint32_t nc = L.ncand;
             if (threadIdx.x == 0) {
-                uint32_t b = atomicAdd(em.count, nc);
-                if (b + (uint64_t)nc > em.cap) {
+                const unsigned long long b = atomicAdd(em.count, (unsigned long long)nc);
+                if (b + nc > em.cap) {
                     atomicOr(em.overflow, 1u);  // the call is redone with more room
-                    b = kEmpty;
+                    L.base = kEmpty;
+                } else {
+                    L.base = (uint32_t)b;
                 }
-                L.base = b;
             }
             __syncthreads();
             const uint32_t base = L.base;
@@ -703,7 +704,7 @@ hipError_t spgemm_run(const SpgemmArgs &a, uint32_t gcap, hipStream_t s) {
     Postings P{a.kt->uk_start, a.post_rec};
     Emit em{a.d_count, a.d_overflow, a.d_key, a.d_cnt, a.d_s1, a.d_s2, a.d_dir, a.cap, a.nbits};
     hipError_t e;
-    if ((e = fill<uint32_t>(a.d_count, 1, 0u, s)) != hipSuccess) return e;
+    if ((e = fill<unsigned long long>(a.d_count, 1, 0ull, s)) != hipSuccess) return e;
     if ((e = fill<uint32_t>(a.d_overflow, 1, 0u, s)) != hipSuccess) return e;
     // spilled rows (too many candidates for LDS) join the big-row list
     // LDS per block: 51 KB (three blocks per CU), 78 KB (two), 150 KB (one)

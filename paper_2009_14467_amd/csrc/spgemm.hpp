@@ -64,7 +64,8 @@ struct SpgemmArgs {
     uint2 *post_rec;
     int64_t nnz;
     // directional entries
-    uint32_t *d_count, *d_overflow;
+    unsigned long long *d_count;  // directional entries requested (may exceed cap)
+    uint32_t *d_overflow;
     uint64_t *d_key;
     uint32_t *d_cnt, *d_s1, *d_s2, *d_dir;
     uint32_t cap;

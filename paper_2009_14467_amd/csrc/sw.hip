@@ -1709,6 +1709,8 @@ static int blocks_for_bin(int bin) {
 
 // Only the multi-strip bins use the boundary buffers (one per wave of the
 // grid, 32-bit or 16-bit kernel).
+int sw_one_strip_max_rows() { return kWave * kSingleBins; }
+
 int64_t sw_scratch_waves() {
     int64_t w = 0;
     for (int b = kMultiBin; b < kNumBins; ++b) {
@@ -1719,7 +1721,12 @@ int64_t sw_scratch_waves() {
     return w;
 }
 
-bool sw16_supported(const Scoring &sc) { return sc.gap_open + sc.gap_extend >= 4; }
+// The 16-bit profile holds each biased score s + o + e in one byte, with
+// s <= 11 in BLOSUM62; other gap costs run in 32-bit lanes.
+bool sw16_supported(const Scoring &sc) {
+    const int oe = sc.gap_open + sc.gap_extend;
+    return oe >= 4 && oe + 11 <= 255;
+}
 
 bool sw_bin_is16(int bin, int max16) {
     return (bin < kSingleBins || bin >= kMulti16Bin) && rows_of_bin(bin) <= max16;

@@ -22,4 +22,5 @@ def test_defaults(monkeypatch):
 
     monkeypatch.setattr(sys, "argv", ["bench.py"])
     a = bench.parse()
-    assert (a.gpus, a.steps, a.warmup, a.workload, a.pairs) == (1, 3, 1, "mid", 0)
+    assert (a.gpus, a.steps, a.warmup, a.workload, a.pairs) == (1, 3, 1, "large", 0)
+    assert not a.no_autotune and not a.no_graph and not a.no_mlp

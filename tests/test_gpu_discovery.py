@@ -123,6 +123,21 @@ def test_substitutes(gpu, orc, k, m, ck, alpha):
     _compare(got, want)
 
 
+def test_heavy_tail_discovery_k5_m25(gpu, orc):
+    """The heavy-tail setting: k = 5 with 25 substitute k-mers, >= 2 shared,
+    on the heavy recipe (40% divergence) scaled to 16 families, one of which
+    descends from a 28k-residue ancestor, so A S rows of tens of thousands of
+    entries and k = 5 postings shared by many sequences are both present."""
+    from synth import workload
+
+    s = workload("heavy", n_families=16)
+    assert np.diff(s.offsets).max() > 20000
+    want = orc.candidates(orc.encode(s.residues), s.offsets, 5, ck_min=2, n_subs=25)
+    assert len(want["lo"]) > 20000
+    got = _gpu_candidates(gpu, s.residues, s.offsets, k=5, ck_min=2, n_subs=25)
+    _compare(got, want)
+
+
 def test_substitutes_m0_equals_exact(gpu, orc):
     s = _random_set(3, 60, 0, 50, "ACDEF")
     a = _gpu_candidates(gpu, s.residues, s.offsets, k=3, ck_min=1, n_subs=0)

@@ -1,8 +1,13 @@
-"""Parity at the benchmark's full size: the mid workload (50,000 sequences,
-2,000 families x 25, k = 6 with 25 substitute k-mers, >= 2 shared) in the
-launch configuration bench.py times (one pastis_search).
+"""Parity at the benchmark's full sizes, in the launch configurations
+bench.py times (one pastis_search):
+  * large: 250,000 sequences (10,000 families x 20 + 50,000 singletons,
+    lengths up to 5,000), exact 6-mers, >= 2 shared; schedule chosen by the
+    autotuner and the SW stage replayed as a captured HIP graph;
+  * mid: 50,000 sequences (2,000 families x 25), 25 substitute 6-mers,
+    >= 2 shared; the library's schedule, direct launches.
+Both are searched with SW and with XD.
 
-The oracle cannot redo the whole search in test time, so it computes sampled
+The oracle cannot redo a whole search in test time, so it computes sampled
 pairs one by one: every same-family pair of 24 random families, and 3,000
 random pairs.  The sample is drawn from the generator's labels and a seeded
 RNG, never from the GPU's output.  Properties that hold at any size are
@@ -13,7 +18,7 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 
-PARAMS = dict(k=6, n_subs=25, ck_min=2)
+PARAMS = {"mid": dict(k=6, n_subs=25, ck_min=2), "large": dict(k=6, n_subs=0, ck_min=2)}
 
 
 def _dev(x, gpu):
@@ -29,17 +34,27 @@ def _key(lo, hi):
     return (np.asarray(lo, np.uint64) << np.uint64(32)) | np.asarray(hi, np.uint64)
 
 
-@pytest.fixture(scope="module")
-def mid(gpu, orc):
+@pytest.fixture(scope="module", params=["mid", "large"])
+def mid(request, gpu, orc):
     import paper_2009_14467_amd as P
     from synth import workload
 
-    s = workload("mid")
+    name = request.param
+    prm = PARAMS[name]
+    s = workload(name)
     res, off = _dev(s.residues, gpu), _dev(s.offsets, gpu)
-    ctx = P.Context(P.Params(**PARAMS))
+    if name == "large":
+        ctx = P.Context(P.Params(graph_mode=True, **prm))
+        ctx.autotune(res, off, max_pairs=400_000)
+    else:
+        ctx = P.Context(P.Params(**prm))
     edges = ctx.search(res, off)
+    if name == "large":
+        assert ctx.search(res, off).tobytes() == edges.tobytes()  # a replay of the captured graph
+        assert ctx.stats()["sw_graph"] > 0
     st = ctx.stats()
     nc = int(st["n_candidates"])
+    xd_edges = P.Context(P.Params(align_mode="xd", **prm)).search(res, off)
     c = {k: v.cpu().numpy().view(np.uint32) for k, v in ctx.candidates(nc).items()}
     codes = orc.encode(s.residues)
     # the sample: all pairs inside 24 random families, and random pairs
@@ -60,8 +75,9 @@ def mid(gpu, orc):
     hi = np.concatenate(hi).astype(np.uint32)
     k = np.unique(_key(lo, hi))
     lo, hi = (k >> np.uint64(32)).astype(np.uint32), (k & np.uint64(0xFFFFFFFF)).astype(np.uint32)
-    want = orc.pair_counts(codes, s.offsets, lo, hi, PARAMS["k"], n_subs=PARAMS["n_subs"])
-    return dict(s=s, res=res, off=off, edges=edges, stats=st, cand=c, codes=codes, lo=lo, hi=hi, want=want)
+    want = orc.pair_counts(codes, s.offsets, lo, hi, prm["k"], n_subs=prm["n_subs"])
+    return dict(s=s, res=res, off=off, edges=edges, xd_edges=xd_edges, stats=st, cand=c, codes=codes, lo=lo, hi=hi,
+                want=want, prm=prm, name=name)
 
 
 def test_candidates_on_sampled_pairs(mid):
@@ -72,7 +88,7 @@ def test_candidates_on_sampled_pairs(mid):
     q = _key(mid["lo"], mid["hi"])
     at = np.minimum(np.searchsorted(skeys, q), skeys.size - 1)
     found = skeys[at] == q
-    expect = want["count"] >= PARAMS["ck_min"]
+    expect = want["count"] >= mid["prm"]["ck_min"]
     assert expect.sum() > 2000  # family pairs and chance candidates are both present
     np.testing.assert_array_equal(found, expect)
     g = order[at[found]]
@@ -86,24 +102,26 @@ def test_candidate_set_properties(mid):
     assert (c["lo"] < c["hi"]).all() and (c["hi"] < s.n).all()
     keys = _key(c["lo"], c["hi"])
     assert np.unique(keys).size == keys.size
-    assert (c["count"] >= PARAMS["ck_min"]).all()
+    prm = mid["prm"]
+    assert (c["count"] >= prm["ck_min"]).all()
     # two shared k-mers give two distinct seed keys, inside both sequences
     assert (c["seed1"] < c["seed2"]).all() and (c["seed2"] != 0xFFFFFFFF).all()
     for f in ("seed1", "seed2"):
         p_lo, p_hi = c[f] >> 16, c[f] & 0xFFFF
-        assert (p_lo <= L[c["lo"]] - PARAMS["k"]).all() and (p_hi <= L[c["hi"]] - PARAMS["k"]).all()
+        assert (p_lo <= L[c["lo"]] - prm["k"]).all() and (p_hi <= L[c["hi"]] - prm["k"]).all()
 
 
-def test_edges_on_sampled_pairs(mid, orc):
+@pytest.mark.parametrize("mode", ["sw", "xd"])
+def test_edges_on_sampled_pairs(mid, orc, mode):
     from test_gpu_search import _compare_edges
 
-    s, want = mid["s"], mid["want"]
-    cand = want["count"] >= PARAMS["ck_min"]
+    s, want, prm = mid["s"], mid["want"], mid["prm"]
+    cand = want["count"] >= prm["ck_min"]
     lo, hi = mid["lo"][cand], mid["hi"][cand]
-    rec = orc.align_pairs(mid["codes"], s.offsets, lo, hi, want["seed1"][cand], want["seed2"][cand], mode="sw",
-                          k=PARAMS["k"])
+    rec = orc.align_pairs(mid["codes"], s.offsets, lo, hi, want["seed1"][cand], want["seed2"][cand], mode=mode,
+                          k=prm["k"])
     oe = orc.records_to_edges(lo, hi, want["count"][cand], rec, np.diff(s.offsets))
-    e = mid["edges"]
+    e = mid["edges"] if mode == "sw" else mid["xd_edges"]
     sel = np.isin(_key(e["i"], e["j"]), _key(mid["lo"], mid["hi"]))
     assert oe.size > 1000
     _compare_edges(e[sel], oe)
@@ -142,8 +160,8 @@ def test_align_pairs_sample(gpu, mid, orc, mode):
     pick = np.sort(rng.choice(mid["lo"].size, 2000, replace=False))
     lo, hi = mid["lo"][pick], mid["hi"][pick]
     s1, s2 = want["seed1"][pick], want["seed2"][pick]
-    ref = orc.align_pairs(mid["codes"], s.offsets, lo, hi, s1, s2, mode=mode, k=PARAMS["k"])
-    ctx = P.Context(P.Params(align_mode=mode, full_records=True, **PARAMS))
+    ref = orc.align_pairs(mid["codes"], s.offsets, lo, hi, s1, s2, mode=mode, k=mid["prm"]["k"])
+    ctx = P.Context(P.Params(align_mode=mode, full_records=True, **mid["prm"]))
     got = P.records_to_numpy(ctx.align_pairs(mid["res"], mid["off"], _dev(lo, gpu), _dev(hi, gpu), _dev(s1, gpu),
                                              _dev(s2, gpu)))
     assert FIELDS[-1] == "cells"

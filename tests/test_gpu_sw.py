@@ -345,3 +345,24 @@ def test_rejects_sequences_beyond_u16_positions(gpu):
     ctx = P.Context(P.Params())
     with pytest.raises(P.PastisError):
         ctx.search(_to_dev(s.residues, gpu), _to_dev(s.offsets, gpu))
+
+
+@pytest.mark.parametrize("go,ge", [(5, 2), (250, 10), (2, 1), (240, 4)])
+def test_sw_other_gap_costs(gpu, orc, tiny, go, ge):
+    """Gap costs away from 11/1: the 16-bit profile holds s + o + e in a byte,
+    so o + e above 244 (and below 4) must run in 32-bit lanes; every width and
+    record mode still matches the oracle, and so do the search's edges."""
+    import paper_2009_14467_amd as P
+
+    s, cand, _ = tiny
+    codes = orc.encode(s.residues)
+    want = orc.align_pairs(codes, s.offsets, cand["lo"], cand["hi"], mode="sw", gap_open=go, gap_extend=ge)
+    gaps = dict(gap_open=go, gap_extend=ge)
+    _compare(_gpu_records(gpu, s, cand["lo"], cand["hi"], full_records=True, **gaps), want)
+    for width in (0, 16, 32):
+        _check16(_gpu_records(gpu, s, cand["lo"], cand["hi"], score_width=width, **gaps), want)
+    res, off = _to_dev(s.residues, gpu), _to_dev(s.offsets, gpu)
+    want_e = orc.search(s.residues, s.offsets, k=6, ck_min=1, mode="sw", **gaps)
+    for width in (0, 16):
+        got_e = P.Context(P.Params(k=6, ck_min=1, score_width=width, **gaps)).search(res, off)
+        assert got_e.size == want_e.size and got_e.tobytes() == want_e.tobytes()

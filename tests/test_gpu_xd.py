@@ -88,14 +88,17 @@ def test_xd_seed_positions_and_missing_seeds(gpu, orc):
     _compare(got, want)
 
 
-def test_search_xd_tiny(gpu, orc):
+@pytest.mark.parametrize("weight", ["ani", "ns"])
+def test_search_xd_tiny(gpu, orc, weight):
+    """XD search edges against the oracle, with the identity weight and cut,
+    and with the normalised score (no cut, no traceback fields)."""
     import paper_2009_14467_amd as P
     from synth import workload
 
     from test_gpu_search import _compare_edges
 
     s = workload("tiny")
-    want = orc.search(s.residues, s.offsets, k=6, ck_min=1, mode="xd")
-    ctx = P.Context(P.Params(k=6, ck_min=1, align_mode="xd"))
+    want = orc.search(s.residues, s.offsets, k=6, ck_min=1, mode="xd", weight=weight)
+    ctx = P.Context(P.Params(k=6, ck_min=1, align_mode="xd", weight_mode=weight))
     got = ctx.search(_dev(s.residues, gpu), _dev(s.offsets, gpu))
     _compare_edges(got, want)

@@ -203,6 +203,28 @@ pastis_status pastis_align_pairs(pastis_ctx *ctx, const uint8_t *residues, const
                                  int input_on_device, const uint32_t *pi, const uint32_t *pj, const uint32_t *seed1,
                                  const uint32_t *seed2, int64_t npairs, pastis_pair_record *out, void *stream);
 
+/* pastis_align_pairs for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and records, with every buffer of the call
+ * carved from a static workspace of PASTIS_NOALLOC_BYTES per GPU (held
+ * until the process ends) instead of the context's allocations.  Inputs and
+ * outputs as for pastis_align_pairs with input_on_device = 1: residues,
+ * offsets, pi, pj, seeds and out are all device memory, borrowed until the
+ * stream reaches the end of the call's work.  Smith-Waterman only
+ * (align_mode SW), direct launches (graph_mode is ignored).  The workspace
+ * holds the residue codes (one byte each) and about 100 bytes per pair;
+ * every sequence of the set must have at most 1,024 residues (longer ones
+ * need boundary rows of the long-sequence bins, tens of MiB per residue of
+ * length).  A call that needs more than the workspace returns
+ * PASTIS_E_CAPACITY without writing out.  Calls that overlap on one GPU (from
+ * any context or thread) race on the workspace and must not be issued.
+ * Errors otherwise as for pastis_align_pairs. */
+#define PASTIS_NOALLOC_BYTES (48u << 20)
+pastis_status pastis_align_pairs_noalloc(pastis_ctx *ctx, const uint8_t *residues, const int64_t *offsets, int64_t n,
+                                         const uint32_t *pi, const uint32_t *pj, const uint32_t *seed1,
+                                         const uint32_t *seed2, int64_t npairs, pastis_pair_record *out,
+                                         void *stream);
+
 /* Candidate discovery (Sections IV-A to IV-C, threshold of Section VI): k-mers
  * of every sequence (A), the m nearest substitutes of every distinct k-mer
  * when n_subs > 0 (S), the sparse product A A^T or (A S) A^T under the count +

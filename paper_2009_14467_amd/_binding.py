@@ -216,6 +216,8 @@ _SIGNATURES = [
     ("pastis_encode", ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int, _VP, _VP]),
     ("pastis_align_pairs", ctypes.c_int,
      [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_int, _VP, _VP, _VP, _VP, ctypes.c_int64, _VP, _VP]),
+    ("pastis_align_pairs_noalloc", ctypes.c_int,
+     [_VP, _VP, _VP, ctypes.c_int64, _VP, _VP, _VP, _VP, ctypes.c_int64, _VP, _VP]),
     ("pastis_stats", ctypes.c_int, [_VP, ctypes.POINTER(_Stats)]),
     ("pastis_discover", ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_int, _VP, ctypes.POINTER(ctypes.c_int64)]),
     ("pastis_candidates_copy", ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_int64, ctypes.c_int, _VP]),

@@ -1,6 +1,7 @@
 // C ABI entry points: context, staging, error handling, and the align stage.
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 
 #include "internal.hpp"
 #include "prim.hpp"
@@ -20,6 +21,24 @@ pastis_status hip_error(pastis_ctx *ctx, hipError_t e, const char *what) {
 
 pastis_status ensure(pastis_ctx *ctx, int id, size_t bytes, void **out) {
     if (bytes == 0) bytes = 256;
+    if (ctx->arena) {
+        // a no-allocation call: carve the buffer from the device workspace
+        // (once per id and call, as the cached buffers are grow-only)
+        if (ctx->arena_len[id] >= bytes) {
+            *out = ctx->arena + ctx->arena_off[id];
+            return PASTIS_OK;
+        }
+        const size_t off = (ctx->arena_used + 255) & ~(size_t)255;
+        if (off + bytes > ctx->arena_cap)
+            return set_error(ctx, PASTIS_E_CAPACITY,
+                             "the call needs more than the " + std::to_string(ctx->arena_cap) +
+                                 " bytes of the no-allocation workspace");
+        ctx->arena_off[id] = off;
+        ctx->arena_len[id] = bytes;
+        ctx->arena_used = off + bytes;
+        *out = ctx->arena + off;
+        return PASTIS_OK;
+    }
     DeviceBuffer &b = ctx->buf[id];
     if (b.bytes < bytes) {
         if (b.ptr) {
@@ -41,6 +60,8 @@ pastis_status ensure(pastis_ctx *ctx, int id, size_t bytes, void **out) {
 }
 
 pastis_status ensure_pinned(pastis_ctx *ctx, size_t bytes, void **out) {
+    if (ctx->arena && ctx->h_pinned_bytes < bytes)
+        return set_error(ctx, PASTIS_E_INVAL, "a no-allocation call takes device inputs and outputs only");
     if (ctx->h_pinned_bytes < bytes) {
         if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
         ctx->h_pinned = nullptr;
@@ -77,6 +98,31 @@ hipError_t stage_collect(pastis_ctx *ctx, hipStream_t s) {
 }  // namespace pastis
 
 namespace {
+
+// Workspace of pastis_align_pairs_noalloc: every buffer such a call uses is
+// carved from it.  Each GPU holds its own copy until the process ends; all
+// calls on one GPU share it.  Host code reaches it only through the address
+// hipGetSymbolAddress gives for the current device (the array's name is a
+// host-side stand-in there).
+static __device__ __align__(256) unsigned char scratch[PASTIS_NOALLOC_BYTES];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};
+
+// This device's address of the workspace, looked up once per device with
+// the device current (context creation).
+hipError_t bind_scratch(int device, char **out) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = (char *)p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
 
 pastis_status validate(const pastis_params *p, std::string &why) {
     if (p->k < 1 || p->k > 6) return why = "k must be in 1..6", PASTIS_E_INVAL;
@@ -437,6 +483,11 @@ pastis_status pastis_create(const pastis_params *p, int device, pastis_ctx **out
     pastis_ctx *ctx = new pastis_ctx();
     ctx->params = *p;
     ctx->device = device;
+    if (bind_scratch(device, &ctx->noalloc_ws) != hipSuccess) {
+        (void)hipGetLastError();
+        delete ctx;
+        return PASTIS_E_DEVICE;
+    }
     // 25 x 25 scoring table: residues 0..23 plus the pad code, whose scores
     // are the most negative int8 so padded cells never raise a maximum.
     int8_t table[25 * 25];
@@ -596,6 +647,32 @@ pastis_status pastis_align_pairs(pastis_ctx *ctx, const uint8_t *residues, const
                                  const uint32_t *seed2, int64_t npairs, pastis_pair_record *out, void *stream) {
     if (!ctx) return PASTIS_E_INVAL;
     return align_pairs_impl(ctx, residues, offsets, n, input_on_device, pi, pj, seed1, seed2, npairs, out, stream);
+}
+
+pastis_status pastis_align_pairs_noalloc(pastis_ctx *ctx, const uint8_t *residues, const int64_t *offsets, int64_t n,
+                                         const uint32_t *pi, const uint32_t *pj, const uint32_t *seed1,
+                                         const uint32_t *seed2, int64_t npairs, pastis_pair_record *out,
+                                         void *stream) {
+    if (!ctx) return PASTIS_E_INVAL;
+    if (ctx->params.align_mode != PASTIS_ALIGN_SW)
+        return set_error(ctx, PASTIS_E_INVAL, "the no-allocation entry point runs Smith-Waterman only");
+    if (!ctx->noalloc_ws) return set_error(ctx, PASTIS_E_STATE, "no workspace bound to this context");
+    // every buffer of this call comes from the device's workspace; graph
+    // mode (whose instantiation allocates) is off for the call
+    struct Guard {
+        pastis_ctx *c;
+        int32_t graph;
+        ~Guard() {
+            c->arena = nullptr;
+            c->params.graph_mode = graph;
+        }
+    } guard{ctx, ctx->params.graph_mode};
+    ctx->params.graph_mode = 0;
+    ctx->arena = ctx->noalloc_ws;
+    ctx->arena_cap = PASTIS_NOALLOC_BYTES;
+    ctx->arena_used = 0;
+    memset(ctx->arena_len, 0, sizeof(ctx->arena_len));
+    return align_pairs_impl(ctx, residues, offsets, n, 1, pi, pj, seed1, seed2, npairs, out, stream);
 }
 
 }  // extern "C"

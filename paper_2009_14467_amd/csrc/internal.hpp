@@ -129,6 +129,12 @@ struct pastis_ctx {
     hipGraphExec_t sw_exec = nullptr;
     uint64_t sw_key = 0;
     bool ev_used[9] = {};
+    // no-allocation calls: while arena is set, every buffer of the call is
+    // carved from it (the per-device static workspace) instead of allocated
+    char *arena = nullptr;
+    char *noalloc_ws = nullptr;  // this device's workspace (pastis_align_pairs_noalloc)
+    size_t arena_cap = 0, arena_used = 0;
+    size_t arena_off[128] = {}, arena_len[128] = {};
 };
 
 namespace pastis {

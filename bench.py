@@ -173,7 +173,7 @@ def cpu_baseline(fs, lo, hi, target_s):
 def set_tuning(ctx, tuning):
     if isinstance(tuning, dict):
         ctx.set_tuning(**{k: tuning[k] for k in ("sw16_max_rows", "sw_direct_pct", "sw_grid_scale",
-                                                  "sw_grid_scale_wide", "sw_intra_pair")})
+                                                  "sw_grid_scale_wide", "sw_intra_pair", "sw16_narrow_rows")})
 
 
 def timed_steps(ctx, args, res, off):

@@ -63,7 +63,10 @@ typedef enum pastis_weight_mode {
  * settings of Section VI: k = 6, BLOSUM62, gap open 11, gap extend 1,
  * x-drop 49, identity >= 30%, coverage >= 70%. */
 typedef struct pastis_params {
-    int32_t k;                /* k-mer length, 1..6 */
+    int32_t k;                /* k-mer length, 1..8 (k <= 6 indexes a dense 24^k map of
+                                 k-mer ids; longer k-mers, whose id space is too large
+                                 for one, are found by binary search over the sorted
+                                 distinct ids of the data) */
     int32_t n_subs;           /* m substitute k-mers per k-mer (0 = exact k-mers), 0..64 */
     int32_t sub_alphabet;     /* residues substitutes are drawn from: 20 (standard) or 24 */
     int32_t ck_min;           /* keep candidate pairs sharing >= ck_min k-mers (>= 1) */
@@ -245,11 +248,12 @@ pastis_status pastis_candidates_copy(pastis_ctx *ctx, uint32_t *lo, uint32_t *hi
                                      uint32_t *seed2, int64_t cap, int dst_on_device, void *stream);
 
 /* The ctx's n_subs nearest substitutes (Section IV-B) of n k-mer ids (radix
- * 24 over the context's k), all device arrays: out_ids / out_dist [n][n_subs],
- * out_count [n] = entries written per k-mer (n_subs unless the k-mer space is
- * smaller).  Within a k-mer the entries are not ordered.
+ * 24 over the context's k, 64-bit: up to 24^8), all device arrays:
+ * out_ids / out_dist [n][n_subs], out_count [n] = entries written per k-mer
+ * (n_subs unless the k-mer space is smaller).  Within a k-mer the entries
+ * are not ordered.
  * Errors: PASTIS_E_INVAL (n_subs == 0 or bad arguments), PASTIS_E_DEVICE. */
-pastis_status pastis_subkmers(pastis_ctx *ctx, const uint32_t *kmer_ids, int64_t n, uint32_t *out_ids,
+pastis_status pastis_subkmers(pastis_ctx *ctx, const uint64_t *kmer_ids, int64_t n, uint64_t *out_ids,
                               int32_t *out_dist, int32_t *out_count, void *stream);
 
 /* Sequences in, weighted similarity edges out (Section II problem, Section IV
@@ -388,7 +392,7 @@ pastis_status pastis_mlp_load(pastis_ctx *ctx, const char *path);
 
 /* ---- schedule of the Smith-Waterman stage ----
  * Knobs of the length-binned launches (every setting gives the same results;
- * only the time changes).  A new context starts at {16, 50, 1, 1, 0}.  pastis_autotune times candidate settings on a
+ * only the time changes).  A new context starts at {16, 50, 1, 1, 0, 4}.  pastis_autotune times candidate settings on a
  * sample of the given sequences' own candidate pairs and keeps the fastest. */
 typedef struct pastis_tuning {
     int32_t sw16_max_rows; /* bins with at most this many rows per lane run two pairs per
@@ -407,20 +411,50 @@ typedef struct pastis_tuning {
                               runs one workgroup of four waves per pair, strips
                               pipelined across the waves (intra-pair mode); 0: one
                               wave per pair (inter-pair mode) */
-    int32_t reserved[3];
+    int32_t sw16_narrow_rows; /* pairs per wavefront of the 16-bit bins of at most 4 rows per
+                                 lane: bins of at most this many rows per lane (0..4) run
+                                 strips of 16 lanes, eight pairs per wave; the others
+                                 strips of 32 lanes, four pairs per wave (a wave's pairs
+                                 share their shorter sequence, so sets with few candidates
+                                 per sequence fill fewer slots of the wider grouping) */
+    int32_t reserved[2];
 } pastis_tuning;
 
 pastis_status pastis_get_tuning(const pastis_ctx *ctx, pastis_tuning *out);
 /* PASTIS_E_INVAL for values out of range. */
 pastis_status pastis_set_tuning(pastis_ctx *ctx, const pastis_tuning *t);
 /* Discovery on the given sequences, then for each knob in turn (16-bit rows,
- * start-bound routing, the two grid scales) the alignment of up to max_pairs of the
- * candidates (an even stride through them) under each candidate value, twice,
- * timed with HIP events on the stream; the fastest setting is kept in ctx and
- * written to *out (may be NULL).  A value replaces the one in force only when
- * it is at least 1% faster on the sample.  The discovery's candidates stay in ctx. */
+ * start-bound routing, the two grid scales, inter- vs intra-pair mode, pairs
+ * per wavefront) the alignment of a sample of the candidates under each
+ * candidate value, twice, timed with HIP events on the stream; the fastest
+ * setting is kept in ctx and written to *out (may be NULL).  The sample is
+ * every candidate whose shorter sequence falls in a hashed subset of the
+ * sequences sized for about max_pairs candidates (at most max_pairs), so the
+ * pairs that share a sequence stay together as in the whole set.  A value
+ * replaces the one in force only when it is at least 1% faster on the
+ * sample.  The discovery's candidates stay in ctx. */
 pastis_status pastis_autotune(pastis_ctx *ctx, const uint8_t *residues, const int64_t *offsets, int64_t n,
                               int input_on_device, int64_t max_pairs, void *stream, pastis_tuning *out);
+
+/* ---- the similarity graph as families (Section VI-B, Table II) ---- */
+
+/* Connected components of the undirected graph on n vertices (sequences)
+ * with the given edges (device pastis_edge [n_edges], e.g. a search result's
+ * device pointer; only i and j are read).  label [n] (device) gets, for
+ * every vertex, the smallest vertex of its component.  PASTIS_E_INVAL if an
+ * endpoint is >= n (label is then undefined). */
+pastis_status pastis_components(pastis_ctx *ctx, const pastis_edge *edges, int64_t n_edges, int64_t n,
+                                uint32_t *label, void *stream);
+/* Weighted precision and recall (host doubles) of a clustering of n
+ * sequences against reference families, both per sequence on the device:
+ * cluster [n] uint32 labels < n, family [n] int32 < n, a negative family
+ * marking a sequence outside every family (a family of its own).  With n_cf
+ * the sequences of cluster c in family f: precision = sum_c max_f n_cf / n
+ * (clusters mixing families lose precision), recall = sum_f max_c n_cf / n
+ * (families split over clusters lose recall).  PASTIS_E_INVAL for labels or
+ * families >= n. */
+pastis_status pastis_cluster_scores(pastis_ctx *ctx, const uint32_t *cluster, const int32_t *family, int64_t n,
+                                    double *precision, double *recall, void *stream);
 
 /* Counters and per-stage times of the last pastis_search / pastis_align_pairs. */
 pastis_status pastis_stats(const pastis_ctx *ctx, pastis_run_stats *out);

@@ -94,7 +94,8 @@ class _Tuning(ctypes.Structure):
         ("sw_grid_scale", ctypes.c_int32),
         ("sw_grid_scale_wide", ctypes.c_int32),
         ("sw_intra_pair", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("sw16_narrow_rows", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 
@@ -128,7 +129,8 @@ class _TrainReport(ctypes.Structure):
 
 def _tuning_dict(t) -> dict:
     return {"sw16_max_rows": t.sw16_max_rows, "sw_direct_pct": t.sw_direct_pct, "sw_grid_scale": t.sw_grid_scale,
-            "sw_grid_scale_wide": t.sw_grid_scale_wide, "sw_intra_pair": t.sw_intra_pair}
+            "sw_grid_scale_wide": t.sw_grid_scale_wide, "sw_intra_pair": t.sw_intra_pair,
+            "sw16_narrow_rows": t.sw16_narrow_rows}
 
 
 class _Stats(ctypes.Structure):
@@ -244,6 +246,9 @@ _SIGNATURES = [
     ("pastis_mlp_train", ctypes.c_int, [_VP, ctypes.POINTER(_TrainOpts), _VP, ctypes.POINTER(_TrainReport)]),
     ("pastis_mlp_save", ctypes.c_int, [_VP, ctypes.c_char_p]),
     ("pastis_mlp_load", ctypes.c_int, [_VP, ctypes.c_char_p]),
+    ("pastis_components", ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int64, _VP, _VP]),
+    ("pastis_cluster_scores", ctypes.c_int,
+     [_VP, _VP, _VP, ctypes.c_int64, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _VP]),
     ("pastis_get_tuning", ctypes.c_int, [_VP, ctypes.POINTER(_Tuning)]),
     ("pastis_set_tuning", ctypes.c_int, [_VP, ctypes.POINTER(_Tuning)]),
     ("pastis_autotune", ctypes.c_int,
@@ -386,12 +391,14 @@ class Context:
         return {k: v[:n_candidates] for k, v in out.items()}
 
     def subkmers(self, kmer_ids, stream=None):
-        """kmer_ids: int32 device tensor of radix-24 ids -> (ids [n, m], dist [n, m], count [n])."""
+        """kmer_ids: int64 device tensor of radix-24 ids -> (ids [n, m] int64, dist [n, m], count [n])."""
         torch = _torch()
+        if kmer_ids.dtype != torch.int64:
+            raise ValueError("k-mer ids are 64-bit")
         n = kmer_ids.numel()
         m = self.params.n_subs
         dev = f"cuda:{self.device}"
-        ids = torch.empty((max(n, 1), m), dtype=torch.int32, device=dev)
+        ids = torch.empty((max(n, 1), m), dtype=torch.int64, device=dev)
         dist = torch.empty((max(n, 1), m), dtype=torch.int32, device=dev)
         cnt = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
         self._check(lib().pastis_subkmers(self._ctx, _dev_ptr(kmer_ids), n, _dev_ptr(ids), _dev_ptr(dist),
@@ -423,11 +430,11 @@ class Context:
         return _tuning_dict(t)
 
     def set_tuning(self, sw16_max_rows: int = 16, sw_direct_pct: int = 50, sw_grid_scale: int = 1,
-                   sw_grid_scale_wide: int = 1, sw_intra_pair: int = 0):
+                   sw_grid_scale_wide: int = 1, sw_intra_pair: int = 0, sw16_narrow_rows: int = 4):
         t = _Tuning()
         t.sw16_max_rows, t.sw_direct_pct = sw16_max_rows, sw_direct_pct
         t.sw_grid_scale, t.sw_grid_scale_wide = sw_grid_scale, sw_grid_scale_wide
-        t.sw_intra_pair = sw_intra_pair
+        t.sw_intra_pair, t.sw16_narrow_rows = sw_intra_pair, sw16_narrow_rows
         self._check(lib().pastis_set_tuning(self._ctx, ctypes.byref(t)))
 
     def autotune(self, residues, offsets, max_pairs: int = 1 << 21, stream=None) -> dict:
@@ -543,6 +550,30 @@ class Context:
 
     def mlp_load(self, path: str):
         self._check(lib().pastis_mlp_load(self._ctx, os.fsencode(path)))
+
+
+    # ---- the similarity graph as families ----
+
+    def components(self, edges, n: int, stream=None):
+        """Component labels [n] (device uint32 as int32: the smallest vertex of
+        each component) of the graph of `edges` (device uint8 tensor of
+        48-byte pastis_edge entries, or a pastis_result's device pointer
+        with its count as (ptr, count))."""
+        torch = _torch()
+        if isinstance(edges, tuple):
+            ptr, m = edges
+        else:
+            ptr, m = _dev_ptr(edges), edges.numel() // EDGE_DTYPE.itemsize
+        out = torch.empty(max(n, 1), dtype=torch.int32, device=f"cuda:{self.device}")
+        self._check(lib().pastis_components(self._ctx, ptr if m else None, m, n, _dev_ptr(out), _stream_ptr(stream)))
+        return out[:n]
+
+    def cluster_scores(self, cluster, family, stream=None):
+        """(weighted precision, weighted recall) of device labels against device families."""
+        p, r = ctypes.c_double(0), ctypes.c_double(0)
+        self._check(lib().pastis_cluster_scores(self._ctx, _dev_ptr(cluster), _dev_ptr(family), cluster.numel(),
+                                                ctypes.byref(p), ctypes.byref(r), _stream_ptr(stream)))
+        return p.value, r.value
 
 
 def records_to_numpy(t) -> np.ndarray:

@@ -11,7 +11,10 @@
 //   postings (A^T): post_seq / post_pos, grouped by distinct k-mer, sequences
 //                   ascending inside a group; uk_id / uk_start index the groups;
 //   rows (A):       row_start[n+1], row_u (distinct k-mer index), row_pos;
-//   kmap:           dense map id -> distinct k-mer index or -1 (24^k entries).
+//   kmap:           dense map id -> distinct k-mer index or -1 (24^k entries),
+//                   for k <= kDenseMapMaxK only.
+// Ids are 64-bit (24^8 < 2^37); a window that runs past its sequence gets
+// the key 24^k, which sorts after every id.
 #include "internal.hpp"
 #include "kmers.hpp"
 #include "prim.hpp"
@@ -33,15 +36,16 @@ __device__ __forceinline__ int64_t seq_of(const int64_t *__restrict__ offsets, i
 }
 
 __global__ void window_keys_kernel(const uint8_t *__restrict__ codes, const int64_t *__restrict__ offsets, int64_t n,
-                                   int64_t n_res, int k, uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+                                   int64_t n_res, int k, uint64_t invalid, uint64_t *__restrict__ keys,
+                                   uint32_t *__restrict__ vals) {
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_res;
          g += (int64_t)gridDim.x * blockDim.x) {
         // skip empty sequences: the owner of residue g is the last i with offsets[i] <= g
         const int64_t i = seq_of(offsets, n, g);
         const int64_t end = offsets[i + 1];
-        uint64_t key = kInvalidKmer;
+        uint64_t key = invalid;
         if (g + k <= end) {
-            uint32_t id = 0;
+            uint64_t id = 0;
             for (int t = 0; t < k; ++t) id = id * 24u + codes[g + t];
             key = id;
         }
@@ -53,11 +57,11 @@ __global__ void window_keys_kernel(const uint8_t *__restrict__ codes, const int6
 // For sorted position x: owning sequence, and whether x starts a new k-mer
 // group or a new (k-mer, sequence) run.
 __global__ void mark_kernel(const uint64_t *__restrict__ skeys, const uint32_t *__restrict__ svals,
-                            const int64_t *__restrict__ offsets, int64_t n, int64_t m, uint32_t *__restrict__ sseq,
-                            uint8_t *__restrict__ keep, uint8_t *__restrict__ newk) {
+                            const int64_t *__restrict__ offsets, int64_t n, int64_t m, uint64_t invalid,
+                            uint32_t *__restrict__ sseq, uint8_t *__restrict__ keep, uint8_t *__restrict__ newk) {
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < m; x += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t key = skeys[x];
-        if (key == kInvalidKmer) {
+        if (key == invalid) {
             keep[x] = 0;
             newk[x] = 0;
             sseq[x] = 0xFFFFFFFFu;
@@ -81,7 +85,7 @@ __global__ void postings_kernel(const uint64_t *__restrict__ skeys, const uint32
                                 const uint8_t *__restrict__ keep, const uint8_t *__restrict__ newk,
                                 const uint32_t *__restrict__ kpos, const uint32_t *__restrict__ upos,
                                 uint32_t *__restrict__ post_seq, uint16_t *__restrict__ post_pos,
-                                uint32_t *__restrict__ post_u, uint32_t *__restrict__ uk_id,
+                                uint32_t *__restrict__ post_u, uint64_t *__restrict__ uk_id,
                                 uint32_t *__restrict__ uk_start, uint32_t *__restrict__ row_cnt) {
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < m; x += (int64_t)gridDim.x * blockDim.x) {
         if (!keep[x]) continue;
@@ -92,7 +96,7 @@ __global__ void postings_kernel(const uint64_t *__restrict__ skeys, const uint32
         post_pos[p] = (uint16_t)((int64_t)svals[x] - offsets[i]);
         post_u[p] = u;
         if (newk[x]) {
-            uk_id[u] = (uint32_t)skeys[x];
+            uk_id[u] = skeys[x];
             uk_start[u] = p;
         }
         atomicAdd(&row_cnt[i], 1u);
@@ -121,7 +125,7 @@ __global__ void rows_kernel(const uint32_t *__restrict__ post_seq, const uint16_
     }
 }
 
-__global__ void kmap_kernel(const uint32_t *__restrict__ uk_id, const uint32_t *__restrict__ nu_p,
+__global__ void kmap_kernel(const uint64_t *__restrict__ uk_id, const uint32_t *__restrict__ nu_p,
                             int32_t *__restrict__ kmap) {
     const uint32_t nu = *nu_p;
     for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < nu; u += gridDim.x * blockDim.x)
@@ -158,6 +162,9 @@ hipError_t build_kmers(const uint8_t *codes, const int64_t *offsets, int64_t n, 
                        KmerTables &kt, void *temp, hipStream_t s) {
     hipError_t e;
     const int64_t m = n_res;
+    const uint64_t invalid = (uint64_t)kmap_entries(k);  // one past the largest id
+    int bits = 8;
+    while (bits < 64 && (invalid >> bits) != 0) ++bits;
     char *tp = (char *)temp;
     auto take = [&](size_t bytes) {
         void *p = tp;
@@ -180,13 +187,13 @@ hipError_t build_kmers(const uint8_t *codes, const int64_t *offsets, int64_t n, 
     if ((e = fill<uint32_t>(kt.row_cnt, n + 1, 0u, s)) != hipSuccess) return e;
     if ((e = fill<uint32_t>(cursor, n + 1, 0u, s)) != hipSuccess) return e;
     if (m > 0) {
-        window_keys_kernel<<<grid_for(m), 256, 0, s>>>(codes, offsets, n, m, k, keys, vals);
+        window_keys_kernel<<<grid_for(m), 256, 0, s>>>(codes, offsets, n, m, k, invalid, keys, vals);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         bool alt = false;
-        if ((e = radix_sort(keys, vals, keys2, vals2, m, 32, stemp, s, &alt)) != hipSuccess) return e;
+        if ((e = radix_sort(keys, vals, keys2, vals2, m, bits, stemp, s, &alt)) != hipSuccess) return e;
         uint64_t *sk = alt ? keys2 : keys;
         uint32_t *sv = alt ? vals2 : vals;
-        mark_kernel<<<grid_for(m), 256, 0, s>>>(sk, sv, offsets, n, m, sseq, keep, newk);
+        mark_kernel<<<grid_for(m), 256, 0, s>>>(sk, sv, offsets, n, m, invalid, sseq, keep, newk);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = exclusive_scan<uint8_t, uint32_t>(keep, m, kpos, kt.counts + 0, stemp, s)) != hipSuccess) return e;
         if ((e = exclusive_scan<uint8_t, uint32_t>(newk, m, upos, kt.counts + 1, stemp, s)) != hipSuccess) return e;
@@ -203,7 +210,7 @@ hipError_t build_kmers(const uint8_t *codes, const int64_t *offsets, int64_t n, 
                                                 cursor, kt.row_u, kt.row_pos);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if (want_kmap) {
+    if (want_kmap && k <= kDenseMapMaxK) {
         if ((e = fill<int>(kt.kmap, kmap_entries(k), -1, s)) != hipSuccess) return e;
         if (m > 0) {
             kmap_kernel<<<grid_for(m), 256, 0, s>>>(kt.uk_id, kt.counts + 1, kt.kmap);

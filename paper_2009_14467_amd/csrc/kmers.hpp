@@ -7,17 +7,21 @@
 
 namespace pastis {
 
-constexpr uint64_t kInvalidKmer = 0xFFFFFFFFull;
+// k-mers of up to this length index the dense id -> distinct-k-mer map
+// (24^6 entries, 764 MB); longer ones are found by binary search over the
+// sorted distinct ids (the map would need 24^7 = 4.6e9 entries and more)
+constexpr int kDenseMapMaxK = 6;
 
 // Device arrays; capacities: n_res entries for postings/rows and distinct
 // k-mers, n + 1 for row bounds, 24^k for kmap.  counts[0] = nnz,
 // counts[1] = number of distinct k-mers, counts[2] = nnz again (row scan).
+// Distinct ids are ascending in uk_id.
 struct KmerTables {
     uint32_t *counts;  // 4 entries
     uint32_t *post_seq;
     uint16_t *post_pos;
     uint32_t *post_u;
-    uint32_t *uk_id;
+    uint64_t *uk_id;     // radix-24 ids, up to 24^8 for k = 8
     uint32_t *uk_start;  // nu + 1
     uint32_t *row_cnt;   // n + 1
     uint32_t *row_start; // n + 1

@@ -191,10 +191,11 @@ pastis_status discover(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, 
     PASTIS_TRY(get(ctx, kDRowU, m, &kt.row_u));
     PASTIS_TRY(get(ctx, kDRowPos, m, &kt.row_pos));
     kt.kmap = nullptr;
-    if (subs) PASTIS_TRY(get(ctx, kDKmap, (size_t)kmap_entries(P.k), &kt.kmap));
+    const bool dense_map = subs && P.k <= kDenseMapMaxK;  // longer k-mers: binary search of the distinct ids
+    if (dense_map) PASTIS_TRY(get(ctx, kDKmap, (size_t)kmap_entries(P.k), &kt.kmap));
     char *temp = nullptr;
     PASTIS_TRY(get(ctx, kDTemp, kmers_temp_bytes(m, n), &temp));
-    HIP_TRY(ctx, build_kmers(codes, st.d_off, n, m, P.k, subs, kt, temp, s), "k-mer kernels");
+    HIP_TRY(ctx, build_kmers(codes, st.d_off, n, m, P.k, dense_map, kt, temp, s), "k-mer kernels");
     HIP_TRY(ctx, stage_end(ctx, kStKmers, s), "event");
     uint32_t kc[4];
     PASTIS_TRY(read_device(ctx, kt.counts, kc, sizeof(kc), s));
@@ -210,7 +211,8 @@ pastis_status discover(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, 
     if (subs) {
         HIP_TRY(ctx, stage_begin(ctx, kStSubs, s), "event");
         const int W = P.n_subs + 1;
-        uint32_t *s_u, *s_cnt, *tmp_ids;
+        uint32_t *s_u, *s_cnt;
+        uint64_t *tmp_ids;
         int8_t *s_d, *tmp_d;
         PASTIS_TRY(get(ctx, kDSu, (size_t)nu * W, &s_u));
         PASTIS_TRY(get(ctx, kDSd, (size_t)nu * W, &s_d));
@@ -402,18 +404,42 @@ pastis_status stage_and_encode(pastis_ctx *ctx, const uint8_t *residues, const i
 pastis_status mlp_filter_candidates(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, int64_t n,
                                    hipStream_t s);
 
-// An even stride of m of the nc candidates (lo, hi, seeds).
+// The tuner's sample keeps every candidate whose shorter sequence (the
+// alignment's rows) falls in a hashed subset of the sequences: the 16-bit
+// pass groups pairs that share that sequence, and an even stride through
+// the candidates would thin those groups out and misjudge the grouping.
+__device__ __forceinline__ uint32_t seq_hash(uint32_t v) {
+    uint32_t h = v * 0x9E3779B1u;
+    h ^= h >> 15;
+    h *= 0x85EBCA77u;
+    return h ^ (h >> 13);
+}
+
+__global__ void tune_flag_kernel(const uint32_t *__restrict__ lo, const uint32_t *__restrict__ hi,
+                                 const int64_t *__restrict__ offsets, int64_t nc, uint64_t thr,
+                                 uint8_t *__restrict__ flag) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t i = lo[c], j = hi[c];  // i < j
+        const int64_t li = offsets[i + 1] - offsets[i], lj = offsets[j + 1] - offsets[j];
+        const uint32_t a = lj < li ? j : i;  // rows: the shorter, the lower index on a tie
+        flag[c] = (uint64_t)seq_hash(a) < thr ? 1 : 0;
+    }
+}
+
 __global__ void tune_sample_kernel(const uint32_t *__restrict__ lo, const uint32_t *__restrict__ hi,
-                                   const uint32_t *__restrict__ s1, const uint32_t *__restrict__ s2, int64_t nc,
+                                   const uint32_t *__restrict__ s1, const uint32_t *__restrict__ s2,
+                                   const uint8_t *__restrict__ flag, const uint32_t *__restrict__ pos, int64_t nc,
                                    int64_t m, uint32_t *__restrict__ olo, uint32_t *__restrict__ ohi,
                                    uint32_t *__restrict__ os1, uint32_t *__restrict__ os2) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= m) return;
-    const int64_t c = (int64_t)((__int128)q * nc / m);
-    olo[q] = lo[c];
-    ohi[q] = hi[c];
-    os1[q] = s1[c];
-    os2[q] = s2[c];
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += (int64_t)gridDim.x * blockDim.x) {
+        if (!flag[c]) continue;
+        const uint32_t q = pos[c];
+        if (q >= (uint64_t)m) continue;
+        olo[q] = lo[c];
+        ohi[q] = hi[c];
+        os1[q] = s1[c];
+        os2[q] = s2[c];
+    }
 }
 
 // Align the ctx's current candidates; records into kDRecords.
@@ -461,7 +487,7 @@ pastis_status pastis_candidates_copy(pastis_ctx *ctx, uint32_t *lo, uint32_t *hi
     return PASTIS_OK;
 }
 
-pastis_status pastis_subkmers(pastis_ctx *ctx, const uint32_t *kmer_ids, int64_t n, uint32_t *out_ids,
+pastis_status pastis_subkmers(pastis_ctx *ctx, const uint64_t *kmer_ids, int64_t n, uint64_t *out_ids,
                               int32_t *out_dist, int32_t *out_count, void *stream) {
     if (!ctx || n < 0 || (n > 0 && (!kmer_ids || !out_ids || !out_dist || !out_count))) return PASTIS_E_INVAL;
     const pastis_params &P = ctx->params;
@@ -640,9 +666,9 @@ pastis_status pastis_set_tuning(pastis_ctx *ctx, const pastis_tuning *t) {
     if (!ctx || !t) return PASTIS_E_INVAL;
     if (t->sw16_max_rows < 0 || t->sw16_max_rows > 16 || t->sw_direct_pct < 0 || t->sw_grid_scale < 1 ||
         t->sw_grid_scale > 64 || t->sw_grid_scale_wide < 1 || t->sw_grid_scale_wide > 64 || t->sw_intra_pair < 0 ||
-        t->sw_intra_pair > 1)
+        t->sw_intra_pair > 1 || t->sw16_narrow_rows < 0 || t->sw16_narrow_rows > 4)
         return set_error(ctx, PASTIS_E_INVAL, "tuning value out of range");
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 2; ++i)
         if (t->reserved[i] != 0) return set_error(ctx, PASTIS_E_INVAL, "reserved fields must be zero");
     ctx->tune = *t;
     return PASTIS_OK;
@@ -659,19 +685,36 @@ pastis_status pastis_autotune(pastis_ctx *ctx, const uint8_t *residues, const in
     int64_t nc = 0;
     PASTIS_TRY(discover(ctx, st, codes, n, s, &nc));
     if (nc > 0 && ctx->params.align_mode == PASTIS_ALIGN_SW) {
-        const int64_t m = std::min<int64_t>(nc, max_pairs);
-        uint32_t *lo, *hi, *s1, *s2;
+        const int64_t cap = std::min<int64_t>(nc, max_pairs);
+        uint32_t *lo, *hi, *s1, *s2, *pos;
+        uint8_t *flag;
+        char *temp;
         pastis_pair_record *rec;
-        PASTIS_TRY(get(ctx, kDTuneLo, m, &lo));
-        PASTIS_TRY(get(ctx, kDTuneHi, m, &hi));
-        PASTIS_TRY(get(ctx, kDTuneS1, m, &s1));
-        PASTIS_TRY(get(ctx, kDTuneS2, m, &s2));
-        PASTIS_TRY(get(ctx, kDTuneRec, m, &rec));
-        tune_sample_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(
-            (const uint32_t *)ctx->buf[kBufCandLo].ptr, (const uint32_t *)ctx->buf[kBufCandHi].ptr,
-            (const uint32_t *)ctx->buf[kBufCandS1].ptr, (const uint32_t *)ctx->buf[kBufCandS2].ptr, nc, m, lo, hi, s1,
-            s2);
+        PASTIS_TRY(get(ctx, kDTuneLo, cap, &lo));
+        PASTIS_TRY(get(ctx, kDTuneHi, cap, &hi));
+        PASTIS_TRY(get(ctx, kDTuneS1, cap, &s1));
+        PASTIS_TRY(get(ctx, kDTuneS2, cap, &s2));
+        PASTIS_TRY(get(ctx, kDTuneRec, cap, &rec));
+        PASTIS_TRY(get(ctx, kDEdgeFlag, nc, &flag));
+        PASTIS_TRY(get(ctx, kDEdgePos, nc + 1, &pos));
+        PASTIS_TRY(get(ctx, kDTemp, scan_temp_bytes(nc) + 4096, &temp));
+        // sequences kept with probability cap / nc (all of them when cap >= nc)
+        const uint64_t thr = cap >= nc ? (1ull << 32) : (uint64_t)(4294967296.0 * (double)cap / (double)nc);
+        const uint32_t *clo = (const uint32_t *)ctx->buf[kBufCandLo].ptr, *chi = (const uint32_t *)ctx->buf[kBufCandHi].ptr;
+        tune_flag_kernel<<<grid_for(nc), 256, 0, s>>>(clo, chi, st.d_off, nc, thr, flag);
         HIP_TRY(ctx, hipGetLastError(), "sample kernel");
+        HIP_TRY(ctx, (exclusive_scan<uint8_t, uint32_t>(flag, nc, pos, pos + nc, temp, s)), "scan");
+        tune_sample_kernel<<<grid_for(nc), 256, 0, s>>>(clo, chi, (const uint32_t *)ctx->buf[kBufCandS1].ptr,
+                                                       (const uint32_t *)ctx->buf[kBufCandS2].ptr, flag, pos, nc, cap,
+                                                       lo, hi, s1, s2);
+        HIP_TRY(ctx, hipGetLastError(), "sample kernel");
+        uint32_t total = 0;
+        PASTIS_TRY(read_device(ctx, pos + nc, &total, sizeof(total), s));
+        const int64_t m = std::min<int64_t>(cap, total);
+        if (m == 0) {
+            if (out) *out = ctx->tune;
+            return PASTIS_OK;
+        }
         // time one alignment of the sample under the current ctx->tune
         auto time_once = [&](double *ms) -> pastis_status {
             ctx->stats = pastis_run_stats{};
@@ -723,6 +766,8 @@ pastis_status pastis_autotune(pastis_ctx *ctx, const uint8_t *residues, const in
         PASTIS_TRY(sweep(&ctx->tune.sw_grid_scale_wide, grid, 3));
         const int intra[] = {0, 1};
         PASTIS_TRY(sweep(&ctx->tune.sw_intra_pair, intra, 2));
+        const int narrow[] = {4, 2, 0};
+        PASTIS_TRY(sweep(&ctx->tune.sw16_narrow_rows, narrow, 3));
     }
     if (out) *out = ctx->tune;
     return PASTIS_OK;

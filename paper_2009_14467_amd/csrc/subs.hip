@@ -58,35 +58,38 @@ struct Walk {
     int rc[kMaxK];
     int minrest[kMaxK + 1];
     int alpha, D;
-    uint32_t r;
+    uint64_t r;
 };
 
-// number of k-mers within distance D (r included when it qualifies)
+// number of k-mers within distance D (r included when it qualifies), or any
+// number >= limit once that many are found: only "at least limit" matters,
+// and a radius can hold up to 20^k k-mers (every k-mer of X is at distance
+// <= 0 from XX...X)
 template <int T, int K>
-__device__ __forceinline__ uint32_t count_within(const Walk &w, int partial) {
+__device__ __forceinline__ uint32_t count_within(const Walk &w, int partial, uint32_t limit) {
     if constexpr (T == K) {
         return 1u;
     } else {
         uint32_t c = 0;
         const int a = w.rc[T];
-        for (int q = 0; q < w.alpha; ++q) {
+        for (int q = 0; q < w.alpha && c < limit; ++q) {
             const int p = partial + w.T->ord_e[a][q];
             if (p + w.minrest[T + 1] > w.D) break;  // children come in expense order
-            c += count_within<T + 1, K>(w, p);
+            c += count_within<T + 1, K>(w, p, limit - c);
         }
         return c;
     }
 }
 
 struct Sink {
-    uint32_t *ids;
+    uint64_t *ids;
     int8_t *dist;
     int n, cap;
 };
 
 // emit every k-mer s != r with Dist < D (expense order)
 template <int T, int K>
-__device__ __forceinline__ void emit_below(const Walk &w, int partial, uint32_t id, Sink &out) {
+__device__ __forceinline__ void emit_below(const Walk &w, int partial, uint64_t id, Sink &out) {
     if constexpr (T == K) {
         if (partial < w.D && id != w.r && out.n < out.cap) {
             out.ids[out.n] = id;
@@ -98,14 +101,14 @@ __device__ __forceinline__ void emit_below(const Walk &w, int partial, uint32_t 
         for (int q = 0; q < w.alpha; ++q) {
             const int p = partial + w.T->ord_e[a][q];
             if (p + w.minrest[T + 1] > w.D - 1) break;
-            emit_below<T + 1, K>(w, p, id * 24u + w.T->ord_b[a][q], out);
+            emit_below<T + 1, K>(w, p, id * 24u + (uint64_t)w.T->ord_b[a][q], out);
         }
     }
 }
 
 // emit k-mers s != r with Dist == D in id order until the sink is full
 template <int T, int K>
-__device__ __forceinline__ void emit_at(const Walk &w, int partial, uint32_t id, Sink &out) {
+__device__ __forceinline__ void emit_at(const Walk &w, int partial, uint64_t id, Sink &out) {
     if constexpr (T == K) {
         if (partial == w.D && id != w.r && out.n < out.cap) {
             out.ids[out.n] = id;
@@ -117,18 +120,18 @@ __device__ __forceinline__ void emit_at(const Walk &w, int partial, uint32_t id,
         for (int b = 0; b < w.alpha && out.n < out.cap; ++b) {
             const int p = partial + w.T->ex[a][b];
             if (p + w.minrest[T + 1] > w.D) continue;
-            emit_at<T + 1, K>(w, p, id * 24u + (uint32_t)b, out);
+            emit_at<T + 1, K>(w, p, id * 24u + (uint64_t)b, out);
         }
     }
 }
 
 template <int K>
-__device__ int nearest(const SubsTables &T, uint32_t r, int alpha, int m, uint32_t *ids, int8_t *dist) {
+__device__ int nearest(const SubsTables &T, uint64_t r, int alpha, int m, uint64_t *ids, int8_t *dist) {
     Walk w;
     w.T = &T;
     w.alpha = alpha;
     w.r = r;
-    uint32_t x = r;
+    uint64_t x = r;
     bool in_alpha = true;
     for (int t = K - 1; t >= 0; --t) {
         w.rc[t] = (int)(x % 24u);
@@ -144,40 +147,55 @@ __device__ int nearest(const SubsTables &T, uint32_t r, int alpha, int m, uint32
     if (want <= 0) return 0;
     // r is within every radius D >= 0 when its residues are all substitutable
     for (w.D = w.minrest[0];; ++w.D) {
-        uint32_t c = count_within<0, K>(w, 0);
+        uint32_t c = count_within<0, K>(w, 0, (uint32_t)want + 1);
         if (in_alpha && w.D >= 0) --c;
         if (c >= (uint32_t)want) break;
     }
     Sink out{ids, dist, 0, want};
-    emit_below<0, K>(w, 0, 0u, out);
-    emit_at<0, K>(w, 0, 0u, out);
+    emit_below<0, K>(w, 0, 0ull, out);
+    emit_at<0, K>(w, 0, 0ull, out);
     return out.n;
 }
 
-__device__ int nearest_k(int k, const SubsTables &T, uint32_t r, int alpha, int m, uint32_t *ids, int8_t *dist) {
+__device__ int nearest_k(int k, const SubsTables &T, uint64_t r, int alpha, int m, uint64_t *ids, int8_t *dist) {
     switch (k) {
         case 1: return nearest<1>(T, r, alpha, m, ids, dist);
         case 2: return nearest<2>(T, r, alpha, m, ids, dist);
         case 3: return nearest<3>(T, r, alpha, m, ids, dist);
         case 4: return nearest<4>(T, r, alpha, m, ids, dist);
         case 5: return nearest<5>(T, r, alpha, m, ids, dist);
-        default: return nearest<6>(T, r, alpha, m, ids, dist);
+        case 6: return nearest<6>(T, r, alpha, m, ids, dist);
+        case 7: return nearest<7>(T, r, alpha, m, ids, dist);
+        default: return nearest<8>(T, r, alpha, m, ids, dist);
     }
+}
+
+// compact index of k-mer id among the nu ascending distinct ids, or -1
+__device__ __forceinline__ int32_t find_compact(const uint64_t *__restrict__ uk_id, uint32_t nu, uint64_t id) {
+    uint32_t lo = 0, hi = nu;  // first index with uk_id >= id in [lo, hi]
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (uk_id[mid] < id)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return (lo < nu && uk_id[lo] == id) ? (int32_t)lo : -1;
 }
 
 // Rows of S for the distinct k-mers of the data: row u holds (m + 1) slots;
 // slot 0 is u itself; present substitutes follow; s_cnt[u] counts them.
-__global__ __launch_bounds__(256) void s_rows_kernel(const uint32_t *__restrict__ uk_id, const uint32_t *__restrict__ nu_p,
+__global__ __launch_bounds__(256) void s_rows_kernel(const uint64_t *__restrict__ uk_id, const uint32_t *__restrict__ nu_p,
                                                      const int32_t *__restrict__ kmap, const int8_t *__restrict__ blosum25,
                                                      int k, int m, int alpha, uint32_t *__restrict__ s_u,
                                                      int8_t *__restrict__ s_d, uint32_t *__restrict__ s_cnt,
-                                                     uint32_t *__restrict__ tmp_ids, int8_t *__restrict__ tmp_d) {
+                                                     uint64_t *__restrict__ tmp_ids, int8_t *__restrict__ tmp_d) {
     __shared__ SubsTables T;
     load_tables(T, blosum25, alpha);
     const uint32_t nu = *nu_p;
     const int W = m + 1;
     for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < nu; u += gridDim.x * blockDim.x) {
-        uint32_t *ids = tmp_ids + (size_t)(blockIdx.x * blockDim.x + threadIdx.x) * m;
+        uint64_t *ids = tmp_ids + (size_t)(blockIdx.x * blockDim.x + threadIdx.x) * m;
         int8_t *dd = tmp_d + (size_t)(blockIdx.x * blockDim.x + threadIdx.x) * m;
         const int got = nearest_k(k, T, uk_id[u], alpha, m, ids, dd);
         uint32_t *row = s_u + (size_t)u * W;
@@ -186,7 +204,7 @@ __global__ __launch_bounds__(256) void s_rows_kernel(const uint32_t *__restrict_
         drow[0] = 0;
         int c = 1;
         for (int q = 0; q < got; ++q) {
-            const int32_t cu = kmap[ids[q]];
+            const int32_t cu = kmap ? kmap[ids[q]] : find_compact(uk_id, nu, ids[q]);
             if (cu < 0) continue;
             row[c] = (uint32_t)cu;
             drow[c] = dd[q];
@@ -197,8 +215,8 @@ __global__ __launch_bounds__(256) void s_rows_kernel(const uint32_t *__restrict_
 }
 
 // Neighbourhoods of arbitrary k-mer ids (checking entry point).
-__global__ void nearest_ids_kernel(const uint32_t *__restrict__ kid, int64_t n, const int8_t *__restrict__ blosum25,
-                                   int k, int m, int alpha, uint32_t *__restrict__ out_ids, int8_t *__restrict__ out_d,
+__global__ void nearest_ids_kernel(const uint64_t *__restrict__ kid, int64_t n, const int8_t *__restrict__ blosum25,
+                                   int k, int m, int alpha, uint64_t *__restrict__ out_ids, int8_t *__restrict__ out_d,
                                    int32_t *__restrict__ out_n) {
     __shared__ SubsTables T;
     load_tables(T, blosum25, alpha);
@@ -210,15 +228,15 @@ __global__ void nearest_ids_kernel(const uint32_t *__restrict__ kid, int64_t n, 
 
 int s_rows_threads() { return 256 * 1024; }
 
-hipError_t launch_s_rows(const uint32_t *uk_id, const uint32_t *nu, const int32_t *kmap, const int8_t *blosum25, int k,
-                         int m, int alpha, uint32_t *s_u, int8_t *s_d, uint32_t *s_cnt, uint32_t *tmp_ids,
+hipError_t launch_s_rows(const uint64_t *uk_id, const uint32_t *nu, const int32_t *kmap, const int8_t *blosum25, int k,
+                         int m, int alpha, uint32_t *s_u, int8_t *s_d, uint32_t *s_cnt, uint64_t *tmp_ids,
                          int8_t *tmp_d, hipStream_t s) {
     s_rows_kernel<<<1024, 256, 0, s>>>(uk_id, nu, kmap, blosum25, k, m, alpha, s_u, s_d, s_cnt, tmp_ids, tmp_d);
     return hipGetLastError();
 }
 
-hipError_t launch_nearest_ids(const uint32_t *kid, int64_t n, const int8_t *blosum25, int k, int m, int alpha,
-                              uint32_t *out_ids, int8_t *out_d, int32_t *out_n, hipStream_t s) {
+hipError_t launch_nearest_ids(const uint64_t *kid, int64_t n, const int8_t *blosum25, int k, int m, int alpha,
+                              uint64_t *out_ids, int8_t *out_d, int32_t *out_n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     int64_t blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;

@@ -1605,20 +1605,28 @@ hipError_t launch_pb(int bin, int blocks, const uint8_t *codes, const PairDesc *
 // waves: one profile per block) and the blocks that fit on the device at once
 constexpr int wpb16(int R) { return 4; }
 // pairs one block of the 16-bit one-strip launch takes per window
-static int pairs_per_block16(int R) { return R <= 4 ? 4 * 8 : R <= 8 ? 4 * 4 : 2 * 4; }
+// narrow: R <= 4 bins in strips of 16 lanes (eight pairs per wave) rather
+// than 32 (four pairs per wave)
+static int pairs_per_block16(int R, bool narrow) { return R <= 4 && narrow ? 4 * 8 : R <= 8 ? 4 * 4 : 2 * 4; }
 static int blocks16(int R) { return R <= 4 ? 256 * 6 : (R > 8 && R <= 12) ? 256 * 4 : 256 * 3; }
 
-// R <= 4: strips of 16 lanes with 4 R rows per lane; R = 5..8: strips of 32
-// lanes with 2 R rows; wider bins: the full-wave kernel
+// R <= 4: strips of 16 lanes with 4 R rows per lane (eight pairs per wave),
+// or, when not narrow, of 32 lanes with 2 R rows (four pairs per wave: fewer
+// pairs that must share their sequence a); R = 5..8: strips of 32 lanes with
+// 2 R rows; wider bins: the full-wave kernel (two pairs per wave)
 template <int R>
-hipError_t launch_p16(int bin, int blocks, const uint8_t *codes, const PairDesc *pairs, const int *idx,
-                      const int *starts, const int8_t *blosum, int go_ge, int ge, SwPass1Out *p1, int *, int64_t,
-                      int *queue, hipStream_t s) {
+hipError_t launch_p16(int bin, int blocks, bool narrow, const uint8_t *codes, const PairDesc *pairs, const int *idx,
+                      const int *starts, const int8_t *blosum, int go_ge, int ge, SwPass1Out *p1, int *queue,
+                      hipStream_t s) {
     constexpr int WPB = wpb16(R);
-    if constexpr (R <= 4)
-        sw16s_pass1_kernel<16, 4 * R, WPB><<<blocks, 64 * WPB, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge,
-                                                                      ge, p1, queue);
-    else if constexpr (R <= 8)
+    if constexpr (R <= 4) {
+        if (narrow)
+            sw16s_pass1_kernel<16, 4 * R, WPB><<<blocks, 64 * WPB, 0, s>>>(codes, pairs, idx, starts, bin, blosum,
+                                                                          go_ge, ge, p1, queue);
+        else
+            sw16s_pass1_kernel<32, 2 * R, WPB><<<blocks, 64 * WPB, 0, s>>>(codes, pairs, idx, starts, bin, blosum,
+                                                                          go_ge, ge, p1, queue);
+    } else if constexpr (R <= 8)
         sw16s_pass1_kernel<32, 2 * R, WPB><<<blocks, 64 * WPB, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge,
                                                                       ge, p1, queue);
     else
@@ -1669,7 +1677,9 @@ const P1Fn kP1[kNumBins] = {launch_p1<1>,  launch_p1<2>,  launch_p1<3>,  launch_
                             launch_p1<11>, launch_p1<12>, launch_p1<13>, launch_p1<14>, launch_p1<15>, launch_p1<16>,
                             launch_p1<9>,  launch_p1<10>, launch_p1<11>, launch_p1<12>, launch_p1<13>, launch_p1<14>,
                             launch_p1<15>, launch_p1<16>};
-const P1Fn kP16[kMax16R] = {launch_p16<1>,  launch_p16<2>,  launch_p16<3>,  launch_p16<4>,
+typedef hipError_t (*P16Fn)(int, int, bool, const uint8_t *, const PairDesc *, const int *, const int *,
+                            const int8_t *, int, int, SwPass1Out *, int *, hipStream_t);
+const P16Fn kP16[kMax16R] = {launch_p16<1>,  launch_p16<2>,  launch_p16<3>,  launch_p16<4>,
                             launch_p16<5>,  launch_p16<6>,  launch_p16<7>,  launch_p16<8>,
                             launch_p16<9>,  launch_p16<10>, launch_p16<11>, launch_p16<12>,
                             launch_p16<13>, launch_p16<14>, launch_p16<15>, launch_p16<16>};
@@ -1735,7 +1745,7 @@ bool sw_bin_is16(int bin, int max16) {
 hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pairs, int64_t npairs,
                      const int8_t *blosum, const Scoring &sc, SwPass1Out *p1, pastis_pair_record *out,
                      const SwWork &wk, int stats_mode, int max16, int grid_scale, int grid_scale_wide, int intra,
-                     bool timed, hipStream_t s) {
+                     int narrow16, bool timed, hipStream_t s) {
     // timed = false (graph capture): no stage or per-bin events
     const bool use16 = max16 > 0;
     auto begin = [&](int st) { return timed ? stage_begin(ctx, st, s) : hipSuccess; };
@@ -1796,8 +1806,8 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
             e = kPI[R - kMultiMinR](bin, codes, pairs, idx1, wk.starts, blosum, go_ge, ge, p1, wk.scratch,
                                     wk.scratch_per_wave, wk.queue, wk.counters + kCounterIntraFlag, st);
         else if (sw_bin_is16(bin, max16))
-            e = kP16[bin](bin, capped(scale * blocks16(R), pairs_per_block16(R)), codes, pairs, idx1,
-                          wk.starts, blosum, go_ge, ge, p1, nullptr, 0, wk.queue, st);
+            e = kP16[bin](bin, capped(scale * blocks16(R), pairs_per_block16(R, R <= narrow16)), R <= narrow16, codes,
+                          pairs, idx1, wk.starts, blosum, go_ge, ge, p1, wk.queue, st);
         else
             e = kP1[bin](bin, capped(scale * blocks_for_bin(bin), wpb32(R)), codes, pairs, idx1,
                          wk.starts, blosum, go_ge, ge, p1, wk.scratch, wk.scratch_per_wave, wk.queue, st);

@@ -138,6 +138,42 @@ def test_heavy_tail_discovery_k5_m25(gpu, orc):
     _compare(got, want)
 
 
+@pytest.mark.parametrize("k,m,ck", [(7, 0, 1), (8, 0, 1), (7, 10, 2), (8, 25, 2), (8, 25, 1)])
+def test_long_kmers_without_dense_map(gpu, orc, k, m, ck):
+    """k = 7 and 8: ids past 32 bits (24^8 > 2^36), no dense id map (the
+    substitutes' compact indices come from a binary search of the sorted
+    distinct ids); candidates, counts and seeds against the oracle."""
+    from synth import workload
+
+    s = workload("tiny", n_families=6)
+    want = orc.candidates(orc.encode(s.residues), s.offsets, k, ck_min=ck, n_subs=m)
+    assert len(want["lo"]) > 200
+    _compare(_gpu_candidates(gpu, s.residues, s.offsets, k=k, ck_min=ck, n_subs=m), want)
+
+
+@pytest.mark.parametrize("mode", ["sw", "xd"])
+def test_search_k8(gpu, orc, mode):
+    """The whole search at k = 8 (seeds of 8 columns in XD) against the oracle."""
+    import paper_2009_14467_amd as P
+    from synth import workload
+
+    from test_gpu_search import _compare_edges
+
+    s = workload("tiny", n_families=8)
+    want = orc.search(s.residues, s.offsets, k=8, n_subs=10, ck_min=1, mode=mode)
+    got = P.Context(P.Params(k=8, n_subs=10, ck_min=1, align_mode=mode)).search(_dev(s.residues, gpu),
+                                                                             _dev(s.offsets, gpu))
+    _compare_edges(got, want)
+
+
+def test_k_out_of_range_is_rejected(gpu):
+    import paper_2009_14467_amd as P
+
+    for k in (0, 9):
+        with pytest.raises(P.PastisError):
+            P.Context(P.Params(k=k))
+
+
 def test_substitutes_m0_equals_exact(gpu, orc):
     s = _random_set(3, 60, 0, 50, "ACDEF")
     a = _gpu_candidates(gpu, s.residues, s.offsets, k=3, ck_min=1, n_subs=0)
@@ -145,7 +181,8 @@ def test_substitutes_m0_equals_exact(gpu, orc):
     _compare(a, want)
 
 
-@pytest.mark.parametrize("k,m,alpha", [(6, 25, 20), (5, 25, 20), (3, 40, 24), (2, 10, 20)])
+@pytest.mark.parametrize("k,m,alpha", [(6, 25, 20), (5, 25, 20), (3, 40, 24), (2, 10, 20), (7, 25, 20), (8, 25, 20),
+                                       (8, 10, 24)])
 def test_subkmers_neighbourhoods(gpu, orc, k, m, alpha):
     import paper_2009_14467_amd as P
 
@@ -157,8 +194,8 @@ def test_subkmers_neighbourhoods(gpu, orc, k, m, alpha):
     # a few k-mers with X (negative expenses) and the extremes
     ids += [orc.kmer_id("X" * k), orc.kmer_id("W" * k), orc.kmer_id("A" * (k - 1) + "C")]
     ctx = P.Context(P.Params(k=k, n_subs=m, sub_alphabet=alpha))
-    gi, gd, gn = ctx.subkmers(_dev(np.array(ids, np.uint32), gpu))
-    gi, gd, gn = gi.cpu().numpy().view(np.uint32), gd.cpu().numpy(), gn.cpu().numpy()
+    gi, gd, gn = ctx.subkmers(_dev(np.array(ids, np.int64), gpu))
+    gi, gd, gn = gi.cpu().numpy(), gd.cpu().numpy(), gn.cpu().numpy()
     for q, r in enumerate(ids):
         wi, wd = orc.subkmers(r, k, m, alpha)
         assert gn[q] == len(wi)

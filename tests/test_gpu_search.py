@@ -71,7 +71,8 @@ def test_search_repeatable(gpu):
 @pytest.mark.parametrize("tuning", [dict(sw16_max_rows=0), dict(sw16_max_rows=8, sw_direct_pct=0),
                                     dict(sw16_max_rows=12, sw_direct_pct=1 << 20, sw_grid_scale=1),
                                     dict(sw16_max_rows=16, sw_direct_pct=25, sw_grid_scale=64, sw_grid_scale_wide=3),
-                                    dict(sw16_max_rows=0, sw_intra_pair=1)])
+                                    dict(sw16_max_rows=0, sw_intra_pair=1), dict(sw16_narrow_rows=0),
+                                    dict(sw16_narrow_rows=2, sw_direct_pct=0)])
 def test_every_schedule_gives_the_same_edges(gpu, orc, tuning):
     """Schedule knobs move time, never results: each setting against the oracle."""
     import paper_2009_14467_amd as P
@@ -97,10 +98,12 @@ def test_autotune_picks_a_valid_schedule(gpu):
     t = ctx.autotune(res, off, max_pairs=2000)
     assert t == ctx.get_tuning()
     assert t["sw16_max_rows"] in (0, 8, 12, 16) and t["sw_grid_scale"] in (1, 2, 4)
-    assert t["sw_grid_scale_wide"] in (1, 2, 4)
+    assert t["sw_grid_scale_wide"] in (1, 2, 4) and t["sw16_narrow_rows"] in (0, 2, 4)
     assert before.tobytes() == ctx.search(res, off).tobytes()
     with pytest.raises(P.PastisError):
         ctx.set_tuning(sw16_max_rows=17)
+    with pytest.raises(P.PastisError):
+        ctx.set_tuning(sw16_narrow_rows=5)
 
 
 def test_graph_mode_replays_match_direct_launches(gpu):

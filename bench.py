@@ -50,20 +50,27 @@ ALGO_OPS_PER_SW_CELL = 11
 # x-drop: the same recurrence plus the drop test per live cell
 ALGO_OPS_PER_XD_CELL = 12
 # HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (KiB per
-# dispatch on the mid workload, profiles/sw_search_mid_kernel_stats.md), scaled
-# by what the counters read for a 1 GiB device copy (FETCH x 2.0, WRITE x 1.0);
-# only for kernels unchanged since those counters were taken
-MEASURED_TRAFFIC_KIB = {"sw16s_pass1_kernel<32, 12, 4>": (1246851.25, 129269.531),
-                        "sw16s_pass1_kernel<16, 16, 4>": (1311538.562, 130976.219),
-                        "sw16_pass1_kernel<9, 4, false>": (592586.188, 58720.5)}
+# dispatch, profiles/sw_search_<workload>_kernel_stats.md), scaled by what the
+# counters read for a 1 GiB device copy (FETCH x 2.0, WRITE x 1.0); keyed by
+# workload and kernel, and only for kernels unchanged since those counters
+# were taken
+MEASURED_TRAFFIC_KIB = {("large", "sw16s_pass1_kernel<32, 14, 4>"): (456576.4, 36155.0),
+                        ("large", "sw16s_pass1_kernel<32, 10, 4>"): (691304.8, 61093.3),
+                        ("mid", "sw16s_pass1_kernel<32, 12, 4>"): (1246851.25, 129269.531),
+                        ("mid", "sw16s_pass1_kernel<16, 16, 4>"): (1311538.562, 130976.219),
+                        ("mid", "sw16_pass1_kernel<9, 4, false>"): (592586.188, 58720.5)}
 # the same counters for the product kernels of candidate discovery (one launch
-# of each per step on the mid workload): their posting reads are scattered
-# (a few bytes per product from lines of 64-128 bytes), so the traffic
-# exceeds the algorithmic bytes many times over
-SPGEMM_TRAFFIC_KIB = {"spgemm_lds_kernel<8192, 3072>": (18749019.875, 1786354.969),
-                      "spgemm_lds_kernel<16384, 2048>": (16981704.562, 2089405.750),
-                      "spgemm_lds_kernel<32768, 4096>": (7057943.812, 1052681.688),
-                      "spgemm_global_kernel": (2245486.812, 1480966.438)}
+# of each per step): their posting reads are scattered (an 8-byte record per
+# product, from lines of 64-128 bytes), so the traffic exceeds the
+# algorithmic bytes many times over
+SPGEMM_TRAFFIC_KIB = {
+    "large": {"spgemm_lds_kernel<8192, 3072>": (23536068.2, 1129332.0),
+              "spgemm_lds_kernel<16384, 2048>": (479785.3, 29702.4)},
+    "mid": {"spgemm_lds_kernel<8192, 3072>": (18749019.875, 1786354.969),
+            "spgemm_lds_kernel<16384, 2048>": (16981704.562, 2089405.750),
+            "spgemm_lds_kernel<32768, 4096>": (7057943.812, 1052681.688),
+            "spgemm_global_kernel": (2245486.812, 1480966.438)},
+}
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
 # method parameters of each workload (Section VI settings: BLOSUM62, gaps
@@ -173,7 +180,8 @@ def cpu_baseline(fs, lo, hi, target_s):
 def set_tuning(ctx, tuning):
     if isinstance(tuning, dict):
         ctx.set_tuning(**{k: tuning[k] for k in ("sw16_max_rows", "sw_direct_pct", "sw_grid_scale",
-                                                  "sw_grid_scale_wide", "sw_intra_pair", "sw16_narrow_rows")})
+                                                  "sw_grid_scale_wide", "sw_intra_pair", "sw16_narrow_rows",
+                                                  "sw_long_blocks")})
 
 
 def timed_steps(ctx, args, res, off):
@@ -209,7 +217,7 @@ def kernel_name(b):
     return "sw_pass1_kernel<%d, %s>" % (R, "true" if b["multi_strip"] else "false")
 
 
-def roofline(st, pass1_ms, traffic_ok):
+def roofline(st, pass1_ms, traffic_ok, workload):
     """The dominant pass-1 kernel (the length bin with the most DP work; one
     launch per step) against the integer VALU peak of its lane width: its
     cells x the method's 11 ops per cell over its HIP-event time on the
@@ -232,8 +240,8 @@ def roofline(st, pass1_ms, traffic_ok):
     kernel_ops = dom["cells"] * ops(dom) / (dom["ms"] * 1e-3) / 1e12
     mix_peak_s = sum(b["cells"] * ALGO_OPS_PER_SW_CELL / (peak_of(b) * 1e12) for b in st["sw_bins"])
     traffic = None
-    if traffic_ok and name in MEASURED_TRAFFIC_KIB:
-        f, w = MEASURED_TRAFFIC_KIB[name]
+    if traffic_ok and (workload, name) in MEASURED_TRAFFIC_KIB:
+        f, w = MEASURED_TRAFFIC_KIB[(workload, name)]
         traffic = 1024 * (FETCH_SCALE * f + WRITE_SCALE * w)
     return {
         "kernel": name,
@@ -249,6 +257,31 @@ def roofline(st, pass1_ms, traffic_ok):
         "kernel_ops_per_cell": ops(dom),
         "frac_kernel_ops": kernel_ops / peak,
         "all_pass1_bins": {"frac_of_mix_peak": mix_peak_s / (pass1_ms * 1e-3)},
+    }
+
+
+def spgemm_line(st, ms, traffic_workload):
+    """Candidate discovery's sparse product against HBM bandwidth.  The
+    compulsory bytes are A and its transpose read once (12 B per nonzero),
+    the candidates written (20 B each) and, with substitutes, S read once (5 B
+    per entry); the stage time also holds the symmetrisation and sort.
+    `traffic` is the product kernels' counted HBM bytes per step."""
+    compulsory = 12 * st["n_kmers"] + 20 * st["n_candidates"] + 5 * st["n_subs_entries"]
+    gbs = compulsory / (ms * 1e-3) / 1e9
+    traffic = None
+    if traffic_workload in SPGEMM_TRAFFIC_KIB:
+        traffic = 1024 * sum(FETCH_SCALE * f + WRITE_SCALE * w for f, w in SPGEMM_TRAFFIC_KIB[traffic_workload].values())
+    return {
+        "products": int(st["spgemm_products"]),
+        "nnz_A": int(st["n_kmers"]),
+        "nnz_S": int(st["n_subs_entries"]),
+        "ms": ms,
+        "products_per_s": st["spgemm_products"] / (ms * 1e-3),
+        "compulsory_bytes": compulsory,
+        "achieved_gb_s": gbs,
+        "peak_gb_s": PEAK_HBM_GBS,
+        "frac": gbs / PEAK_HBM_GBS,
+        "traffic": traffic,
     }
 
 
@@ -392,7 +425,8 @@ def mid_leg(P, args, dev):
         "cells": cells,
         "edges": int(edges.size),
         "stage_ms": dict(zip(STAGE_NAMES, stage)),
-        "roofline": roofline(st, stage[5], args.families is None),
+        "roofline": roofline(st, stage[5], args.families is None, "mid"),
+        "spgemm": spgemm_line(st, stage[3], "mid" if args.families is None else None),
     }
     if not args.no_xd:
         out["xd"] = xd_leg(P, args, params, res, off, int(st["n_candidates"]))
@@ -490,18 +524,8 @@ def main():
         "bound_pass_cells": int(st["bound_pass_cells"]),
         "stage_ms": dict(zip(STAGE_NAMES, stage)),
         "align_gcups": cells / ((stage[5] + stage[6]) * 1e-3) / 1e9,
-        # candidate discovery's product against HBM bandwidth: one 6-byte
-        # posting (sequence u32, position u16) per product is the least the
-        # product must read; the stage time includes symmetrisation and sorting
-        "spgemm": {
-            "products": int(st["spgemm_products"]),
-            "ms": stage[3],
-            "products_per_s": st["spgemm_products"] / (stage[3] * 1e-3),
-            "achieved_gb_s": 6 * st["spgemm_products"] / (stage[3] * 1e-3) / 1e9,
-            "peak_gb_s": PEAK_HBM_GBS,
-            "frac": 6 * st["spgemm_products"] / (stage[3] * 1e-3) / 1e9 / PEAK_HBM_GBS,
-        },
-        "roofline": roofline(st, stage[5], args.families is None),
+        "spgemm": spgemm_line(st, stage[3], args.workload if args.families is None else None),
+        "roofline": roofline(st, stage[5], args.families is None, args.workload),
         "sw_bins": [dict(b, gcups=b["cells"] / max(b["ms"], 1e-9) / 1e6) for b in st["sw_bins"] if b["pairs"]],
         "schedule": tuning if tuning is not None else dict(ctx.get_tuning(), source="library default"),
     }

@@ -168,6 +168,10 @@ typedef struct pastis_run_stats {
      * over every row's entries; the counting and the seed phase each make
      * one such pass) */
     int64_t spgemm_products;
+    /* nnz(S): entries of the substitute matrix's rows over the data's k-mers
+     * (each k-mer itself and its substitutes present in some sequence); 0
+     * with exact k-mers */
+    int64_t n_subs_entries;
 } pastis_run_stats;
 
 typedef struct pastis_ctx pastis_ctx;
@@ -392,7 +396,7 @@ pastis_status pastis_mlp_load(pastis_ctx *ctx, const char *path);
 
 /* ---- schedule of the Smith-Waterman stage ----
  * Knobs of the length-binned launches (every setting gives the same results;
- * only the time changes).  A new context starts at {16, 50, 1, 1, 0, 4}.  pastis_autotune times candidate settings on a
+ * only the time changes).  A new context starts at {16, 50, 1, 1, 0, 4, 4}.  pastis_autotune times candidate settings on a
  * sample of the given sequences' own candidate pairs and keeps the fastest. */
 typedef struct pastis_tuning {
     int32_t sw16_max_rows; /* bins with at most this many rows per lane run two pairs per
@@ -417,7 +421,10 @@ typedef struct pastis_tuning {
                                  strips of 32 lanes, four pairs per wave (a wave's pairs
                                  share their shorter sequence, so sets with few candidates
                                  per sequence fill fewer slots of the wider grouping) */
-    int32_t reserved[2];
+    int32_t sw_long_blocks; /* blocks per CU (1..4) of the multi-strip launches (sequences a
+                               over 1024 rows), which run on the context's second stream
+                               beside the one-strip bins: fewer leave those more waves */
+    int32_t reserved[1];
 } pastis_tuning;
 
 pastis_status pastis_get_tuning(const pastis_ctx *ctx, pastis_tuning *out);
@@ -425,7 +432,7 @@ pastis_status pastis_get_tuning(const pastis_ctx *ctx, pastis_tuning *out);
 pastis_status pastis_set_tuning(pastis_ctx *ctx, const pastis_tuning *t);
 /* Discovery on the given sequences, then for each knob in turn (16-bit rows,
  * start-bound routing, the two grid scales, inter- vs intra-pair mode, pairs
- * per wavefront) the alignment of a sample of the candidates under each
+ * per wavefront, the long bins' grid) the alignment of a sample of the candidates under each
  * candidate value, twice, timed with HIP events on the stream; the fastest
  * setting is kept in ctx and written to *out (may be NULL).  The sample is
  * every candidate whose shorter sequence falls in a hashed subset of the

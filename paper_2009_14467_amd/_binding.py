@@ -95,7 +95,8 @@ class _Tuning(ctypes.Structure):
         ("sw_grid_scale_wide", ctypes.c_int32),
         ("sw_intra_pair", ctypes.c_int32),
         ("sw16_narrow_rows", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("sw_long_blocks", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 1),
     ]
 
 
@@ -130,7 +131,7 @@ class _TrainReport(ctypes.Structure):
 def _tuning_dict(t) -> dict:
     return {"sw16_max_rows": t.sw16_max_rows, "sw_direct_pct": t.sw_direct_pct, "sw_grid_scale": t.sw_grid_scale,
             "sw_grid_scale_wide": t.sw_grid_scale_wide, "sw_intra_pair": t.sw_intra_pair,
-            "sw16_narrow_rows": t.sw16_narrow_rows}
+            "sw16_narrow_rows": t.sw16_narrow_rows, "sw_long_blocks": t.sw_long_blocks}
 
 
 class _Stats(ctypes.Structure):
@@ -159,6 +160,7 @@ class _Stats(ctypes.Structure):
         ("sw_graph", ctypes.c_int32),
         ("sw_graph_pad", ctypes.c_int32),
         ("spgemm_products", ctypes.c_int64),
+        ("n_subs_entries", ctypes.c_int64),
     ]
 
 
@@ -430,11 +432,13 @@ class Context:
         return _tuning_dict(t)
 
     def set_tuning(self, sw16_max_rows: int = 16, sw_direct_pct: int = 50, sw_grid_scale: int = 1,
-                   sw_grid_scale_wide: int = 1, sw_intra_pair: int = 0, sw16_narrow_rows: int = 4):
+                   sw_grid_scale_wide: int = 1, sw_intra_pair: int = 0, sw16_narrow_rows: int = 4,
+                   sw_long_blocks: int = 4):
         t = _Tuning()
         t.sw16_max_rows, t.sw_direct_pct = sw16_max_rows, sw_direct_pct
         t.sw_grid_scale, t.sw_grid_scale_wide = sw_grid_scale, sw_grid_scale_wide
         t.sw_intra_pair, t.sw16_narrow_rows = sw_intra_pair, sw16_narrow_rows
+        t.sw_long_blocks = sw_long_blocks
         self._check(lib().pastis_set_tuning(self._ctx, ctypes.byref(t)))
 
     def autotune(self, residues, offsets, max_pairs: int = 1 << 21, stream=None) -> dict:

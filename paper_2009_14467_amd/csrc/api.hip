@@ -288,7 +288,7 @@ static pastis_status sw_graph(pastis_ctx *ctx, const uint8_t *codes, const PairD
                               const Scoring &sc, SwPass1Out *p1, pastis_pair_record *out, const SwWork &wk,
                               int stats_mode, int max16, hipStream_t s) {
     const int grid = ctx->tune.sw_grid_scale, grid_wide = ctx->tune.sw_grid_scale_wide, intra = ctx->tune.sw_intra_pair;
-    const int narrow = ctx->tune.sw16_narrow_rows;
+    const int narrow = ctx->tune.sw16_narrow_rows, long_blocks = ctx->tune.sw_long_blocks;
     uint64_t key = 0;
     const uint64_t parts[] = {(uint64_t)npairs, (uint64_t)codes, (uint64_t)pairs, (uint64_t)p1, (uint64_t)out,
                               (uint64_t)wk.counters, (uint64_t)wk.bin_of, (uint64_t)wk.counts, (uint64_t)wk.idx,
@@ -297,7 +297,7 @@ static pastis_status sw_graph(pastis_ctx *ctx, const uint8_t *codes, const PairD
                               (uint64_t)wk.sort_temp, (uint64_t)sc.gap_open, (uint64_t)sc.gap_extend,
                               (uint64_t)sc.id_pct, (uint64_t)sc.cov_pct, (uint64_t)sc.direct_pct,
                               (uint64_t)stats_mode, (uint64_t)max16, (uint64_t)grid, (uint64_t)grid_wide, (uint64_t)intra,
-                              (uint64_t)narrow,
+                              (uint64_t)narrow, (uint64_t)long_blocks,
                               (uint64_t)ctx->d_blosum};
     for (uint64_t v : parts) key = mix(key, v);
     hipStream_t gs = ctx->graph_stream;
@@ -308,7 +308,7 @@ static pastis_status sw_graph(pastis_ctx *ctx, const uint8_t *codes, const PairD
         }
         HIP_TRY(ctx, hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal), "graph capture");
         const hipError_t le = launch_sw(ctx, codes, pairs, npairs, ctx->d_blosum, sc, p1, out, wk, stats_mode, max16,
-                                        grid, grid_wide, intra, narrow, false, gs);
+                                        grid, grid_wide, intra, narrow, long_blocks, false, gs);
         hipGraph_t g = nullptr;
         const hipError_t ce = hipStreamEndCapture(gs, &g);
         if (le != hipSuccess || ce != hipSuccess) {
@@ -379,7 +379,7 @@ pastis_status align_core(pastis_ctx *ctx, const Staged &st, const uint8_t *codes
             HIP_TRY(ctx,
                     launch_sw(ctx, codes, (const PairDesc *)pairs, npairs, ctx->d_blosum, sc, (SwPass1Out *)p1, out,
                               wk, stats_mode, max16, ctx->tune.sw_grid_scale, ctx->tune.sw_grid_scale_wide,
-                              ctx->tune.sw_intra_pair, ctx->tune.sw16_narrow_rows, true, s),
+                              ctx->tune.sw_intra_pair, ctx->tune.sw16_narrow_rows, ctx->tune.sw_long_blocks, true, s),
                     "sw kernels");
         }
     } else {

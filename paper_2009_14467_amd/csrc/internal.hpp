@@ -109,7 +109,7 @@ struct pastis_ctx {
     bool records_internal = false;  // the current alignment's records feed edges only
     int last_max16 = 0;             // the last SW call ran 16-bit pass-1 bins up to this R
     uint64_t last_n_dir = 0;        // directional entries of the last candidate discovery
-    pastis_tuning tune{16, 50, 1, 1, 0, 4, {0, 0}};
+    pastis_tuning tune{16, 50, 1, 1, 0, 4, 4, {0}};
     // learned filter
     pastis::MlpState mlp{};
     bool mlp_alloc = false, mlp_set = false;
@@ -241,11 +241,12 @@ int sw_one_strip_max_rows();
 // that skip the statistics pass.  grid_scale multiplies the pass-1 grids;
 // intra = 1 runs pass 1 of the 32-bit multi-strip bins one workgroup per pair;
 // 16-bit bins of at most narrow16 (<= 4) rows per lane run strips of 16 lanes
-// (eight pairs per wave), the other bins up to 8 rows per lane strips of 32.
+// (eight pairs per wave), the other bins up to 8 rows per lane strips of 32;
+// multi-strip launches take at most long_blocks (1..4) blocks per CU.
 hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pairs, int64_t npairs,
                      const int8_t *blosum, const Scoring &sc, SwPass1Out *p1, pastis_pair_record *out,
                      const SwWork &wk, int stats_mode, int max16, int grid_scale, int grid_scale_wide, int intra,
-                     int narrow16, bool timed, hipStream_t s);
+                     int narrow16, int long_blocks, bool timed, hipStream_t s);
 // 16-bit pass 1 needs o + e >= 4 (biased scores stay non-negative).
 bool sw16_supported(const Scoring &sc);
 bool sw_bin_is16(int bin, int max16);

@@ -100,7 +100,8 @@ struct Misc {
     uint32_t *n_cand;             // 1
     uint32_t *n_edges;            // 1
     unsigned long long *products; // 1
-    int *bin_meta;                // 160
+    int *bin_meta;                // 160 (80 words)
+    unsigned long long *nnz_s;    // 1, after bin_meta
 };
 
 pastis_status misc(pastis_ctx *ctx, Misc &m) {
@@ -116,6 +117,7 @@ pastis_status misc(pastis_ctx *ctx, Misc &m) {
     m.n_edges = w + 5;
     m.products = base + 6;
     m.bin_meta = (int *)(base + 8);
+    m.nnz_s = base + 88;
     return PASTIS_OK;
 }
 
@@ -166,6 +168,15 @@ inline unsigned grid_for(int64_t n) {
     int64_t b = (n + 255) / 256;
     if (b > 16384) b = 16384;
     return (unsigned)(b < 1 ? 1 : b);
+}
+
+// *out += sum of a[0..n) (out cleared by the caller)
+__global__ void sum_u32_kernel(const uint32_t *__restrict__ a, int64_t n, unsigned long long *__restrict__ out) {
+    unsigned long long acc = 0;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
+        acc += a[x];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0 && acc) atomicAdd(out, acc);
 }
 
 // Discovery: candidates into kDCand*; returns their count.
@@ -239,6 +250,16 @@ pastis_status discover(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, 
         as.max_ub = M.max_ub;
         as.scan_temp = temp;
         HIP_TRY(ctx, as_stage(as, s), "A S plan");
+        // nnz(S): the kept slots of every row (the k-mer itself and its
+        // present substitutes), for the discovery's traffic accounting
+        HIP_TRY(ctx, fill<unsigned long long>(M.nnz_s, 1, 0ull, s), "reset");
+        if (nu > 0) {
+            sum_u32_kernel<<<grid_for(nu), 256, 0, s>>>(s_cnt, nu, M.nnz_s);
+            HIP_TRY(ctx, hipGetLastError(), "sum kernel");
+        }
+        unsigned long long nnz_s = 0;
+        PASTIS_TRY(read_device(ctx, M.nnz_s, &nnz_s, sizeof(nnz_s), s));
+        ctx->stats.n_subs_entries = (int64_t)nnz_s;
         uint64_t tot = 0;
         unsigned long long mx = 0;
         PASTIS_TRY(read_device(ctx, as.as_start + n, &tot, sizeof(tot), s));
@@ -666,9 +687,10 @@ pastis_status pastis_set_tuning(pastis_ctx *ctx, const pastis_tuning *t) {
     if (!ctx || !t) return PASTIS_E_INVAL;
     if (t->sw16_max_rows < 0 || t->sw16_max_rows > 16 || t->sw_direct_pct < 0 || t->sw_grid_scale < 1 ||
         t->sw_grid_scale > 64 || t->sw_grid_scale_wide < 1 || t->sw_grid_scale_wide > 64 || t->sw_intra_pair < 0 ||
-        t->sw_intra_pair > 1 || t->sw16_narrow_rows < 0 || t->sw16_narrow_rows > 4)
+        t->sw_intra_pair > 1 || t->sw16_narrow_rows < 0 || t->sw16_narrow_rows > 4 || t->sw_long_blocks < 1 ||
+        t->sw_long_blocks > 4)
         return set_error(ctx, PASTIS_E_INVAL, "tuning value out of range");
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 1; ++i)
         if (t->reserved[i] != 0) return set_error(ctx, PASTIS_E_INVAL, "reserved fields must be zero");
     ctx->tune = *t;
     return PASTIS_OK;
@@ -768,6 +790,8 @@ pastis_status pastis_autotune(pastis_ctx *ctx, const uint8_t *residues, const in
         PASTIS_TRY(sweep(&ctx->tune.sw_intra_pair, intra, 2));
         const int narrow[] = {4, 2, 0};
         PASTIS_TRY(sweep(&ctx->tune.sw16_narrow_rows, narrow, 3));
+        const int longb[] = {4, 2, 1};
+        PASTIS_TRY(sweep(&ctx->tune.sw_long_blocks, longb, 3));
     }
     if (out) *out = ctx->tune;
     return PASTIS_OK;

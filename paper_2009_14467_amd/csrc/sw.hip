@@ -1745,8 +1745,13 @@ bool sw_bin_is16(int bin, int max16) {
 hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pairs, int64_t npairs,
                      const int8_t *blosum, const Scoring &sc, SwPass1Out *p1, pastis_pair_record *out,
                      const SwWork &wk, int stats_mode, int max16, int grid_scale, int grid_scale_wide, int intra,
-                     int narrow16, bool timed, hipStream_t s) {
+                     int narrow16, int long_blocks, bool timed, hipStream_t s) {
     // timed = false (graph capture): no stage or per-bin events
+    // multi-strip launches: at most long_blocks blocks per CU (they run beside
+    // the one-strip bins on the second stream; fewer resident waves leave the
+    // one-strip kernels more room).  Fewer blocks than the default never
+    // exceed the boundary buffers, which are sized for the default grids.
+    auto long_cap = [&](int blocks) { return std::min(blocks, 256 * long_blocks); };
     const bool use16 = max16 > 0;
     auto begin = [&](int st) { return timed ? stage_begin(ctx, st, s) : hipSuccess; };
     auto end = [&](int st) { return timed ? stage_end(ctx, st, s) : hipSuccess; };
@@ -1800,8 +1805,8 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
         const int R = rows_of_bin(bin);
         const int scale = bin >= kMultiBin ? 1 : R <= 8 ? grid_scale : grid_scale_wide;
         if (sw_bin_is16(bin, max16) && bin >= kMulti16Bin)
-            e = kP16M[bin - kMulti16Bin](bin, blocks16m(), codes, pairs, idx1, wk.starts, blosum, go_ge, ge, p1,
-                                         wk.scratch, wk.scratch_per_wave, wk.queue, st);
+            e = kP16M[bin - kMulti16Bin](bin, long_cap(blocks16m()), codes, pairs, idx1, wk.starts, blosum, go_ge, ge,
+                                         p1, wk.scratch, wk.scratch_per_wave, wk.queue, st);
         else if (intra && bin >= kMultiBin)
             e = kPI[R - kMultiMinR](bin, codes, pairs, idx1, wk.starts, blosum, go_ge, ge, p1, wk.scratch,
                                     wk.scratch_per_wave, wk.queue, wk.counters + kCounterIntraFlag, st);
@@ -1809,8 +1814,11 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
             e = kP16[bin](bin, capped(scale * blocks16(R), pairs_per_block16(R, R <= narrow16)), R <= narrow16, codes,
                           pairs, idx1, wk.starts, blosum, go_ge, ge, p1, wk.queue, st);
         else
-            e = kP1[bin](bin, capped(scale * blocks_for_bin(bin), wpb32(R)), codes, pairs, idx1,
-                         wk.starts, blosum, go_ge, ge, p1, wk.scratch, wk.scratch_per_wave, wk.queue, st);
+            e = kP1[bin](bin,
+                         capped(bin >= kMultiBin ? long_cap(blocks_for_bin(bin)) : scale * blocks_for_bin(bin),
+                                wpb32(R)),
+                         codes, pairs, idx1, wk.starts, blosum, go_ge, ge, p1, wk.scratch, wk.scratch_per_wave,
+                         wk.queue, st);
         if (e != hipSuccess) return e;
         if ((e = mark(ctx->bin_ev[2 * bin + 1], st)) != hipSuccess) return e;
     }
@@ -1820,6 +1828,9 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
     // (multi-strip bins keep a resident grid: one boundary buffer per wave)
     auto scale2 = [&](int bin) {
         return bin >= kMultiBin ? 1 : rows_of_bin(bin) <= 8 ? grid_scale : grid_scale_wide;
+    };
+    auto blocks2 = [&](int bin) {
+        return bin >= kMultiBin ? long_cap(blocks_for_bin(bin)) : scale2(bin) * blocks_for_bin(bin);
     };
     sw_bin2_kernel<<<nb, 256, 0, s>>>(pairs, p1, npairs, sc.cov_pct, stats_mode, sc.direct_pct, out, wk.bin_of,
                                       wk.counters);
@@ -1832,7 +1843,7 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
             const int bin = (k + kMultiBin) % kNumBins;
             const hipStream_t st = bin >= kMultiBin ? ls : s;
             const int R = rows_of_bin(bin);
-            e = kPB[bin](bin, capped(scale2(bin) * blocks_for_bin(bin), wpb32(R)), codes, pairs,
+            e = kPB[bin](bin, capped(blocks2(bin), wpb32(R)), codes, pairs,
                          wk.idx2, wk.starts2, blosum, go_ge, ge, p1, wk.scratch, wk.scratch_per_wave,
                          wk.queue + kNumBins, st);
             if (e != hipSuccess) return e;
@@ -1848,7 +1859,7 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
         const int bin = (k + kMultiBin) % kNumBins;
         const hipStream_t st = bin >= kMultiBin ? ls : s;
         const int R = rows_of_bin(bin);
-        e = kP2[bin](bin, capped(scale2(bin) * blocks_for_bin(bin), wpb32(R)), codes, pairs,
+        e = kP2[bin](bin, capped(blocks2(bin), wpb32(R)), codes, pairs,
                      wk.idx2, wk.starts2, blosum, go_ge, ge, sc.cov_pct, sc.id_pct, p1, out, wk.scratch,
                      wk.scratch_per_wave, wk.queue + 2 * kNumBins, st);
         if (e != hipSuccess) return e;

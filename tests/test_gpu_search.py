@@ -72,7 +72,8 @@ def test_search_repeatable(gpu):
                                     dict(sw16_max_rows=12, sw_direct_pct=1 << 20, sw_grid_scale=1),
                                     dict(sw16_max_rows=16, sw_direct_pct=25, sw_grid_scale=64, sw_grid_scale_wide=3),
                                     dict(sw16_max_rows=0, sw_intra_pair=1), dict(sw16_narrow_rows=0),
-                                    dict(sw16_narrow_rows=2, sw_direct_pct=0)])
+                                    dict(sw16_narrow_rows=2, sw_direct_pct=0), dict(sw_long_blocks=1),
+                                    dict(sw16_max_rows=0, sw_long_blocks=2)])
 def test_every_schedule_gives_the_same_edges(gpu, orc, tuning):
     """Schedule knobs move time, never results: each setting against the oracle."""
     import paper_2009_14467_amd as P
@@ -104,6 +105,8 @@ def test_autotune_picks_a_valid_schedule(gpu):
         ctx.set_tuning(sw16_max_rows=17)
     with pytest.raises(P.PastisError):
         ctx.set_tuning(sw16_narrow_rows=5)
+    with pytest.raises(P.PastisError):
+        ctx.set_tuning(sw_long_blocks=0)
 
 
 def test_graph_mode_replays_match_direct_launches(gpu):

@@ -59,17 +59,29 @@ MEASURED_TRAFFIC_KIB = {("large", "sw16s_pass1_kernel<32, 14, 4>"): (456576.4, 3
                         ("mid", "sw16s_pass1_kernel<32, 12, 4>"): (1246851.25, 129269.531),
                         ("mid", "sw16s_pass1_kernel<16, 16, 4>"): (1311538.562, 130976.219),
                         ("mid", "sw16_pass1_kernel<9, 4, false>"): (592586.188, 58720.5)}
-# the same counters for the product kernels of candidate discovery (one launch
-# of each per step): their posting reads are scattered (an 8-byte record per
-# product, from lines of 64-128 bytes), so the traffic exceeds the
-# algorithmic bytes many times over
+# the same counters for the kernels of the sparse-product stage (one launch of
+# each per step): the row scan that sizes each row's table, the headed
+# posting records, and the product kernels (LDS tables of 2K..32K slots, and
+# global-memory tables for the largest rows).  A row entry's posting list is a
+# scattered read (a header and its records share a line), so the traffic
+# exceeds the compulsory bytes several times over.
 SPGEMM_TRAFFIC_KIB = {
-    "large": {"spgemm_lds_kernel<8192, 3072>": (23536068.2, 1129332.0),
-              "spgemm_lds_kernel<16384, 2048>": (479785.3, 29702.4)},
-    "mid": {"spgemm_lds_kernel<8192, 3072>": (18749019.875, 1786354.969),
-            "spgemm_lds_kernel<16384, 2048>": (16981704.562, 2089405.750),
-            "spgemm_lds_kernel<32768, 4096>": (7057943.812, 1052681.688),
-            "spgemm_global_kernel": (2245486.812, 1480966.438)},
+    "large": {"work_kernel": (5585523.6, 20248.8),
+              "posting_records_kernel": (508038.6, 957027.9),
+              "spgemm_lds_kernel<2048, 1024>": (3997231.4, 1536517.8),
+              "spgemm_lds_kernel<4096, 2048>": (4927850.7, 1673725.1),
+              "spgemm_lds_kernel<8192, 3072>": (1750050.0, 676925.6),
+              "spgemm_lds_kernel<16384, 2048>": (211802.2, 88293.9),
+              "spgemm_lds_kernel<32768, 4096>": (6824.4, 3674.4),
+              "spgemm_global_kernel": (23.2, 131072.0)},
+    "mid": {"work_kernel": (11050645.5, 4945.4),
+            "posting_records_kernel": (114681.5, 240936.1),
+            "spgemm_lds_kernel<2048, 1024>": (189618.7, 47680.3),
+            "spgemm_lds_kernel<4096, 2048>": (1782295.7, 507212.2),
+            "spgemm_lds_kernel<8192, 3072>": (5915061.0, 2196867.1),
+            "spgemm_lds_kernel<16384, 2048>": (5803903.4, 2948258.8),
+            "spgemm_lds_kernel<32768, 4096>": (2212431.1, 1422611.3),
+            "spgemm_global_kernel": (1748012.2, 1480848.1)},
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
@@ -107,7 +119,8 @@ def parse():
     ap.add_argument("--no-graph", action="store_true",
                     help="time the step with direct launches only (default: the SW stage replayed as a HIP graph)")
     ap.add_argument("--no-mid", action="store_true", help="skip the mid-workload sub-object")
-    ap.add_argument("--ns", action="store_true", help="also time the normalised-score weight mode (no traceback)")
+    ap.add_argument("--no-ns", action="store_true",
+                    help="skip the normalised-score weight leg (no statistics pass)")
     ap.add_argument("--pairs", type=int, default=0,
                     help="also time the alignment stage alone on this many seeded pairs (0: off)")
     ap.add_argument("--tune-pairs", type=int, default=2_000_000, help="candidate sample size of the autotuner")
@@ -265,7 +278,8 @@ def spgemm_line(st, ms, traffic_workload):
     compulsory bytes are A and its transpose read once (12 B per nonzero),
     the candidates written (20 B each) and, with substitutes, S read once (5 B
     per entry); the stage time also holds the symmetrisation and sort.
-    `traffic` is the product kernels' counted HBM bytes per step."""
+    `traffic` is the counted HBM bytes per step of the stage's row scan,
+    posting records and product kernels."""
     compulsory = 12 * st["n_kmers"] + 20 * st["n_candidates"] + 5 * st["n_subs_entries"]
     gbs = compulsory / (ms * 1e-3) / 1e9
     traffic = None
@@ -534,7 +548,7 @@ def main():
     if not args.no_xd:
         line["xd"] = xd_leg(P, args, params, res, off, n_cand)
         note(f"xd: {line['xd']['ms_per_step']:.1f} ms per step")
-    if args.ns:
+    if not args.no_ns:
         nctx = P.Context(P.Params(weight_mode="ns", **params))
         set_tuning(nctx, tuning)
         nms, _, nstage, _ = timed_steps(nctx, args, res, off)

@@ -28,7 +28,10 @@
  *     any other byte is rejected with PASTIS_E_BAD_RESIDUE.
  *   - Sequence lengths must be <= 65535 (positions are 16-bit in the kernels);
  *     longer sequences are rejected with PASTIS_E_INVAL.  Sequences shorter
- *     than k are valid and yield no k-mers; n = 0 yields no edges.
+ *     than k are valid and yield no k-mers; n = 0 yields no edges.  A call
+ *     that discovers candidates (pastis_discover, pastis_search and the
+ *     calls built on them) takes fewer than 2^30 residues in total (k-mer
+ *     entries are indexed in 31 bits); more give PASTIS_E_INVAL.
  */
 #ifndef PASTIS_H
 #define PASTIS_H
@@ -104,7 +107,10 @@ typedef struct pastis_params {
 
 /* One similarity edge, 48 bytes.  i < j; edges are sorted by (i, j).
  * Positions are 0-based and inclusive.  identity = matches / columns and
- * ns_weight = score / min(len_i, len_j), both IEEE float32 round-to-nearest. */
+ * ns_weight = score / min(len_i, len_j), both IEEE float32 round-to-nearest.
+ * Edges of weight_mode NS carry no traceback results: begins and ends are
+ * 0xFFFFFFFF and matches, columns and identity 0 (the weight needs only the
+ * score, so the search skips the passes that find them). */
 typedef struct pastis_edge {
     uint32_t i, j;
     int32_t score;

@@ -313,8 +313,9 @@ def records_to_edges(pi, pj, counts, rec, lengths, weight: str = "ani") -> np.nd
     ANI mode keeps pairs that pass the identity/coverage cut, weight =
     matches/columns in float32 (Section VI-B).  NS mode keeps every pair with
     a positive score, weight = score / shorter length, and no cut-off
-    (Section VI-B); its edges carry no traceback statistics (begins reported
-    as 0xFFFFFFFF, matches, columns and identity as 0).
+    (Section VI-B); the weight needs only the score, so its edges carry no
+    traceback statistics and no alignment coordinates (begins and ends
+    reported as 0xFFFFFFFF, matches, columns and identity as 0).
     """
     pi = np.asarray(pi, dtype=np.uint32)
     pj = np.asarray(pj, dtype=np.uint32)
@@ -345,9 +346,10 @@ def records_to_edges(pi, pj, counts, rec, lengths, weight: str = "ani") -> np.nd
     short = np.minimum(lens[lo], lens[hi]).astype(np.float32)
     e["ns_weight"] = r["score"].astype(np.float32) / short
     if weight == "ns":
-        # the normalised score needs no traceback (Section VI-B): the
-        # traceback statistics are not part of an NS edge
-        e["beg_i"] = e["beg_j"] = 0xFFFFFFFF
+        # the normalised score needs only the score (Section VI-B): the
+        # traceback statistics and the alignment's extent are not part of an
+        # NS edge
+        e["beg_i"] = e["beg_j"] = e["end_i"] = e["end_j"] = 0xFFFFFFFF
         e["matches"] = e["columns"] = 0
         e["identity"] = 0.0
     order = np.lexsort((e["j"], e["i"]))

@@ -366,8 +366,9 @@ pastis_status align_core(pastis_ctx *ctx, const Staged &st, const uint8_t *codes
     const int stats_mode = P.full_records ? 1 : (P.weight_mode == PASTIS_WEIGHT_NS ? 2 : 0);
     if (P.align_mode == PASTIS_ALIGN_SW) {
         // 16-bit pass 1 on request, or by default where its records stay
-        // inside the search (they omit end_b of pairs without statistics)
-        const bool use16 = sw16_supported(sc) && stats_mode == 0 &&
+        // inside the search (they omit end_b of pairs without statistics,
+        // which no edge then reports)
+        const bool use16 = sw16_supported(sc) && stats_mode != 1 &&
                            (P.score_width == 16 || (P.score_width == 0 && ctx->records_internal));
         const int max16 = !use16 ? 0 : P.score_width == 16 ? 16 : ctx->tune.sw16_max_rows;
         if (max16 > 0) PASTIS_TRY(make_sort_work(ctx, npairs, wk));

@@ -11,8 +11,10 @@
 //   postings (A^T): post_seq / post_pos, grouped by distinct k-mer, sequences
 //                   ascending inside a group; uk_id / uk_start index the groups;
 //   rows (A):       row_start[n+1], row_u (distinct k-mer index), row_pos;
-//   kmap:           dense map id -> distinct k-mer index or -1 (24^k entries),
-//                   for k <= kDenseMapMaxK only.
+//   kmap:           dense map id -> head of the distinct k-mer's posting group
+//                   (uk_start[u] + u) or -1 (24^k entries), for k <=
+//                   kDenseMapMaxK only;
+//   row_h (if set): per row entry, the head of its k-mer's posting group.
 // Ids are 64-bit (24^8 < 2^37); a window that runs past its sequence gets
 // the key 24^k, which sorts after every id.
 #include "internal.hpp"
@@ -114,22 +116,25 @@ __global__ void close_kernel(const uint32_t *__restrict__ nnz, const uint32_t *_
 
 __global__ void rows_kernel(const uint32_t *__restrict__ post_seq, const uint16_t *__restrict__ post_pos,
                             const uint32_t *__restrict__ post_u, const uint32_t *__restrict__ nnz_p,
-                            const uint32_t *__restrict__ row_start, uint32_t *__restrict__ cursor,
-                            uint32_t *__restrict__ row_u, uint16_t *__restrict__ row_pos) {
+                            const uint32_t *__restrict__ row_start, const uint32_t *__restrict__ uk_start,
+                            uint32_t *__restrict__ cursor, uint32_t *__restrict__ row_u, uint16_t *__restrict__ row_pos,
+                            uint32_t *__restrict__ row_h) {
     const uint32_t nnz = *nnz_p;
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < nnz; p += gridDim.x * blockDim.x) {
         const uint32_t i = post_seq[p];
+        const uint32_t u = post_u[p];
         const uint32_t slot = row_start[i] + atomicAdd(&cursor[i], 1u);
-        row_u[slot] = post_u[p];
+        row_u[slot] = u;
         row_pos[slot] = post_pos[p];
+        if (row_h) row_h[slot] = uk_start[u] + u;  // postings are grouped by u: these reads run in order
     }
 }
 
-__global__ void kmap_kernel(const uint64_t *__restrict__ uk_id, const uint32_t *__restrict__ nu_p,
-                            int32_t *__restrict__ kmap) {
+__global__ void kmap_kernel(const uint64_t *__restrict__ uk_id, const uint32_t *__restrict__ uk_start,
+                            const uint32_t *__restrict__ nu_p, int32_t *__restrict__ kmap) {
     const uint32_t nu = *nu_p;
     for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < nu; u += gridDim.x * blockDim.x)
-        kmap[uk_id[u]] = (int32_t)u;
+        kmap[uk_id[u]] = (int32_t)(uk_start[u] + u);
 }
 
 inline unsigned grid_for(int64_t n) {
@@ -207,13 +212,13 @@ hipError_t build_kmers(const uint8_t *codes, const int64_t *offsets, int64_t n, 
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (m > 0) {
         rows_kernel<<<grid_for(m), 256, 0, s>>>(kt.post_seq, kt.post_pos, kt.post_u, kt.counts + 0, kt.row_start,
-                                                cursor, kt.row_u, kt.row_pos);
+                                                kt.uk_start, cursor, kt.row_u, kt.row_pos, kt.row_h);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (want_kmap && k <= kDenseMapMaxK) {
         if ((e = fill<int>(kt.kmap, kmap_entries(k), -1, s)) != hipSuccess) return e;
         if (m > 0) {
-            kmap_kernel<<<grid_for(m), 256, 0, s>>>(kt.uk_id, kt.counts + 1, kt.kmap);
+            kmap_kernel<<<grid_for(m), 256, 0, s>>>(kt.uk_id, kt.uk_start, kt.counts + 1, kt.kmap);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
     }

@@ -13,7 +13,12 @@ namespace pastis {
 constexpr int kDenseMapMaxK = 6;
 
 // Device arrays; capacities: n_res entries for postings/rows and distinct
-// k-mers, n + 1 for row bounds, 24^k for kmap.  counts[0] = nnz,
+// k-mers, n + 1 for row bounds, 24^k for kmap.  The product stage reads the
+// postings as headed records: group u occupies records head(u) ..
+// head(u) + len(u), a header (len(u), u) followed by its (sequence,
+// position) records, with head(u) = uk_start[u] + u; a row entry or a
+// substitute then names its posting list by head(u), and one line holds both
+// the list's length and its first records.  counts[0] = nnz,
 // counts[1] = number of distinct k-mers, counts[2] = nnz again (row scan).
 // Distinct ids are ascending in uk_id.
 struct KmerTables {
@@ -27,7 +32,10 @@ struct KmerTables {
     uint32_t *row_start; // n + 1
     uint32_t *row_u;
     uint16_t *row_pos;
-    int32_t *kmap;
+    // optional (may be null): per row entry, the index of its k-mer's group
+    // header in the headed posting records, head(u) = uk_start[u] + u
+    uint32_t *row_h;
+    int32_t *kmap;  // id -> head(u) of the distinct k-mer u, or -1
 };
 
 size_t kmers_temp_bytes(int64_t n_res, int64_t n);

@@ -25,4 +25,24 @@ size_t radix_temp_bytes(int64_t n);
 hipError_t radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, int64_t n, int bits,
                       void *temp, hipStream_t s, bool *result_in_alt);
 
+// Workgroups go to the chip's eight XCDs round-robin by id, and each XCD has
+// its own L2.  Items [0, n) are split into eight contiguous segments, one per
+// XCD, and a unit (a block, or one of `per` waves of a block) walks its XCD's
+// segment with the stride of that XCD's units: items processed at the same
+// time on one XCD are then neighbours, and neighbouring rows of the k-mer
+// matrix (members of one family) share posting lists, which the L2 then
+// serves once.  A grid of fewer than eight blocks uses one segment per
+// block, so any grid covers every item exactly once.
+struct XcdWalk {
+    int64_t first, end, step;
+};
+__device__ __forceinline__ XcdWalk xcd_walk(int64_t n, int per = 1, int sub = 0) {
+    const int segs = gridDim.x < 8u ? (int)gridDim.x : 8;
+    const int x = (int)(blockIdx.x % segs);
+    const int64_t blocks_x = ((int64_t)gridDim.x - x + segs - 1) / segs;
+    const int64_t seg = (n + segs - 1) / segs;
+    const int64_t b = x * seg, e = b + seg < n ? b + seg : n;
+    return {b + (int64_t)(blockIdx.x / segs) * per + sub, e, blocks_x * per};
+}
+
 }  // namespace pastis

@@ -72,6 +72,8 @@ enum DiscBuf {
     kDTuneS2,
     kDTuneRec,
     kDPostRec,
+    kDRowH,
+    kDStage,
     kDEnd
 };
 static_assert(kDEnd <= kNumBufs, "buffer ids");
@@ -155,8 +157,10 @@ __global__ void edge_write_kernel(const pastis_pair_record *__restrict__ rec, co
         const int64_t li = offsets[i + 1] - offsets[i], lj = offsets[j + 1] - offsets[j];
         e.ns_weight = __fdiv_rn((float)r.score, (float)(li < lj ? li : lj));
         if (ns_mode) {
-            // the normalised score needs no traceback: its statistics are not computed
-            e.beg_i = e.beg_j = 0xFFFFFFFFu;
+            // the normalised score needs only the score: the traceback
+            // statistics and the alignment's extent are not computed (16-bit
+            // pass 1 finds no end column)
+            e.beg_i = e.beg_j = e.end_i = e.end_j = 0xFFFFFFFFu;
             e.matches = e.columns = 0;
             e.identity = 0.0f;
         }
@@ -185,6 +189,9 @@ pastis_status discover(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, 
     const pastis_params &P = ctx->params;
     const int64_t m = st.n_res;
     const bool subs = P.n_subs > 0;
+    // k-mer entries and posting-group heads (entries + groups <= 2 * residues)
+    // are 31-bit indices
+    if (m >= (1ll << 30)) return set_error(ctx, PASTIS_E_INVAL, "a discovery takes fewer than 2^30 residues");
     Misc M;
     PASTIS_TRY(misc(ctx, M));
 
@@ -201,6 +208,8 @@ pastis_status discover(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, 
     PASTIS_TRY(get(ctx, kDRowStart, n + 1, &kt.row_start));
     PASTIS_TRY(get(ctx, kDRowU, m, &kt.row_u));
     PASTIS_TRY(get(ctx, kDRowPos, m, &kt.row_pos));
+    kt.row_h = nullptr;
+    if (!subs) PASTIS_TRY(get(ctx, kDRowH, m, &kt.row_h));  // the exact product's entries
     kt.kmap = nullptr;
     const bool dense_map = subs && P.k <= kDenseMapMaxK;  // longer k-mers: binary search of the distinct ids
     if (dense_map) PASTIS_TRY(get(ctx, kDKmap, (size_t)kmap_entries(P.k), &kt.kmap));
@@ -231,8 +240,8 @@ pastis_status discover(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, 
         PASTIS_TRY(get(ctx, kDStmpIds, (size_t)s_rows_threads() * P.n_subs, &tmp_ids));
         PASTIS_TRY(get(ctx, kDStmpD, (size_t)s_rows_threads() * P.n_subs, &tmp_d));
         HIP_TRY(ctx,
-                launch_s_rows(kt.uk_id, kt.counts + 1, kt.kmap, ctx->d_blosum, P.k, P.n_subs, P.sub_alphabet, s_u, s_d,
-                              s_cnt, tmp_ids, tmp_d, s),
+                launch_s_rows(kt.uk_id, kt.counts + 1, kt.uk_start, kt.kmap, ctx->d_blosum, P.k, P.n_subs,
+                              P.sub_alphabet, s_u, s_d, s_cnt, tmp_ids, tmp_d, s),
                 "S kernel");
         AsArgs as{};
         as.kt = &kt;
@@ -281,7 +290,7 @@ pastis_status discover(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, 
         sp.ent_dp = as.as_dp;
     } else {
         sp.row_start32 = kt.row_start;
-        sp.ent_s = kt.row_u;
+        sp.ent_s = kt.row_h;
         sp.ent_pos16 = kt.row_pos;
     }
 
@@ -294,7 +303,8 @@ pastis_status discover(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, 
     sp.max_big = M.max_big;
     sp.products = M.products;
     PASTIS_TRY(get(ctx, kDBigRows, n, &sp.big_rows));
-    PASTIS_TRY(get(ctx, kDPostRec, nnz, &sp.post_rec));
+    PASTIS_TRY(get(ctx, kDPostRec, nnz + nu, &sp.post_rec));
+    PASTIS_TRY(get(ctx, kDStage, spgemm_stage_entries(), &sp.stage));
     sp.nnz = nnz;
     sp.n_big = M.n_big;
     sp.d_count = M.d_count;
@@ -756,17 +766,20 @@ pastis_status pastis_autotune(pastis_ctx *ctx, const uint8_t *residues, const in
             return PASTIS_OK;
         };
         double cur = 0;
-        PASTIS_TRY(measure(&cur));  // also warms the buffers up
-        PASTIS_TRY(measure(&cur));
+        PASTIS_TRY(measure(&cur));  // warms the buffers up
         const int rows16[] = {16, 12, 8, 0};
         const int direct[] = {0, 25, 50, 100, 200, 1 << 20};
         const int grid[] = {1, 2, 4};
         // a value replaces the one in force only when it is at least 1%
         // faster on the sample: smaller differences are within timing noise
-        // and need not carry over to the whole candidate set
+        // and need not carry over to the whole candidate set.  The value in
+        // force is timed again first, so each knob's values are compared
+        // under the same conditions (clocks, caches) rather than against a
+        // figure taken several sweeps earlier.
         auto sweep = [&](int32_t *knob, const int *vals, int nv) -> pastis_status {
             const int32_t keep = *knob;
             int32_t best_v = keep;
+            PASTIS_TRY(measure(&cur));
             double best_ms = cur;
             for (int i = 0; i < nv; ++i) {
                 if (vals[i] == keep) continue;

@@ -13,11 +13,15 @@
 // One workgroup owns one row.  Entries are expanded in chunks: the posting
 // lengths of a chunk are prefix-summed in LDS and every thread takes products
 // by binary search, so a long posting list is shared by the whole group.
-// Phase 1 counts into an LDS hash whose 32-bit slots pack (j << 14 | count);
-// entries reaching the threshold get a candidate slot; phase 2 replays the
-// products and keeps the two smallest seed keys of candidates only (lock-free:
-// the key displaced from the first slot falls to the second).  Rows too large
-// for LDS use the same scheme with 64-bit slots in global memory.
+// Phase 1 counts into an LDS hash whose 32-bit slots pack (j << 14 | count)
+// and stages every product's (slot, seed key) in a per-block buffer; entries
+// reaching the threshold get a candidate slot; phase 2 replays the stage and
+// keeps the two smallest seed keys of candidates only (lock-free: the key
+// displaced from the first slot falls to the second).  Rows too large for LDS
+// use the same scheme with 64-bit slots in global memory, where phase 2
+// expands the row again.
+#include <algorithm>
+
 #include "internal.hpp"
 #include "kmers.hpp"
 #include "prim.hpp"
@@ -31,13 +35,18 @@ hipError_t launch_bins(const int8_t *bin_of, int64_t n, int nbins, int *counts, 
 namespace {
 
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+constexpr int kProductTiers = 5;  // LDS tables of 2K, 4K, 8K, 16K and 32K slots
+// blocks per launch of each tier: resident blocks per CU (LDS and wave
+// limits) times the 256 CUs
+constexpr int kTierBlocks[kProductTiers] = {256 * 8, 256 * 5, 256 * 3, 256 * 2, 256};
 constexpr int kChunk = 512;
 constexpr int kThreads = 256;
 
 __device__ __forceinline__ uint32_t hash32(uint32_t x) { return x * 0x9E3779B1u; }
 
-// A row's entries: exact (A_i: k-mer index + position) or substitute
-// ((A S)_i: substitute index + (distance, position)).
+// A row's entries: exact (A_i: k-mer + position) or substitute ((A S)_i:
+// substitute + (distance, position)); a k-mer is named by the header index of
+// its posting group.
 struct RowView {
     const uint32_t *start32;  // exact: row_start [n+1]
     const uint64_t *start64;  // substitutes: as_start [n+1]
@@ -61,11 +70,12 @@ struct RowView {
     }
 };
 
-// Postings of A^T: uk_start[s] .. uk_start[s + 1] index the (sequence,
-// position) records of k-mer s, one 8-byte record each, so a product reads
-// one line for both.
+// Postings of A^T as headed records: an entry names its k-mer's group by
+// the index h of its header; rec[h] = (length, distinct k-mer index) and the
+// group's (sequence, position) records follow at h + 1.  The header shares a
+// line with the first records, so an entry costs one scattered line for its
+// length and (for the usual short lists) its products.
 struct Postings {
-    const uint32_t *uk_start;
     const uint2 *rec;
 };
 
@@ -102,8 +112,9 @@ __device__ __forceinline__ void emit(const Emit &em, uint32_t i, uint32_t j, uin
     em.dir[slot] = i < j ? 0u : 1u;
 }
 
-// Chunk expansion shared by both phases and both table kinds: calls
-// f(pos_i, j, pos_j) for every product of entries [c0, c0 + ce) of row i.
+// Chunk expansion shared by both table kinds: calls f(pos_i, j, pos_j, q)
+// for every product of row i, q numbering the row's products from 0 (the
+// same numbers in every expansion of the row); returns the product count.
 struct ChunkLds {
     uint32_t pref[kChunk + 1];
     uint32_t pbeg[kChunk];
@@ -112,27 +123,26 @@ struct ChunkLds {
 };
 
 template <typename F>
-__device__ __forceinline__ void expand_row(const RowView &rv, const Postings &P, uint32_t i, ChunkLds &C, F &&f) {
+__device__ __forceinline__ uint32_t expand_row(const RowView &rv, const Postings &P, uint32_t i, ChunkLds &C, F &&f) {
     uint64_t b, e;
     rv.bounds(i, b, e);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t done = 0;
     for (uint64_t c0 = b; c0 < e; c0 += kChunk) {
         const int ce = (int)((e - c0) < (uint64_t)kChunk ? (e - c0) : (uint64_t)kChunk);
         // lengths of this chunk's posting lists, prefix-summed over the block
         uint32_t len0 = 0, len1 = 0;
         const int t0 = threadIdx.x * 2, t1 = t0 + 1;
         if (t0 < ce) {
-            const uint32_t s = rv.ent_s[c0 + t0];
-            const uint32_t pb = P.uk_start[s];
-            len0 = P.uk_start[s + 1] - pb;
-            C.pbeg[t0] = pb;
+            const uint32_t h = rv.ent_s[c0 + t0];
+            len0 = P.rec[h].x;
+            C.pbeg[t0] = h + 1;
             C.epos[t0] = rv.pos(c0 + t0);
         }
         if (t1 < ce) {
-            const uint32_t s = rv.ent_s[c0 + t1];
-            const uint32_t pb = P.uk_start[s];
-            len1 = P.uk_start[s + 1] - pb;
-            C.pbeg[t1] = pb;
+            const uint32_t h = rv.ent_s[c0 + t1];
+            len1 = P.rec[h].x;
+            C.pbeg[t1] = h + 1;
             C.epos[t1] = rv.pos(c0 + t1);
         }
         uint32_t v = len0 + len1, inc = v;
@@ -162,10 +172,12 @@ __device__ __forceinline__ void expand_row(const RowView &rv, const Postings &P,
                     hi = mid;
             }
             const uint2 r = P.rec[C.pbeg[lo] + (p - C.pref[lo])];
-            f(C.epos[lo], r.x, r.y);
+            f(C.epos[lo], r.x, r.y, done + p);
         }
+        done += total;
         __syncthreads();
     }
+    return done;
 }
 
 // ------------------------------------------------------------ LDS kernel
@@ -190,29 +202,37 @@ template <int CAP, int CC>
 __global__ __launch_bounds__(kThreads) void spgemm_lds_kernel(RowView rv, Postings P, const int *__restrict__ idx,
                                                               const int *__restrict__ starts, int bin, int ck,
                                                               Emit em, uint32_t *__restrict__ spill_rows,
-                                                              uint32_t *__restrict__ spill_count) {
+                                                              uint32_t *__restrict__ spill_count,
+                                                              uint2 *__restrict__ stage_all) {
     static_assert(CC < (1 << 14), "candidate tags fit 14 bits");
     __shared__ RowLds<CAP, CC> L;
     constexpr uint32_t mask = CAP - 1;
+    // this block's stage: (slot, seed key) of each product of the current
+    // row, kEmpty for the skipped ones (a row has at most 3/4 CAP products)
+    uint2 *stage = stage_all + (size_t)blockIdx.x * (3 * CAP / 4);
     for (int t = threadIdx.x; t < CAP; t += kThreads) L.slot[t] = kEmpty;
     if (threadIdx.x == 0) {
         L.ncand = 0;
         L.spill = 0;
     }
     __syncthreads();
-    const int end = starts[bin + 1];
-    for (int w = starts[bin] + blockIdx.x; w < end; w += gridDim.x) {
-        const uint32_t i = (uint32_t)idx[w];
+    const int b0 = starts[bin];
+    const XcdWalk it = xcd_walk(starts[bin + 1] - b0);
+    for (int64_t t = it.first; t < it.end; t += it.step) {
+        const uint32_t i = (uint32_t)idx[b0 + t];
         const bool exact = rv.exact;
-        // phase 1: counts
-        expand_row(rv, P, i, L.chunk, [&](uint32_t, uint32_t j, uint32_t) {
-            if (j == i || (exact && j < i)) return;
+        // phase 1: counts, and each product's slot and seed key staged
+        const uint32_t total = expand_row(rv, P, i, L.chunk, [&](uint32_t pi, uint32_t j, uint32_t pj, uint32_t q) {
+            if (j == i || (exact && j < i)) {
+                stage[q] = make_uint2(kEmpty, 0u);
+                return;
+            }
             uint32_t h = hash32(j) & mask;
             for (;;) {
                 uint32_t v = L.slot[h];
                 if (v == kEmpty) {
                     const uint32_t old = atomicCAS(&L.slot[h], kEmpty, (j << 14) | 1u);
-                    if (old == kEmpty) return;
+                    if (old == kEmpty) break;
                     v = old;
                 }
                 if ((v >> 14) == j) {
@@ -220,10 +240,11 @@ __global__ __launch_bounds__(kThreads) void spgemm_lds_kernel(RowView rv, Postin
                     // with 64-bit slots (the table keeps fewer than CAP keys,
                     // so later probes still end)
                     if ((atomicAdd(&L.slot[h], 1u) & 0x3FFFu) == 0x3FFFu) L.spill = 1;
-                    return;
+                    break;
                 }
                 h = (h + 1) & mask;
             }
+            stage[q] = make_uint2(h, seed_key(i, j, pi, pj));
         });
         __syncthreads();
         for (int t = threadIdx.x; t < CAP; t += kThreads) {
@@ -271,18 +292,14 @@ __global__ __launch_bounds__(kThreads) void spgemm_lds_kernel(RowView rv, Postin
                 }
                 __threadfence_block();
                 __syncthreads();
-                // phase 2: seeds of candidate entries
-                expand_row(rv, P, i, L.chunk, [&](uint32_t pi, uint32_t j, uint32_t pj) {
-                    if (j == i || (exact && j < i)) return;
-                    uint32_t h = hash32(j) & mask;
-                    uint32_t v = L.slot[h];
-                    while ((v >> 14) != j) {
-                        h = (h + 1) & mask;
-                        v = L.slot[h];
-                    }
-                    const uint32_t tag = v & 0x3FFFu;
-                    if (tag) seed_min2(&em.s1[base + tag - 1], &em.s2[base + tag - 1], seed_key(i, j, pi, pj));
-                });
+                // phase 2: seeds of candidate entries, from the stage (its
+                // slots now hold j << 14 | candidate + 1, or 0 for none)
+                for (uint32_t q = threadIdx.x; q < total; q += kThreads) {
+                    const uint2 r = stage[q];
+                    if (r.x == kEmpty) continue;
+                    const uint32_t tag = L.slot[r.x] & 0x3FFFu;
+                    if (tag) seed_min2(&em.s1[base + tag - 1], &em.s2[base + tag - 1], r.y);
+                }
             }
         }
         __syncthreads();
@@ -324,7 +341,7 @@ __global__ __launch_bounds__(kThreads) void spgemm_global_kernel(RowView rv, Pos
         uint32_t rcap = 4096;
         while (rcap < want && rcap < cap) rcap <<= 1;
         const uint32_t mask = rcap - 1;
-        expand_row(rv, P, i, C, [&](uint32_t, uint32_t j, uint32_t) {
+        expand_row(rv, P, i, C, [&](uint32_t, uint32_t j, uint32_t, uint32_t) {
             if (j == i || (exact && j < i)) return;
             uint32_t h = hash32(j) & mask;
             for (;;) {
@@ -361,7 +378,7 @@ __global__ __launch_bounds__(kThreads) void spgemm_global_kernel(RowView rv, Pos
         __threadfence_block();
         __syncthreads();
         if (ncand > 0) {
-            expand_row(rv, P, i, C, [&](uint32_t pi, uint32_t j, uint32_t pj) {
+            expand_row(rv, P, i, C, [&](uint32_t pi, uint32_t j, uint32_t pj, uint32_t) {
                 if (j == i || (exact && j < i)) return;
                 uint32_t h = hash32(j) & mask;
                 unsigned long long v = slot[h];
@@ -453,9 +470,10 @@ __global__ __launch_bounds__(kThreads) void as_lds_kernel(AsIn in, const int *__
     }
     if (threadIdx.x == 0) n_out = 0;
     __syncthreads();
-    const int end = starts[bin + 1];
-    for (int w = starts[bin] + blockIdx.x; w < end; w += gridDim.x) {
-        const uint32_t i = (uint32_t)idx[w];
+    const int b0 = starts[bin];
+    const XcdWalk it = xcd_walk(starts[bin + 1] - b0);
+    for (int64_t t = it.first; t < it.end; t += it.step) {
+        const uint32_t i = (uint32_t)idx[b0 + t];
         as_reduce(in, i, tab, CAP - 1);
         __syncthreads();
         const uint64_t base = as_start[i];
@@ -531,8 +549,8 @@ __global__ __launch_bounds__(256) void as_ub_kernel(AsIn in, int64_t n, uint32_t
                                                     uint32_t *__restrict__ as_len, int8_t *__restrict__ bin_of,
                                                     unsigned long long *__restrict__ max_ub) {
     const int lane = threadIdx.x & 63;
-    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / 64);
-    for (int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; i < n; i += waves) {
+    const XcdWalk it = xcd_walk(n, blockDim.x / 64, threadIdx.x / 64);
+    for (int64_t i = it.first; i < it.end; i += it.step) {
         uint32_t s = 0;
         for (uint32_t x = in.row_start[i] + lane; x < in.row_start[i + 1]; x += 64) s += in.s_cnt[in.row_u[x]];
 #pragma unroll
@@ -547,10 +565,17 @@ __global__ __launch_bounds__(256) void as_ub_kernel(AsIn in, int64_t n, uint32_t
     }
 }
 
-__global__ void posting_records_kernel(const uint32_t *__restrict__ seq, const uint16_t *__restrict__ pos, int64_t n,
-                                       uint2 *__restrict__ rec) {
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
-        rec[x] = make_uint2(seq[x], (uint32_t)pos[x]);
+// headed records: posting x of group u goes to x + u + 1; the group's first
+// posting also writes the header (length, u) just before it
+__global__ void posting_records_kernel(const uint32_t *__restrict__ seq, const uint16_t *__restrict__ pos,
+                                       const uint32_t *__restrict__ post_u, const uint32_t *__restrict__ uk_start,
+                                       int64_t n, uint2 *__restrict__ rec) {
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t u = post_u[x];
+        const uint32_t b = uk_start[u];
+        rec[x + u + 1] = make_uint2(seq[x], (uint32_t)pos[x]);
+        if ((uint32_t)x == b) rec[x + u] = make_uint2(uk_start[u + 1] - b, u);
+    }
 }
 
 // products of row i (postings visited), and the row's bin; one wave per row
@@ -561,15 +586,12 @@ __global__ __launch_bounds__(256) void work_kernel(RowView rv, Postings P, int64
                                                    uint32_t *__restrict__ big_rows, uint32_t *__restrict__ n_big,
                                                    unsigned long long *__restrict__ products) {
     const int lane = threadIdx.x & 63;
-    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / 64);
-    for (int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; i < n; i += waves) {
+    const XcdWalk it = xcd_walk(n, blockDim.x / 64, threadIdx.x / 64);
+    for (int64_t i = it.first; i < it.end; i += it.step) {
         uint64_t b, e;
         rv.bounds((uint32_t)i, b, e);
         uint64_t w = 0;
-        for (uint64_t x = b + lane; x < e; x += 64) {
-            const uint32_t s = rv.ent_s[x];
-            w += P.uk_start[s + 1] - P.uk_start[s];
-        }
+        for (uint64_t x = b + lane; x < e; x += 64) w += P.rec[rv.ent_s[x]].x;
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
             const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)w, off, 64);
@@ -579,19 +601,16 @@ __global__ __launch_bounds__(256) void work_kernel(RowView rv, Postings P, int64
         if (lane != 0) continue;
         work[i] = w;
         if (w) atomicAdd(products, (unsigned long long)w);
-        int8_t bin;
-        if (w == 0)
-            bin = -1;
-        else if (n_big_ok && w <= 6144)
-            bin = 0;  // 8192 slots
-        else if (n_big_ok && w <= 12288)
-            bin = 1;  // 16384 slots
-        else if (n_big_ok && w <= 24576)
-            bin = 2;  // 32768 slots
-        else
-            bin = -1;
+        // tables of 2^(11 + bin) slots hold rows of up to 3/4 of that many products
+        int8_t bin = -1;
+        if (w > 0 && n_big_ok)
+            for (int b = 0; b < kProductTiers; ++b)
+                if (w <= (3ull << (9 + b))) {
+                    bin = (int8_t)b;
+                    break;
+                }
         bin_of[i] = bin;
-        if (w > 0 && (!n_big_ok || w > 24576)) {
+        if (w > 0 && bin < 0) {
             big_rows[atomicAdd(n_big, 1u)] = (uint32_t)i;
             atomicMax(max_big, (unsigned long long)w);
         }
@@ -649,6 +668,12 @@ inline unsigned grid_for(int64_t n) {
 
 }  // namespace
 
+size_t spgemm_stage_entries() {
+    size_t m = 0;
+    for (int b = 0; b < kProductTiers; ++b) m = std::max(m, (size_t)kTierBlocks[b] * (3u << (9 + b)));
+    return m;
+}
+
 int key_bits(int64_t n) {
     int b = 1;
     while (b < 32 && (1ll << b) < n) ++b;
@@ -686,36 +711,47 @@ hipError_t as_run(const AsArgs &a, uint32_t gcap, hipStream_t s) {
 
 hipError_t spgemm_plan(const SpgemmArgs &a, hipStream_t s) {
     RowView rv{a.row_start32, a.row_start64, a.row_len, a.ent_s, a.ent_pos16, a.ent_dp, a.exact};
-    Postings P{a.kt->uk_start, a.post_rec};
+    Postings P{a.post_rec};
     hipError_t e;
     if ((e = fill<unsigned long long>(a.max_big, 1, 0ull, s)) != hipSuccess) return e;
     if ((e = fill<uint32_t>(a.n_big, 2, 0u, s)) != hipSuccess) return e;
     if ((e = fill<unsigned long long>(a.products, 1, 0ull, s)) != hipSuccess) return e;
-    posting_records_kernel<<<grid_for(a.nnz), 256, 0, s>>>(a.kt->post_seq, a.kt->post_pos, a.nnz, a.post_rec);
+    posting_records_kernel<<<grid_for(a.nnz), 256, 0, s>>>(a.kt->post_seq, a.kt->post_pos, a.kt->post_u,
+                                                            a.kt->uk_start, a.nnz, a.post_rec);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     work_kernel<<<grid_for(64 * a.n), 256, 0, s>>>(rv, P, a.n, a.n < (1ll << 18) ? 1 : 0, a.work, a.bin_of,
                                                    a.max_big, a.big_rows, a.n_big, a.products);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    return launch_bins(a.bin_of, a.n, 3, a.bins.counts, a.bins.starts, a.bins.cursor, a.bins.idx, s);
+    return launch_bins(a.bin_of, a.n, kProductTiers, a.bins.counts, a.bins.starts, a.bins.cursor, a.bins.idx, s);
 }
 
 hipError_t spgemm_run(const SpgemmArgs &a, uint32_t gcap, hipStream_t s) {
     RowView rv{a.row_start32, a.row_start64, a.row_len, a.ent_s, a.ent_pos16, a.ent_dp, a.exact};
-    Postings P{a.kt->uk_start, a.post_rec};
+    Postings P{a.post_rec};
     Emit em{a.d_count, a.d_overflow, a.d_key, a.d_cnt, a.d_s1, a.d_s2, a.d_dir, a.cap, a.nbits};
     hipError_t e;
     if ((e = fill<unsigned long long>(a.d_count, 1, 0ull, s)) != hipSuccess) return e;
     if ((e = fill<uint32_t>(a.d_overflow, 1, 0u, s)) != hipSuccess) return e;
-    // spilled rows (too many candidates for LDS) join the big-row list
-    // LDS per block: 51 KB (three blocks per CU), 78 KB (two), 150 KB (one)
-    spgemm_lds_kernel<8192, 3072><<<768, kThreads, 0, s>>>(rv, P, a.bins.idx, a.bins.starts, 0, a.ck, em,
-                                                            a.big_rows, a.n_big);
+    // spilled rows (too many candidates for LDS) join the big-row list.
+    // LDS per block: 18 KB (eight blocks per CU, the wave limit), 30 KB
+    // (five), 51 KB (three), 78 KB (two), 150 KB (one).  The kernel is bound
+    // by the latency of its dependent loads (entry, posting header, records),
+    // so the small tables, where most rows of short sequences land, pay off
+    // through the blocks they keep resident.
+    spgemm_lds_kernel<2048, 1024><<<kTierBlocks[0], kThreads, 0, s>>>(rv, P, a.bins.idx, a.bins.starts, 0, a.ck,
+                                                                      em, a.big_rows, a.n_big, a.stage);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    spgemm_lds_kernel<16384, 2048><<<512, kThreads, 0, s>>>(rv, P, a.bins.idx, a.bins.starts, 1, a.ck, em,
-                                                             a.big_rows, a.n_big);
+    spgemm_lds_kernel<4096, 2048><<<kTierBlocks[1], kThreads, 0, s>>>(rv, P, a.bins.idx, a.bins.starts, 1, a.ck,
+                                                                      em, a.big_rows, a.n_big, a.stage);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    spgemm_lds_kernel<32768, 4096><<<256, kThreads, 0, s>>>(rv, P, a.bins.idx, a.bins.starts, 2, a.ck, em,
-                                                             a.big_rows, a.n_big);
+    spgemm_lds_kernel<8192, 3072><<<kTierBlocks[2], kThreads, 0, s>>>(rv, P, a.bins.idx, a.bins.starts, 2, a.ck,
+                                                                      em, a.big_rows, a.n_big, a.stage);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    spgemm_lds_kernel<16384, 2048><<<kTierBlocks[3], kThreads, 0, s>>>(rv, P, a.bins.idx, a.bins.starts, 3, a.ck,
+                                                                       em, a.big_rows, a.n_big, a.stage);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    spgemm_lds_kernel<32768, 4096><<<kTierBlocks[4], kThreads, 0, s>>>(rv, P, a.bins.idx, a.bins.starts, 4, a.ck,
+                                                                       em, a.big_rows, a.n_big, a.stage);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (gcap > 0) {
         spgemm_global_kernel<<<a.global_blocks, kThreads, 0, s>>>(rv, P, a.big_rows, a.n_big, a.work, a.ck, em,

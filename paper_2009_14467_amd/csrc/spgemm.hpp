@@ -60,7 +60,8 @@ struct SpgemmArgs {
     unsigned long long *max_big;
     unsigned long long *products;  // postings visited by one pass over the rows
     uint32_t *big_rows, *n_big;  // n_big: 2 counters
-    // the postings of A^T as one (sequence, position) record each (nnz of them)
+    // the postings of A^T as headed records (nnz + distinct k-mers of them);
+    // ent_s holds the header index of each entry's posting group
     uint2 *post_rec;
     int64_t nnz;
     // directional entries
@@ -73,7 +74,10 @@ struct SpgemmArgs {
     unsigned long long *gtables;
     uint32_t *gcand;
     int global_blocks;
+    // per-block product stages of the LDS kernels (spgemm_stage_entries())
+    uint2 *stage;
 };
+size_t spgemm_stage_entries();
 hipError_t spgemm_plan(const SpgemmArgs &a, hipStream_t s);
 hipError_t spgemm_run(const SpgemmArgs &a, uint32_t gcap, hipStream_t s);
 

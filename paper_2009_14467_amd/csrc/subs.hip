@@ -184,8 +184,11 @@ __device__ __forceinline__ int32_t find_compact(const uint64_t *__restrict__ uk_
 }
 
 // Rows of S for the distinct k-mers of the data: row u holds (m + 1) slots;
-// slot 0 is u itself; present substitutes follow; s_cnt[u] counts them.
+// slot 0 is u itself; present substitutes follow; s_cnt[u] counts them.  A
+// slot names its k-mer v by the head of v's posting group, uk_start[v] + v
+// (the dense map holds heads already).
 __global__ __launch_bounds__(256) void s_rows_kernel(const uint64_t *__restrict__ uk_id, const uint32_t *__restrict__ nu_p,
+                                                     const uint32_t *__restrict__ uk_start,
                                                      const int32_t *__restrict__ kmap, const int8_t *__restrict__ blosum25,
                                                      int k, int m, int alpha, uint32_t *__restrict__ s_u,
                                                      int8_t *__restrict__ s_d, uint32_t *__restrict__ s_cnt,
@@ -200,13 +203,19 @@ __global__ __launch_bounds__(256) void s_rows_kernel(const uint64_t *__restrict_
         const int got = nearest_k(k, T, uk_id[u], alpha, m, ids, dd);
         uint32_t *row = s_u + (size_t)u * W;
         int8_t *drow = s_d + (size_t)u * W;
-        row[0] = u;
+        row[0] = uk_start[u] + u;
         drow[0] = 0;
         int c = 1;
         for (int q = 0; q < got; ++q) {
-            const int32_t cu = kmap ? kmap[ids[q]] : find_compact(uk_id, nu, ids[q]);
-            if (cu < 0) continue;
-            row[c] = (uint32_t)cu;
+            int64_t hv = -1;
+            if (kmap) {
+                hv = kmap[ids[q]];
+            } else {
+                const int32_t cu = find_compact(uk_id, nu, ids[q]);
+                if (cu >= 0) hv = (int64_t)uk_start[cu] + cu;
+            }
+            if (hv < 0) continue;
+            row[c] = (uint32_t)hv;
             drow[c] = dd[q];
             ++c;
         }
@@ -228,10 +237,11 @@ __global__ void nearest_ids_kernel(const uint64_t *__restrict__ kid, int64_t n, 
 
 int s_rows_threads() { return 256 * 1024; }
 
-hipError_t launch_s_rows(const uint64_t *uk_id, const uint32_t *nu, const int32_t *kmap, const int8_t *blosum25, int k,
-                         int m, int alpha, uint32_t *s_u, int8_t *s_d, uint32_t *s_cnt, uint64_t *tmp_ids,
-                         int8_t *tmp_d, hipStream_t s) {
-    s_rows_kernel<<<1024, 256, 0, s>>>(uk_id, nu, kmap, blosum25, k, m, alpha, s_u, s_d, s_cnt, tmp_ids, tmp_d);
+hipError_t launch_s_rows(const uint64_t *uk_id, const uint32_t *nu, const uint32_t *uk_start, const int32_t *kmap,
+                         const int8_t *blosum25, int k, int m, int alpha, uint32_t *s_u, int8_t *s_d, uint32_t *s_cnt,
+                         uint64_t *tmp_ids, int8_t *tmp_d, hipStream_t s) {
+    s_rows_kernel<<<1024, 256, 0, s>>>(uk_id, nu, uk_start, kmap, blosum25, k, m, alpha, s_u, s_d, s_cnt, tmp_ids,
+                                       tmp_d);
     return hipGetLastError();
 }
 

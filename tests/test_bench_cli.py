@@ -23,4 +23,4 @@ def test_defaults(monkeypatch):
     monkeypatch.setattr(sys, "argv", ["bench.py"])
     a = bench.parse()
     assert (a.gpus, a.steps, a.warmup, a.workload, a.pairs) == (1, 3, 1, "large", 0)
-    assert not a.no_autotune and not a.no_graph and not a.no_mlp
+    assert not a.no_autotune and not a.no_graph and not a.no_mlp and not a.no_ns

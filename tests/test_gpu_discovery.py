@@ -75,12 +75,22 @@ def test_exact_large_rows_use_global_tables(gpu, orc):
 
 @pytest.mark.parametrize("ck", [1, 2])
 def test_exact_rows_of_every_table_size(gpu, orc, ck):
-    """Posting lists of ~1,600 entries: rows of 3 to 38 k-mers span every
-    table size (8K, 16K and 32K LDS slots, global memory), and most rows have
-    more candidates than their LDS table stages, so the global redo of
+    """Posting lists of ~1,600 entries: rows of 1 to 38 k-mers span the
+    larger table sizes (4K to 32K LDS slots, global memory), and most rows
+    have more candidates than their LDS table stages, so the global redo of
     those rows is exercised too."""
     s = _random_set(91 + ck, 5000, 3, 40, "ACDE")
     want = orc.candidates(orc.encode(s.residues), s.offsets, 3, ck_min=ck)
+    _compare(_gpu_candidates(gpu, s.residues, s.offsets, k=3, ck_min=ck), want)
+
+
+@pytest.mark.parametrize("ck", [1, 2])
+def test_exact_rows_of_the_small_tables(gpu, orc, ck):
+    """Posting lists of ~260 entries: rows of 1 to 18 k-mers fill the 2K, 4K
+    and 8K-slot tables."""
+    s = _random_set(57 + ck, 6000, 3, 20, "ACDEFG")
+    want = orc.candidates(orc.encode(s.residues), s.offsets, 3, ck_min=ck)
+    assert len(want["lo"]) > 10000
     _compare(_gpu_candidates(gpu, s.residues, s.offsets, k=3, ck_min=ck), want)
 
 

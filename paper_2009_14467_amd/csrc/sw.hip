@@ -1433,8 +1433,9 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_pass2_kernel(const uint8_t *
 #pragma unroll
                 for (int p = 0; p < 6; ++p) nb[p] = vload(bnd + p * plane + lane);
             }
-            const int steps = lb + kWave - 1;
-            for (int t = 0; t < steps; ++t) {
+            const int steps = __builtin_amdgcn_readfirstlane(lb + kWave - 1);
+            // one column step; true once the search has found the end column
+            auto step = [&](const int t) -> bool {
                 if ((t & (kWave - 1)) == 0) {
                     chunk = nx;
                     const int c = t + kWave + lane;
@@ -1449,23 +1450,37 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_pass2_kernel(const uint8_t *
                     }
                 }
                 const int bt = __builtin_amdgcn_readlane(chunk, t & (kWave - 1));
-                int in_h = 0, in_f = kNeg;
-                unsigned in_hb = 0, in_hm = 0, in_fb = 0, in_fm = 0;
-                if (MULTI && from_above && t < lb) {
-                    const int tt = t & (kWave - 1);
-                    in_h = __builtin_amdgcn_readlane(cb[0], tt);
-                    in_f = __builtin_amdgcn_readlane(cb[1], tt);
-                    in_hb = (unsigned)__builtin_amdgcn_readlane(cb[2], tt);
-                    in_hm = (unsigned)__builtin_amdgcn_readlane(cb[3], tt);
-                    in_fb = (unsigned)__builtin_amdgcn_readlane(cb[4], tt);
-                    in_fm = (unsigned)__builtin_amdgcn_readlane(cb[5], tt);
+                int rh, rf;
+                unsigned rhb, rhm, rfb, rfm;
+                if (MULTI) {
+                    int in_h = 0, in_f = kNeg;
+                    unsigned in_hb = 0, in_hm = 0, in_fb = 0, in_fm = 0;
+                    if (from_above && t < lb) {
+                        const int tt = t & (kWave - 1);
+                        in_h = __builtin_amdgcn_readlane(cb[0], tt);
+                        in_f = __builtin_amdgcn_readlane(cb[1], tt);
+                        in_hb = (unsigned)__builtin_amdgcn_readlane(cb[2], tt);
+                        in_hm = (unsigned)__builtin_amdgcn_readlane(cb[3], tt);
+                        in_fb = (unsigned)__builtin_amdgcn_readlane(cb[4], tt);
+                        in_fm = (unsigned)__builtin_amdgcn_readlane(cb[5], tt);
+                    }
+                    rh = shr1(in_h, hlast);
+                    rf = shr1(in_f, flast);
+                    rhb = (unsigned)shr1((int)in_hb, (int)hb_last);
+                    rhm = (unsigned)shr1((int)in_hm, (int)hm_last);
+                    rfb = (unsigned)shr1((int)in_fb, (int)fb_last);
+                    rfm = (unsigned)shr1((int)in_fm, (int)fm_last);
+                } else {
+                    // row -1 above a single strip: H = 0 with empty
+                    // statistics, F closed; the zero-filling shift writes
+                    // lane 0's zeros itself
+                    rh = shr1z(hlast);
+                    rf = shr1(kNeg, flast);
+                    rhb = (unsigned)shr1z((int)hb_last);
+                    rhm = (unsigned)shr1z((int)hm_last);
+                    rfb = (unsigned)shr1z((int)fb_last);
+                    rfm = (unsigned)shr1z((int)fm_last);
                 }
-                const int rh = shr1(in_h, hlast);
-                const int rf = shr1(in_f, flast);
-                const unsigned rhb = (unsigned)shr1((int)in_hb, (int)hb_last);
-                const unsigned rhm = (unsigned)shr1((int)in_hm, (int)hm_last);
-                const unsigned rfb = (unsigned)shr1((int)in_fb, (int)fb_last);
-                const unsigned rfm = (unsigned)shr1((int)in_fm, (int)fm_last);
                 cres = shr1(bt, cres);
                 const int j = t - lane;
                 const ProfWord<R> pw = prof[cres][lane];
@@ -1536,7 +1551,23 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_pass2_kernel(const uint8_t *
                     bnd[4 * plane + j] = (int)fb_last;
                     bnd[5 * plane + j] = (int)fm_last;
                 }
-                if (search && last && __builtin_amdgcn_readlane(fend, kWave - 1) >= 0) break;
+                return search && last && __builtin_amdgcn_readlane(fend, kWave - 1) >= 0;
+            };
+            if constexpr (MULTI && R >= 14) {
+                // the boundary planes leave no registers for a second step
+                for (int t = 0; t < steps; ++t)
+                    if (step(t)) break;
+            } else {
+                // two steps per iteration, so the rows' registers need no rotation
+                int t = 0;
+                bool done = false;
+                for (; t + 1 < steps; t += 2) {
+                    if (step(t) || step(t + 1)) {
+                        done = true;
+                        break;
+                    }
+                }
+                if (!done && t < steps) step(t);
             }
             if (MULTI) __threadfence_block();
         }

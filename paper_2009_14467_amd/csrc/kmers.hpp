@@ -19,7 +19,7 @@ constexpr int kDenseMapMaxK = 6;
 // position) records, with head(u) = uk_start[u] + u; a row entry or a
 // substitute then names its posting list by head(u), and one line holds both
 // the list's length and its first records.  counts[0] = nnz,
-// counts[1] = number of distinct k-mers, counts[2] = nnz again (row scan).
+// counts[1] = number of distinct k-mers.
 // Distinct ids are ascending in uk_id.
 struct KmerTables {
     uint32_t *counts;  // 4 entries
@@ -28,7 +28,6 @@ struct KmerTables {
     uint32_t *post_u;
     uint64_t *uk_id;     // radix-24 ids, up to 24^8 for k = 8
     uint32_t *uk_start;  // nu + 1
-    uint32_t *row_cnt;   // n + 1
     uint32_t *row_start; // n + 1
     uint32_t *row_u;
     uint16_t *row_pos;

@@ -27,7 +27,6 @@ enum DiscBuf {
     kDPostU,
     kDUkId,
     kDUkStart,
-    kDRowCnt,
     kDRowStart,
     kDRowU,
     kDRowPos,
@@ -204,7 +203,6 @@ pastis_status discover(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, 
     PASTIS_TRY(get(ctx, kDPostU, m, &kt.post_u));
     PASTIS_TRY(get(ctx, kDUkId, m, &kt.uk_id));
     PASTIS_TRY(get(ctx, kDUkStart, m + 1, &kt.uk_start));
-    PASTIS_TRY(get(ctx, kDRowCnt, n + 1, &kt.row_cnt));
     PASTIS_TRY(get(ctx, kDRowStart, n + 1, &kt.row_start));
     PASTIS_TRY(get(ctx, kDRowU, m, &kt.row_u));
     PASTIS_TRY(get(ctx, kDRowPos, m, &kt.row_pos));

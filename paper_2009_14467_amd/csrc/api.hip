@@ -230,6 +230,7 @@ pastis_status reset_flags(pastis_ctx *ctx, unsigned long long **d_flags, hipStre
 }
 
 pastis_status make_sw_work(pastis_ctx *ctx, int64_t npairs, int max_len, SwWork &wk) {
+    sw_init_occupancy();
     void *p = nullptr;
     PASTIS_TRY(ensure(ctx, kBufBinOf, (size_t)std::max<int64_t>(npairs, 1), &p));
     wk.bin_of = (int8_t *)p;

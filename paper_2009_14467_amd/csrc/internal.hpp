@@ -233,6 +233,9 @@ hipError_t launch_xd(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
                      const int8_t *blosum, const Scoring &sc, int k, pastis_pair_record *out, uint32_t *redo,
                      uint32_t *n_redo, int *gring, unsigned long long *counters, hipStream_t s);
 int64_t sw_scratch_waves();
+// Queries the resident blocks of the SW kernels whose grids follow their
+// occupancy (once per process, before any launch is captured).
+void sw_init_occupancy();
 // Sequences a of at most this many rows run in one strip (no boundary rows).
 int sw_one_strip_max_rows();
 

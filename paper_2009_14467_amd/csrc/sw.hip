@@ -31,6 +31,8 @@
 #include <algorithm>
 #include <type_traits>
 
+#include <utility>
+
 #include "internal.hpp"
 #include "prim.hpp"
 
@@ -1375,12 +1377,14 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_pass2_kernel(const uint8_t *
                                                        pastis_pair_record *__restrict__ out,
                                                        int *__restrict__ scratch, int64_t scratch_per_wave, int *queue) {
     constexpr int WPB = wpb32(R);
-    __shared__ ProfWord<R> prof_all[WPB][kProfCodes][kWave];
+    // no per-wave profile: a row's score against the column residue is read
+    // from the 625-byte table, so LDS does not limit the waves per SIMD
+    // (occupancy matters here: the statistics selects are long dependent
+    // chains)
     __shared__ int8_t sblosum[kProfCodes * kProfCodes];
     load_blosum(sblosum, blosum);
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
-    ProfWord<R>(*prof)[kWave] = prof_all[wave];
     const int64_t gwave = (int64_t)blockIdx.x * WPB + wave;
     // strip bottom row per column: H, F, H.beg, H.md, F.beg, F.md
     int *bnd = scratch + gwave * scratch_per_wave;
@@ -1404,12 +1408,13 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_pass2_kernel(const uint8_t *
         int fend = -1;
         for (int s = 0; s < nstrips; ++s) {
             const int base = s * RS - top + lane * R;
-            build_profile<R>(prof, sblosum, a, la, base, lane);
             int ar[R];
+            const int8_t *srow[R];  // the row's scores, indexed by the column residue
             unsigned rowpart[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 ar[r] = (base + r >= 0 && base + r < la) ? (int)a[base + r] : kPadCode;
+                srow[r] = sblosum + ar[r] * kProfCodes;
                 rowpart[r] = (unsigned)(base + r) << 16;
             }
             const bool from_above = s > 0;
@@ -1483,7 +1488,6 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_pass2_kernel(const uint8_t *
                 }
                 cres = shr1(bt, cres);
                 const int j = t - lane;
-                const ProfWord<R> pw = prof[cres][lane];
                 const unsigned colpart = (unsigned)j & 0xFFFFu;
                 int hd = hprev, gu = rh - go_ge, fu = rf;
                 unsigned db = db_prev, dm = dm_prev, ub = rhb, um = rhm, fb = rfb, fm = rfm;
@@ -1502,7 +1506,7 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_pass2_kernel(const uint8_t *
                     const unsigned nfb = fe ? fb : ub;
                     const unsigned nfm = fe ? fm : um;
                     // diagonal; a zero predecessor starts a new path at this cell
-                    const int d = hd + sigma_at<R>(pw, r);
+                    const int d = hd + (int)srow[r][cres];
                     const int h = max(max(d, 0), max(e, f));
                     const bool start = hd == 0;
                     const unsigned xb = start ? (rowpart[r] | colpart) : db;
@@ -1731,7 +1735,32 @@ const P2Fn kP2[kNumBins] = {launch_p2<1>,  launch_p2<2>,  launch_p2<3>,  launch_
                             launch_p2<9>,  launch_p2<10>, launch_p2<11>, launch_p2<12>, launch_p2<13>, launch_p2<14>,
                             launch_p2<15>, launch_p2<16>};
 
+// Resident blocks per CU of the one-strip statistics kernels: they keep no
+// profile in LDS, so registers set their occupancy, which the runtime reports
+// for the compiled code; a grid of that many blocks per CU drains each bin.
+int stats_blocks_per_cu[kMaxR + 1];
+
+template <int R>
+void stats_occupancy() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sw_pass2_kernel<R, false>, 64 * wpb32(R), 0) != hipSuccess ||
+        nb < 1) {
+        (void)hipGetLastError();
+        nb = 2;
+    }
+    stats_blocks_per_cu[R] = nb;
+}
+
+template <int... Rs>
+void stats_occupancy_all(std::integer_sequence<int, Rs...>) {
+    (stats_occupancy<Rs + 1>(), ...);
+}
+
 }  // namespace
+
+void sw_init_occupancy() {
+    if (stats_blocks_per_cu[1] == 0) stats_occupancy_all(std::make_integer_sequence<int, kMaxR>{});
+}
 
 int sw_num_bins() { return kNumBins; }
 
@@ -1863,6 +1892,10 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
     auto blocks2 = [&](int bin) {
         return bin >= kMultiBin ? long_cap(blocks_for_bin(bin)) : scale2(bin) * blocks_for_bin(bin);
     };
+    auto blocks_stats = [&](int bin) {
+        const int per_cu = stats_blocks_per_cu[rows_of_bin(bin)];
+        return bin >= kMultiBin || per_cu < 1 ? blocks2(bin) : scale2(bin) * 256 * per_cu;
+    };
     sw_bin2_kernel<<<nb, 256, 0, s>>>(pairs, p1, npairs, sc.cov_pct, stats_mode, sc.direct_pct, out, wk.bin_of,
                                       wk.counters);
     if ((e = launch_bins(wk.bin_of, npairs, kNumBins, wk.counts, wk.starts2, wk.cursor, wk.idx2, s)) != hipSuccess)
@@ -1890,7 +1923,7 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
         const int bin = (k + kMultiBin) % kNumBins;
         const hipStream_t st = bin >= kMultiBin ? ls : s;
         const int R = rows_of_bin(bin);
-        e = kP2[bin](bin, capped(blocks2(bin), wpb32(R)), codes, pairs,
+        e = kP2[bin](bin, capped(blocks_stats(bin), wpb32(R)), codes, pairs,
                      wk.idx2, wk.starts2, blosum, go_ge, ge, sc.cov_pct, sc.id_pct, p1, out, wk.scratch,
                      wk.scratch_per_wave, wk.queue + 2 * kNumBins, st);
         if (e != hipSuccess) return e;

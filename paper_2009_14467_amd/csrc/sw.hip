@@ -1639,11 +1639,19 @@ hipError_t launch_pb(int bin, int blocks, const uint8_t *codes, const PairDesc *
 // waves per block of the 16-bit pass (strips: one profile per wave; full
 // waves: one profile per block) and the blocks that fit on the device at once
 constexpr int wpb16(int R) { return 4; }
+// one-strip bins of more than 512 rows share a profile between the waves of a
+// block, and a block runs one round per distinct sequence a of its window:
+// two waves (four pairs) per block keep those rounds few where sequences have
+// few partners, and eight (six) such blocks per CU keep four (three) waves
+// per SIMD within LDS
+constexpr int kWpbShared = 2;
 // pairs one block of the 16-bit one-strip launch takes per window
 // narrow: R <= 4 bins in strips of 16 lanes (eight pairs per wave) rather
 // than 32 (four pairs per wave)
-static int pairs_per_block16(int R, bool narrow) { return R <= 4 && narrow ? 4 * 8 : R <= 8 ? 4 * 4 : 2 * 4; }
-static int blocks16(int R) { return R <= 4 ? 256 * 6 : (R > 8 && R <= 12) ? 256 * 4 : 256 * 3; }
+static int pairs_per_block16(int R, bool narrow) {
+    return R <= 4 && narrow ? 4 * 8 : R <= 8 ? 4 * 4 : 2 * kWpbShared;
+}
+static int blocks16(int R) { return R <= 4 ? 256 * 6 : R <= 8 ? 256 * 3 : R <= 12 ? 256 * 8 : 256 * 6; }
 
 // R <= 4: strips of 16 lanes with 4 R rows per lane (eight pairs per wave),
 // or, when not narrow, of 32 lanes with 2 R rows (four pairs per wave: fewer
@@ -1665,8 +1673,9 @@ hipError_t launch_p16(int bin, int blocks, bool narrow, const uint8_t *codes, co
         sw16s_pass1_kernel<32, 2 * R, WPB><<<blocks, 64 * WPB, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge,
                                                                       ge, p1, queue);
     else
-        sw16_pass1_kernel<R, WPB, false><<<blocks, 64 * WPB, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge,
-                                                                    ge, p1, nullptr, 0, queue);
+        sw16_pass1_kernel<R, kWpbShared, false><<<blocks, 64 * kWpbShared, 0, s>>>(codes, pairs, idx, starts, bin,
+                                                                                  blosum, go_ge, ge, p1, nullptr, 0,
+                                                                                  queue);
     return hipGetLastError();
 }
 

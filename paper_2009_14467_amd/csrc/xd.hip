@@ -243,33 +243,39 @@ constexpr int kDppWaveRor1 = 0x13C;  // lane l receives lane l-1 (lane 0 from 63
 // register is needed
 __device__ __forceinline__ int ror1(int v) { return __builtin_amdgcn_mov_dpp(v, kDppWaveRor1, 0xF, 0xF, false); }
 
+// A ring holds residue codes times MUL (T wide enough): the rows' stream
+// keeps code * 25, so a code pair's table index is one add.
+template <typename T, int MUL>
 struct Stream {
     const uint8_t *p;
     int len, dir;
-    uint8_t *ring;  // 256 entries, index & 255
-    int next;       // chunks [0, next) are in the ring
-    int pending;    // this lane's element of chunk `next`, loaded ahead
+    T *ring;      // 256 entries, index & 255
+    int next;     // chunks [0, next) are in the ring
+    int pending;  // this lane's element of chunk `next` (times MUL), loaded ahead
 };
 
-__device__ __forceinline__ int stream_elem(const Stream &w, int c, int lane) {
+template <typename T, int MUL>
+__device__ __forceinline__ int stream_elem(const Stream<T, MUL> &w, int c, int lane) {
     const int t = c * kWave + lane;
-    return t < w.len ? (int)w.p[(int64_t)t * w.dir] : kPadCode;
+    return (t < w.len ? (int)w.p[(int64_t)t * w.dir] : kPadCode) * MUL;
 }
 
-__device__ __forceinline__ void stream_init(Stream &w, int lane) {
-    w.ring[lane] = (uint8_t)stream_elem(w, 0, lane);
-    w.ring[kWave + lane] = (uint8_t)stream_elem(w, 1, lane);
-    w.ring[2 * kWave + lane] = (uint8_t)kPadCode;  // every ring byte is a valid code
-    w.ring[3 * kWave + lane] = (uint8_t)kPadCode;
+template <typename T, int MUL>
+__device__ __forceinline__ void stream_init(Stream<T, MUL> &w, int lane) {
+    w.ring[lane] = (T)stream_elem(w, 0, lane);
+    w.ring[kWave + lane] = (T)stream_elem(w, 1, lane);
+    w.ring[2 * kWave + lane] = (T)(kPadCode * MUL);  // every ring entry is a valid code
+    w.ring[3 * kWave + lane] = (T)(kPadCode * MUL);
     w.pending = stream_elem(w, 2, lane);
     w.next = 2;
 }
 
 // make every index <= frontier + 64 readable; frontier (wave-uniform) grows
 // by at most one per call, so one chunk at a time suffices
-__device__ __forceinline__ void stream_ensure(Stream &w, int frontier, int lane) {
+template <typename T, int MUL>
+__device__ __forceinline__ void stream_ensure(Stream<T, MUL> &w, int frontier, int lane) {
     if ((frontier >> 6) + 1 >= w.next) {
-        w.ring[(w.next & 3) * kWave + lane] = (uint8_t)w.pending;
+        w.ring[(w.next & 3) * kWave + lane] = (T)w.pending;
         ++w.next;
         w.pending = stream_elem(w, w.next, lane);
     }
@@ -297,9 +303,11 @@ __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlan
 __device__ __forceinline__ bool in_range(int x, int base, int len) { return (unsigned)(x - base) < (unsigned)len; }
 
 __device__ Ext extend_reg(const uint8_t *a0, int la, int adir, const uint8_t *b0, int lb, int bdir,
-                          const int8_t *sbl, int o, int e, int X, uint8_t *ring_a, uint8_t *ring_b, int lane) {
+                          const int8_t *sbl, const unsigned *minc, int o, int e, int X, uint16_t *ring_a,
+                          uint8_t *ring_b, int lane) {
     const int oe = o + e;
-    Stream sa{a0, la, adir, ring_a, 0, 0}, sb{b0, lb, bdir, ring_b, 0, 0};
+    Stream<uint16_t, kProfCodes> sa{a0, la, adir, ring_a, 0, 0};
+    Stream<uint8_t, 1> sb{b0, lb, bdir, ring_b, 0, 0};
     stream_init(sa, lane);
     stream_init(sb, lane);
     // anti-diagonal 0: the anchor in lane 0
@@ -363,8 +371,8 @@ __device__ Ext extend_reg(const uint8_t *a0, int la, int adir, const uint8_t *b0
         // residues of the diagonal move (ring indices always in range)
         stream_ensure(sa, hi - 1, lane);
         stream_ensure(sb, d - lo - 1, lane);
-        const int ca = ring_a[(u - 1) & 255], cb = ring_b[(v - 1) & 255];
-        const int sig = sbl[ca * kProfCodes + cb];
+        const int cab = (int)ring_a[(u - 1) & 255] + (int)ring_b[(v - 1) & 255];  // a * 25 + b
+        const int sig = sbl[cab];
         const int e_ext = El - e, e_open = Hl - oe;
         const bool ee = e_ext >= e_open;
         const int E_ = max(e_ext, e_open);
@@ -372,16 +380,13 @@ __device__ Ext extend_reg(const uint8_t *a0, int la, int adir, const uint8_t *b0
         const bool fe = f_ext >= f_open;
         const int F_ = max(f_ext, f_open);
         const int D_ = Hd + sig;  // dead predecessors stay far below kNeg / 2
-        const unsigned sD = sHd + (ca == cb ? 0x10001u : 1u);
+        const unsigned sD = sHd + minc[cab];
         const int H_ = max(D_, max(E_, F_));
         const unsigned sE_ = ee ? SE1 : SH1;
         const unsigned sF_ = fe ? rSF : rSH;
-        // the diagonal wins ties; H_ - D_ >= 0, so min(H_ - D_, 1) - 1 is an
-        // all-ones mask exactly when it wins (arithmetic rather than a select,
-        // which would be turned into a branch around the diagonal's counts)
+        // the diagonal wins ties
         const unsigned sEF = H_ == E_ ? sE_ : sF_;
-        const unsigned dmask = (unsigned)min(H_ - D_, 1) - 1u;
-        const unsigned sH_ = sEF + ((sD - sEF) & dmask);
+        const unsigned sH_ = H_ == D_ ? sD : sEF;
         const bool any = u <= hi && max(Hd, max(Hu, Hl)) > kNeg / 2;
         const bool live = any && H_ >= best - X;
         cells += any ? 1 : 0;
@@ -429,11 +434,13 @@ struct SeedAln {
     bool overflow;
 };
 
-// GLOBAL = false: the register band (rings = two 256-entry LDS rings);
+// GLOBAL = false: the register band (rings: 256 entries of code * 25 as
+// uint16, then 256 codes; minc: the statistics increment of each code pair);
 // GLOBAL = true: the ring in global memory.
 template <bool GLOBAL>
 __device__ SeedAln align_seed(const uint8_t *a, int la, const uint8_t *b, int lb, int pa, int pb, int k,
-                              const int8_t *sbl, int o, int e, int X, const Ring &R, uint8_t *rings, int lane) {
+                              const int8_t *sbl, const unsigned *minc, int o, int e, int X, const Ring &R,
+                              uint8_t *rings, int lane) {
     int sc = 0, sm = 0;
     for (int t = 0; t < k; ++t) {
         const int ca = a[pa + t], cb = b[pb + t];
@@ -445,10 +452,13 @@ __device__ SeedAln align_seed(const uint8_t *a, int la, const uint8_t *b, int lb
         rt = extend<true>(a + pa + k, la - pa - k, 1, b + pb + k, lb - pb - k, 1, sbl, o, e, X, R, lane);
         lf = extend<true>(a + pa - 1, pa, -1, b + pb - 1, pb, -1, sbl, o, e, X, R, lane);
     } else {
-        rt = extend_reg(a + pa + k, la - pa - k, 1, b + pb + k, lb - pb - k, 1, sbl, o, e, X, rings, rings + 256,
+        uint16_t *ring_a = (uint16_t *)rings;  // 256 entries of code * 25
+        uint8_t *ring_b = rings + 512;
+        rt = extend_reg(a + pa + k, la - pa - k, 1, b + pb + k, lb - pb - k, 1, sbl, minc, o, e, X, ring_a, ring_b,
                         lane);
         lf = rt.overflow ? rt
-                         : extend_reg(a + pa - 1, pa, -1, b + pb - 1, pb, -1, sbl, o, e, X, rings, rings + 256, lane);
+                         : extend_reg(a + pa - 1, pa, -1, b + pb - 1, pb, -1, sbl, minc, o, e, X, ring_a, ring_b,
+                                      lane);
     }
     SeedAln s;
     s.score = lf.score + sc + rt.score;
@@ -479,8 +489,14 @@ __global__ __launch_bounds__(256) void xd_kernel(const uint8_t *__restrict__ cod
                                                  uint32_t *__restrict__ redo, uint32_t *__restrict__ n_redo,
                                                  int *__restrict__ gring, unsigned long long *__restrict__ counters) {
     __shared__ int8_t sbl[kProfCodes * kProfCodes];
-    for (int t = threadIdx.x; t < kProfCodes * kProfCodes; t += blockDim.x) sbl[t] = blosum[t];
-    __shared__ uint8_t lds_rings[GLOBAL ? 1 : kWavesPerBlock * 512];
+    // per code pair: identical pairs << 16 | diagonal columns added by a match
+    // or mismatch column (codes compared, as everywhere: two pad codes match)
+    __shared__ unsigned minc[kProfCodes * kProfCodes];
+    for (int t = threadIdx.x; t < kProfCodes * kProfCodes; t += blockDim.x) {
+        sbl[t] = blosum[t];
+        minc[t] = t / kProfCodes == t % kProfCodes ? 0x10001u : 1u;
+    }
+    __shared__ __align__(16) uint8_t lds_rings[GLOBAL ? 1 : kWavesPerBlock * 768];
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int64_t gwave = (int64_t)blockIdx.x * kWavesPerBlock + wave;
@@ -496,7 +512,7 @@ __global__ __launch_bounds__(256) void xd_kernel(const uint8_t *__restrict__ cod
         R.SE = (unsigned *)(base + 12 * R.cap);
         R.SF = (unsigned *)(base + 15 * R.cap);
     } else {
-        rings = lds_rings + wave * 512;
+        rings = lds_rings + wave * 768;
     }
     const int64_t count = GLOBAL ? (int64_t)*n_redo : npairs;
     unsigned long long my_cells = 0;
@@ -531,7 +547,7 @@ __global__ __launch_bounds__(256) void xd_kernel(const uint8_t *__restrict__ cod
         for (int s = 0; s < 2; ++s) {
             if (pa[s] < 0) continue;
             const SeedAln t =
-                align_seed<GLOBAL>(a, pd.la, b, pd.lb, pa[s], pb[s], k, sbl, o, e, X, R, rings, lane);
+                align_seed<GLOBAL>(a, pd.la, b, pd.lb, pa[s], pb[s], k, sbl, minc, o, e, X, R, rings, lane);
             overflow |= t.overflow;
             cells += t.cells;
             const bool pass = passes(t, pd.la, id_pct, cov_pct);

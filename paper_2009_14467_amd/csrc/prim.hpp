@@ -29,10 +29,11 @@ hipError_t radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32
 // its own L2.  Items [0, n) are split into eight contiguous segments, one per
 // XCD, and a unit (a block, or one of `per` waves of a block) walks its XCD's
 // segment with the stride of that XCD's units: items processed at the same
-// time on one XCD are then neighbours, and neighbouring rows of the k-mer
-// matrix (members of one family) share posting lists, which the L2 then
-// serves once.  A grid of fewer than eight blocks uses one segment per
-// block, so any grid covers every item exactly once.
+// time on one XCD are then neighbours in the caller's order, so where that
+// order groups related rows (sequences sorted or clustered by similarity),
+// the posting lists they share are served by one L2.  A grid of fewer than
+// eight blocks uses one segment per block, so any grid covers every item
+// exactly once.
 struct XcdWalk {
     int64_t first, end, step;
 };

@@ -54,11 +54,13 @@ ALGO_OPS_PER_XD_CELL = 12
 # counters read for a 1 GiB device copy (FETCH x 2.0, WRITE x 1.0); keyed by
 # workload and kernel, and only for kernels unchanged since those counters
 # were taken
-MEASURED_TRAFFIC_KIB = {("large", "sw16s_pass1_kernel<32, 14, 4>"): (456576.4, 36155.0),
+MEASURED_TRAFFIC_KIB = {("large", "sw16s_pass1_kernel<32, 14, 4>"): (456809.3, 36151.0),
+                        ("large", "sw16s_pass1_kernel<32, 12, 4>"): (548476.9, 45754.0),
                         ("large", "sw16s_pass1_kernel<32, 10, 4>"): (691304.8, 61093.3),
-                        ("mid", "sw16s_pass1_kernel<32, 12, 4>"): (1246851.25, 129269.531),
-                        ("mid", "sw16s_pass1_kernel<16, 16, 4>"): (1311538.562, 130976.219),
-                        ("mid", "sw16_pass1_kernel<9, 4, false>"): (592586.188, 58720.5)}
+                        ("mid", "sw16s_pass1_kernel<32, 12, 4>"): (1247195.8, 129271.6),
+                        ("mid", "sw16s_pass1_kernel<32, 14, 4>"): (962258.3, 99917.6),
+                        ("mid", "sw16s_pass1_kernel<16, 16, 4>"): (1312067.5, 130976.7),
+                        ("mid", "sw16_pass1_kernel<9, 2, false>"): (598679.5, 65335.5)}
 # the same counters for the kernels of the sparse-product stage (one launch of
 # each per step): the row scan that sizes each row's table, the headed
 # posting records, and the product kernels (LDS tables of 2K..32K slots, and

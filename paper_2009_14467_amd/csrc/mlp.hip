@@ -12,9 +12,11 @@
 // H^T = W X^T, with v_mfma_f32_16x16x16bf16: the 16x16 accumulator of an
 // output-feature tile (lane l: features 4*(l/16)..+3 of pair l%16) is exactly
 // the B operand of the next layer's K tile, so layers chain in registers.
-// Training stores activations and gradients feature-major ([feature][pair],
-// bf16) so both operands of the weight-gradient GEMMs (reductions over the
-// batch) load 4 consecutive bf16 per lane.
+// Training stores activations and gradients by tile of 16 pairs, feature by
+// feature inside a tile ([pair / 16][feature][pair % 16], bf16): a wave's
+// stores of one array share one address with immediate offsets, and both
+// operands of the weight-gradient GEMMs (reductions over the batch) load 4
+// consecutive pairs of a feature per lane, 512 contiguous bytes per wave.
 #include <cmath>
 
 #include "internal.hpp"
@@ -178,10 +180,44 @@ __global__ __launch_bounds__(256) void forward_kernel(const float *__restrict__ 
     }
 }
 
+// One Adam step of parameter x (Kingma & Ba, bias-corrected moments) when
+// A.update, then its bf16 copies from the fp32 master.
+struct AdamArgs {
+    float *theta, *m, *v;
+    uint16_t *W1b, *W2b, *W2Tb, *w3b;
+    float lr, b1, b2, eps, c1, c2;
+    int update;
+};
+
+__device__ __forceinline__ void adam_one(const AdamArgs &A, int x, float g) {
+    float w = A.theta[x];
+    if (A.update) {
+        const float mm = A.b1 * A.m[x] + (1.f - A.b1) * g;
+        const float vv = A.b2 * A.v[x] + (1.f - A.b2) * g * g;
+        A.m[x] = mm;
+        A.v[x] = vv;
+        w -= A.lr * (mm / A.c1) / (sqrtf(vv / A.c2) + A.eps);
+        A.theta[x] = w;
+    }
+    const uint16_t h = to_bf16(w);
+    if (x < kMlpOffB1) {
+        A.W1b[x] = h;
+    } else if (x >= kMlpOffW2 && x < kMlpOffB2) {
+        const int r = (x - kMlpOffW2) / kH, c = (x - kMlpOffW2) % kH;
+        A.W2b[r * kH + c] = h;
+        A.W2Tb[c * kH + r] = h;
+    } else if (x >= kMlpOffW3 && x < kMlpOffB3) {
+        A.w3b[x - kMlpOffW3] = h;
+    }
+}
+
 // Forward + backward of 16 pairs per wave for one minibatch.  Pairs of the
 // batch are examples order[off + p]; p >= count are padding (zero input and
-// gradient).  Writes ZT [16][B], H1 [128][B], DH2 [128][B], DH1 [128][B]
-// (bf16, feature-major) and accumulates bias / w3 gradients and the loss.
+// gradient).  Writes ZT, H1, DH2 and DH1 (bf16, [B / 16][feature][16]) and,
+// per block, the sums of the loss and of the bias /
+// w3 gradients over its pairs into part[block][kMlpPartN] (slot 0 the loss,
+// then b1, b2, w3, b3), in a fixed order: no atomics, so a minibatch's
+// gradient is the same on every run.
 struct Train {
     const float *X;
     const uint8_t *labels;
@@ -190,62 +226,99 @@ struct Train {
     int B;               // padded batch size (multiple of 16)
     float pos_weight, inv_n;
     uint16_t *ZT, *H1, *DH2, *DH1;
-    float *g_b1, *g_b2, *g_w3, *g_b3, *loss;
+    float *part;
 };
 
-__global__ __launch_bounds__(256) void train_tile_kernel(Net N, Train T) {
-    const int lane = threadIdx.x & 63, col = lane & 15, kg = lane >> 4;
-    const int tiles = T.B / 16;
-    for (int tile = blockIdx.x * 4 + (threadIdx.x >> 6); tile < tiles; tile += gridDim.x * 4) {
+// Part slots: the gradient of parameter x >= kMlpOffB2 (b2, w3, b3 are
+// contiguous there) sits in slot kPartB2 + x - kMlpOffB2.
+constexpr int kPartB1 = 1, kPartB2 = 1 + kH, kPartW3 = 1 + 2 * kH, kPartB3 = 1 + 3 * kH;
+
+// Sums v[0..N) of every lane over the 16 lanes of its lane group (same
+// lane >> 4), reduce-scatter style: after the four exchange steps lane col
+// holds the group's totals of v[N/16 * col .. + N/16) in v[0 .. N/16).  Each
+// step hands half of the remaining values to the partner lane, so the wave
+// does N - N/16 exchanges instead of 4N.
+template <int N>
+__device__ __forceinline__ void group_reduce_scatter(float (&v)[N], int col) {
+#pragma unroll
+    for (int m = 8, half = N / 2; m >= 1; m >>= 1, half >>= 1) {
+        const bool up = (col & m) != 0;
+#pragma unroll
+        for (int q = 0; q < half; ++q) {
+            const float lo = v[q], hi = v[half + q];  // values, so the selects below are not on addresses
+            const float keep = up ? hi : lo, give = up ? lo : hi;
+            v[q] = keep + __shfl_xor(give, m, 64);
+        }
+    }
+}
+
+__global__ __launch_bounds__(64 * kMlpTrainWaves) void train_tile_kernel(Net N, Train T) {
+    constexpr int W = kMlpTrainWaves;
+    __shared__ float acc_lds[W][kMlpPartN];  // one row per wave
+    const int lane = threadIdx.x & 63, col = lane & 15, kg = lane >> 4, w = threadIdx.x >> 6;
+    for (int x = threadIdx.x; x < W * kMlpPartN; x += blockDim.x) (&acc_lds[0][0])[x] = 0.f;
+    __syncthreads();
+    float *my = acc_lds[w];
+    const int tile = blockIdx.x * W + w;  // the grid holds one wave per tile
+    if (tile < T.B / 16) {
         const int pb = tile * 16 + col;  // pair index within the batch
         const bool valid = pb < T.count;
         const int64_t ex = valid ? (int64_t)T.order[T.off + pb] : 0;
         float zf[4];
         const bf16x4 z = input_operand(T.X, ex, valid, kg, N, zf);
+        uint16_t *const zt = T.ZT + (size_t)tile * kIn * 16 + col;
+        uint16_t *const h1 = T.H1 + (size_t)tile * kH * 16 + col;
+        uint16_t *const dh2 = T.DH2 + (size_t)tile * kH * 16 + col;
+        uint16_t *const dh1 = T.DH1 + (size_t)tile * kH * 16 + col;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) T.ZT[(size_t)(4 * kg + i) * T.B + pb] = (uint16_t)z[i];
+        for (int i = 0; i < 4; ++i) zt[(4 * kg + i) * 16] = (uint16_t)z[i];
         Fwd o;
         forward_tile(z, N, lane, o);
         const float t = valid ? (float)T.labels[ex] : 0.f;
         const float s = 1.f / (1.f + expf(-o.y));
         const float dy = valid ? (T.pos_weight * t * (s - 1.f) + (1.f - t) * s) * T.inv_n : 0.f;
-        if (lane < 16 && valid) {
-            // softplus(-y) = -log(s), softplus(y) = y - log(s)... computed stably
-            const float sp_neg = fmaxf(-o.y, 0.f) + log1pf(expf(-fabsf(o.y)));
-            const float sp_pos = fmaxf(o.y, 0.f) + log1pf(expf(-fabsf(o.y)));
-            atomicAdd(T.loss, (T.pos_weight * t * sp_neg + (1.f - t) * sp_pos) * T.inv_n);
-        }
-        float sdy = dy;  // sum over the 16 pairs of the lane group
+        // loss: softplus(-y) for positives, softplus(y) for negatives, computed stably
+        const float sp = log1pf(expf(-fabsf(o.y)));
+        float lo = valid ? (T.pos_weight * t * (fmaxf(-o.y, 0.f) + sp) + (1.f - t) * (fmaxf(o.y, 0.f) + sp)) * T.inv_n
+                         : 0.f;
+        float sdy = dy;
 #pragma unroll
-        for (int m = 1; m < 16; m <<= 1) sdy += __shfl_xor(sdy, m, 64);
-        if (lane == 0) atomicAdd(T.g_b3, sdy);
+        for (int m = 1; m < 16; m <<= 1) {
+            lo += __shfl_xor(lo, m, 64);
+            sdy += __shfl_xor(sdy, m, 64);
+        }
+        if (lane == 0) {
+            my[0] += lo;
+            my[kPartB3] += sdy;
+        }
         // layer 3 / layer 2 backward, in the accumulator layout
         bf16x4 dh2op[8];
+        float gw3[32], gb2[32];  // [4 * t2 + i]: feature 16 * t2 + 4 * kg + i
 #pragma unroll
         for (int t2 = 0; t2 < 8; ++t2) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int f = 16 * t2 + 4 * kg + i;
-                float gw3 = dy * o.h2[t2][i];
+                gw3[4 * t2 + i] = dy * o.h2[t2][i];
                 const float d = o.a2p[t2][i] > 0.f ? dy * from_bf16(N.w3b[f]) : 0.f;
-                float gb2 = d;
+                gb2[4 * t2 + i] = d;
                 const uint16_t db = to_bf16(d);
                 dh2op[t2][i] = (short)db;
-                T.DH2[(size_t)f * T.B + pb] = db;
-                T.H1[(size_t)f * T.B + pb] = (uint16_t)o.h1[t2][i];
-                // sum over the 16 pairs of this lane group
-#pragma unroll
-                for (int m = 1; m < 16; m <<= 1) {
-                    gw3 += __shfl_xor(gw3, m, 64);
-                    gb2 += __shfl_xor(gb2, m, 64);
-                }
-                if (col == 0) {
-                    atomicAdd(&T.g_w3[f], gw3);
-                    atomicAdd(&T.g_b2[f], gb2);
-                }
+                dh2[f * 16] = db;
+                h1[f * 16] = (uint16_t)o.h1[t2][i];
             }
         }
+        group_reduce_scatter(gw3, col);
+        group_reduce_scatter(gb2, col);
+        // lane col now holds j = 2 col, 2 col + 1: feature 16 (j / 4) + 4 kg + j % 4
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int j = 2 * col + r, f = 16 * (j >> 2) + 4 * kg + (j & 3);
+            my[kPartW3 + f] += gw3[r];
+            my[kPartB2 + f] += gb2[r];
+        }
         // dH1 = W2^T dH2 (transposed weights as the A operand)
+        float gb1[32];
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
@@ -256,62 +329,105 @@ __global__ __launch_bounds__(256) void train_tile_kernel(Net N, Train T) {
             for (int i = 0; i < 4; ++i) {
                 const int f = 16 * t + 4 * kg + i;
                 const float d = o.a1p[t][i] > 0.f ? acc[i] : 0.f;
-                float gb1 = d;
-                T.DH1[(size_t)f * T.B + pb] = to_bf16(d);
-#pragma unroll
-                for (int m = 1; m < 16; m <<= 1) gb1 += __shfl_xor(gb1, m, 64);
-                if (col == 0) atomicAdd(&T.g_b1[f], gb1);
+                gb1[4 * t + i] = d;
+                dh1[f * 16] = to_bf16(d);
             }
         }
-    }
-}
-
-// C[M][N] = sum_k A[m][k] * Bm[n][k] for bf16 A [M][K], Bm [N][K] (K contiguous,
-// K a multiple of 16); one wave per 16x16 output tile.
-__global__ __launch_bounds__(256) void gemm_nt_kernel(const uint16_t *__restrict__ A, const uint16_t *__restrict__ Bm,
-                                                      int M, int Nn, int K, float *__restrict__ C) {
-    const int lane = threadIdx.x & 63, col = lane & 15, kg = lane >> 4;
-    const int tiles_n = Nn / 16, tiles = (M / 16) * tiles_n;
-    for (int tile = blockIdx.x * 4 + (threadIdx.x >> 6); tile < tiles; tile += gridDim.x * 4) {
-        const int mt = tile / tiles_n, nt = tile % tiles_n;
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        const uint16_t *ap = A + (size_t)(16 * mt + col) * K + 4 * kg;
-        const uint16_t *bp = Bm + (size_t)(16 * nt + col) * K + 4 * kg;
-        for (int k0 = 0; k0 < K; k0 += 16) acc = mfma(load4(ap + k0), load4(bp + k0), acc);
+        group_reduce_scatter(gb1, col);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) C[(size_t)(16 * mt + 4 * kg + i) * Nn + 16 * nt + col] = acc[i];
+        for (int r = 0; r < 2; ++r) {
+            const int j = 2 * col + r;
+            my[kPartB1 + 16 * (j >> 2) + 4 * kg + (j & 3)] += gb1[r];
+        }
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < kMlpPartN; x += blockDim.x) {
+        float a = acc_lds[0][x];
+#pragma unroll
+        for (int i = 1; i < W; ++i) a += acc_lds[i][x];
+        T.part[(size_t)blockIdx.x * kMlpPartN + x] = a;
     }
 }
 
-// Adam on the fp32 masters, then fresh bf16 copies; clears the atomically
-// accumulated gradients.  grad layout = parameter layout.
-__global__ void adam_kernel(float *__restrict__ theta, float *__restrict__ m, float *__restrict__ v,
-                            float *__restrict__ grad, int n, float lr, float b1, float b2, float eps, float c1, float c2,
-                            uint16_t *__restrict__ W1b, uint16_t *__restrict__ W2b, uint16_t *__restrict__ W2Tb,
-                            uint16_t *__restrict__ w3b, int update) {
-    for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x) {
-        float w = theta[x];
-        if (update) {
-            const float g = grad[x];
-            const float mm = b1 * m[x] + (1.f - b1) * g;
-            const float vv = b2 * v[x] + (1.f - b2) * g * g;
-            m[x] = mm;
-            v[x] = vv;
-            w -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
-            theta[x] = w;
-        }
-        grad[x] = 0.f;
-        const uint16_t h = to_bf16(w);
-        if (x < kMlpOffB1) {
-            W1b[x] = h;
-        } else if (x >= kMlpOffW2 && x < kMlpOffB2) {
-            const int r = (x - kMlpOffW2) / kH, c = (x - kMlpOffW2) % kH;
-            W2b[r * kH + c] = h;
-            W2Tb[c * kH + r] = h;
-        } else if (x >= kMlpOffW3 && x < kMlpOffB3) {
-            w3b[x - kMlpOffW3] = h;
-        }
+// Weight gradients over one minibatch, split over the pairs: dW2 = DH2 H1^T
+// (64 tiles of 16x16) and dW1 = DH1 Z^T (8 tiles), each over chunks of
+// kMlpSplitK pairs.  One wave per (tile, chunk); chunk c's partial products
+// go to wp2 + c * 128 * 128 and wp1 + c * 128 * 16 ([row][col] as the
+// parameters), to be summed in chunk order.
+__global__ __launch_bounds__(256) void wgrad_kernel(const uint16_t *__restrict__ DH2, const uint16_t *__restrict__ H1,
+                                                    const uint16_t *__restrict__ DH1,
+                                                    const uint16_t *__restrict__ ZT, int B, int chunks,
+                                                    float *__restrict__ wp2, float *__restrict__ wp1) {
+    constexpr int kTiles2 = (kH / 16) * (kH / 16), kTiles = kTiles2 + kH / 16;
+    const int lane = threadIdx.x & 63, col = lane & 15, kg = lane >> 4;
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wave >= kTiles * chunks) return;
+    const int tile = wave % kTiles, c = wave / kTiles;
+    const uint16_t *A, *Bm;
+    float *C;
+    int Nn, mt, nt;
+    if (tile < kTiles2) {
+        A = DH2, Bm = H1, Nn = kH, mt = tile / (kH / 16), nt = tile % (kH / 16), C = wp2 + (size_t)c * kH * kH;
+    } else {
+        A = DH1, Bm = ZT, Nn = kIn, mt = tile - kTiles2, nt = 0, C = wp1 + (size_t)c * kH * kIn;
     }
+    // pair tiles [t0, t1) of this chunk; a tile of A holds kH features, of Bm Nn
+    const int t0 = c * (kMlpSplitK / 16), t1 = min(B / 16, t0 + kMlpSplitK / 16);
+    const uint16_t *ap = A + (size_t)t0 * kH * 16 + (16 * mt + col) * 16 + 4 * kg;
+    const uint16_t *bp = Bm + (size_t)t0 * Nn * 16 + (16 * nt + col) * 16 + 4 * kg;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+    for (int t = t0; t < t1; ++t, ap += kH * 16, bp += Nn * 16) acc = mfma(load4(ap), load4(bp), acc);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) C[(size_t)(16 * mt + 4 * kg + i) * Nn + 16 * nt + col] = acc[i];
+}
+
+// The minibatch gradient from the partials, summed in a fixed order, then
+// (A.update) the Adam step of every parameter.  Threads [0, nW) take one
+// weight of W1 or W2 each (sum over the chunks); then one wave per part slot
+// sums the blocks' values (lane-strided, then a fixed shuffle tree) into the
+// bias / w3 gradient, and slot 0 adds the batch loss to *loss.  The gradient
+// is written to grad either way.
+__global__ __launch_bounds__(256) void grad_reduce_kernel(const float *__restrict__ part, int nblk,
+                                                          const float *__restrict__ wp2,
+                                                          const float *__restrict__ wp1, int chunks,
+                                                          float *__restrict__ grad, float *__restrict__ loss,
+                                                          AdamArgs A) {
+    constexpr int nW1 = kH * kIn, nW2 = kH * kH, nW = nW1 + nW2;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < nW) {
+        const bool w1 = x < nW1;
+        const float *src = w1 ? wp1 + x : wp2 + (x - nW1);
+        const size_t stride = w1 ? nW1 : nW2;
+        float a = 0.f;
+#pragma unroll 8
+        for (int c = 0; c < chunks; ++c) a += src[(size_t)c * stride];
+        const int px = w1 ? kMlpOffW1 + x : kMlpOffW2 + x - nW1;
+        grad[px] = a;
+        if (A.update) adam_one(A, px, a);
+        return;
+    }
+    const int wbase = (nW + 255) / 256 * 4;  // first wave of the slot sums
+    const int slot = blockIdx.x * 4 + (threadIdx.x >> 6) - wbase, lane = threadIdx.x & 63;
+    if (slot < 0 || slot >= kMlpPartN) return;
+    float a = 0.f;
+    for (int b = lane; b < nblk; b += 64) a += part[(size_t)b * kMlpPartN + slot];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) a += __shfl_xor(a, m, 64);
+    if (lane != 0) return;
+    if (slot == 0) {
+        *loss += a;
+        return;
+    }
+    const int px = slot < kPartB2 ? kMlpOffB1 + slot - kPartB1 : kMlpOffB2 + slot - kPartB2;
+    grad[px] = a;
+    if (A.update) adam_one(A, px, a);
+}
+
+// bf16 copies of the fp32 masters (no update).
+__global__ void refresh_kernel(AdamArgs A) {
+    for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < kMlpParams; x += gridDim.x * blockDim.x)
+        adam_one(A, x, 0.f);
 }
 
 // mean / std (population) of each feature column, fp64 accumulation
@@ -391,11 +507,29 @@ Net net_of(const MlpState &S) {
     return N;
 }
 
+AdamArgs adam_args(const MlpState &S, float lr, int step) {
+    AdamArgs A;
+    A.theta = S.theta;
+    A.m = S.m;
+    A.v = S.v;
+    A.W1b = S.W1b;
+    A.W2b = S.W2b;
+    A.W2Tb = S.W2Tb;
+    A.w3b = S.w3b;
+    A.b1 = 0.9f;
+    A.b2 = 0.999f;
+    A.eps = 1e-8f;
+    A.lr = lr;
+    A.update = step > 0;
+    A.c1 = step > 0 ? 1.f - powf(A.b1, (float)step) : 1.f;
+    A.c2 = step > 0 ? 1.f - powf(A.b2, (float)step) : 1.f;
+    return A;
+}
+
 }  // namespace
 
 hipError_t mlp_refresh(const MlpState &S, hipStream_t s) {
-    adam_kernel<<<grid_for(kMlpParams), 256, 0, s>>>(S.theta, S.m, S.v, S.grad, kMlpParams, 0.f, 0.f, 0.f, 0.f, 1.f,
-                                                      1.f, S.W1b, S.W2b, S.W2Tb, S.w3b, 0);
+    refresh_kernel<<<grid_for(kMlpParams), 256, 0, s>>>(adam_args(S, 0.f, 0));
     return hipGetLastError();
 }
 
@@ -433,7 +567,8 @@ hipError_t mlp_moments(const float *X, int64_t n, double *acc, float *mean, floa
 }
 
 hipError_t mlp_batch_grad(const MlpState &S, const float *X, const uint8_t *labels, const int32_t *order, int64_t off,
-                          int64_t count, int B, float pos_weight, float *loss, hipStream_t s) {
+                          int64_t count, int B, float pos_weight, float *loss, float lr, int step, hipStream_t s) {
+    if (B <= 0 || B % 16 || B > S.batch_cap || count > B) return hipErrorInvalidValue;
     Train T;
     T.X = X;
     T.labels = labels;
@@ -447,29 +582,23 @@ hipError_t mlp_batch_grad(const MlpState &S, const float *X, const uint8_t *labe
     T.H1 = S.H1;
     T.DH2 = S.DH2;
     T.DH1 = S.DH1;
-    T.g_b1 = S.grad + kMlpOffB1;
-    T.g_b2 = S.grad + kMlpOffB2;
-    T.g_w3 = S.grad + kMlpOffW3;
-    T.g_b3 = S.grad + kMlpOffB3;
-    T.loss = loss;
-    const int tiles = B / 16;
-    train_tile_kernel<<<(tiles + 3) / 4, 256, 0, s>>>(net_of(S), T);
+    T.part = S.part;
+    const int tiles = B / 16, nblk = (tiles + kMlpTrainWaves - 1) / kMlpTrainWaves;  // rows of part
+    train_tile_kernel<<<nblk, 64 * kMlpTrainWaves, 0, s>>>(net_of(S), T);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // dW2 = DH2 H1^T over the batch, dW1 = DH1 Z^T
-    gemm_nt_kernel<<<16, 256, 0, s>>>(S.DH2, S.H1, kH, kH, B, S.grad + kMlpOffW2);
+    const int chunks = (B + kMlpSplitK - 1) / kMlpSplitK;  // <= batch_cap / kMlpSplitK
+    float *wp2 = S.wpart, *wp1 = S.wpart + (size_t)chunks * kH * kH;
+    const int waves = (kH / 16 * kH / 16 + kH / 16) * chunks;
+    wgrad_kernel<<<(waves + 3) / 4, 256, 0, s>>>(S.DH2, S.H1, S.DH1, S.ZT, B, chunks, wp2, wp1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    gemm_nt_kernel<<<2, 256, 0, s>>>(S.DH1, S.ZT, kH, kIn, B, S.grad + kMlpOffW1);
+    const int nW = kH * kIn + kH * kH;
+    const int rblocks = (nW + 255) / 256 + (kMlpPartN + 3) / 4;
+    grad_reduce_kernel<<<rblocks, 256, 0, s>>>(S.part, nblk, wp2, wp1, chunks, S.grad, loss,
+                                                adam_args(S, lr, step));
     return hipGetLastError();
 }
 
-hipError_t mlp_adam(const MlpState &S, float lr, int step, hipStream_t s) {
-    const float b1 = 0.9f, b2 = 0.999f;
-    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
-    adam_kernel<<<grid_for(kMlpParams), 256, 0, s>>>(S.theta, S.m, S.v, S.grad, kMlpParams, lr, b1, b2, 1e-8f, c1, c2,
-                                                      S.W1b, S.W2b, S.W2Tb, S.w3b, 1);
-    return hipGetLastError();
-}
 
 hipError_t mlp_keep(const float *logits, int64_t n, float tau, uint8_t *keep, hipStream_t s) {
     if (n <= 0) return hipSuccess;

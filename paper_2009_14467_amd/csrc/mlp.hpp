@@ -16,6 +16,13 @@ constexpr int kMlpOffB2 = kMlpOffW2 + kMlpHidden * kMlpHidden;
 constexpr int kMlpOffW3 = kMlpOffB2 + kMlpHidden;
 constexpr int kMlpOffB3 = kMlpOffW3 + kMlpHidden;
 constexpr int kMlpParams = kMlpOffB3 + 1;
+// per-block partial sums of one training minibatch: loss, b1, b2, w3, b3;
+// a training block holds kMlpTrainWaves waves of 16 pairs each
+constexpr int kMlpPartN = 1 + 3 * kMlpHidden + 1;
+constexpr int kMlpTrainWaves = 4;
+// the weight-gradient reductions over a minibatch are split into chunks of
+// this many pairs, one wave per (output tile, chunk)
+constexpr int kMlpSplitK = 256;
 
 // Device state of the network (owned by the context).
 struct MlpState {
@@ -25,6 +32,8 @@ struct MlpState {
     double *moments;                       // 2 * kMlpIn
     uint16_t *ZT, *H1, *DH2, *DH1;         // per-batch activations, feature-major
     int batch_cap;                         // pairs the activation buffers hold
+    float *part;                           // [batch_cap / (16 * kMlpTrainWaves)][kMlpPartN] block partials
+    float *wpart;                          // [batch_cap / kMlpSplitK][W2 then W1] chunk partials
     // labelled examples collected for training: features [pool_cap][16], labels
     float *pool_X = nullptr;
     uint8_t *pool_y = nullptr;
@@ -37,9 +46,12 @@ hipError_t mlp_features(const uint8_t *codes, const int64_t *offsets, int64_t n,
                         int64_t npairs, float *comp, float *F, hipStream_t s);
 hipError_t mlp_forward(const MlpState &S, const float *X, int64_t n, float *logits, hipStream_t s);
 hipError_t mlp_moments(const float *X, int64_t n, double *acc, float *mean, float *stdv, hipStream_t s);
+// Gradient of the weighted logistic loss over examples order[off .. off +
+// count) (B = count rounded up to 16) into S.grad, the batch loss added to
+// *loss; step > 0 also takes Adam step number `step` at learning rate lr.
+// The sums run in a fixed order: the same inputs give the same bits.
 hipError_t mlp_batch_grad(const MlpState &S, const float *X, const uint8_t *labels, const int32_t *order, int64_t off,
-                          int64_t count, int B, float pos_weight, float *loss, hipStream_t s);
-hipError_t mlp_adam(const MlpState &S, float lr, int step, hipStream_t s);
+                          int64_t count, int B, float pos_weight, float *loss, float lr, int step, hipStream_t s);
 hipError_t mlp_keep(const float *logits, int64_t n, float tau, uint8_t *keep, hipStream_t s);
 hipError_t mlp_check_order(const int32_t *order, int64_t n, int64_t limit, unsigned long long *flag, hipStream_t s);
 hipError_t compact5(const uint8_t *keep, const uint32_t *pos, int64_t n, const uint32_t *const in[5],

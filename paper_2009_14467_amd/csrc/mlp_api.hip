@@ -43,6 +43,9 @@ pastis_status mlp_alloc(pastis_ctx *ctx) {
     PASTIS_TRY(grab((void **)&S.H1, 2 * (size_t)kMlpHidden * kMaxBatch));
     PASTIS_TRY(grab((void **)&S.DH2, 2 * (size_t)kMlpHidden * kMaxBatch));
     PASTIS_TRY(grab((void **)&S.DH1, 2 * (size_t)kMlpHidden * kMaxBatch));
+    PASTIS_TRY(grab((void **)&S.part, sizeof(float) * (size_t)(kMaxBatch / (16 * kMlpTrainWaves)) * kMlpPartN));
+    PASTIS_TRY(grab((void **)&S.wpart, sizeof(float) * (size_t)(kMaxBatch / kMlpSplitK) *
+                                           (kMlpHidden * kMlpHidden + kMlpHidden * kMlpIn)));
     ctx->mlp_alloc = true;
     return PASTIS_OK;
 }
@@ -57,7 +60,7 @@ pastis_status need_net(pastis_ctx *ctx) {
 void mlp_free(pastis_ctx *ctx) {
     MlpState &S = ctx->mlp;
     void *ps[] = {S.theta, S.m, S.v, S.grad, S.W1b, S.W2b, S.W2Tb, S.w3b, S.mean, S.stdv, S.moments,
-                  S.ZT, S.H1, S.DH2, S.DH1, S.pool_X, S.pool_y};
+                  S.ZT, S.H1, S.DH2, S.DH1, S.part, S.wpart, S.pool_X, S.pool_y};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     S = MlpState{};
@@ -156,9 +159,9 @@ pastis_status run_epoch(pastis_ctx *ctx, const float *X, const uint8_t *labels, 
         const int64_t off = b * batch, cnt = std::min<int64_t>(batch, n - off);
         const int B = (int)((cnt + 15) / 16 * 16);
         HIP_TRY(ctx,
-                mlp_batch_grad(ctx->mlp, X, labels, order, off, cnt, B, pos_weight, (float *)lossd + b, s),
-                "gradient kernels");
-        HIP_TRY(ctx, mlp_adam(ctx->mlp, lr, ++ctx->mlp_step, s), "adam kernel");
+                mlp_batch_grad(ctx->mlp, X, labels, order, off, cnt, B, pos_weight, (float *)lossd + b, lr,
+                               ++ctx->mlp_step, s),
+                "gradient and Adam kernels");
     }
     std::vector<float> h((size_t)nb);
     PASTIS_TRY(read_device(ctx, lossd, h.data(), sizeof(float) * nb, s));
@@ -276,8 +279,9 @@ pastis_status pastis_mlp_grad(pastis_ctx *ctx, const float *X, const uint8_t *la
     HIP_TRY(ctx, iota((uint32_t *)order, n, s), "iota");
     HIP_TRY(ctx, fill<uint32_t>((uint32_t *)lossd, 1, 0u, s), "reset");
     const int B = (int)((n + 15) / 16 * 16);
-    HIP_TRY(ctx, mlp_refresh(ctx->mlp, s), "refresh");  // clears accumulated gradients
-    HIP_TRY(ctx, mlp_batch_grad(ctx->mlp, X, labels, (const int32_t *)order, 0, n, B, pos_weight, (float *)lossd, s),
+    HIP_TRY(ctx, mlp_refresh(ctx->mlp, s), "refresh");
+    HIP_TRY(ctx,
+            mlp_batch_grad(ctx->mlp, X, labels, (const int32_t *)order, 0, n, B, pos_weight, (float *)lossd, 0.f, 0, s),
             "gradient kernels");
     HIP_TRY(ctx, hipStreamSynchronize(s), "sync");
     HIP_TRY(ctx, hipMemcpy(grad, ctx->mlp.grad, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost), "copy");

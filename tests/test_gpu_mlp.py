@@ -88,8 +88,12 @@ def test_forward_matches_oracle(gpu, n):
     assert (err <= 2e-2 * (1 + np.abs(want))).all(), err.max()
 
 
-@pytest.mark.parametrize("n,pw", [(16, 1.0), (999, 3.0), (4096, 10.0)])
+@pytest.mark.parametrize("n,pw", [(16, 1.0), (999, 3.0), (4096, 10.0), (65536, 2.0)])
 def test_gradient_matches_oracle(gpu, n, pw):
+    """One minibatch gradient, from 16 pairs to the largest batch (65,536
+    pairs: 1,024 blocks of partial sums, 256 chunks of the weight-gradient
+    reduction); the reductions run in a fixed order, so a second call gives
+    the same bits."""
     import paper_2009_14467_amd as P
 
     theta = _net(2)
@@ -100,6 +104,8 @@ def test_gradient_matches_oracle(gpu, n, pw):
     ctx = P.Context()
     ctx.mlp_set(theta, mean, std)
     loss, g = ctx.mlp_grad(_dev(X, gpu), _dev(t, gpu), pos_weight=pw)
+    loss2, g2 = ctx.mlp_grad(_dev(X, gpu), _dev(t, gpu), pos_weight=pw)
+    assert loss2 == loss and g2.tobytes() == g.tobytes()
     wl, wg = M.backward(theta, M.normalise(X, mean, std), t, pw)
     assert loss == pytest.approx(wl, rel=1e-5)
     o = 0

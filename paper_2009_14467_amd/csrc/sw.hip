@@ -1380,9 +1380,17 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_pass2_kernel(const uint8_t *
     // no per-wave profile: a row's score against the column residue is read
     // from the 625-byte table, so LDS does not limit the waves per SIMD
     // (occupancy matters here: the statistics selects are long dependent
-    // chains)
-    __shared__ int8_t sblosum[kProfCodes * kProfCodes];
-    load_blosum(sblosum, blosum);
+    // chains).  Entries are 32-bit; the statistics increment of each code
+    // pair (0x10001 for identical codes, else 1) follows the scores, so a
+    // cell reads it at its score's address plus a constant.  Column residues
+    // travel as byte offsets (code * 4) into a row of the table.
+    constexpr int kTab = kProfCodes * kProfCodes;
+    __shared__ int stab[2 * kTab];
+    for (int t = threadIdx.x; t < kTab; t += blockDim.x) {
+        stab[t] = blosum[t];
+        stab[kTab + t] = t / kProfCodes == t % kProfCodes ? 0x10001 : 1;
+    }
+    __syncthreads();
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
     const int64_t gwave = (int64_t)blockIdx.x * WPB + wave;
@@ -1408,13 +1416,12 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_pass2_kernel(const uint8_t *
         int fend = -1;
         for (int s = 0; s < nstrips; ++s) {
             const int base = s * RS - top + lane * R;
-            int ar[R];
-            const int8_t *srow[R];  // the row's scores, indexed by the column residue
+            const char *srow[R];  // the row's table entries, at byte offset code * 4
             unsigned rowpart[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                ar[r] = (base + r >= 0 && base + r < la) ? (int)a[base + r] : kPadCode;
-                srow[r] = sblosum + ar[r] * kProfCodes;
+                const int ar = (base + r >= 0 && base + r < la) ? (int)a[base + r] : kPadCode;
+                srow[r] = (const char *)(stab + ar * kProfCodes);
                 rowpart[r] = (unsigned)(base + r) << 16;
             }
             const bool from_above = s > 0;
@@ -1429,10 +1436,10 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_pass2_kernel(const uint8_t *
                 E[r] = kNeg;
                 sHb[r] = sHm[r] = sEb[r] = sEm[r] = 0u;
             }
-            int hlast = 0, flast = kNeg, hprev = 0, cres = kPadCode, chunk = kPadCode;
+            int hlast = 0, flast = kNeg, hprev = 0, cres = 4 * kPadCode, chunk = 4 * kPadCode;
             unsigned hb_last = 0, hm_last = 0, fb_last = 0, fm_last = 0, db_prev = 0, dm_prev = 0;
             // chunked, one-ahead prefetch of residues and boundary planes (see pass 1)
-            int nx = (lane < lb) ? (int)b[lane] : kPadCode;
+            int nx = 4 * ((lane < lb) ? (int)b[lane] : kPadCode);
             int cb[6] = {0, kNeg, 0, 0, 0, 0}, nb[6] = {0, kNeg, 0, 0, 0, 0};
             if (MULTI && from_above && lane < lb) {
 #pragma unroll
@@ -1444,7 +1451,7 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_pass2_kernel(const uint8_t *
                 if ((t & (kWave - 1)) == 0) {
                     chunk = nx;
                     const int c = t + kWave + lane;
-                    nx = (c < lb) ? (int)b[c] : kPadCode;
+                    nx = 4 * ((c < lb) ? (int)b[c] : kPadCode);
                     if (MULTI && from_above) {
 #pragma unroll
                         for (int p = 0; p < 6; ++p) cb[p] = nb[p];
@@ -1506,11 +1513,11 @@ __global__ __launch_bounds__(64 * wpb32(R)) void sw_pass2_kernel(const uint8_t *
                     const unsigned nfb = fe ? fb : ub;
                     const unsigned nfm = fe ? fm : um;
                     // diagonal; a zero predecessor starts a new path at this cell
-                    const int d = hd + (int)srow[r][cres];
+                    const int d = hd + *(const int *)(srow[r] + cres);
                     const int h = max(max(d, 0), max(e, f));
                     const bool start = hd == 0;
                     const unsigned xb = start ? (rowpart[r] | colpart) : db;
-                    const unsigned xm = (start ? 0u : dm) + ((ar[r] == cres) ? 0x10001u : 1u);
+                    const unsigned xm = (start ? 0u : dm) + *(const unsigned *)(srow[r] + 4 * kTab + cres);
                     const bool is_d = h == d, is_e = h == e;
                     const unsigned hb = is_d ? xb : (is_e ? eb : nfb);
                     const unsigned hm = is_d ? xm : (is_e ? em : nfm);

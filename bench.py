@@ -66,16 +66,18 @@ MEASURED_TRAFFIC_KIB = {("large", "sw16s_pass1_kernel<32, 14, 4>"): (456809.3, 3
 # posting records, and the product kernels (LDS tables of 2K..32K slots, and
 # global-memory tables for the largest rows).  A row entry's posting list is a
 # scattered read (a header and its records share a line), so the traffic
-# exceeds the compulsory bytes several times over.
+# exceeds the compulsory bytes several times over.  Exact rows carry their
+# entries' posting lengths, so on large the row scan reads rows only; the
+# substitute rows of mid still read each entry's header.
 SPGEMM_TRAFFIC_KIB = {
-    "large": {"work_kernel": (5585523.6, 20248.8),
-              "posting_records_kernel": (508038.6, 957027.9),
-              "spgemm_lds_kernel<2048, 1024>": (3997231.4, 1536517.8),
-              "spgemm_lds_kernel<4096, 2048>": (4927850.7, 1673725.1),
-              "spgemm_lds_kernel<8192, 3072>": (1750050.0, 676925.6),
-              "spgemm_lds_kernel<16384, 2048>": (211802.2, 88293.9),
-              "spgemm_lds_kernel<32768, 4096>": (6824.4, 3674.4),
-              "spgemm_global_kernel": (23.2, 131072.0)},
+    "large": {"work_kernel": (168254.0, 10210.0),
+              "posting_records_kernel": (508027.0, 957270.0),
+              "spgemm_lds_kernel<2048, 1024>": (3272355.0, 1548712.0),
+              "spgemm_lds_kernel<4096, 2048>": (3412137.0, 1716871.0),
+              "spgemm_lds_kernel<8192, 3072>": (1335028.0, 687789.0),
+              "spgemm_lds_kernel<16384, 2048>": (166609.0, 89104.0),
+              "spgemm_lds_kernel<32768, 4096>": (6701.0, 3696.0),
+              "spgemm_global_kernel": (24.0, 131072.0)},
     "mid": {"work_kernel": (11050645.5, 4945.4),
             "posting_records_kernel": (114681.5, 240936.1),
             "spgemm_lds_kernel<2048, 1024>": (189618.7, 47680.3),

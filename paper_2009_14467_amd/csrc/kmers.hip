@@ -17,7 +17,8 @@
 //   kmap:           dense map id -> head of the distinct k-mer's posting group
 //                   (uk_start[u] + u) or -1 (24^k entries), for k <=
 //                   kDenseMapMaxK only;
-//   row_h (if set): per row entry, the head of its k-mer's posting group.
+//   row_h (if set): per row entry, the head of its k-mer's posting group;
+//   row_len (if set with row_h): per row entry, the length of that group.
 // Ids are 64-bit (24^8 < 2^37); a window that runs past its sequence gets
 // the key 24^k, which sorts after every id.
 #include "internal.hpp"
@@ -135,14 +136,19 @@ __global__ void close_kernel(const uint32_t *__restrict__ nnz, const uint32_t *_
 __global__ void rows_kernel(const uint32_t *__restrict__ gent, const uint32_t *__restrict__ gslot,
                             const uint32_t *__restrict__ gseq, const int64_t *__restrict__ offsets, int64_t m,
                             const uint32_t *__restrict__ uk_start, uint32_t *__restrict__ row_u,
-                            uint16_t *__restrict__ row_pos, uint32_t *__restrict__ row_h) {
+                            uint16_t *__restrict__ row_pos, uint32_t *__restrict__ row_h,
+                            uint32_t *__restrict__ row_len) {
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < m; g += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t u = gent[g];
         if (u == kNone) continue;
         const uint32_t slot = gslot[g];
         row_u[slot] = u;
         row_pos[slot] = (uint16_t)(g - offsets[gseq[g]]);
-        if (row_h) row_h[slot] = uk_start[u] + u;
+        if (row_h) {
+            const uint32_t b = uk_start[u];
+            row_h[slot] = b + u;
+            if (row_len) row_len[slot] = uk_start[u + 1] - b;
+        }
     }
 }
 
@@ -233,7 +239,7 @@ hipError_t build_kmers(const uint8_t *codes, const int64_t *offsets, int64_t n, 
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (m > 0) {
         rows_kernel<<<grid_for(m), 256, 0, s>>>(gent, gslot, gseq, offsets, m, kt.uk_start, kt.row_u, kt.row_pos,
-                                                kt.row_h);
+                                                kt.row_h, kt.row_len);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (want_kmap && k <= kDenseMapMaxK) {

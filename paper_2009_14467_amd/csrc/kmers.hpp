@@ -34,6 +34,10 @@ struct KmerTables {
     // optional (may be null): per row entry, the index of its k-mer's group
     // header in the headed posting records, head(u) = uk_start[u] + u
     uint32_t *row_h;
+    // optional, set with row_h: per row entry, the length of that group
+    // (uk_start[u + 1] - uk_start[u]), so the row scan and the product read
+    // it in row order instead of from the scattered group header
+    uint32_t *row_len;
     int32_t *kmap;  // id -> head(u) of the distinct k-mer u, or -1
 };
 

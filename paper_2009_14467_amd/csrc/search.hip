@@ -72,6 +72,7 @@ enum DiscBuf {
     kDTuneRec,
     kDPostRec,
     kDRowH,
+    kDRowLen,
     kDStage,
     kDEnd
 };
@@ -207,7 +208,11 @@ pastis_status discover(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, 
     PASTIS_TRY(get(ctx, kDRowU, m, &kt.row_u));
     PASTIS_TRY(get(ctx, kDRowPos, m, &kt.row_pos));
     kt.row_h = nullptr;
-    if (!subs) PASTIS_TRY(get(ctx, kDRowH, m, &kt.row_h));  // the exact product's entries
+    kt.row_len = nullptr;
+    if (!subs) {  // the exact product's entries
+        PASTIS_TRY(get(ctx, kDRowH, m, &kt.row_h));
+        PASTIS_TRY(get(ctx, kDRowLen, m, &kt.row_len));
+    }
     kt.kmap = nullptr;
     const bool dense_map = subs && P.k <= kDenseMapMaxK;  // longer k-mers: binary search of the distinct ids
     if (dense_map) PASTIS_TRY(get(ctx, kDKmap, (size_t)kmap_entries(P.k), &kt.kmap));
@@ -289,6 +294,7 @@ pastis_status discover(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, 
     } else {
         sp.row_start32 = kt.row_start;
         sp.ent_s = kt.row_h;
+        sp.ent_len = kt.row_len;
         sp.ent_pos16 = kt.row_pos;
     }
 

@@ -55,6 +55,7 @@ struct RowView {
     const uint16_t *ent_pos16;  // exact
     const uint32_t *ent_dp;     // substitutes: ((d + 128) << 16) | pos
     int exact;
+    const uint32_t *ent_len;    // exact: the posting length of each entry (else read from the header)
 
     __device__ __forceinline__ void bounds(uint32_t i, uint64_t &b, uint64_t &e) const {
         if (exact) {
@@ -74,7 +75,9 @@ struct RowView {
 // the index h of its header; rec[h] = (length, distinct k-mer index) and the
 // group's (sequence, position) records follow at h + 1.  The header shares a
 // line with the first records, so an entry costs one scattered line for its
-// length and (for the usual short lists) its products.
+// length and (for the usual short lists) its products.  Rows of A carry each
+// entry's length beside it, so for them the row scan reads no header and the
+// product's first scattered access is the records themselves.
 struct Postings {
     const uint2 *rec;
 };
@@ -135,13 +138,13 @@ __device__ __forceinline__ uint32_t expand_row(const RowView &rv, const Postings
         const int t0 = threadIdx.x * 2, t1 = t0 + 1;
         if (t0 < ce) {
             const uint32_t h = rv.ent_s[c0 + t0];
-            len0 = P.rec[h].x;
+            len0 = rv.ent_len ? rv.ent_len[c0 + t0] : P.rec[h].x;
             C.pbeg[t0] = h + 1;
             C.epos[t0] = rv.pos(c0 + t0);
         }
         if (t1 < ce) {
             const uint32_t h = rv.ent_s[c0 + t1];
-            len1 = P.rec[h].x;
+            len1 = rv.ent_len ? rv.ent_len[c0 + t1] : P.rec[h].x;
             C.pbeg[t1] = h + 1;
             C.epos[t1] = rv.pos(c0 + t1);
         }
@@ -591,7 +594,11 @@ __global__ __launch_bounds__(256) void work_kernel(RowView rv, Postings P, int64
         uint64_t b, e;
         rv.bounds((uint32_t)i, b, e);
         uint64_t w = 0;
-        for (uint64_t x = b + lane; x < e; x += 64) w += P.rec[rv.ent_s[x]].x;
+        if (rv.ent_len) {
+            for (uint64_t x = b + lane; x < e; x += 64) w += rv.ent_len[x];
+        } else {
+            for (uint64_t x = b + lane; x < e; x += 64) w += P.rec[rv.ent_s[x]].x;
+        }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
             const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)w, off, 64);
@@ -710,7 +717,7 @@ hipError_t as_run(const AsArgs &a, uint32_t gcap, hipStream_t s) {
 }
 
 hipError_t spgemm_plan(const SpgemmArgs &a, hipStream_t s) {
-    RowView rv{a.row_start32, a.row_start64, a.row_len, a.ent_s, a.ent_pos16, a.ent_dp, a.exact};
+    RowView rv{a.row_start32, a.row_start64, a.row_len, a.ent_s, a.ent_pos16, a.ent_dp, a.exact, a.ent_len};
     Postings P{a.post_rec};
     hipError_t e;
     if ((e = fill<unsigned long long>(a.max_big, 1, 0ull, s)) != hipSuccess) return e;
@@ -726,7 +733,7 @@ hipError_t spgemm_plan(const SpgemmArgs &a, hipStream_t s) {
 }
 
 hipError_t spgemm_run(const SpgemmArgs &a, uint32_t gcap, hipStream_t s) {
-    RowView rv{a.row_start32, a.row_start64, a.row_len, a.ent_s, a.ent_pos16, a.ent_dp, a.exact};
+    RowView rv{a.row_start32, a.row_start64, a.row_len, a.ent_s, a.ent_pos16, a.ent_dp, a.exact, a.ent_len};
     Postings P{a.post_rec};
     Emit em{a.d_count, a.d_overflow, a.d_key, a.d_cnt, a.d_s1, a.d_s2, a.d_dir, a.cap, a.nbits};
     hipError_t e;
@@ -735,7 +742,8 @@ hipError_t spgemm_run(const SpgemmArgs &a, uint32_t gcap, hipStream_t s) {
     // spilled rows (too many candidates for LDS) join the big-row list.
     // LDS per block: 18 KB (eight blocks per CU, the wave limit), 30 KB
     // (five), 51 KB (three), 78 KB (two), 150 KB (one).  The kernel is bound
-    // by the latency of its dependent loads (entry, posting header, records),
+    // by the latency of its dependent loads (entry, then posting header or
+    // records),
     // so the small tables, where most rows of short sequences land, pay off
     // through the blocks they keep resident.
     spgemm_lds_kernel<2048, 1024><<<kTierBlocks[0], kThreads, 0, s>>>(rv, P, a.bins.idx, a.bins.starts, 0, a.ck,

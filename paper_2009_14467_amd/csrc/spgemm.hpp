@@ -50,6 +50,7 @@ struct SpgemmArgs {
     const uint64_t *row_start64;
     const uint32_t *row_len;
     const uint32_t *ent_s;
+    const uint32_t *ent_len;  // posting length of each entry, or null (read from its header)
     const uint16_t *ent_pos16;
     const uint32_t *ent_dp;
     int64_t n;

@@ -234,15 +234,16 @@ pastis_status make_sw_work(pastis_ctx *ctx, int64_t npairs, int max_len, SwWork 
     void *p = nullptr;
     PASTIS_TRY(ensure(ctx, kBufBinOf, (size_t)std::max<int64_t>(npairs, 1), &p));
     wk.bin_of = (int8_t *)p;
-    PASTIS_TRY(ensure(ctx, kBufBinMeta, sizeof(int) * 256 + sizeof(unsigned long long) * kNumCounters, &p));
+    PASTIS_TRY(ensure(ctx, kBufBinMeta, sizeof(int) * 384 + sizeof(unsigned long long) * kNumCounters, &p));
     wk.counts = (int *)p;
-    wk.counters = (unsigned long long *)((int *)p + 256);
-    // counts: 32 bins; starts, starts2: 33 bounds each; cursor: 32; three
-    // work queues of 32 bins
+    wk.counters = (unsigned long long *)((int *)p + 384);
+    // counts: 32 bins; starts, starts2: 33 bounds each; cursor, split: 32;
+    // four work queues of 32 bins
     wk.starts = wk.counts + 32;
     wk.starts2 = wk.counts + 72;
     wk.cursor = wk.counts + 112;
-    wk.queue = wk.counts + 160;
+    wk.split = wk.counts + 144;
+    wk.queue = wk.counts + 176;
     PASTIS_TRY(ensure(ctx, kBufIdx, sizeof(int) * (size_t)std::max<int64_t>(npairs, 1), &p));
     wk.idx = (int *)p;
     PASTIS_TRY(ensure(ctx, kBufIdx2, sizeof(int) * (size_t)std::max<int64_t>(npairs, 1), &p));

@@ -216,7 +216,11 @@ struct SwWork {
     int *idx, *idx2;
     int *scratch;
     int64_t scratch_per_wave;
-    int *queue;  // work-queue counters: pass 1, start bound, statistics (32 bins each)
+    int *queue;  // work-queue counters: pass 1, start bound, statistics, pass 1 of the taller half (32 bins each)
+    // per bin: the first pass-1 item of its taller half (16-bit strip bins of
+    // up to 8 rows per lane split their pairs by rows: up to 64 R - 32 rows,
+    // and more)
+    int *split;
     // pairing of the 16-bit pass (pairs sorted by bin, then longer b first)
     uint64_t *sort_keys = nullptr, *sort_keys_alt = nullptr;
     uint32_t *sort_vals_alt = nullptr;

@@ -159,6 +159,13 @@ __device__ __forceinline__ int64_t take(int *queue, const int *starts, int bin, 
     return starts[bin] + (int64_t)__builtin_amdgcn_readfirstlane(v);
 }
 
+// the same from a counter of its own over items [begin, ...)
+__device__ __forceinline__ int64_t take_from(int *counter, int begin, int count) {
+    int v = 0;
+    if ((threadIdx.x & (kWave - 1)) == 0) v = atomicAdd(counter, count);
+    return begin + (int64_t)__builtin_amdgcn_readfirstlane(v);
+}
+
 // ---------------------------------------------------------------- pass 1
 
 // max(x - y, 0) for x >= 0, y >= 0 (one clamped subtract)
@@ -866,11 +873,15 @@ __device__ __forceinline__ int wave_max_i32(int v) {
 }
 
 
+// One launch takes one half of a bin's pairs (sorted by rows class first):
+// half 0 the items [starts[bin], split[bin]), half 1 [split[bin],
+// starts[bin + 1]), each with its own work-queue counter.
 template <int S, int RP, int WPB>
 __global__ __launch_bounds__(64 * WPB) void sw16s_pass1_kernel(const uint8_t *__restrict__ codes,
                                                                const PairDesc *__restrict__ pairs,
                                                                const int *__restrict__ idx,
-                                                               const int *__restrict__ starts, int bin,
+                                                               const int *__restrict__ starts,
+                                                               const int *__restrict__ split, int bin, int half,
                                                                const int8_t *__restrict__ blosum, int go_ge, int ge,
                                                                SwPass1Out *__restrict__ out, int *queue) {
     static_assert((S == 16 || S == 32) && RP <= kMax16R, "strip shape");
@@ -882,11 +893,13 @@ __global__ __launch_bounds__(64 * WPB) void sw16s_pass1_kernel(const uint8_t *__
     const int wave = threadIdx.x / kWave;
     const int pos = lane % S, strip = lane / S, cl = lane & 15;
     ProfWord<RP>(*prof)[S] = prof_all[wave];
-    const int item_end = starts[bin + 1];
+    const int item_begin = half ? split[bin] : starts[bin];
+    const int item_end = half ? starts[bin + 1] : split[bin];
+    int *const counter = queue + (half ? 3 * kNumBins : 0) + bin;
     const uint32_t OE2 = (uint32_t)go_ge * 0x10001u, GE2 = (uint32_t)ge * 0x10001u;
     const uint32_t G0 = ((uint32_t)(-go_ge) & 0xFFFFu) * 0x10001u;  // G of an H = 0 cell
 
-    for (int64_t w = take(queue, starts, bin, NI); w < item_end; w = take(queue, starts, bin, NI)) {
+    for (int64_t w = take_from(counter, item_begin, NI); w < item_end; w = take_from(counter, item_begin, NI)) {
         const int nit = (int)min((int64_t)NI, item_end - w);
         const int iP = 2 * strip, iQ = iP + 1;
         const int qP = iP < nit ? idx[w + iP] : -1;
@@ -1033,17 +1046,41 @@ __global__ __launch_bounds__(64 * WPB) void sw16s_pass1_kernel(const uint8_t *__
     }
 }
 
-// sort keys of the pairing: bin, then sequence a (low 24 bits of its index;
-// the kernel checks equality itself), then the longer b first
+// sort keys of the pairing: bin, then the rows class (strip bins of up to
+// 8 rows per lane: sequences a of more than 64 R - 32 rows in class 1, which
+// the strip kernel runs with one row per lane more than class 0), then
+// sequence a (low 24 bits of its index; the kernel checks equality itself),
+// then the longer b first
 constexpr int kPairKeyBits = 48;
+constexpr int kSplitBins = 8;  // one-strip bins 0..7 (up to 8 rows per lane)
 __global__ void sw_pair_keys_kernel(const PairDesc *__restrict__ pairs, const int8_t *__restrict__ bin_of,
                                     int64_t npairs, uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= npairs) return;
     const PairDesc pd = pairs[q];
-    keys[q] = ((uint64_t)(uint8_t)bin_of[q] << 40) | ((uint64_t)((uint32_t)pd.a_seq & 0xFFFFFFu) << 16) |
+    const int bin = (uint8_t)bin_of[q];
+    const int tall = bin < kSplitBins && pd.la > kWave * (bin + 1) - kWave / 2;
+    keys[q] = ((uint64_t)(2 * bin + tall) << 40) | ((uint64_t)((uint32_t)pd.a_seq & 0xFFFFFFu) << 16) |
               (uint64_t)(0xFFFF - pd.lb);
     vals[q] = (uint32_t)q;
+}
+
+// split[bin] = the first sorted item of the bin's rows class 1 (a lower
+// bound over the bin's keys)
+__global__ void sw_split_kernel(const uint64_t *__restrict__ keys, const int *__restrict__ starts,
+                                int *__restrict__ split) {
+    const int bin = threadIdx.x;
+    if (bin >= kNumBins) return;
+    int lo = starts[bin], hi = starts[bin + 1];
+    const uint64_t k1 = (uint64_t)(2 * bin + 1) << 40;
+    while (lo < hi) {
+        const int mid = lo + (hi - lo) / 2;
+        if (keys[mid] < k1)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    split[bin] = lo;
 }
 
 // ---------------------------------------------------------------- between the passes
@@ -1065,7 +1102,7 @@ __device__ __forceinline__ int rows_bin(int rows) {
 __global__ void sw_bin1_kernel(const PairDesc *__restrict__ pairs, int64_t npairs, int8_t *__restrict__ bin_of,
                                unsigned long long *__restrict__ counters, int *__restrict__ queue) {
     // the work queues of this call's launches (pass 1, start bound, statistics)
-    if (blockIdx.x == 0 && threadIdx.x < 3 * kNumBins) queue[threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < 4 * kNumBins) queue[threadIdx.x] = 0;
     __shared__ unsigned long long cells[kNumBins];
     if (threadIdx.x < kNumBins) cells[threadIdx.x] = 0;
     __syncthreads();
@@ -1666,23 +1703,33 @@ static int blocks16(int R) { return R <= 4 ? 256 * 6 : R <= 8 ? 256 * 3 : R <= 1
 // 2 R rows; wider bins: the full-wave kernel (two pairs per wave)
 template <int R>
 hipError_t launch_p16(int bin, int blocks, bool narrow, const uint8_t *codes, const PairDesc *pairs, const int *idx,
-                      const int *starts, const int8_t *blosum, int go_ge, int ge, SwPass1Out *p1, int *queue,
-                      hipStream_t s) {
+                      const int *starts, const int *split, const int8_t *blosum, int go_ge, int ge, SwPass1Out *p1,
+                      int *queue, hipStream_t s) {
     constexpr int WPB = wpb16(R);
+    // strips: rows class 0 (at most 64 R - 32 rows) with one row per lane
+    // less in 32-lane strips (two in 16-lane ones), then class 1
     if constexpr (R <= 4) {
-        if (narrow)
-            sw16s_pass1_kernel<16, 4 * R, WPB><<<blocks, 64 * WPB, 0, s>>>(codes, pairs, idx, starts, bin, blosum,
-                                                                          go_ge, ge, p1, queue);
-        else
-            sw16s_pass1_kernel<32, 2 * R, WPB><<<blocks, 64 * WPB, 0, s>>>(codes, pairs, idx, starts, bin, blosum,
-                                                                          go_ge, ge, p1, queue);
-    } else if constexpr (R <= 8)
-        sw16s_pass1_kernel<32, 2 * R, WPB><<<blocks, 64 * WPB, 0, s>>>(codes, pairs, idx, starts, bin, blosum, go_ge,
-                                                                      ge, p1, queue);
-    else
+        if (narrow) {
+            sw16s_pass1_kernel<16, 4 * R - 2, WPB><<<blocks, 64 * WPB, 0, s>>>(codes, pairs, idx, starts, split, bin, 0,
+                                                                              blosum, go_ge, ge, p1, queue);
+            sw16s_pass1_kernel<16, 4 * R, WPB><<<blocks, 64 * WPB, 0, s>>>(codes, pairs, idx, starts, split, bin, 1,
+                                                                          blosum, go_ge, ge, p1, queue);
+        } else {
+            sw16s_pass1_kernel<32, 2 * R - 1, WPB><<<blocks, 64 * WPB, 0, s>>>(codes, pairs, idx, starts, split, bin, 0,
+                                                                              blosum, go_ge, ge, p1, queue);
+            sw16s_pass1_kernel<32, 2 * R, WPB><<<blocks, 64 * WPB, 0, s>>>(codes, pairs, idx, starts, split, bin, 1,
+                                                                          blosum, go_ge, ge, p1, queue);
+        }
+    } else if constexpr (R <= 8) {
+        sw16s_pass1_kernel<32, 2 * R - 1, WPB><<<blocks, 64 * WPB, 0, s>>>(codes, pairs, idx, starts, split, bin, 0,
+                                                                          blosum, go_ge, ge, p1, queue);
+        sw16s_pass1_kernel<32, 2 * R, WPB><<<blocks, 64 * WPB, 0, s>>>(codes, pairs, idx, starts, split, bin, 1,
+                                                                      blosum, go_ge, ge, p1, queue);
+    } else {
         sw16_pass1_kernel<R, kWpbShared, false><<<blocks, 64 * kWpbShared, 0, s>>>(codes, pairs, idx, starts, bin,
                                                                                   blosum, go_ge, ge, p1, nullptr, 0,
                                                                                   queue);
+    }
     return hipGetLastError();
 }
 
@@ -1729,7 +1776,7 @@ const P1Fn kP1[kNumBins] = {launch_p1<1>,  launch_p1<2>,  launch_p1<3>,  launch_
                             launch_p1<9>,  launch_p1<10>, launch_p1<11>, launch_p1<12>, launch_p1<13>, launch_p1<14>,
                             launch_p1<15>, launch_p1<16>};
 typedef hipError_t (*P16Fn)(int, int, bool, const uint8_t *, const PairDesc *, const int *, const int *,
-                            const int8_t *, int, int, SwPass1Out *, int *, hipStream_t);
+                            const int *, const int8_t *, int, int, SwPass1Out *, int *, hipStream_t);
 const P16Fn kP16[kMax16R] = {launch_p16<1>,  launch_p16<2>,  launch_p16<3>,  launch_p16<4>,
                             launch_p16<5>,  launch_p16<6>,  launch_p16<7>,  launch_p16<8>,
                             launch_p16<9>,  launch_p16<10>, launch_p16<11>, launch_p16<12>,
@@ -1869,6 +1916,8 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
                             kPairKeyBits, wk.sort_temp, s, &alt)) != hipSuccess)
             return e;
         if (alt) idx1 = (const int *)wk.sort_vals_alt;
+        sw_split_kernel<<<1, 64, 0, s>>>(alt ? wk.sort_keys_alt : wk.sort_keys, wk.starts, wk.split);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if ((e = end(kStSched)) != hipSuccess || (e = begin(kStAlign1)) != hipSuccess || (e = fork(0)) != hipSuccess)
         return e;
@@ -1888,7 +1937,7 @@ hipError_t launch_sw(pastis_ctx *ctx, const uint8_t *codes, const PairDesc *pair
                                     wk.scratch_per_wave, wk.queue, wk.counters + kCounterIntraFlag, st);
         else if (sw_bin_is16(bin, max16))
             e = kP16[bin](bin, capped(scale * blocks16(R), pairs_per_block16(R, R <= narrow16)), R <= narrow16, codes,
-                          pairs, idx1, wk.starts, blosum, go_ge, ge, p1, wk.queue, st);
+                          pairs, idx1, wk.starts, wk.split, blosum, go_ge, ge, p1, wk.queue, st);
         else
             e = kP1[bin](bin,
                          capped(bin >= kMultiBin ? long_cap(blocks_for_bin(bin)) : scale * blocks_for_bin(bin),

@@ -81,11 +81,15 @@ def test_forward_matches_oracle(gpu, n):
     ctx.mlp_set(theta, mean, std)
     y = ctx.mlp_forward(_dev(X, gpu)).cpu().numpy().astype(np.float64)
     want, _ = M.forward(theta, M.normalise(X, mean, std))
-    err = np.abs(y - want)
-    # fp32 accumulation against fp64: ~1e-6 relative, plus a rare one-ulp
-    # difference of a bf16 activation rounded from a value on a rounding tie
-    assert np.median(err) <= 1e-5 * (1 + np.median(np.abs(want)))
-    assert (err <= 2e-2 * (1 + np.abs(want))).all(), err.max()
+    rel = np.abs(y - want) / (1 + np.abs(want))
+    # fp32 accumulation against fp64: float32 rounding almost everywhere; a
+    # pre-activation within that rounding of a bf16 rounding boundary can
+    # round to the neighbouring bf16 value, which moves the logit by up to a
+    # few 1e-3 (a float32 model of the kernel's sums, in another order, does
+    # so for 0.04% of 70,001 rows, by at most 3.9e-3)
+    assert np.median(rel) <= 1e-6
+    assert (rel > 1e-4).sum() <= max(1, 5e-3 * n), np.sort(rel)[-10:]
+    assert rel.max() <= 1e-2, rel.max()
 
 
 @pytest.mark.parametrize("n,pw", [(16, 1.0), (999, 3.0), (4096, 10.0), (65536, 2.0)])

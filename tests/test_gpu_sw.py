@@ -183,15 +183,20 @@ def test_sw16_records_tiny(gpu, tiny):
     assert have.sum() >= (want["passed"] == 1).sum() > 0
 
 
-def test_sw16_every_one_strip_bin_and_odd_counts(gpu, orc):
+@pytest.mark.parametrize("narrow", [0, 4])
+def test_sw16_every_one_strip_bin_and_odd_counts(gpu, orc, narrow):
     """Rows 1..1024 (one-strip bins R = 1..16) with odd pair counts per bin,
     so the last wave of a bin carries one pair, and several pairs sharing
-    their shorter sequence (the 16-bit pass pairs those in one wave)."""
+    their shorter sequence (the 16-bit pass pairs those in one wave).  Bins
+    of up to 8 rows per lane run in two rows classes (up to 64 R - 32 rows,
+    and more): both sides of every class boundary are here, in strips of 32
+    lanes (narrow 0) and, up to 4 rows per lane, of 16 (narrow 4)."""
     from synth.families import FamilySet
 
     rng = np.random.default_rng(8)
     lens = [1, 2, 63, 64, 65, 100, 128, 129, 191, 192, 193, 255, 256, 257, 320, 321, 383, 384, 385, 448, 449, 511,
             512, 513, 640, 641, 768, 769, 896, 897, 1023, 1024]
+    lens += [64 * R - 32 + d for R in range(1, 9) for d in (0, 1)]
     seqs = []
     for L in lens:
         a = rng.integers(0, 20, L)
@@ -213,7 +218,8 @@ def test_sw16_every_one_strip_bin_and_odd_counts(gpu, orc):
     lo = np.concatenate([lo, a.astype(np.uint32)])
     hi = np.concatenate([hi, b.astype(np.uint32)])
     want = orc.align_pairs(codes, s.offsets, lo, hi, mode="sw")
-    got = _gpu_records(gpu, s, lo, hi, score_width=16)
+    tuning = dict(sw16_max_rows=16, sw16_narrow_rows=narrow)
+    got = _gpu_records(gpu, s, lo, hi, tuning=tuning, score_width=16)
     _check16(got, want)
 
 

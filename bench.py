@@ -52,15 +52,9 @@ ALGO_OPS_PER_XD_CELL = 12
 # HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (KiB per
 # dispatch, profiles/sw_search_<workload>_kernel_stats.md), scaled by what the
 # counters read for a 1 GiB device copy (FETCH x 2.0, WRITE x 1.0); keyed by
-# workload and kernel, and only for kernels unchanged since those counters
-# were taken
-MEASURED_TRAFFIC_KIB = {("large", "sw16s_pass1_kernel<32, 14, 4>"): (456809.3, 36151.0),
-                        ("large", "sw16s_pass1_kernel<32, 12, 4>"): (548476.9, 45754.0),
-                        ("large", "sw16s_pass1_kernel<32, 10, 4>"): (691304.8, 61093.3),
-                        ("mid", "sw16s_pass1_kernel<32, 12, 4>"): (1247195.8, 129271.6),
-                        ("mid", "sw16s_pass1_kernel<32, 14, 4>"): (962258.3, 99917.6),
-                        ("mid", "sw16s_pass1_kernel<16, 16, 4>"): (1312067.5, 130976.7),
-                        ("mid", "sw16_pass1_kernel<9, 2, false>"): (598679.5, 65335.5)}
+# workload and kernel (a strip bin's two launches: their sum), and only for
+# kernels unchanged since those counters were taken
+MEASURED_TRAFFIC_KIB = {("mid", "sw16_pass1_kernel<9, 2, false>"): (598679.5, 65335.5)}
 # the same counters for the kernels of the sparse-product stage (one launch of
 # each per step): the row scan that sizes each row's table, the headed
 # posting records, and the product kernels (LDS tables of 2K..32K slots, and
@@ -221,22 +215,27 @@ def timed_steps(ctx, args, res, off):
 STAGE_NAMES = ["encode", "kmers", "subs_AS", "spgemm", "schedule", "sw_pass1", "sw_pass2", "edges", "mlp_filter"]
 
 
-def kernel_name(b):
+def kernel_name(b, narrow):
+    """The pass-1 kernel(s) of a length bin.  A 16-bit strip bin (up to 8 rows
+    per lane) is two launches back to back on one stream: the sequences of up
+    to 64 R - 32 rows with one row per lane less (two in 16-lane strips),
+    then the rest; its events span both."""
     R = b["rows_per_lane"]
     if b["bits"] == 16:
         if b["multi_strip"]:
             return "sw16_pass1_kernel<%d, 4, true>" % R
-        if R <= 4:
-            return "sw16s_pass1_kernel<16, %d, 4>" % (4 * R)
         if R <= 8:
-            return "sw16s_pass1_kernel<32, %d, 4>" % (2 * R)
-        return "sw16_pass1_kernel<%d, 4, false>" % R
+            S = 16 if R <= min(narrow, 4) else 32
+            rp = 64 * R // S
+            return "sw16s_pass1_kernel<%d, %d, 4> + sw16s_pass1_kernel<%d, %d, 4>" % (S, rp - 32 // S, S, rp)
+        return "sw16_pass1_kernel<%d, 2, false>" % R
     return "sw_pass1_kernel<%d, %s>" % (R, "true" if b["multi_strip"] else "false")
 
 
-def roofline(st, pass1_ms, traffic_ok, workload):
+def roofline(st, pass1_ms, traffic_ok, workload, narrow):
     """The dominant pass-1 kernel (the length bin with the most DP work; one
-    launch per step) against the integer VALU peak of its lane width: its
+    launch per step, or for a 16-bit strip bin its two rows classes back to
+    back on one stream) against the integer VALU peak of its lane width: its
     cells x the method's 11 ops per cell over its HIP-event time on the
     stream it was launched on.  The kernel's own formulation count (10 or 9
     ops per cell) is reported beside it."""
@@ -251,7 +250,7 @@ def roofline(st, pass1_ms, traffic_ok, workload):
     # stream beside the one-strip bins, so their event spans include time
     # shared with other kernels
     dom = max(st["sw_bins"], key=lambda b: b["cells"] / peak_of(b))
-    name = kernel_name(dom)
+    name = kernel_name(dom, narrow)
     peak = peak_of(dom)
     achieved = dom["cells"] * ALGO_OPS_PER_SW_CELL / (dom["ms"] * 1e-3) / 1e12
     kernel_ops = dom["cells"] * ops(dom) / (dom["ms"] * 1e-3) / 1e12
@@ -443,7 +442,7 @@ def mid_leg(P, args, dev):
         "cells": cells,
         "edges": int(edges.size),
         "stage_ms": dict(zip(STAGE_NAMES, stage)),
-        "roofline": roofline(st, stage[5], args.families is None, "mid"),
+        "roofline": roofline(st, stage[5], args.families is None, "mid", ctx.get_tuning()["sw16_narrow_rows"]),
         "spgemm": spgemm_line(st, stage[3], "mid" if args.families is None else None),
     }
     if not args.no_xd:
@@ -543,7 +542,8 @@ def main():
         "stage_ms": dict(zip(STAGE_NAMES, stage)),
         "align_gcups": cells / ((stage[5] + stage[6]) * 1e-3) / 1e9,
         "spgemm": spgemm_line(st, stage[3], args.workload if args.families is None else None),
-        "roofline": roofline(st, stage[5], args.families is None, args.workload),
+        "roofline": roofline(st, stage[5], args.families is None, args.workload,
+                             ctx.get_tuning()["sw16_narrow_rows"]),
         "sw_bins": [dict(b, gcups=b["cells"] / max(b["ms"], 1e-9) / 1e6) for b in st["sw_bins"] if b["pairs"]],
         "schedule": tuning if tuning is not None else dict(ctx.get_tuning(), source="library default"),
     }

@@ -590,6 +590,10 @@ __global__ __launch_bounds__(256) void work_kernel(RowView rv, Postings P, int64
                                                    unsigned long long *__restrict__ products) {
     const int lane = threadIdx.x & 63;
     const XcdWalk it = xcd_walk(n, blockDim.x / 64, threadIdx.x / 64);
+    // the products of this wave's rows, added to *products once per block
+    // (one atomic per row would serialise on the one address)
+    __shared__ unsigned long long wave_products[4];
+    unsigned long long mine = 0;
     for (int64_t i = it.first; i < it.end; i += it.step) {
         uint64_t b, e;
         rv.bounds((uint32_t)i, b, e);
@@ -607,7 +611,7 @@ __global__ __launch_bounds__(256) void work_kernel(RowView rv, Postings P, int64
         }
         if (lane != 0) continue;
         work[i] = w;
-        if (w) atomicAdd(products, (unsigned long long)w);
+        mine += w;
         // tables of 2^(11 + bin) slots hold rows of up to 3/4 of that many products
         int8_t bin = -1;
         if (w > 0 && n_big_ok)
@@ -621,6 +625,13 @@ __global__ __launch_bounds__(256) void work_kernel(RowView rv, Postings P, int64
             big_rows[atomicAdd(n_big, 1u)] = (uint32_t)i;
             atomicMax(max_big, (unsigned long long)w);
         }
+    }
+    if (lane == 0) wave_products[threadIdx.x / 64] = mine;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int k = 0; k < (int)(blockDim.x / 64); ++k) t += wave_products[k];
+        if (t) atomicAdd(products, t);
     }
 }
 

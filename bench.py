@@ -54,7 +54,18 @@ ALGO_OPS_PER_XD_CELL = 12
 # counters read for a 1 GiB device copy (FETCH x 2.0, WRITE x 1.0); keyed by
 # workload and kernel (a strip bin's two launches: their sum), and only for
 # kernels unchanged since those counters were taken
-MEASURED_TRAFFIC_KIB = {("mid", "sw16_pass1_kernel<9, 2, false>"): (598679.5, 65335.5)}
+MEASURED_TRAFFIC_KIB = {
+    ("large", "sw16s_pass1_kernel<32, 9, 4> + sw16s_pass1_kernel<32, 10, 4>"): (690921.8, 61408.1),
+    ("large", "sw16s_pass1_kernel<32, 11, 4> + sw16s_pass1_kernel<32, 12, 4>"): (547528.0, 46008.4),
+    ("large", "sw16s_pass1_kernel<32, 13, 4> + sw16s_pass1_kernel<32, 14, 4>"): (455427.8, 36399.1),
+    ("large", "sw16s_pass1_kernel<32, 15, 4> + sw16s_pass1_kernel<32, 16, 4>"): (338204.5, 25847.9),
+    ("mid", "sw16s_pass1_kernel<32, 9, 4> + sw16s_pass1_kernel<32, 10, 4>"): (1448538.3, 152318.8),
+    ("mid", "sw16s_pass1_kernel<32, 11, 4> + sw16s_pass1_kernel<32, 12, 4>"): (1247457.2, 129179.6),
+    ("mid", "sw16s_pass1_kernel<32, 13, 4> + sw16s_pass1_kernel<32, 14, 4>"): (963765.3, 99901.9),
+    ("mid", "sw16s_pass1_kernel<32, 15, 4> + sw16s_pass1_kernel<32, 16, 4>"): (720340.5, 75905.5),
+    ("mid", "sw16_pass1_kernel<9, 2, false>"): (599016.3, 65330.9),
+    ("mid", "sw16_pass1_kernel<10, 2, false>"): (348997.0, 40725.4),
+}
 # the same counters for the kernels of the sparse-product stage (one launch of
 # each per step): the row scan that sizes each row's table, the headed
 # posting records, and the product kernels (LDS tables of 2K..32K slots, and
@@ -64,14 +75,14 @@ MEASURED_TRAFFIC_KIB = {("mid", "sw16_pass1_kernel<9, 2, false>"): (598679.5, 65
 # entries' posting lengths, so on large the row scan reads rows only; the
 # substitute rows of mid still read each entry's header.
 SPGEMM_TRAFFIC_KIB = {
-    "large": {"work_kernel": (168254.0, 10210.0),
-              "posting_records_kernel": (508027.0, 957270.0),
-              "spgemm_lds_kernel<2048, 1024>": (3272355.0, 1548712.0),
-              "spgemm_lds_kernel<4096, 2048>": (3412137.0, 1716871.0),
-              "spgemm_lds_kernel<8192, 3072>": (1335028.0, 687789.0),
-              "spgemm_lds_kernel<16384, 2048>": (166609.0, 89104.0),
-              "spgemm_lds_kernel<32768, 4096>": (6701.0, 3696.0),
-              "spgemm_global_kernel": (24.0, 131072.0)},
+    "large": {"work_kernel": (168185.5, 2846.8),
+              "posting_records_kernel": (507980.1, 957224.5),
+              "spgemm_lds_kernel<2048, 1024>": (3272292.0, 1548512.7),
+              "spgemm_lds_kernel<4096, 2048>": (3412265.7, 1717051.6),
+              "spgemm_lds_kernel<8192, 3072>": (1335208.7, 687771.6),
+              "spgemm_lds_kernel<16384, 2048>": (166640.3, 89087.3),
+              "spgemm_lds_kernel<32768, 4096>": (6702.5, 3697.2),
+              "spgemm_global_kernel": (22.9, 131072.0)},
     "mid": {"work_kernel": (11050645.5, 4945.4),
             "posting_records_kernel": (114681.5, 240936.1),
             "spgemm_lds_kernel<2048, 1024>": (189618.7, 47680.3),

@@ -445,7 +445,12 @@ pastis_status pastis_set_tuning(pastis_ctx *ctx, const pastis_tuning *t);
  * sequences sized for about max_pairs candidates (at most max_pairs), so the
  * pairs that share a sequence stay together as in the whole set.  A value
  * replaces the one in force only when it is at least 1% faster on the
- * sample.  The discovery's candidates stay in ctx. */
+ * sample.  When the sample is smaller than the candidate set, three knobs
+ * whose effect lies in the tails of the launches, which shrink with the
+ * sample (start-bound routing: 25, 50, 75, 100; inter- vs intra-pair mode;
+ * the long bins' grid), are then timed once more per value on all the
+ * candidates, where a 0.5% margin applies.  The discovery's candidates stay
+ * in ctx. */
 pastis_status pastis_autotune(pastis_ctx *ctx, const uint8_t *residues, const int64_t *offsets, int64_t n,
                               int input_on_device, int64_t max_pairs, void *stream, pastis_tuning *out);
 

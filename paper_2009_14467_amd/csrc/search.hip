@@ -772,7 +772,7 @@ pastis_status pastis_autotune(pastis_ctx *ctx, const uint8_t *residues, const in
         double cur = 0;
         PASTIS_TRY(measure(&cur));  // warms the buffers up
         const int rows16[] = {16, 12, 8, 0};
-        const int direct[] = {0, 25, 50, 100, 200, 1 << 20};
+        const int direct[] = {0, 25, 50, 75, 100, 200, 1 << 20};
         const int grid[] = {1, 2, 4};
         // a value replaces the one in force only when it is at least 1%
         // faster on the sample: smaller differences are within timing noise
@@ -800,7 +800,7 @@ pastis_status pastis_autotune(pastis_ctx *ctx, const uint8_t *residues, const in
             return PASTIS_OK;
         };
         PASTIS_TRY(sweep(&ctx->tune.sw16_max_rows, rows16, 4));
-        PASTIS_TRY(sweep(&ctx->tune.sw_direct_pct, direct, 6));
+        PASTIS_TRY(sweep(&ctx->tune.sw_direct_pct, direct, 7));
         PASTIS_TRY(sweep(&ctx->tune.sw_grid_scale, grid, 3));
         PASTIS_TRY(sweep(&ctx->tune.sw_grid_scale_wide, grid, 3));
         const int intra[] = {0, 1};
@@ -809,6 +809,56 @@ pastis_status pastis_autotune(pastis_ctx *ctx, const uint8_t *residues, const in
         PASTIS_TRY(sweep(&ctx->tune.sw16_narrow_rows, narrow, 3));
         const int longb[] = {4, 2, 1};
         PASTIS_TRY(sweep(&ctx->tune.sw_long_blocks, longb, 3));
+        // The knobs whose best value depends on the tails of the launches
+        // (the start-bound routing, and inter- vs intra-pair mode and the grid
+        // of the multi-strip bins, whose few long pairs set those tails) are
+        // refined on the whole candidate set, since a sample shortens the
+        // tails: on the large workload a 2M-pair sample chose 25% routing,
+        // and all 8.9M candidates run 1% faster at 75%.  One warm-up run at
+        // the full size, then one run per value; a value replaces the one in
+        // force when at least 0.5% faster (whole-set runs vary less than
+        // sample runs).
+        if (m < nc) {
+            pastis_pair_record *rec_all = nullptr;
+            PASTIS_TRY(get(ctx, kDTuneRec, nc, &rec_all));
+            const uint32_t *cs1 = (const uint32_t *)ctx->buf[kBufCandS1].ptr;
+            const uint32_t *cs2 = (const uint32_t *)ctx->buf[kBufCandS2].ptr;
+            auto time_all = [&](double *ms) -> pastis_status {
+                ctx->stats = pastis_run_stats{};
+                ctx->records_internal = true;
+                const pastis_status r = align_core(ctx, st, codes, n, clo, chi, cs1, cs2, nc, rec_all, s);
+                ctx->records_internal = false;
+                PASTIS_TRY(r);
+                HIP_TRY(ctx, stage_collect(ctx, s), "sync");
+                *ms = ctx->stats.ms_stage[kStSched] + ctx->stats.ms_stage[kStAlign1] + ctx->stats.ms_stage[kStAlign2];
+                return PASTIS_OK;
+            };
+            double all_ms = 0;
+            PASTIS_TRY(time_all(&all_ms));
+            PASTIS_TRY(time_all(&all_ms));
+            auto refine = [&](int32_t *knob, const int *vals, int nv) -> pastis_status {
+                const int32_t keep = *knob;
+                int32_t best_v = keep;
+                double best_ms = all_ms;
+                for (int i = 0; i < nv; ++i) {
+                    if (vals[i] == keep) continue;
+                    *knob = vals[i];
+                    double ms = 0;
+                    PASTIS_TRY(time_all(&ms));
+                    if (ms < 0.995 * best_ms) {
+                        best_ms = ms;
+                        best_v = vals[i];
+                    }
+                }
+                *knob = best_v;
+                all_ms = best_ms;
+                return PASTIS_OK;
+            };
+            const int route[] = {25, 50, 75, 100};
+            PASTIS_TRY(refine(&ctx->tune.sw_direct_pct, route, 4));
+            PASTIS_TRY(refine(&ctx->tune.sw_intra_pair, intra, 2));
+            PASTIS_TRY(refine(&ctx->tune.sw_long_blocks, longb, 3));
+        }
     }
     if (out) *out = ctx->tune;
     return PASTIS_OK;

@@ -76,10 +76,11 @@ __global__ __launch_bounds__(kScanThreads) void scan_tiles_kernel(const TIn *__r
 
 // ---- radix sort (8-bit digits, stable) ----
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 8;  // per thread per pass over a tile
+constexpr int kSortItems = 16;  // per thread per pass over a tile
 constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kWavesPerSortBlock = kSortThreads / kWave;
 constexpr int kWaveTile = kSortTile / kWavesPerSortBlock;  // consecutive elements per wave
+constexpr int kWaveChunks = kWaveTile / kWave;
 
 __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint64_t *__restrict__ keys, int64_t n,
                                                                   int shift, int nblocks, uint32_t *__restrict__ hist) {
@@ -96,36 +97,80 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint64_t
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
+// One tile per block.  The tile is ranked stably by digit in LDS (each wave
+// ranks its contiguous quarter 64 elements at a time with ballots), then
+// written out in digit order, so a digit's run of the tile goes to
+// consecutive addresses from consecutive threads.
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals, int64_t n, int shift, int nblocks,
     const uint64_t *__restrict__ offs, uint64_t *__restrict__ okeys, uint32_t *__restrict__ ovals) {
-    __shared__ uint32_t whist[kWavesPerSortBlock][256];
-    __shared__ uint64_t wbase[kWavesPerSortBlock][256];
+    __shared__ uint64_t skey[kSortTile];
+    __shared__ uint32_t sval[kSortTile];
+    __shared__ uint32_t whist[kWavesPerSortBlock][256];  // then each wave's next local slot per digit
+    __shared__ uint32_t dstart[256];                     // the digit's first slot in the tile
+    __shared__ uint64_t gbase[256];                      // the digit's first output address of this tile
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     for (int d = threadIdx.x; d < kWavesPerSortBlock * 256; d += kSortThreads) (&whist[0][0])[d] = 0;
     __syncthreads();
-    const int64_t wstart = (int64_t)blockIdx.x * kSortTile + (int64_t)wave * kWaveTile;
-    for (int c = 0; c < kWaveTile; c += kWave) {
-        const int64_t i = wstart + c + lane;
-        if (i < n) atomicAdd(&whist[wave][(keys[i] >> shift) & 0xFF], 1u);
+    const int64_t tstart = (int64_t)blockIdx.x * kSortTile;
+    const int64_t wstart = tstart + (int64_t)wave * kWaveTile;
+    uint64_t k[kWaveChunks];
+    uint32_t v[kWaveChunks];
+#pragma unroll
+    for (int c = 0; c < kWaveChunks; ++c) {
+        const int64_t i = wstart + c * kWave + lane;
+        const bool ok = i < n;
+        k[c] = ok ? keys[i] : 0;
+        v[c] = ok ? vals[i] : 0;
+        if (ok) atomicAdd(&whist[wave][(k[c] >> shift) & 0xFF], 1u);
     }
     __syncthreads();
     {
         const int d = threadIdx.x;  // 256 threads, one digit each
-        uint64_t run = offs[(int64_t)d * nblocks + blockIdx.x];
+        gbase[d] = offs[(int64_t)d * nblocks + blockIdx.x];
+        uint32_t tot = 0;
+        for (int w = 0; w < kWavesPerSortBlock; ++w) tot += whist[w][d];
+        dstart[d] = tot;  // the digit's count, scanned below
+    }
+    __syncthreads();
+    // exclusive scan of the 256 counts (one wave, four per lane)
+    if (wave == 0) {
+        uint32_t c4[4], sum = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            c4[j] = dstart[4 * lane + j];
+            sum += c4[j];
+        }
+        uint32_t inc = sum;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t o = (uint32_t)__shfl_up((int)inc, off, kWave);
+            if (lane >= off) inc += o;
+        }
+        uint32_t run = inc - sum;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            dstart[4 * lane + j] = run;
+            run += c4[j];
+        }
+    }
+    __syncthreads();
+    {
+        const int d = threadIdx.x;
+        uint32_t run = dstart[d];
         for (int w = 0; w < kWavesPerSortBlock; ++w) {
-            wbase[w][d] = run;
-            run += whist[w][d];
+            const uint32_t c = whist[w][d];
+            whist[w][d] = run;
+            run += c;
         }
     }
     __syncthreads();
     const uint64_t lt = (1ull << lane) - 1ull;
-    for (int c = 0; c < kWaveTile; c += kWave) {
-        const int64_t i = wstart + c + lane;
+#pragma unroll
+    for (int c = 0; c < kWaveChunks; ++c) {
+        const int64_t i = wstart + c * kWave + lane;
         const bool ok = i < n;
-        const uint64_t key = ok ? keys[i] : 0;
-        const uint32_t val = ok ? vals[i] : 0;
-        const int d = (int)((key >> shift) & 0xFF);
+        const int d = (int)((k[c] >> shift) & 0xFF);
         uint64_t peers = __ballot(ok);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -133,15 +178,24 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
             peers &= ((d >> b) & 1) ? bal : ~bal;
         }
         const int before = __popcll(peers & lt);
-        uint64_t pos = 0;
-        if (ok) pos = wbase[wave][d] + (uint64_t)before;
+        uint32_t slot = 0;
+        if (ok) slot = whist[wave][d] + (uint32_t)before;
         __builtin_amdgcn_wave_barrier();
-        if (ok && before == 0) wbase[wave][d] += (uint64_t)__popcll(peers);
+        if (ok && before == 0) whist[wave][d] += (uint32_t)__popcll(peers);
         __builtin_amdgcn_wave_barrier();
         if (ok) {
-            okeys[pos] = key;
-            ovals[pos] = val;
+            skey[slot] = k[c];
+            sval[slot] = v[c];
         }
+    }
+    __syncthreads();
+    const int count = (int)((n - tstart) < (int64_t)kSortTile ? (n - tstart) : (int64_t)kSortTile);
+    for (int p = threadIdx.x; p < count; p += kSortThreads) {
+        const uint64_t key = skey[p];
+        const int d = (int)((key >> shift) & 0xFF);
+        const uint64_t pos = gbase[d] + (uint64_t)(p - (int)dstart[d]);
+        okeys[pos] = key;
+        ovals[pos] = sval[p];
     }
 }
 

@@ -33,6 +33,11 @@ constexpr int kWavesPerBlock = 4;
 constexpr int kNeg = -(1 << 28);
 constexpr int kGlobalCap = 65536;
 constexpr int kProfCodes = kAlpha + 1;
+// extensions of at most this many rows and columns keep both sequences whole
+// in the wave's LDS buffer (kWaveLds bytes, also the two rings' home)
+constexpr int kWholeMax = 1024;
+constexpr int kWaveLds = 3 * (kWholeMax + 64);
+static_assert(kWaveLds >= 768, "the rings fit the buffer");
 
 struct Ring {
     int *H, *E, *F;
@@ -302,14 +307,29 @@ __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlan
 // (unsigned)(x - base) < len: x in [base, base + len) with one compare
 __device__ __forceinline__ bool in_range(int x, int base, int len) { return (unsigned)(x - base) < (unsigned)len; }
 
+// WHOLE: both extension sequences fit the wave's LDS buffer whole (at most
+// kWholeMax residues each): ring_a[u] holds the code of row u - 1 times 25
+// (pad codes at 0 and past la) and ring_b[v + 63] the code of column v - 1
+// (pad codes before and after), so every lane's reads stay in the buffer
+// without index masks or refills.  Otherwise both stream through 256-entry
+// rings.
+template <bool WHOLE>
 __device__ Ext extend_reg(const uint8_t *a0, int la, int adir, const uint8_t *b0, int lb, int bdir,
                           const int8_t *sbl, const unsigned *minc, int o, int e, int X, uint16_t *ring_a,
                           uint8_t *ring_b, int lane) {
     const int oe = o + e;
     Stream<uint16_t, kProfCodes> sa{a0, la, adir, ring_a, 0, 0};
     Stream<uint8_t, 1> sb{b0, lb, bdir, ring_b, 0, 0};
-    stream_init(sa, lane);
-    stream_init(sb, lane);
+    if constexpr (WHOLE) {
+        for (int t = lane; t < la + kWave; t += kWave)
+            ring_a[t] = (uint16_t)((t >= 1 && t <= la ? (int)a0[(int64_t)(t - 1) * adir] : kPadCode) * kProfCodes);
+        for (int t = lane; t < lb + kWave; t += kWave)
+            ring_b[t] = (uint8_t)(t >= kWave ? (int)b0[(int64_t)(t - kWave) * bdir] : kPadCode);
+        __builtin_amdgcn_wave_barrier();
+    } else {
+        stream_init(sa, lane);
+        stream_init(sb, lane);
+    }
     // anti-diagonal 0: the anchor in lane 0
     int H1 = lane == 0 ? 0 : kNeg, E1 = kNeg, F1 = kNeg;
     unsigned SH1 = 0u, SE1 = 0u, SF1 = 0u;
@@ -368,10 +388,15 @@ __device__ Ext extend_reg(const uint8_t *a0, int la, int adir, const uint8_t *b0
         const unsigned sHd = VSH;
         VH = rH;
         VSH = rSH;
-        // residues of the diagonal move (ring indices always in range)
-        stream_ensure(sa, hi - 1, lane);
-        stream_ensure(sb, d - lo - 1, lane);
-        const int cab = (int)ring_a[(u - 1) & 255] + (int)ring_b[(v - 1) & 255];  // a * 25 + b
+        // residues of the diagonal move (indices always in range)
+        int cab;  // a * 25 + b
+        if constexpr (WHOLE) {
+            cab = (int)ring_a[u] + (int)ring_b[v + kWave - 1];
+        } else {
+            stream_ensure(sa, hi - 1, lane);
+            stream_ensure(sb, d - lo - 1, lane);
+            cab = (int)ring_a[(u - 1) & 255] + (int)ring_b[(v - 1) & 255];
+        }
         const int sig = sbl[cab];
         const int e_ext = El - e, e_open = Hl - oe;
         const bool ee = e_ext >= e_open;
@@ -452,13 +477,20 @@ __device__ SeedAln align_seed(const uint8_t *a, int la, const uint8_t *b, int lb
         rt = extend<true>(a + pa + k, la - pa - k, 1, b + pb + k, lb - pb - k, 1, sbl, o, e, X, R, lane);
         lf = extend<true>(a + pa - 1, pa, -1, b + pb - 1, pb, -1, sbl, o, e, X, R, lane);
     } else {
-        uint16_t *ring_a = (uint16_t *)rings;  // 256 entries of code * 25
-        uint8_t *ring_b = rings + 512;
-        rt = extend_reg(a + pa + k, la - pa - k, 1, b + pb + k, lb - pb - k, 1, sbl, minc, o, e, X, ring_a, ring_b,
-                        lane);
-        lf = rt.overflow ? rt
-                         : extend_reg(a + pa - 1, pa, -1, b + pb - 1, pb, -1, sbl, minc, o, e, X, ring_a, ring_b,
-                                      lane);
+        // whole sequences: kWholeMax + 64 entries of code * 25, then as many
+        // codes; rings: 256 entries of code * 25, then 256 codes
+        uint16_t *ring_a = (uint16_t *)rings;
+        uint8_t *whole_b = rings + 2 * (kWholeMax + kWave), *ring_b = rings + 512;
+        const int ra = la - pa - k, rb = lb - pb - k;
+        rt = ra <= kWholeMax && rb <= kWholeMax
+                 ? extend_reg<true>(a + pa + k, ra, 1, b + pb + k, rb, 1, sbl, minc, o, e, X, ring_a, whole_b, lane)
+                 : extend_reg<false>(a + pa + k, ra, 1, b + pb + k, rb, 1, sbl, minc, o, e, X, ring_a, ring_b, lane);
+        if (rt.overflow)
+            lf = rt;
+        else if (pa <= kWholeMax && pb <= kWholeMax)
+            lf = extend_reg<true>(a + pa - 1, pa, -1, b + pb - 1, pb, -1, sbl, minc, o, e, X, ring_a, whole_b, lane);
+        else
+            lf = extend_reg<false>(a + pa - 1, pa, -1, b + pb - 1, pb, -1, sbl, minc, o, e, X, ring_a, ring_b, lane);
     }
     SeedAln s;
     s.score = lf.score + sc + rt.score;
@@ -496,7 +528,7 @@ __global__ __launch_bounds__(256) void xd_kernel(const uint8_t *__restrict__ cod
         sbl[t] = blosum[t];
         minc[t] = t / kProfCodes == t % kProfCodes ? 0x10001u : 1u;
     }
-    __shared__ __align__(16) uint8_t lds_rings[GLOBAL ? 1 : kWavesPerBlock * 768];
+    __shared__ __align__(16) uint8_t lds_rings[GLOBAL ? 1 : kWavesPerBlock * kWaveLds];
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int64_t gwave = (int64_t)blockIdx.x * kWavesPerBlock + wave;
@@ -512,7 +544,7 @@ __global__ __launch_bounds__(256) void xd_kernel(const uint8_t *__restrict__ cod
         R.SE = (unsigned *)(base + 12 * R.cap);
         R.SF = (unsigned *)(base + 15 * R.cap);
     } else {
-        rings = lds_rings + wave * 768;
+        rings = lds_rings + wave * kWaveLds;
     }
     const int64_t count = GLOBAL ? (int64_t)*n_redo : npairs;
     unsigned long long my_cells = 0;

@@ -496,6 +496,7 @@ def main():
         ctx.set_tuning(**{k: int(v) for k, v in knobs.items()})
         tuning = dict(ctx.get_tuning(), source="--schedule")
     elif not args.no_autotune:
+        note(f"tuning the schedule on a sample of up to {args.tune_pairs} candidates")
         t0 = time.perf_counter()
         tuning = ctx.autotune(res, off, max_pairs=args.tune_pairs)
         torch.cuda.synchronize()

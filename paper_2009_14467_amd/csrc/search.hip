@@ -835,6 +835,11 @@ pastis_status pastis_autotune(pastis_ctx *ctx, const uint8_t *residues, const in
             };
             double all_ms = 0;
             PASTIS_TRY(time_all(&all_ms));
+            // at most about 8 more runs: skipped where one takes over 2 s
+            if (all_ms > 2000.0) {
+                if (out) *out = ctx->tune;
+                return PASTIS_OK;
+            }
             PASTIS_TRY(time_all(&all_ms));
             auto refine = [&](int32_t *knob, const int *vals, int nv) -> pastis_status {
                 const int32_t keep = *knob;

@@ -449,8 +449,9 @@ pastis_status pastis_set_tuning(pastis_ctx *ctx, const pastis_tuning *t);
  * whose effect lies in the tails of the launches, which shrink with the
  * sample (start-bound routing: 25, 50, 75, 100; inter- vs intra-pair mode;
  * the long bins' grid), are then timed once more per value on all the
- * candidates, where a 0.5% margin applies (skipped when one alignment of all
- * the candidates takes over 2 s).  The discovery's candidates stay in ctx. */
+ * candidates, where a 0.5% margin applies (skipped for sets of over 2^26
+ * candidates, or when one alignment of all of them takes over 2 s).  The
+ * discovery's candidates stay in ctx. */
 pastis_status pastis_autotune(pastis_ctx *ctx, const uint8_t *residues, const int64_t *offsets, int64_t n,
                               int input_on_device, int64_t max_pairs, void *stream, pastis_tuning *out);
 

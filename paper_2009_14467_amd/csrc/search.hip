@@ -817,8 +817,9 @@ pastis_status pastis_autotune(pastis_ctx *ctx, const uint8_t *residues, const in
         // and all 8.9M candidates run 1% faster at 75%.  One warm-up run at
         // the full size, then one run per value; a value replaces the one in
         // force when at least 0.5% faster (whole-set runs vary less than
-        // sample runs).
-        if (m < nc) {
+        // sample runs).  Sets of over 2^26 candidates (3 GB of records) are
+        // not refined.
+        if (m < nc && nc <= ((int64_t)1 << 26)) {
             pastis_pair_record *rec_all = nullptr;
             PASTIS_TRY(get(ctx, kDTuneRec, nc, &rec_all));
             const uint32_t *cs1 = (const uint32_t *)ctx->buf[kBufCandS1].ptr;

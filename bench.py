@@ -55,16 +55,16 @@ ALGO_OPS_PER_XD_CELL = 12
 # workload and kernel (a strip bin's two launches: their sum), and only for
 # kernels unchanged since those counters were taken
 MEASURED_TRAFFIC_KIB = {
-    ("large", "sw16s_pass1_kernel<32, 9, 4> + sw16s_pass1_kernel<32, 10, 4>"): (690921.8, 61408.1),
-    ("large", "sw16s_pass1_kernel<32, 11, 4> + sw16s_pass1_kernel<32, 12, 4>"): (547528.0, 46008.4),
-    ("large", "sw16s_pass1_kernel<32, 13, 4> + sw16s_pass1_kernel<32, 14, 4>"): (455427.8, 36399.1),
-    ("large", "sw16s_pass1_kernel<32, 15, 4> + sw16s_pass1_kernel<32, 16, 4>"): (338204.5, 25847.9),
-    ("mid", "sw16s_pass1_kernel<32, 9, 4> + sw16s_pass1_kernel<32, 10, 4>"): (1448538.3, 152318.8),
-    ("mid", "sw16s_pass1_kernel<32, 11, 4> + sw16s_pass1_kernel<32, 12, 4>"): (1247457.2, 129179.6),
-    ("mid", "sw16s_pass1_kernel<32, 13, 4> + sw16s_pass1_kernel<32, 14, 4>"): (963765.3, 99901.9),
-    ("mid", "sw16s_pass1_kernel<32, 15, 4> + sw16s_pass1_kernel<32, 16, 4>"): (720340.5, 75905.5),
-    ("mid", "sw16_pass1_kernel<9, 2, false>"): (599016.3, 65330.9),
-    ("mid", "sw16_pass1_kernel<10, 2, false>"): (348997.0, 40725.4),
+    ("large", "sw16s_pass1_kernel<32, 9, 4> + sw16s_pass1_kernel<32, 10, 4>"): (690858.6, 61411.7),
+    ("large", "sw16s_pass1_kernel<32, 11, 4> + sw16s_pass1_kernel<32, 12, 4>"): (547507.7, 46009.6),
+    ("large", "sw16s_pass1_kernel<32, 13, 4> + sw16s_pass1_kernel<32, 14, 4>"): (455684.8, 36387.2),
+    ("large", "sw16s_pass1_kernel<32, 15, 4> + sw16s_pass1_kernel<32, 16, 4>"): (338121.6, 25849.5),
+    ("mid", "sw16s_pass1_kernel<32, 9, 4> + sw16s_pass1_kernel<32, 10, 4>"): (1448426.2, 152314.0),
+    ("mid", "sw16s_pass1_kernel<32, 11, 4> + sw16s_pass1_kernel<32, 12, 4>"): (1247509.3, 129182.3),
+    ("mid", "sw16s_pass1_kernel<32, 13, 4> + sw16s_pass1_kernel<32, 14, 4>"): (963776.0, 99906.1),
+    ("mid", "sw16s_pass1_kernel<32, 15, 4> + sw16s_pass1_kernel<32, 16, 4>"): (720457.1, 75910.6),
+    ("mid", "sw16_pass1_kernel<9, 2, false>"): (599028.2, 65327.9),
+    ("mid", "sw16_pass1_kernel<10, 2, false>"): (348941.0, 40720.7),
 }
 # the same counters for the kernels of the sparse-product stage (one launch of
 # each per step): the row scan that sizes each row's table, the headed
@@ -75,22 +75,22 @@ MEASURED_TRAFFIC_KIB = {
 # entries' posting lengths, so on large the row scan reads rows only; the
 # substitute rows of mid still read each entry's header.
 SPGEMM_TRAFFIC_KIB = {
-    "large": {"work_kernel": (168185.5, 2846.8),
-              "posting_records_kernel": (507980.1, 957224.5),
-              "spgemm_lds_kernel<2048, 1024>": (3272292.0, 1548512.7),
-              "spgemm_lds_kernel<4096, 2048>": (3412265.7, 1717051.6),
-              "spgemm_lds_kernel<8192, 3072>": (1335208.7, 687771.6),
-              "spgemm_lds_kernel<16384, 2048>": (166640.3, 89087.3),
-              "spgemm_lds_kernel<32768, 4096>": (6702.5, 3697.2),
-              "spgemm_global_kernel": (22.9, 131072.0)},
-    "mid": {"work_kernel": (11050645.5, 4945.4),
-            "posting_records_kernel": (114681.5, 240936.1),
-            "spgemm_lds_kernel<2048, 1024>": (189618.7, 47680.3),
-            "spgemm_lds_kernel<4096, 2048>": (1782295.7, 507212.2),
-            "spgemm_lds_kernel<8192, 3072>": (5915061.0, 2196867.1),
-            "spgemm_lds_kernel<16384, 2048>": (5803903.4, 2948258.8),
-            "spgemm_lds_kernel<32768, 4096>": (2212431.1, 1422611.3),
-            "spgemm_global_kernel": (1748012.2, 1480848.1)},
+    "large": {"work_kernel": (168184.7, 2846.7),
+              "posting_records_kernel": (507979.7, 957138.4),
+              "spgemm_lds_kernel<2048, 1024>": (3272152.0, 1548491.2),
+              "spgemm_lds_kernel<4096, 2048>": (3412106.8, 1716966.8),
+              "spgemm_lds_kernel<8192, 3072>": (1335173.5, 687799.4),
+              "spgemm_lds_kernel<16384, 2048>": (166611.3, 89088.7),
+              "spgemm_lds_kernel<32768, 4096>": (6703.3, 3697.6),
+              "spgemm_global_kernel": (23.3, 131072.0)},
+    "mid": {"work_kernel": (10991613.1, 3746.7),
+            "posting_records_kernel": (114679.5, 241049.4),
+            "spgemm_lds_kernel<2048, 1024>": (189456.2, 47655.7),
+            "spgemm_lds_kernel<4096, 2048>": (1779433.5, 507194.9),
+            "spgemm_lds_kernel<8192, 3072>": (5913474.1, 2197085.2),
+            "spgemm_lds_kernel<16384, 2048>": (5810882.0, 2948496.0),
+            "spgemm_lds_kernel<32768, 4096>": (2212974.0, 1422669.8),
+            "spgemm_global_kernel": (1747741.1, 1480869.8)},
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 

@@ -514,8 +514,12 @@ __device__ __forceinline__ bool passes(const SeedAln &s, int la, int id_pct, int
 // GLOBAL = false: every pair of [0, npairs), LDS ring; pairs whose band
 // outgrows it are listed in redo[] and left for GLOBAL = true, which walks
 // that list with rings in global memory.
+// The register band asks for eight waves per SIMD (at most 64 registers):
+// its per-anti-diagonal chain of LDS reads (residues, then score and
+// statistics increment) needs the other waves to hide it (0.82 s at six
+// waves per SIMD against 0.74 s at eight on the large workload).
 template <bool GLOBAL>
-__global__ __launch_bounds__(256) void xd_kernel(const uint8_t *__restrict__ codes, const PairDesc *__restrict__ pairs,
+__global__ __launch_bounds__(256, GLOBAL ? 1 : 8) void xd_kernel(const uint8_t *__restrict__ codes, const PairDesc *__restrict__ pairs,
                                                  int64_t npairs, const int8_t *__restrict__ blosum, int k, int o, int e,
                                                  int X, int id_pct, int cov_pct, pastis_pair_record *__restrict__ out,
                                                  uint32_t *__restrict__ redo, uint32_t *__restrict__ n_redo,

@@ -102,7 +102,23 @@ typedef struct pastis_params {
                                  entries, else the last call's count plus a quarter); a
                                  discovery that needs more is redone once with room for
                                  all of its entries.  >= 0 */
-    int32_t reserved[4];      /* must be zero */
+    int32_t block_entries;    /* pastis_search only: the most directional candidate
+                                 entries one row block of the discovery may hold (0: the
+                                 2^32 - 16 that 32-bit indices allow).  A block is the set
+                                 of pairs whose lower sequence index falls in a range;
+                                 the search starts with one block of every sequence and
+                                 halves a block whose entries exceed this, then discovers,
+                                 aligns and cuts the blocks one after the other, so the
+                                 discovery's memory follows one block's entries (24 bytes
+                                 each, plus the sort's second buffer) and the edges are
+                                 the same as in one block.  A block of one sequence that
+                                 still exceeds it fails with PASTIS_E_CAPACITY.  With
+                                 several blocks, pastis_candidates_copy has nothing to
+                                 copy after the search (PASTIS_E_STATE).  The
+                                 substitute product runs every row from a block's first
+                                 sequence on, once per block.  >= 0 (the future work of
+                                 Section VII: B formed, aligned and freed in parts) */
+    int32_t reserved[3];      /* must be zero */
 } pastis_params;
 
 /* One similarity edge, 48 bytes.  i < j; edges are sorted by (i, j).

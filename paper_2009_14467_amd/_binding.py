@@ -83,7 +83,8 @@ class _Params(ctypes.Structure):
         ("filter_mode", ctypes.c_int32),
         ("graph_mode", ctypes.c_int32),
         ("candidate_room", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("block_entries", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -184,6 +185,7 @@ class Params:
     filter_mode: str = "none"  # "none" | "mlp" (the learned filter, set with Context.mlp_set)
     graph_mode: bool = False  # replay the alignment stage as a captured HIP graph
     candidate_room: int = 0  # initial room for directional candidates (0: automatic)
+    block_entries: int = 0  # search: most directional entries per row block (0: the 32-bit limit)
 
     def to_c(self) -> _Params:
         p = _Params()
@@ -203,6 +205,7 @@ class Params:
         p.filter_mode = {"none": 0, "mlp": 1}[self.filter_mode]
         p.graph_mode = int(self.graph_mode)
         p.candidate_room = self.candidate_room
+        p.block_entries = self.block_entries
         return p
 
 

@@ -145,7 +145,8 @@ pastis_status validate(const pastis_params *p, std::string &why) {
     if (p->filter_mode != 0 && p->filter_mode != 1) return why = "filter_mode must be 0 or 1", PASTIS_E_INVAL;
     if (p->graph_mode != 0 && p->graph_mode != 1) return why = "graph_mode must be 0 or 1", PASTIS_E_INVAL;
     if (p->candidate_room < 0) return why = "candidate_room must be >= 0", PASTIS_E_INVAL;
-    for (int t = 0; t < 4; ++t)
+    if (p->block_entries < 0) return why = "block_entries must be >= 0", PASTIS_E_INVAL;
+    for (int t = 0; t < 3; ++t)
         if (p->reserved[t] != 0) return why = "reserved fields must be zero", PASTIS_E_INVAL;
     return PASTIS_OK;
 }

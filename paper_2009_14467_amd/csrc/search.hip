@@ -4,6 +4,8 @@
 // the discovery stage and the result handle.
 #include <algorithm>
 #include <chrono>
+#include <utility>
+#include <vector>
 
 #include "internal.hpp"
 #include "kmers.hpp"
@@ -183,9 +185,24 @@ __global__ void sum_u32_kernel(const uint32_t *__restrict__ a, int64_t n, unsign
     if ((threadIdx.x & 63) == 0 && acc) atomicAdd(out, acc);
 }
 
-// Discovery: candidates into kDCand*; returns their count.
-pastis_status discover(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, int64_t n, hipStream_t s,
-                       int64_t *n_cand_out) {
+// Directional entries are indexed with 32 bits downstream.
+constexpr uint64_t kMaxDir = 0xFFFFFFF0ull;
+
+// What the sparse product of every row block reads: the k-mer tables and,
+// with substitutes, the rows of A S.  Built once per call; sp.kt points at kt.
+struct DiscTables {
+    KmerTables kt;
+    SpgemmArgs sp{};
+    int64_t nnz = 0, nu = 0;
+    size_t temp_bytes = 0;  // the k-mer stage's temporary buffer (kDTemp)
+    DiscTables() = default;
+    DiscTables(const DiscTables &) = delete;
+    DiscTables &operator=(const DiscTables &) = delete;
+};
+
+// Discovery, first part: k-mers, and S and A S with substitutes.
+pastis_status discover_tables(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, int64_t n, hipStream_t s,
+                              DiscTables &dt) {
     const pastis_params &P = ctx->params;
     const int64_t m = st.n_res;
     const bool subs = P.n_subs > 0;
@@ -197,7 +214,7 @@ pastis_status discover(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, 
 
     // ---- k-mers
     HIP_TRY(ctx, stage_begin(ctx, kStKmers, s), "event");
-    KmerTables kt;
+    KmerTables &kt = dt.kt;
     PASTIS_TRY(get(ctx, kDKCounts, 4, &kt.counts));
     PASTIS_TRY(get(ctx, kDPostSeq, m, &kt.post_seq));
     PASTIS_TRY(get(ctx, kDPostPos, m, &kt.post_pos));
@@ -217,16 +234,19 @@ pastis_status discover(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, 
     const bool dense_map = subs && P.k <= kDenseMapMaxK;  // longer k-mers: binary search of the distinct ids
     if (dense_map) PASTIS_TRY(get(ctx, kDKmap, (size_t)kmap_entries(P.k), &kt.kmap));
     char *temp = nullptr;
-    PASTIS_TRY(get(ctx, kDTemp, kmers_temp_bytes(m, n), &temp));
+    dt.temp_bytes = kmers_temp_bytes(m, n);
+    PASTIS_TRY(get(ctx, kDTemp, dt.temp_bytes, &temp));
     HIP_TRY(ctx, build_kmers(codes, st.d_off, n, m, P.k, dense_map, kt, temp, s), "k-mer kernels");
     HIP_TRY(ctx, stage_end(ctx, kStKmers, s), "event");
     uint32_t kc[4];
     PASTIS_TRY(read_device(ctx, kt.counts, kc, sizeof(kc), s));
     const int64_t nnz = kc[0], nu = kc[1];
+    dt.nnz = nnz;
+    dt.nu = nu;
     ctx->stats.n_kmers = nnz;
 
     // ---- substitute rows and A S
-    SpgemmArgs sp{};
+    SpgemmArgs &sp = dt.sp;
     sp.kt = &kt;
     sp.n = n;
     sp.ck = P.ck_min;
@@ -297,6 +317,25 @@ pastis_status discover(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, 
         sp.ent_len = kt.row_len;
         sp.ent_pos16 = kt.row_pos;
     }
+    return PASTIS_OK;
+}
+
+// Discovery, second part: the candidate pairs (lo, hi) with r0 <= lo < r1
+// into kBufCand*, sorted by (lo, hi); their count in *n_cand_out.  A block
+// whose directional entries would exceed `limit` sets *split (when it may
+// be split and holds more than one sequence) and produces nothing; otherwise
+// such a block fails with PASTIS_E_CAPACITY.
+pastis_status discover_block(pastis_ctx *ctx, DiscTables &dt, int64_t n, int64_t r0, int64_t r1, uint64_t limit,
+                             bool may_split, hipStream_t s, int64_t *n_cand_out, bool *split) {
+    const pastis_params &P = ctx->params;
+    Misc M;
+    PASTIS_TRY(misc(ctx, M));
+    const int64_t nnz = dt.nnz, nu = dt.nu;
+    SpgemmArgs sp = dt.sp;
+    sp.kt = &dt.kt;
+    sp.blk_lo = (uint32_t)r0;
+    sp.blk_hi = (uint32_t)r1;
+    if (split) *split = false;
 
     // ---- sparse product
     HIP_TRY(ctx, stage_begin(ctx, kStSpgemm, s), "event");
@@ -333,8 +372,8 @@ pastis_status discover(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, 
     uint64_t want = std::max<uint64_t>({(uint64_t)4 * n, 1ull << 20, ctx->last_n_dir + ctx->last_n_dir / 4});
     if (dir_ub <= (1ull << 28)) want = std::max(want, dir_ub);
     if (P.candidate_room > 0) want = (uint64_t)P.candidate_room;  // the caller's setting
-    constexpr uint64_t kMaxDir = 0xFFFFFFF0ull;  // entries are indexed with 32 bits downstream
-    uint32_t cap = (uint32_t)std::min<uint64_t>({want, dir_ub, kMaxDir});
+    limit = std::min(limit, kMaxDir);
+    uint32_t cap = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>({want, dir_ub, limit}));
     for (int attempt = 0;; ++attempt) {
         sp.cap = cap;
         PASTIS_TRY(get(ctx, kDDirKey, cap, &sp.d_key));
@@ -351,15 +390,21 @@ pastis_status discover(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, 
         PASTIS_TRY(read_device(ctx, M.d_overflow, &ovf, sizeof(ovf), s));
         if (!ovf) break;
         // the 64-bit counter holds every entry the run asked for, so one redo
-        // with that much room succeeds; a count beyond 32-bit indexing cannot
+        // with that much room succeeds; a count beyond the limit cannot
         unsigned long long need = 0;
         PASTIS_TRY(read_device(ctx, M.d_count, &need, sizeof(need), s));
-        if (need > kMaxDir || attempt >= 2)
+        if (need > limit && may_split && r1 - r0 > 1) {
+            HIP_TRY(ctx, stage_end(ctx, kStSpgemm, s), "event");
+            *split = true;
+            *n_cand_out = 0;
+            return PASTIS_OK;
+        }
+        if (need > limit || attempt >= 2)
             return set_error(ctx, PASTIS_E_CAPACITY,
                              "candidate discovery produced " + std::to_string(need) +
-                                 " directional entries; at most " + std::to_string(kMaxDir) +
-                                 " fit one call (split the sequences or raise ck_min)");
-        cap = (uint32_t)std::min<uint64_t>(need + need / 4 + 1024, kMaxDir);
+                                 " directional entries; at most " + std::to_string(limit) +
+                                 " fit one block (raise block_entries or ck_min, or split the sequences)");
+        cap = (uint32_t)std::min<uint64_t>(need + need / 4 + 1024, limit);
         // redo from the planned state: restore the big-row count of the plan
         HIP_TRY(ctx, fill<uint32_t>(sp.n_big, 1, nb0, s), "reset");
     }
@@ -385,7 +430,7 @@ pastis_status discover(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, 
     PASTIS_TRY(get(ctx, kDOpos, n_dir, &sy.opos));
     sy.d_ncand = M.n_cand;
     sy.nbits = sp.nbits;
-    PASTIS_TRY(get(ctx, kDTemp, std::max(kmers_temp_bytes(m, n), radix_temp_bytes(n_dir) + scan_temp_bytes(n_dir)),
+    PASTIS_TRY(get(ctx, kDTemp, std::max(dt.temp_bytes, radix_temp_bytes(n_dir) + scan_temp_bytes(n_dir)),
                    (char **)&sy.sort_temp));
     PASTIS_TRY(get(ctx, kBufCandLo, n_dir, &sy.out.lo));
     PASTIS_TRY(get(ctx, kBufCandHi, n_dir, &sy.out.hi));
@@ -406,6 +451,61 @@ pastis_status discover(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, 
     ctx->n_seqs_last = n;
     ctx->have_candidates = true;
     return PASTIS_OK;
+}
+
+// Discovery of every candidate pair at once.
+pastis_status discover(pastis_ctx *ctx, const Staged &st, const uint8_t *codes, int64_t n, hipStream_t s,
+                       int64_t *n_cand_out) {
+    DiscTables dt;
+    PASTIS_TRY(discover_tables(ctx, st, codes, n, s, dt));
+    return discover_block(ctx, dt, n, 0, n, kMaxDir, false, s, n_cand_out, nullptr);
+}
+
+// Counts of one row block that a search in several blocks adds up (stage
+// times add up in ms_stage by themselves; per-bin shapes are the same in
+// every block).
+using StatCount = int64_t pastis_run_stats::*;
+constexpr StatCount kBlockCounts[] = {
+    &pastis_run_stats::n_candidates,     &pastis_run_stats::n_aligned,        &pastis_run_stats::n_edges,
+    &pastis_run_stats::cells,            &pastis_run_stats::stats_pass_pairs, &pastis_run_stats::int32_pairs,
+    &pastis_run_stats::bound_pass_pairs, &pastis_run_stats::bound_pass_cells, &pastis_run_stats::stats_pass_cells,
+    &pastis_run_stats::spgemm_products};
+
+void clear_block_stats(pastis_run_stats &b) {
+    for (StatCount m : kBlockCounts) b.*m = 0;
+    for (int i = 0; i < 32; ++i) {
+        b.sw_bin_pairs[i] = 0;
+        b.sw_bin_cells[i] = 0;
+        b.sw_bin_ms[i] = 0.0;
+    }
+}
+
+void add_block_stats(pastis_run_stats &acc, const pastis_run_stats &b) {
+    for (StatCount m : kBlockCounts) acc.*m += b.*m;
+    acc.sw_bins = b.sw_bins;
+    acc.sw_graph = b.sw_graph;
+    for (int i = 0; i < 32; ++i) {
+        acc.sw_bin_rows[i] = b.sw_bin_rows[i];
+        acc.sw_bin_multi[i] = b.sw_bin_multi[i];
+        acc.sw_bin_bits[i] = b.sw_bin_bits[i];
+        acc.sw_bin_pairs[i] += b.sw_bin_pairs[i];
+        acc.sw_bin_cells[i] += b.sw_bin_cells[i];
+        acc.sw_bin_ms[i] += b.sw_bin_ms[i];
+    }
+}
+
+void set_block_stats(pastis_run_stats &dst, const pastis_run_stats &acc) {
+    for (StatCount m : kBlockCounts) dst.*m = acc.*m;
+    dst.sw_bins = acc.sw_bins;
+    dst.sw_graph = acc.sw_graph;
+    for (int i = 0; i < 32; ++i) {
+        dst.sw_bin_rows[i] = acc.sw_bin_rows[i];
+        dst.sw_bin_multi[i] = acc.sw_bin_multi[i];
+        dst.sw_bin_bits[i] = acc.sw_bin_bits[i];
+        dst.sw_bin_pairs[i] = acc.sw_bin_pairs[i];
+        dst.sw_bin_cells[i] = acc.sw_bin_cells[i];
+        dst.sw_bin_ms[i] = acc.sw_bin_ms[i];
+    }
 }
 
 pastis_status begin_call(pastis_ctx *ctx) {
@@ -554,55 +654,112 @@ pastis_status pastis_search(pastis_ctx *ctx, const uint8_t *residues, const int6
     Staged st;
     uint8_t *codes = nullptr;
     PASTIS_TRY(stage_and_encode(ctx, residues, offsets, n, input_on_device, s, st, &codes));
-    int64_t nc = 0;
-    PASTIS_TRY(discover(ctx, st, codes, n, s, &nc));
-    if (ctx->params.filter_mode == 1) {
-        PASTIS_TRY(mlp_filter_candidates(ctx, st, codes, n, s));
-        nc = ctx->n_candidates;
-    }
-    pastis_pair_record *rec = nullptr;
-    PASTIS_TRY(align_candidates(ctx, st, codes, n, s, &rec));
-    // edges
+    DiscTables dt;
+    PASTIS_TRY(discover_tables(ctx, st, codes, n, s, dt));
     Misc M;
     PASTIS_TRY(misc(ctx, M));
-    HIP_TRY(ctx, stage_begin(ctx, kStFilter, s), "event");
-    uint8_t *flag = nullptr;
-    uint32_t *pos = nullptr;
-    PASTIS_TRY(get(ctx, kDEdgeFlag, nc, &flag));
-    PASTIS_TRY(get(ctx, kDEdgePos, nc, &pos));
-    char *temp = nullptr;
-    PASTIS_TRY(get(ctx, kDTemp, scan_temp_bytes(nc) + 4096, &temp));
     const int ns = ctx->params.weight_mode == PASTIS_WEIGHT_NS;
-    if (nc > 0) {
-        edge_flag_kernel<<<grid_for(nc), 256, 0, s>>>(rec, nc, ns, flag);
-        HIP_TRY(ctx, hipGetLastError(), "edge kernel");
+    const uint64_t limit = ctx->params.block_entries > 0 ? (uint64_t)ctx->params.block_entries : kMaxDir;
+    // Row blocks (the pairs whose lower index falls in [r0, r1)), the next
+    // one last.  A block whose discovery would exceed the limit is halved;
+    // blocks run in order of r0, so their edges, each sorted, concatenate
+    // into the sorted edge list.
+    std::vector<std::pair<int64_t, int64_t>> todo{{0, n}};
+    struct Parts {
+        std::vector<std::pair<pastis_edge *, int64_t>> v;
+        ~Parts() {
+            for (auto &p : v)
+                if (p.first) (void)hipFree(p.first);
+        }
+    } parts;
+    pastis_run_stats acc{};
+    int64_t n_edges = 0;
+    while (!todo.empty()) {
+        const std::pair<int64_t, int64_t> blk = todo.back();
+        todo.pop_back();
+        clear_block_stats(ctx->stats);
+        int64_t nc = 0;
+        bool split = false;
+        PASTIS_TRY(discover_block(ctx, dt, n, blk.first, blk.second, limit, true, s, &nc, &split));
+        if (split) {
+            const int64_t mid = blk.first + (blk.second - blk.first) / 2;
+            todo.push_back({mid, blk.second});
+            todo.push_back({blk.first, mid});
+            continue;
+        }
+        if (ctx->params.filter_mode == 1) {
+            PASTIS_TRY(mlp_filter_candidates(ctx, st, codes, n, s));
+            nc = ctx->n_candidates;
+        }
+        pastis_pair_record *rec = nullptr;
+        PASTIS_TRY(align_candidates(ctx, st, codes, n, s, &rec));
+        // edges
+        HIP_TRY(ctx, stage_begin(ctx, kStFilter, s), "event");
+        uint8_t *flag = nullptr;
+        uint32_t *pos = nullptr;
+        PASTIS_TRY(get(ctx, kDEdgeFlag, nc, &flag));
+        PASTIS_TRY(get(ctx, kDEdgePos, nc, &pos));
+        char *temp = nullptr;
+        PASTIS_TRY(get(ctx, kDTemp, std::max(dt.temp_bytes, scan_temp_bytes(nc) + 4096), &temp));
+        if (nc > 0) {
+            edge_flag_kernel<<<grid_for(nc), 256, 0, s>>>(rec, nc, ns, flag);
+            HIP_TRY(ctx, hipGetLastError(), "edge kernel");
+        }
+        HIP_TRY(ctx, (exclusive_scan<uint8_t, uint32_t>(flag, nc, pos, M.n_edges, temp, s)), "scan");
+        uint32_t ne = 0;
+        PASTIS_TRY(read_device(ctx, M.n_edges, &ne, sizeof(ne), s));
+        pastis_edge *d = nullptr;
+        if (ne > 0) {
+            if (hipMalloc(&d, sizeof(pastis_edge) * ne) != hipSuccess) {
+                (void)hipGetLastError();
+                return set_error(ctx, PASTIS_E_NOMEM, "edge allocation failed");
+            }
+            parts.v.push_back({d, (int64_t)ne});
+            edge_write_kernel<<<grid_for(nc), 256, 0, s>>>(
+                rec, flag, pos, nc, (const uint32_t *)ctx->buf[kBufCandLo].ptr,
+                (const uint32_t *)ctx->buf[kBufCandHi].ptr, (const uint32_t *)ctx->buf[kBufCandCnt].ptr, st.d_off, ns,
+                d);
+            HIP_TRY(ctx, hipGetLastError(), "edge kernel");
+        }
+        HIP_TRY(ctx, stage_end(ctx, kStFilter, s), "event");
+        HIP_TRY(ctx, stage_collect(ctx, s), "sync");
+        ctx->stats.n_edges = ne;
+        n_edges += ne;
+        add_block_stats(acc, ctx->stats);
+        // the candidate buffers keep only the last block's pairs
+        if (blk.first > 0 || blk.second < n) ctx->have_candidates = false;
     }
-    HIP_TRY(ctx, (exclusive_scan<uint8_t, uint32_t>(flag, nc, pos, M.n_edges, temp, s)), "scan");
-    uint32_t ne = 0;
-    PASTIS_TRY(read_device(ctx, M.n_edges, &ne, sizeof(ne), s));
+    set_block_stats(ctx->stats, acc);
     pastis_result *res = new pastis_result();
     res->device = ctx->device;
-    res->n = ne;
-    if (ne > 0) {
-        if (hipMalloc(&res->d_edges, sizeof(pastis_edge) * ne) != hipSuccess) {
+    res->n = n_edges;
+    if (parts.v.size() == 1) {
+        res->d_edges = parts.v[0].first;
+        parts.v[0].first = nullptr;
+    } else if (n_edges > 0) {
+        if (hipMalloc(&res->d_edges, sizeof(pastis_edge) * n_edges) != hipSuccess) {
             (void)hipGetLastError();
             delete res;
             return set_error(ctx, PASTIS_E_NOMEM, "edge allocation failed");
         }
-        edge_write_kernel<<<grid_for(nc), 256, 0, s>>>(rec, flag, pos, nc, (const uint32_t *)ctx->buf[kBufCandLo].ptr,
-                                                        (const uint32_t *)ctx->buf[kBufCandHi].ptr,
-                                                        (const uint32_t *)ctx->buf[kBufCandCnt].ptr, st.d_off, ns,
-                                                        res->d_edges);
-        hipError_t e = hipGetLastError();
+        int64_t at = 0;
+        for (auto &p : parts.v) {
+            const hipError_t e = hipMemcpyAsync(res->d_edges + at, p.first, sizeof(pastis_edge) * p.second,
+                                                hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) {
+                (void)hipFree(res->d_edges);
+                delete res;
+                return hip_error(ctx, e, "copy");
+            }
+            at += p.second;
+        }
+        const hipError_t e = hipStreamSynchronize(s);  // before the parts are freed
         if (e != hipSuccess) {
             (void)hipFree(res->d_edges);
             delete res;
-            return hip_error(ctx, e, "edge kernel");
+            return hip_error(ctx, e, "sync");
         }
     }
-    HIP_TRY(ctx, stage_end(ctx, kStFilter, s), "event");
-    HIP_TRY(ctx, stage_collect(ctx, s), "sync");
-    ctx->stats.n_edges = ne;
     ctx->stats.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     *out = res;
     return PASTIS_OK;

@@ -56,6 +56,19 @@ struct RowView {
     const uint32_t *ent_dp;     // substitutes: ((d + 128) << 16) | pos
     int exact;
     const uint32_t *ent_len;    // exact: the posting length of each entry (else read from the header)
+    // row block: only pairs whose lower index lies in [blk_lo, blk_hi) are kept
+    uint32_t blk_lo, blk_hi;
+
+    // a product (i, j) that names no pair of this block: the diagonal, the
+    // lower triangle of the (symmetric) exact product, or a pair whose lower
+    // index lies outside the block
+    __device__ __forceinline__ bool skip(uint32_t i, uint32_t j) const {
+        const uint32_t lo = i < j ? i : j;
+        return j == i || (exact && j < i) || lo - blk_lo >= blk_hi - blk_lo;
+    }
+    // rows whose products can name a pair of the block: its own rows, and
+    // with substitutes (both directions are counted) every later row too
+    __device__ __forceinline__ bool active(uint32_t i) const { return i >= blk_lo && (!exact || i < blk_hi); }
 
     __device__ __forceinline__ void bounds(uint32_t i, uint64_t &b, uint64_t &e) const {
         if (exact) {
@@ -223,10 +236,9 @@ __global__ __launch_bounds__(kThreads) void spgemm_lds_kernel(RowView rv, Postin
     const XcdWalk it = xcd_walk(starts[bin + 1] - b0);
     for (int64_t t = it.first; t < it.end; t += it.step) {
         const uint32_t i = (uint32_t)idx[b0 + t];
-        const bool exact = rv.exact;
         // phase 1: counts, and each product's slot and seed key staged
         const uint32_t total = expand_row(rv, P, i, L.chunk, [&](uint32_t pi, uint32_t j, uint32_t pj, uint32_t q) {
-            if (j == i || (exact && j < i)) {
+            if (rv.skip(i, j)) {
                 stage[q] = make_uint2(kEmpty, 0u);
                 return;
             }
@@ -339,13 +351,12 @@ __global__ __launch_bounds__(kThreads) void spgemm_global_kernel(RowView rv, Pos
     const uint32_t nrows = *nrows_p;
     for (uint32_t w = blockIdx.x; w < nrows; w += gridDim.x) {
         const uint32_t i = rows[w];
-        const bool exact = rv.exact;
         uint64_t want = 2 * work[i];
         uint32_t rcap = 4096;
         while (rcap < want && rcap < cap) rcap <<= 1;
         const uint32_t mask = rcap - 1;
         expand_row(rv, P, i, C, [&](uint32_t, uint32_t j, uint32_t, uint32_t) {
-            if (j == i || (exact && j < i)) return;
+            if (rv.skip(i, j)) return;
             uint32_t h = hash32(j) & mask;
             for (;;) {
                 unsigned long long v = slot[h];
@@ -382,7 +393,7 @@ __global__ __launch_bounds__(kThreads) void spgemm_global_kernel(RowView rv, Pos
         __syncthreads();
         if (ncand > 0) {
             expand_row(rv, P, i, C, [&](uint32_t pi, uint32_t j, uint32_t pj, uint32_t) {
-                if (j == i || (exact && j < i)) return;
+                if (rv.skip(i, j)) return;
                 uint32_t h = hash32(j) & mask;
                 unsigned long long v = slot[h];
                 while ((uint32_t)(v >> 32) != j) {
@@ -597,6 +608,7 @@ __global__ __launch_bounds__(256) void work_kernel(RowView rv, Postings P, int64
     for (int64_t i = it.first; i < it.end; i += it.step) {
         uint64_t b, e;
         rv.bounds((uint32_t)i, b, e);
+        if (!rv.active((uint32_t)i)) e = b;  // no pair of the block: no products, no bin
         uint64_t w = 0;
         if (rv.ent_len) {
             for (uint64_t x = b + lane; x < e; x += 64) w += rv.ent_len[x];
@@ -728,7 +740,8 @@ hipError_t as_run(const AsArgs &a, uint32_t gcap, hipStream_t s) {
 }
 
 hipError_t spgemm_plan(const SpgemmArgs &a, hipStream_t s) {
-    RowView rv{a.row_start32, a.row_start64, a.row_len, a.ent_s, a.ent_pos16, a.ent_dp, a.exact, a.ent_len};
+    RowView rv{a.row_start32, a.row_start64, a.row_len, a.ent_s, a.ent_pos16, a.ent_dp, a.exact, a.ent_len,
+               a.blk_lo, a.blk_hi};
     Postings P{a.post_rec};
     hipError_t e;
     if ((e = fill<unsigned long long>(a.max_big, 1, 0ull, s)) != hipSuccess) return e;
@@ -744,7 +757,8 @@ hipError_t spgemm_plan(const SpgemmArgs &a, hipStream_t s) {
 }
 
 hipError_t spgemm_run(const SpgemmArgs &a, uint32_t gcap, hipStream_t s) {
-    RowView rv{a.row_start32, a.row_start64, a.row_len, a.ent_s, a.ent_pos16, a.ent_dp, a.exact, a.ent_len};
+    RowView rv{a.row_start32, a.row_start64, a.row_len, a.ent_s, a.ent_pos16, a.ent_dp, a.exact, a.ent_len,
+               a.blk_lo, a.blk_hi};
     Postings P{a.post_rec};
     Emit em{a.d_count, a.d_overflow, a.d_key, a.d_cnt, a.d_s1, a.d_s2, a.d_dir, a.cap, a.nbits};
     hipError_t e;

@@ -54,6 +54,8 @@ struct SpgemmArgs {
     const uint16_t *ent_pos16;
     const uint32_t *ent_dp;
     int64_t n;
+    // row block: the pairs (lo, hi) with blk_lo <= lo < blk_hi ([0, n) for all)
+    uint32_t blk_lo, blk_hi;
     int ck;
     uint64_t *work;
     int8_t *bin_of;

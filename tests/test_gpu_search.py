@@ -133,3 +133,61 @@ def test_graph_mode_replays_match_direct_launches(gpu):
     _compare_edges(graph.search(r2, o2), eager.search(r2, o2))
     assert graph.stats()["sw_graph"] == 1
     _compare_edges(graph.search(res, off), want)
+
+
+ROW_BLOCK_CASES = {
+    "exact-sw": dict(k=6, ck_min=1),
+    "subs-sw": dict(k=6, n_subs=25, ck_min=2),
+    "exact-xd": dict(k=6, ck_min=1, align_mode="xd"),
+    "subs-ns-graph": dict(k=5, n_subs=10, ck_min=2, weight_mode="ns", graph_mode=True),
+}
+
+
+@pytest.mark.parametrize("case", sorted(ROW_BLOCK_CASES))
+def test_row_blocks_give_the_same_edges(gpu, orc, case):
+    """Discovery, alignment and the cut run block by block when the
+    directional entries exceed block_entries (the pairs of a range of lower
+    indices per block, halved until each fits): the same edges, counts and
+    cells as one block, and the oracle's edges."""
+    import paper_2009_14467_amd as P
+    from synth import workload
+
+    s = workload("tiny", n_families=8)
+    res, off = _dev(s.residues, gpu), _dev(s.offsets, gpu)
+    kw = ROW_BLOCK_CASES[case]
+    one = P.Context(P.Params(**kw))
+    want = one.search(res, off)
+    st1 = one.stats()
+    nc = int(st1["n_candidates"])
+    assert nc > 200
+    one.candidates(nc)  # one block keeps its candidates
+    blocks = P.Context(P.Params(block_entries=max(nc // 6, 8), **kw))
+    got = blocks.search(res, off)
+    assert got.tobytes() == want.tobytes()
+    st = blocks.stats()
+    for f in ("n_candidates", "n_aligned", "n_edges", "cells", "stats_pass_pairs", "stats_pass_cells",
+              "bound_pass_pairs", "bound_pass_cells"):
+        assert st[f] == st1[f], f
+    with pytest.raises(P.PastisError) as e:
+        blocks.candidates(nc)  # several blocks: the candidate buffers hold only the last one
+    assert e.value.status == 6  # PASTIS_E_STATE
+    if case == "exact-sw":
+        oracle_kw = {k: v for k, v in kw.items() if k != "align_mode"}
+        _compare_edges(got, orc.search(s.residues, s.offsets, mode="sw", **oracle_kw))
+    # the substitute product of a block counts both directions of its pairs:
+    # a repeat of the blocked search is byte-identical too
+    assert blocks.search(res, off).tobytes() == want.tobytes()
+
+
+def test_row_block_of_one_sequence_over_the_limit_fails(gpu):
+    import paper_2009_14467_amd as P
+    from synth import make_family_set
+
+    s = make_family_set(n_families=2, family_size=4, mean_len=200, min_len=100, max_len=300, divergence=0.2,
+                        stream=91)
+    ctx = P.Context(P.Params(k=4, ck_min=1, block_entries=1))
+    with pytest.raises(P.PastisError) as e:
+        ctx.search(_dev(s.residues, gpu), _dev(s.offsets, gpu))
+    assert e.value.status == 5  # PASTIS_E_CAPACITY
+    with pytest.raises(P.PastisError):
+        P.Context(P.Params(block_entries=-1))

@@ -119,6 +119,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large", choices=["tiny", "mid", "large", "heavy"])
     ap.add_argument("--families", type=int, default=None, help="scale the workload down (tests)")
+    ap.add_argument("--block-entries", type=int, default=0,
+                    help="search in row blocks of at most this many directional candidate entries (0: one block)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-filter leg")
     ap.add_argument("--mlp-epochs", type=int, default=4)
@@ -480,6 +482,8 @@ def main():
     over = {} if args.families is None else {"n_families": args.families}
     fs = workload(args.workload, **over)
     params = dict(WORKLOAD_PARAMS[args.workload])
+    if args.block_entries > 0:
+        params["block_entries"] = args.block_entries
     dev = torch.device("cuda:0")
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)

@@ -249,7 +249,8 @@ constexpr int kDppWaveRor1 = 0x13C;  // lane l receives lane l-1 (lane 0 from 63
 __device__ __forceinline__ int ror1(int v) { return __builtin_amdgcn_mov_dpp(v, kDppWaveRor1, 0xF, 0xF, false); }
 
 // A ring holds residue codes times MUL (T wide enough): the rows' stream
-// keeps code * 25, so a code pair's table index is one add.
+// keeps code * 100 and the columns' code * 4, so one add gives a code pair's
+// byte offset into the 25 x 25 tables of 32-bit entries.
 template <typename T, int MUL>
 struct Stream {
     const uint8_t *p;
@@ -307,24 +308,32 @@ __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlan
 // (unsigned)(x - base) < len: x in [base, base + len) with one compare
 __device__ __forceinline__ bool in_range(int x, int base, int len) { return (unsigned)(x - base) < (unsigned)len; }
 
+// Lane masks of one compare each (a ballot of a computed predicate costs a
+// select and a second compare).  A lane that is not live holds kNeg in H1,
+// below every bound these take, so H1 alone tells live lanes, those above
+// the best score, and those equal to a live maximum.
+__device__ __forceinline__ unsigned long long wave_mask_ne(int x, int y) { return __builtin_amdgcn_sicmp(x, y, 33); }
+__device__ __forceinline__ unsigned long long wave_mask_gt(int x, int y) { return __builtin_amdgcn_sicmp(x, y, 38); }
+__device__ __forceinline__ unsigned long long wave_mask_eq(int x, int y) { return __builtin_amdgcn_sicmp(x, y, 32); }
+
 // WHOLE: both extension sequences fit the wave's LDS buffer whole (at most
-// kWholeMax residues each): ring_a[u] holds the code of row u - 1 times 25
+// kWholeMax residues each): ring_a[u] holds the code of row u - 1 times 100
 // (pad codes at 0 and past la) and ring_b[v + 63] the code of column v - 1
-// (pad codes before and after), so every lane's reads stay in the buffer
+// times 4 (pad codes before and after), so every lane's reads stay in the buffer
 // without index masks or refills.  Otherwise both stream through 256-entry
 // rings.
 template <bool WHOLE>
 __device__ Ext extend_reg(const uint8_t *a0, int la, int adir, const uint8_t *b0, int lb, int bdir,
-                          const int8_t *sbl, const unsigned *minc, int o, int e, int X, uint16_t *ring_a,
+                          const int *sbl4, const unsigned *minc, int o, int e, int X, uint16_t *ring_a,
                           uint8_t *ring_b, int lane) {
     const int oe = o + e;
-    Stream<uint16_t, kProfCodes> sa{a0, la, adir, ring_a, 0, 0};
-    Stream<uint8_t, 1> sb{b0, lb, bdir, ring_b, 0, 0};
+    Stream<uint16_t, 4 * kProfCodes> sa{a0, la, adir, ring_a, 0, 0};
+    Stream<uint8_t, 4> sb{b0, lb, bdir, ring_b, 0, 0};
     if constexpr (WHOLE) {
         for (int t = lane; t < la + kWave; t += kWave)
-            ring_a[t] = (uint16_t)((t >= 1 && t <= la ? (int)a0[(int64_t)(t - 1) * adir] : kPadCode) * kProfCodes);
+            ring_a[t] = (uint16_t)((t >= 1 && t <= la ? (int)a0[(int64_t)(t - 1) * adir] : kPadCode) * 4 * kProfCodes);
         for (int t = lane; t < lb + kWave; t += kWave)
-            ring_b[t] = (uint8_t)(t >= kWave ? (int)b0[(int64_t)(t - kWave) * bdir] : kPadCode);
+            ring_b[t] = (uint8_t)((t >= kWave ? (int)b0[(int64_t)(t - kWave) * bdir] : kPadCode) * 4);
         __builtin_amdgcn_wave_barrier();
     } else {
         stream_init(sa, lane);
@@ -397,7 +406,7 @@ __device__ Ext extend_reg(const uint8_t *a0, int la, int adir, const uint8_t *b0
             stream_ensure(sb, d - lo - 1, lane);
             cab = (int)ring_a[(u - 1) & 255] + (int)ring_b[(v - 1) & 255];
         }
-        const int sig = sbl[cab];
+        const int sig = *(const int *)((const char *)sbl4 + cab);
         const int e_ext = El - e, e_open = Hl - oe;
         const bool ee = e_ext >= e_open;
         const int E_ = max(e_ext, e_open);
@@ -405,7 +414,7 @@ __device__ Ext extend_reg(const uint8_t *a0, int la, int adir, const uint8_t *b0
         const bool fe = f_ext >= f_open;
         const int F_ = max(f_ext, f_open);
         const int D_ = Hd + sig;  // dead predecessors stay far below kNeg / 2
-        const unsigned sD = sHd + minc[cab];
+        const unsigned sD = sHd + *(const unsigned *)((const char *)minc + cab);
         const int H_ = max(D_, max(E_, F_));
         const unsigned sE_ = ee ? SE1 : SH1;
         const unsigned sF_ = fe ? rSF : rSH;
@@ -423,7 +432,7 @@ __device__ Ext extend_reg(const uint8_t *a0, int la, int adir, const uint8_t *b0
         SF1 = sF_;
         // live range and best cell of this anti-diagonal (u = lo + rotated lane)
         const int sh = lo & (kWave - 1);
-        const unsigned long long lm = rotr64(__ballot(live), sh);
+        const unsigned long long lm = rotr64(wave_mask_ne(H1, kNeg), sh);
         c2 = c1;
         n2 = n1;
         l2 = l1;
@@ -433,10 +442,10 @@ __device__ Ext extend_reg(const uint8_t *a0, int la, int adir, const uint8_t *b0
         if (lm == 0ull) break;
         l1 = lo + __ffsll((long long)lm) - 1;
         m1 = lo + 64 - __clzll((long long)lm) - l1;
-        const unsigned long long up = __ballot(live && H_ > best);
+        const unsigned long long up = wave_mask_gt(H1, best);
         if (up != 0ull) {
             const int dbest = wave_max_dpp(live ? H_ : INT_MIN);
-            const unsigned long long hit = rotr64(__ballot(live && H_ == dbest), sh);
+            const unsigned long long hit = rotr64(wave_mask_eq(H1, dbest), sh);
             const int off = __ffsll((long long)hit) - 1;
             best = dbest;
             bu = lo + off;
@@ -459,12 +468,14 @@ struct SeedAln {
     bool overflow;
 };
 
-// GLOBAL = false: the register band (rings: 256 entries of code * 25 as
-// uint16, then 256 codes; minc: the statistics increment of each code pair);
+// GLOBAL = false: the register band (rings: 256 entries of code * 100 as
+// uint16, then 256 of code * 4; sbl4 and minc: the score and the statistics
+// increment of each code pair, 32-bit);
 // GLOBAL = true: the ring in global memory.
 template <bool GLOBAL>
 __device__ SeedAln align_seed(const uint8_t *a, int la, const uint8_t *b, int lb, int pa, int pb, int k,
-                              const int8_t *sbl, const unsigned *minc, int o, int e, int X, const Ring &R,
+                              const int8_t *sbl, const int *sbl4, const unsigned *minc, int o, int e, int X,
+                              const Ring &R,
                               uint8_t *rings, int lane) {
     int sc = 0, sm = 0;
     for (int t = 0; t < k; ++t) {
@@ -477,20 +488,20 @@ __device__ SeedAln align_seed(const uint8_t *a, int la, const uint8_t *b, int lb
         rt = extend<true>(a + pa + k, la - pa - k, 1, b + pb + k, lb - pb - k, 1, sbl, o, e, X, R, lane);
         lf = extend<true>(a + pa - 1, pa, -1, b + pb - 1, pb, -1, sbl, o, e, X, R, lane);
     } else {
-        // whole sequences: kWholeMax + 64 entries of code * 25, then as many
-        // codes; rings: 256 entries of code * 25, then 256 codes
+        // whole sequences: kWholeMax + 64 entries of code * 100, then as many
+        // of code * 4; rings: 256 entries of code * 100, then 256 of code * 4
         uint16_t *ring_a = (uint16_t *)rings;
         uint8_t *whole_b = rings + 2 * (kWholeMax + kWave), *ring_b = rings + 512;
         const int ra = la - pa - k, rb = lb - pb - k;
         rt = ra <= kWholeMax && rb <= kWholeMax
-                 ? extend_reg<true>(a + pa + k, ra, 1, b + pb + k, rb, 1, sbl, minc, o, e, X, ring_a, whole_b, lane)
-                 : extend_reg<false>(a + pa + k, ra, 1, b + pb + k, rb, 1, sbl, minc, o, e, X, ring_a, ring_b, lane);
+                 ? extend_reg<true>(a + pa + k, ra, 1, b + pb + k, rb, 1, sbl4, minc, o, e, X, ring_a, whole_b, lane)
+                 : extend_reg<false>(a + pa + k, ra, 1, b + pb + k, rb, 1, sbl4, minc, o, e, X, ring_a, ring_b, lane);
         if (rt.overflow)
             lf = rt;
         else if (pa <= kWholeMax && pb <= kWholeMax)
-            lf = extend_reg<true>(a + pa - 1, pa, -1, b + pb - 1, pb, -1, sbl, minc, o, e, X, ring_a, whole_b, lane);
+            lf = extend_reg<true>(a + pa - 1, pa, -1, b + pb - 1, pb, -1, sbl4, minc, o, e, X, ring_a, whole_b, lane);
         else
-            lf = extend_reg<false>(a + pa - 1, pa, -1, b + pb - 1, pb, -1, sbl, minc, o, e, X, ring_a, ring_b, lane);
+            lf = extend_reg<false>(a + pa - 1, pa, -1, b + pb - 1, pb, -1, sbl4, minc, o, e, X, ring_a, ring_b, lane);
     }
     SeedAln s;
     s.score = lf.score + sc + rt.score;
@@ -525,11 +536,15 @@ __global__ __launch_bounds__(256, GLOBAL ? 1 : 8) void xd_kernel(const uint8_t *
                                                  uint32_t *__restrict__ redo, uint32_t *__restrict__ n_redo,
                                                  int *__restrict__ gring, unsigned long long *__restrict__ counters) {
     __shared__ int8_t sbl[kProfCodes * kProfCodes];
+    // the register band reads scores and statistics increments at the byte
+    // offset 4 * (code_a * 25 + code_b) of 32-bit tables
     // per code pair: identical pairs << 16 | diagonal columns added by a match
     // or mismatch column (codes compared, as everywhere: two pad codes match)
     __shared__ unsigned minc[kProfCodes * kProfCodes];
+    __shared__ int sbl4[GLOBAL ? 1 : kProfCodes * kProfCodes];
     for (int t = threadIdx.x; t < kProfCodes * kProfCodes; t += blockDim.x) {
         sbl[t] = blosum[t];
+        if constexpr (!GLOBAL) sbl4[t] = blosum[t];
         minc[t] = t / kProfCodes == t % kProfCodes ? 0x10001u : 1u;
     }
     __shared__ __align__(16) uint8_t lds_rings[GLOBAL ? 1 : kWavesPerBlock * kWaveLds];
@@ -583,7 +598,7 @@ __global__ __launch_bounds__(256, GLOBAL ? 1 : 8) void xd_kernel(const uint8_t *
         for (int s = 0; s < 2; ++s) {
             if (pa[s] < 0) continue;
             const SeedAln t =
-                align_seed<GLOBAL>(a, pd.la, b, pd.lb, pa[s], pb[s], k, sbl, minc, o, e, X, R, rings, lane);
+                align_seed<GLOBAL>(a, pd.la, b, pd.lb, pa[s], pb[s], k, sbl, sbl4, minc, o, e, X, R, rings, lane);
             overflow |= t.overflow;
             cells += t.cells;
             const bool pass = passes(t, pd.la, id_pct, cov_pct);

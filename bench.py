@@ -548,6 +548,7 @@ def main():
         },
         "pairs_per_s": n_cand / (ms_step * 1e-3),
         "candidates": n_cand,
+        "row_blocks": int(st["n_row_blocks"]),
         "cells": cells,
         "edges": int(edges.size),
         "direct_launch": {"ms_per_step": d_ms, "gcups": cells / (d_ms * 1e-3) / 1e9},

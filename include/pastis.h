@@ -194,6 +194,9 @@ typedef struct pastis_run_stats {
      * (each k-mer itself and its substitutes present in some sequence); 0
      * with exact k-mers */
     int64_t n_subs_entries;
+    /* row blocks the last pastis_search ran (1 unless block_entries split
+     * its discovery); 0 after the other calls */
+    int64_t n_row_blocks;
 } pastis_run_stats;
 
 typedef struct pastis_ctx pastis_ctx;

@@ -162,6 +162,7 @@ class _Stats(ctypes.Structure):
         ("sw_graph_pad", ctypes.c_int32),
         ("spgemm_products", ctypes.c_int64),
         ("n_subs_entries", ctypes.c_int64),
+        ("n_row_blocks", ctypes.c_int64),
     ]
 
 

@@ -673,7 +673,7 @@ pastis_status pastis_search(pastis_ctx *ctx, const uint8_t *residues, const int6
         }
     } parts;
     pastis_run_stats acc{};
-    int64_t n_edges = 0;
+    int64_t n_edges = 0, n_blocks = 0;
     while (!todo.empty()) {
         const std::pair<int64_t, int64_t> blk = todo.back();
         todo.pop_back();
@@ -687,6 +687,7 @@ pastis_status pastis_search(pastis_ctx *ctx, const uint8_t *residues, const int6
             todo.push_back({blk.first, mid});
             continue;
         }
+        ++n_blocks;
         if (ctx->params.filter_mode == 1) {
             PASTIS_TRY(mlp_filter_candidates(ctx, st, codes, n, s));
             nc = ctx->n_candidates;
@@ -730,6 +731,7 @@ pastis_status pastis_search(pastis_ctx *ctx, const uint8_t *residues, const int6
         if (blk.first > 0 || blk.second < n) ctx->have_candidates = false;
     }
     set_block_stats(ctx->stats, acc);
+    ctx->stats.n_row_blocks = n_blocks;
     pastis_result *res = new pastis_result();
     res->device = ctx->device;
     res->n = n_edges;

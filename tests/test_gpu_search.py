@@ -165,6 +165,7 @@ def test_row_blocks_give_the_same_edges(gpu, orc, case):
     got = blocks.search(res, off)
     assert got.tobytes() == want.tobytes()
     st = blocks.stats()
+    assert st1["n_row_blocks"] == 1 and st["n_row_blocks"] >= 4
     for f in ("n_candidates", "n_aligned", "n_edges", "cells", "stats_pass_pairs", "stats_pass_cells",
               "bound_pass_pairs", "bound_pass_cells"):
         assert st[f] == st1[f], f

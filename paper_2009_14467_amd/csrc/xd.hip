@@ -347,22 +347,16 @@ __device__ Ext extend_reg(const uint8_t *a0, int la, int adir, const uint8_t *b0
     // computed (c) and live (l) row ranges of anti-diagonals d-1 and d-2 as
     // (first row, count); count 0 = empty
     int c1 = 0, n1 = 1, l1 = 0, m1 = 1;
-    int c2 = 0, n2 = 0, l2 = 0, m2 = 0;
+    int c2 = 0, n2 = 0, l2 = 1 << 24, m2 = -(1 << 24);
     int best = 0, bu = 0, bv = 0;
     unsigned bmd = 0u;
     int cells = 0;
     bool overflow = false;
     const int dmax = la + lb;
     for (int d = 1; d <= dmax; ++d) {
-        int lo = INT_MAX, hi = -1;
-        if (m1 > 0) {
-            lo = l1;
-            hi = l1 + m1;
-        }
-        if (m2 > 0) {
-            lo = min(lo, l2 + 1);
-            hi = max(hi, l2 + m2);
-        }
+        // both live ranges are non-empty: an empty one ends the loop, and
+        // the one before anti-diagonal 0 is a range that bounds nothing
+        int lo = min(l1, l2 + 1), hi = max(l1 + m1, l2 + m2);
         lo = uni(max(lo, max(0, d - lb)));
         hi = uni(min(hi, min(d, la)));
         if (lo > hi) break;

@@ -344,19 +344,19 @@ __device__ Ext extend_reg(const uint8_t *a0, int la, int adir, const uint8_t *b0
     unsigned SH1 = 0u, SE1 = 0u, SF1 = 0u;
     int VH = kNeg;  // lane u-1's H two anti-diagonals back (rotated one step ago)
     unsigned VSH = 0u;
-    // computed (c) and live (l) row ranges of anti-diagonals d-1 and d-2 as
-    // (first row, count); count 0 = empty
-    int c1 = 0, n1 = 1, l1 = 0, m1 = 1;
-    int c2 = 0, n2 = 0, l2 = 1 << 24, m2 = -(1 << 24);
+    // computed row ranges of anti-diagonals d-1 and d-2 as (first row,
+    // count), and their live rows [s, e); s2p is d-2's first live row plus
+    // one.  The range before anti-diagonal 0 bounds nothing.
+    int c1 = 0, n1 = 1, s1 = 0, e1 = 1;
+    int c2 = 0, n2 = 0, s2p = 1 << 24, e2 = -(1 << 24);
     int best = 0, bu = 0, bv = 0;
     unsigned bmd = 0u;
     int cells = 0;
     bool overflow = false;
-    const int dmax = la + lb;
-    for (int d = 1; d <= dmax; ++d) {
-        // both live ranges are non-empty: an empty one ends the loop, and
-        // the one before anti-diagonal 0 is a range that bounds nothing
-        int lo = min(l1, l2 + 1), hi = max(l1 + m1, l2 + m2);
+    // past anti-diagonal la + lb the range is empty (lo >= d - lb > la >= hi)
+    for (int d = 1;; ++d) {
+        // both live ranges are non-empty: an empty one ends the loop
+        int lo = min(s1, s2p), hi = max(e1, e2);
         lo = uni(max(lo, max(0, d - lb)));
         hi = uni(min(hi, min(d, la)));
         if (lo > hi) break;
@@ -377,7 +377,7 @@ __device__ Ext extend_reg(const uint8_t *a0, int la, int adir, const uint8_t *b0
         // that row was not computed.  Only a band of 64 rows reuses a lane
         // for another row, and then the ranges are checked.
         int Hu = rH, Fu = rF, Hl = H1, El = E1, Hd = VH;
-        if (n1 == kWave || n2 == kWave) {
+        if ((n1 | n2) & kWave) {  // a width of 64 (widths never exceed it)
             const int nh = uni(max(min(c1 + n1, d) - c1, 0));  // rows of d-1 in [c1, d-1]
             const bool okv = in_range(u, c1 + 1, n1);
             const bool okh = in_range(u, c1, nh);
@@ -429,13 +429,13 @@ __device__ Ext extend_reg(const uint8_t *a0, int la, int adir, const uint8_t *b0
         const unsigned long long lm = rotr64(wave_mask_ne(H1, kNeg), sh);
         c2 = c1;
         n2 = n1;
-        l2 = l1;
-        m2 = m1;
+        s2p = s1 + 1;
+        e2 = e1;
         c1 = lo;
         n1 = hi - lo + 1;
         if (lm == 0ull) break;
-        l1 = lo + __ffsll((long long)lm) - 1;
-        m1 = lo + 64 - __clzll((long long)lm) - l1;
+        s1 = lo + __ffsll((long long)lm) - 1;
+        e1 = lo + 64 - __clzll((long long)lm);
         const unsigned long long up = wave_mask_gt(H1, best);
         if (up != 0ull) {
             const int dbest = wave_max_dpp(live ? H_ : INT_MIN);

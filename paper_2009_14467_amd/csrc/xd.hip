@@ -305,6 +305,13 @@ __device__ __forceinline__ int wave_max_dpp(int v) {
 
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// An empty statement that hands x back in a scalar register: it emits no
+// instruction, but the compiler can no longer fold the expressions on its two
+// sides into one three-operand vector max / min, which would move the
+// wave-uniform band range through vector registers and back (seven vector
+// instructions instead of four scalar ones per anti-diagonal)
+__device__ __forceinline__ void sgpr_opaque(int &x) { asm("" : "+s"(x)); }
+
 // (unsigned)(x - base) < len: x in [base, base + len) with one compare
 __device__ __forceinline__ bool in_range(int x, int base, int len) { return (unsigned)(x - base) < (unsigned)len; }
 
@@ -357,8 +364,11 @@ __device__ Ext extend_reg(const uint8_t *a0, int la, int adir, const uint8_t *b0
     for (int d = 1;; ++d) {
         // both live ranges are non-empty: an empty one ends the loop
         int lo = min(s1, s2p), hi = max(e1, e2);
-        lo = uni(max(lo, max(0, d - lb)));
-        hi = uni(min(hi, min(d, la)));
+        int lo_floor = max(0, d - lb), hi_ceil = min(d, la);
+        sgpr_opaque(lo_floor);
+        sgpr_opaque(hi_ceil);
+        lo = max(lo, lo_floor);
+        hi = min(hi, hi_ceil);
         if (lo > hi) break;
         if (hi - lo + 1 > kWave) {
             overflow = true;

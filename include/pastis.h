@@ -107,7 +107,8 @@ typedef struct pastis_params {
                                  2^32 - 16 that 32-bit indices allow).  A block is the set
                                  of pairs whose lower sequence index falls in a range;
                                  the search starts with one block of every sequence and
-                                 halves a block whose entries exceed this, then discovers,
+                                 splits a block whose entries exceed this (into parts
+                                 sized from the entries it asked for), then discovers,
                                  aligns and cuts the blocks one after the other, so the
                                  discovery's memory follows one block's entries (24 bytes
                                  each, plus the sort's second buffer) and the edges are

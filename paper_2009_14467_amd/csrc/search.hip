@@ -4,6 +4,7 @@
 // the discovery stage and the result handle.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <utility>
 #include <vector>
 
@@ -322,11 +323,12 @@ pastis_status discover_tables(pastis_ctx *ctx, const Staged &st, const uint8_t *
 
 // Discovery, second part: the candidate pairs (lo, hi) with r0 <= lo < r1
 // into kBufCand*, sorted by (lo, hi); their count in *n_cand_out.  A block
-// whose directional entries would exceed `limit` sets *split (when it may
-// be split and holds more than one sequence) and produces nothing; otherwise
-// such a block fails with PASTIS_E_CAPACITY.
+// whose directional entries would exceed `limit` sets *split_need to the
+// entries it asked for (when it may be split and holds more than one
+// sequence) and produces nothing; otherwise such a block fails with
+// PASTIS_E_CAPACITY.
 pastis_status discover_block(pastis_ctx *ctx, DiscTables &dt, int64_t n, int64_t r0, int64_t r1, uint64_t limit,
-                             bool may_split, hipStream_t s, int64_t *n_cand_out, bool *split) {
+                             bool may_split, hipStream_t s, int64_t *n_cand_out, uint64_t *split_need) {
     const pastis_params &P = ctx->params;
     Misc M;
     PASTIS_TRY(misc(ctx, M));
@@ -335,7 +337,7 @@ pastis_status discover_block(pastis_ctx *ctx, DiscTables &dt, int64_t n, int64_t
     sp.kt = &dt.kt;
     sp.blk_lo = (uint32_t)r0;
     sp.blk_hi = (uint32_t)r1;
-    if (split) *split = false;
+    if (split_need) *split_need = 0;
 
     // ---- sparse product
     HIP_TRY(ctx, stage_begin(ctx, kStSpgemm, s), "event");
@@ -395,7 +397,7 @@ pastis_status discover_block(pastis_ctx *ctx, DiscTables &dt, int64_t n, int64_t
         PASTIS_TRY(read_device(ctx, M.d_count, &need, sizeof(need), s));
         if (need > limit && may_split && r1 - r0 > 1) {
             HIP_TRY(ctx, stage_end(ctx, kStSpgemm, s), "event");
-            *split = true;
+            *split_need = need;
             *n_cand_out = 0;
             return PASTIS_OK;
         }
@@ -661,7 +663,7 @@ pastis_status pastis_search(pastis_ctx *ctx, const uint8_t *residues, const int6
     const int ns = ctx->params.weight_mode == PASTIS_WEIGHT_NS;
     const uint64_t limit = ctx->params.block_entries > 0 ? (uint64_t)ctx->params.block_entries : kMaxDir;
     // Row blocks (the pairs whose lower index falls in [r0, r1)), the next
-    // one last.  A block whose discovery would exceed the limit is halved;
+    // one last.  A block whose discovery would exceed the limit is split;
     // blocks run in order of r0, so their edges, each sorted, concatenate
     // into the sorted edge list.
     std::vector<std::pair<int64_t, int64_t>> todo{{0, n}};
@@ -679,12 +681,32 @@ pastis_status pastis_search(pastis_ctx *ctx, const uint8_t *residues, const int6
         todo.pop_back();
         clear_block_stats(ctx->stats);
         int64_t nc = 0;
-        bool split = false;
-        PASTIS_TRY(discover_block(ctx, dt, n, blk.first, blk.second, limit, true, s, &nc, &split));
-        if (split) {
-            const int64_t mid = blk.first + (blk.second - blk.first) / 2;
-            todo.push_back({mid, blk.second});
-            todo.push_back({blk.first, mid});
+        uint64_t need = 0;
+        PASTIS_TRY(discover_block(ctx, dt, n, blk.first, blk.second, limit, true, s, &nc, &need));
+        if (need) {
+            // split into enough parts for the entries it asked for, with a
+            // quarter to spare, at rows that give each part an equal share of
+            // pairs if those spread evenly (row x is the lower index of about
+            // n - 1 - x pairs); a part that still overflows is split again
+            const int64_t r0 = blk.first, r1 = blk.second;
+            const int64_t k = std::max<int64_t>(
+                2, std::min<int64_t>(r1 - r0, (int64_t)std::ceil(1.25 * (double)need / (double)limit)));
+            auto area = [&](int64_t x) { return 0.5 * (double)(x - r0) * (double)(2 * n - r0 - x + 1); };
+            std::vector<int64_t> cut{r0};
+            for (int64_t i = 1; i < k; ++i) {
+                const double target = area(r1) * (double)i / (double)k;
+                int64_t lo_x = cut.back() + 1, hi_x = r1 - (k - i);  // leave a row for each later part
+                while (lo_x < hi_x) {
+                    const int64_t mid = lo_x + (hi_x - lo_x) / 2;
+                    if (area(mid) >= target)
+                        hi_x = mid;
+                    else
+                        lo_x = mid + 1;
+                }
+                cut.push_back(lo_x);
+            }
+            cut.push_back(r1);
+            for (size_t i = cut.size() - 1; i > 0; --i) todo.push_back({cut[i - 1], cut[i]});
             continue;
         }
         ++n_blocks;

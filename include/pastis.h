@@ -465,10 +465,10 @@ pastis_status pastis_set_tuning(pastis_ctx *ctx, const pastis_tuning *t);
  * sequences sized for about max_pairs candidates (at most max_pairs), so the
  * pairs that share a sequence stay together as in the whole set.  A value
  * replaces the one in force only when it is at least 1% faster on the
- * sample.  When the sample is smaller than the candidate set, three knobs
+ * sample.  When the sample is smaller than the candidate set, the knobs
  * whose effect lies in the tails of the launches, which shrink with the
  * sample (start-bound routing: 25, 50, 75, 100; inter- vs intra-pair mode;
- * the long bins' grid), are then timed once more per value on all the
+ * the long bins' grid; the two grid scales), are then timed once more per value on all the
  * candidates, where a 0.5% margin applies (skipped for sets of over 2^26
  * candidates, or when one alignment of all of them takes over 2 s).  The
  * discovery's candidates stay in ctx. */

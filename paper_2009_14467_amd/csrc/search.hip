@@ -1017,7 +1017,7 @@ pastis_status pastis_autotune(pastis_ctx *ctx, const uint8_t *residues, const in
             };
             double all_ms = 0;
             PASTIS_TRY(time_all(&all_ms));
-            // at most about 8 more runs: skipped where one takes over 2 s
+            // at most about 12 more runs: skipped where one takes over 2 s
             if (all_ms > 2000.0) {
                 if (out) *out = ctx->tune;
                 return PASTIS_OK;
@@ -1045,6 +1045,10 @@ pastis_status pastis_autotune(pastis_ctx *ctx, const uint8_t *residues, const in
             PASTIS_TRY(refine(&ctx->tune.sw_direct_pct, route, 4));
             PASTIS_TRY(refine(&ctx->tune.sw_intra_pair, intra, 2));
             PASTIS_TRY(refine(&ctx->tune.sw_long_blocks, longb, 3));
+            // the grids of the one-strip bins, whose ends also shorten with
+            // the sample (about 1% of large's step between their values)
+            PASTIS_TRY(refine(&ctx->tune.sw_grid_scale_wide, grid, 3));
+            PASTIS_TRY(refine(&ctx->tune.sw_grid_scale, grid, 3));
         }
     }
     if (out) *out = ctx->tune;

@@ -428,9 +428,14 @@ __device__ Ext extend_reg(const uint8_t *a0, int la, int adir, const uint8_t *b0
         const bool any = u <= hi && max(Hd, max(Hu, Hl)) > kNeg / 2;
         const bool live = any && H_ >= best - X;
         cells += any ? 1 : 0;
+        // Only H is cleared where the cell is dead.  A dead cell's E and F
+        // are at most its H, below best - X; the gap chains they start only
+        // fall, while best - X only rises, so they never reach a live
+        // cell's H (nor tie with it) and choose neither its value nor its
+        // statistics.
         H1 = live ? H_ : kNeg;
-        E1 = live ? E_ : kNeg;
-        F1 = live ? F_ : kNeg;
+        E1 = E_;
+        F1 = F_;
         SH1 = sH_;
         SE1 = sE_;
         SF1 = sF_;
